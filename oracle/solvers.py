@@ -1,0 +1,90 @@
+"""Iterative solvers on a (local) operator W_L (test infrastructure only).
+
+Objective (Section 2.3, eq. priorsys), taken literally - no 1/2 on the data term:
+
+    min_{x in D}  ||W_L x - b||_2^2 + lambda * TV(x),   D = {x >= 0}.
+
+Chambolle-Pock (the primal-dual method the paper cites among solvers for
+eq. priorsys; Chambolle & Pock 2011, Algorithm 1 with theta = 1) on
+K = [W_L; grad], F(v, g) = ||v - b||^2 + lambda sum_j ||g_j||_2, G = indicator(D):
+
+    y  <- (y + sigma (W_L xbar - b)) / (1 + sigma/2)        prox of sigma F1*
+    z  <- proj_{||z_j|| <= lambda}(z + sigma grad xbar)      prox of sigma F2*
+    x+ <- max(0, x - tau (W_L^T y - div z))                  prox of tau G
+    xbar <- x+ + theta (x+ - x);  x <- x+
+
+Start x = xbar = 0, y = 0, z = 0 (the local iterations of the paper also start
+from zero images).  Step sizes sigma = tau = 1/L with L^2 = 1.01 * lambda_max
+(W_L^T W_L - Laplacian) from a power iteration (CP requires sigma tau L^2 < 1).
+
+Nonnegative SIRT: eq. sirtit with the box projection of eq. sirtbox (l = 0,
+r = +inf), alpha = 1/(N_theta N_d) as fixed in Section 3.1.
+"""
+
+import numpy as np
+
+from .tv import grad, div, tv_iso, tv_aniso
+
+
+def _apply_k(WL, shape, x):
+    return WL @ x.ravel(), grad(x.reshape(shape))
+
+
+def power_norm_sq(WL, shape, iters=100):
+    """lambda_max(W_L^T W_L + grad^T grad) by power iteration from the all-ones image."""
+    v = np.ones(shape)
+    est = 0.0
+    for _ in range(iters):
+        w = (WL.T @ (WL @ v.ravel())).reshape(shape) - div(grad(v))
+        est = float(np.linalg.norm(w) / np.linalg.norm(v))
+        v = w / np.linalg.norm(w)
+    return est
+
+
+def cp_steps(WL, shape, iters=100, safety=1.01):
+    """sigma = tau = 1 / sqrt(safety * ||K||^2)."""
+    L2 = safety * power_norm_sq(WL, shape, iters)
+    s = 1.0 / np.sqrt(L2)
+    return s, s
+
+
+def cp_tv_nonneg(WL, b, shape, lam, sigma, tau, iters, theta=1.0, half=False, aniso=False,
+                 nonneg=True, x0=None, callback=None):
+    """K Chambolle-Pock iterations; returns the final primal iterate (rows, cols)."""
+    b = np.asarray(b, dtype=np.float64).ravel()
+    x = np.zeros(shape) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    xbar = x.copy()
+    y = np.zeros(WL.shape[0])
+    z = np.zeros((2,) + tuple(shape))
+    dual_scale = 1.0 + (sigma if half else sigma / 2.0)
+    for it in range(iters):
+        y = (y + sigma * (WL @ xbar.ravel() - b)) / dual_scale
+        z = z + sigma * grad(xbar)
+        if aniso:
+            z = np.clip(z, -lam, lam)
+        else:
+            nrm = np.sqrt(z[0] ** 2 + z[1] ** 2)
+            z = z / np.maximum(1.0, nrm / lam) if lam > 0 else np.zeros_like(z)
+        xn = x - tau * ((WL.T @ y).reshape(shape) - div(z))
+        if nonneg:
+            xn = np.maximum(0.0, xn)
+        xbar = xn + theta * (xn - x)
+        x = xn
+        if callback is not None:
+            callback(it, x)
+    return x
+
+
+def cp_objective(WL, b, x, lam, half=False, aniso=False):
+    r = WL @ np.asarray(x).ravel() - np.asarray(b).ravel()
+    data = float(r @ r) * (0.5 if half else 1.0)
+    return data + lam * (tv_aniso(x) if aniso else tv_iso(x))
+
+
+def sirt_nonneg(WL, b, shape, alpha, iters, lo=0.0, hi=np.inf, x0=None):
+    """x <- clip(x + alpha W_L^T (b - W_L x), lo, hi), from x0 = 0."""
+    b = np.asarray(b, dtype=np.float64).ravel()
+    x = np.zeros(int(np.prod(shape))) if x0 is None else np.asarray(x0, np.float64).ravel().copy()
+    for _ in range(iters):
+        x = np.clip(x + alpha * (WL.T @ (b - WL @ x)), lo, hi)
+    return x.reshape(shape)

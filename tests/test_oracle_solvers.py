@@ -1,0 +1,159 @@
+"""Pins for the oracle's solvers: Chambolle-Pock for eq. (priorsys) with TV and x >= 0,
+nonnegative SIRT (eq. sirtit + eq. sirtbox), and the power-iteration step size."""
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.optimize as sopt
+import scipy.sparse as sp
+
+import oracle
+
+
+def _grad_matrix(rows, cols):
+    """Forward differences (Neumann) as an explicit 2P x P matrix, built by loops -
+    independent of the oracle's array code."""
+    P = rows * cols
+    D = np.zeros((2 * P, P))
+    for r in range(rows):
+        for c in range(cols):
+            j = r * cols + c
+            if r + 1 < rows:
+                D[j, j] -= 1.0
+                D[j, j + cols] += 1.0
+            if c + 1 < cols:
+                D[P + j, j] -= 1.0
+                D[P + j, j + 1] += 1.0
+    return D
+
+
+def _admm_tv_nonneg(W, b, rows, cols, lam, rho=None, iters=100000):
+    """Independent minimiser of ||Wx - b||^2 + lam sum_j ||(Dx)_j||_2 s.t. x >= 0 (ADMM
+    with splittings u = Dx, v = x; dense Cholesky solves)."""
+    P = rows * cols
+    D = _grad_matrix(rows, cols)
+    if rho is None:
+        rho = float(np.linalg.norm(W, 2) ** 2)
+    A = 2 * W.T @ W + rho * D.T @ D + rho * np.eye(P)
+    cf = sla.cho_factor(A)
+    Wb2 = 2 * W.T @ b
+    u = np.zeros(2 * P); a = np.zeros(2 * P)
+    v = np.zeros(P); c = np.zeros(P)
+    for _ in range(iters):
+        x = sla.cho_solve(cf, Wb2 + rho * D.T @ (u - a) + rho * (v - c))
+        Dx = D @ x
+        q = Dx + a
+        nrm = np.sqrt(q[:P] ** 2 + q[P:] ** 2)
+        scale = np.maximum(0.0, 1.0 - (lam / rho) / np.maximum(nrm, 1e-300))
+        u = np.concatenate([q[:P] * scale, q[P:] * scale])
+        v = np.maximum(0.0, x + c)
+        a += Dx - u
+        c += x - v
+    return v.reshape(rows, cols)
+
+
+def test_power_iteration_matches_eigvalsh():
+    g = oracle.make_geometry(8, 6, 12)
+    rect = (0, 0, 8, 8)
+    WL = oracle.sparse_local(g, rect)
+    D = _grad_matrix(8, 8)
+    M = WL.toarray().T @ WL.toarray() + D.T @ D
+    lam_max = np.linalg.eigvalsh(M)[-1]
+    assert oracle.power_norm_sq(WL, (8, 8), iters=500) == pytest.approx(lam_max, rel=1e-9)
+    s, t = oracle.cp_steps(WL, (8, 8), iters=500)
+    assert s * t * lam_max < 1.0
+
+
+@pytest.mark.parametrize("n,na,nd,lam", [(8, 6, 12, 3.0), (12, 5, 17, 1.5)])
+def test_cp_converges_to_independent_admm_minimiser(n, na, nd, lam):
+    """CP's objective approaches the minimum found by an independent ADMM minimiser
+    (ADMM itself agrees across penalty parameters to 1e-8), on tiny problems with TV
+    and x >= 0 active.  CP's objective gap decays like O(1/k): under 3e-5 relative
+    after 40000 iterations and at least 4x smaller than after 10000."""
+    g = oracle.make_geometry(n, na, nd)
+    rng = np.random.default_rng(n)
+    truth = np.zeros((n, n))
+    truth[2:n - 3, 3:n - 2] = 1.0
+    truth[4:6, 4:7] = 0.0
+    WL = oracle.sparse_local(g)
+    b = WL @ truth.ravel() + 0.3 * rng.standard_normal(WL.shape[0])
+    W = WL.toarray()
+    rho = float(np.linalg.norm(W, 2) ** 2)
+    f1 = oracle.cp_objective(WL, b, _admm_tv_nonneg(W, b, n, n, lam, rho=rho, iters=10000), lam)
+    f2 = oracle.cp_objective(WL, b, _admm_tv_nonneg(W, b, n, n, lam, rho=rho / 10, iters=10000), lam)
+    assert abs(f1 - f2) <= 1e-8 * f1
+    s, t = oracle.cp_steps(WL, (n, n), iters=300)
+    gaps = []
+    x_cp = None
+
+    def cb(it, x):
+        nonlocal x_cp
+        if it + 1 in (10000, 40000):
+            gaps.append(oracle.cp_objective(WL, b, x, lam) - f1)
+            x_cp = x
+    oracle.cp_tv_nonneg(WL, b, (n, n), lam, s, t, 40000, callback=cb)
+    assert x_cp.min() >= 0.0 and (x_cp == 0).sum() > 0          # nonnegativity active
+    assert gaps[1] >= -1e-9 * f1                                  # ADMM found the minimum
+    assert gaps[1] <= 3e-5 * f1, gaps
+    assert gaps[1] * 4 <= gaps[0], gaps
+
+
+def test_cp_unregularised_converges_to_exact_solution():
+    """lambda = 0 and no prox: with consistent data and W_L of full column rank, CP
+    converges to the unique solution (the phantom)."""
+    g = oracle.make_geometry(32, 64, 48)
+    rng = np.random.default_rng(5)
+    truth = rng.random((8, 8))
+    rect = (12, 12, 8, 8)
+    WL = oracle.sparse_local(g, rect)
+    b = WL @ truth.ravel()
+    assert np.linalg.matrix_rank(WL.toarray()) == 64
+    s, t = oracle.cp_steps(WL, (8, 8))
+    x = oracle.cp_tv_nonneg(WL, b, (8, 8), 0.0, s, t, 5000, nonneg=False)
+    assert np.abs(x - truth).max() < 1e-6
+
+
+def test_cp_half_flag_changes_dual_prox():
+    g = oracle.make_geometry(8, 4, 12)
+    WL = oracle.sparse_local(g)
+    b = WL @ np.ones(64)
+    x1 = oracle.cp_tv_nonneg(WL, b, (8, 8), 0.1, 0.1, 0.1, 5)
+    x2 = oracle.cp_tv_nonneg(WL, b, (8, 8), 0.1, 0.1, 0.1, 5, half=True)
+    assert np.abs(x1 - x2).max() > 1e-6
+
+
+def test_cp_is_stable_under_data_perturbation():
+    """A 1e-6 relative change of b moves the 100th iterate by <= 1e-5 relative:
+    FP32-level input differences cannot be amplified past the 1e-3 parity bar."""
+    g = oracle.make_geometry(64, 32, 96)
+    rng = np.random.default_rng(6)
+    truth = np.zeros((64, 64)); truth[10:50, 20:40] = 1.0
+    WL = oracle.sparse_local(g)
+    b = WL @ truth.ravel() + 0.5 * rng.standard_normal(WL.shape[0])
+    s, t = oracle.cp_steps(WL, (64, 64))
+    x1 = oracle.cp_tv_nonneg(WL, b, (64, 64), 5.0, s, t, 100)
+    db = 1e-6 * np.linalg.norm(b) * rng.standard_normal(len(b)) / np.sqrt(len(b))
+    x2 = oracle.cp_tv_nonneg(WL, b + db, (64, 64), 5.0, s, t, 100)
+    assert np.linalg.norm(x2 - x1) <= 1e-5 * np.linalg.norm(x1)
+
+
+def test_sirt_nonneg_reaches_nnls_solution():
+    """Projected Landweber with alpha = 1/(N_theta N_d) converges to the
+    nonnegative least-squares solution (compared with scipy's NNLS)."""
+    g = oracle.make_geometry(6, 8, 10)
+    rng = np.random.default_rng(7)
+    WL = oracle.sparse_local(g)
+    b = WL @ (rng.random(36) - 0.3) + 0.05 * rng.standard_normal(WL.shape[0])
+    alpha = 1.0 / (8 * 10)
+    x = oracle.sirt_nonneg(WL, b, (6, 6), alpha, 60000)
+    ref, _ = sopt.nnls(WL.toarray(), b, maxiter=10000)
+    assert np.abs(x.ravel() - ref).max() < 1e-8
+
+
+def test_sirt_step_is_stable_for_workload_geometry():
+    """alpha ||W_L||^2 < 2 for the 128-grid workload's local part (Landweber condition)."""
+    import scipy.sparse.linalg as sla2
+    g = oracle.make_geometry(128, 32, 192)
+    WL = oracle.sparse_local(g, (32, 32, 64, 64))
+    smax = sla2.svds(WL, k=1, return_singular_vectors=False)[0]
+    assert smax ** 2 / (32 * 192) < 2.0
