@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Benchmark of the local-ROI hot path on one MI355X.
+
+One step = one complete local reconstruction of the single-ROI workload:
+1024^2 grid, 128 angles, 1536 bins, Poisson noise (I0 = 1e4), 128^2 ROI with
+a 32 px margin (192^2 extended part): Ram-Lak FBP exterior estimate of the
+whole sinogram, exterior subtraction on the ROI's detector band, 300 CP
+iterations (TV lambda = 0.02 + nonnegativity), crop.  The sinogram is resident
+in HBM before timing starts.  The CP step size is a per-(geometry, shape)
+plan computed once by a power iteration and cached, like an FFT plan.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Roofline peaks.  FP/BP are bound by the vector ALU (nothing is a dense
+# contraction and the algorithmic intensity is ~10-60 updates per HBM byte):
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.32e12 FP32 lane-instructions/s,
+# and one Joseph update needs at least 4.5 of them (per pair of taps: position,
+# clamp, fraction, index, address, then difference, FMA and sum).
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+OPS_PER_UPDATE = 4.5
+PEAK_UPDATES = VALU_LANE_OPS / OPS_PER_UPDATE
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(d, cfg, roi, margin):
+    """The FP64 oracle on a bounded sample of the same workload: full FBP,
+    exterior subtraction, step size and 10 of the 300 CP iterations; the full
+    solve time is the sum with the iteration time scaled by 30."""
+    import oracle
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    geo = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    sino = d["sino"].astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    xe = oracle.fbp_ramlak(geo, sino, workers=cores)
+    t_fbp = time.perf_counter() - t0
+    ext = oracle.roi_extend(roi, margin, cfg["n"])
+    t0 = time.perf_counter()
+    WL = oracle.sparse_local(geo, ext)
+    used = np.zeros(geo.n_angles * geo.n_det, bool)
+    used[np.unique(WL.tocoo().row)] = True
+    b = oracle.exterior_subtract(geo, sino, xe, ext, bins=used.reshape(geo.n_angles, geo.n_det))
+    t_ext = time.perf_counter() - t0
+    shape = (ext[2], ext[3])
+    t0 = time.perf_counter()
+    s, t = oracle.cp_steps(WL, shape)
+    t_step = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.cp_tv_nonneg(WL, b, shape, cfg["lam"], s, t, 10)
+    t_10 = time.perf_counter() - t0
+    est = t_fbp + t_ext + t_step + t_10 * cfg["iters"] / 10.0
+    log(f"cpu oracle: fbp {t_fbp:.2f}s ext {t_ext:.2f}s step {t_step:.2f}s 10 its {t_10:.2f}s "
+        f"-> {est:.1f}s per solve")
+    return {"value": 1.0 / est, "unit": "ROI solves/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 NumPy oracle: full Ram-Lak FBP (cores worker processes), exterior "
+                      "subtraction, power-iteration step size and 10 of the 300 CP iterations "
+                      "(single thread); the 300-iteration solve time is extrapolated "
+                      f"(measured {t_fbp + t_ext + t_step + t_10:.1f}s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "ROI solves are independent and would be sharded across GPUs without "
+              "per-iteration communication, but no multi-GPU path is built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1604_02292_amd import Context, make_params
+
+    d = synth.make_inputs("c2", with_image=False)
+    cfg = d["cfg"]
+    r0, c0, rr, cc, margin = synth.roi_list("c2")[0]
+    roi = (r0, c0, rr, cc)
+    ctx = Context(0, workspace_bytes=8 << 30)
+    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    prm = make_params(roi, margin, "cp", cfg["lam"], cfg["iters"])
+    sino = torch.from_numpy(d["sino"].astype(np.float32)).cuda()
+    out = torch.empty((rr, cc), dtype=torch.float32, device="cuda")
+    ext = ctx.tomo_roi_ext(g, roi, margin)
+    nnz = ctx.tomo_roi_nnz(g, ext)
+
+    for _ in range(args.warmup):
+        ctx.roi_solve(g, sino, prm, out)
+    torch.cuda.synchronize()
+
+    # timed region: per-step latency (launch to completion) with HIP events
+    # around every FP / BP launch of the iterations, on the solve's stream
+    ctx.tomo_kernel_timing(True)
+    ctx.tomo_kernel_time(0, reset=True)
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        ctx.roi_solve(g, sino, prm, out)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    t_end = time.perf_counter()
+    ctx.tomo_kernel_timing(False)
+    n_fp, ms_fp = ctx.tomo_kernel_time(0)
+    n_bp, ms_bp = ctx.tomo_kernel_time(1)
+    total = t_end - t_start
+    fp_us = 1e3 * ms_fp / max(1, n_fp)
+    bp_us = 1e3 * ms_bp / max(1, n_bp)
+    fp_rate = nnz / (fp_us * 1e-6)
+    bp_rate = nnz / (bp_us * 1e-6)
+    log(f"steps {args.steps} total {total:.3f}s; fp {n_fp} launches avg {fp_us:.2f}us "
+        f"({fp_rate / 1e9:.1f} Gupd/s), bp {n_bp} avg {bp_us:.2f}us ({bp_rate / 1e9:.1f} Gupd/s); "
+        f"nnz/launch {nnz}")
+    dom_bp = ms_bp >= ms_fp
+    rate = bp_rate if dom_bp else fp_rate
+    roofline = {"bound": "alu", "kernel": "bp_kernel" if dom_bp else "fp_kernel",
+                "achieved": rate / 1e9, "peak": PEAK_UPDATES / 1e9, "unit": "Gupdate/s",
+                "frac": rate / PEAK_UPDATES, "traffic": None,
+                "avg_launch_us": bp_us if dom_bp else fp_us, "updates_per_launch": nnz}
+    res = {
+        "metric": "ROI solves/s (single 128^2 ROI, 300 CP-TV iterations, FBP exterior)",
+        "value": args.steps / total, "unit": "ROI solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded random-ellipse phantom, exact line integrals, Poisson noise)",
+        "config": {"workload": "single-roi-1024: 1024^2 grid, 128 angles, 1536 bins, "
+                               "128^2 ROI + 32 px margin, CP-TV lambda 0.02 + nonneg, 300 its",
+                   "extended_roi": list(ext)},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "fp_updates_per_s": fp_rate, "bp_updates_per_s": bp_rate,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(d, cfg, roi, margin)
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * tomo.h - C ABI of the MI355X local-ROI tomography library.
+ *
+ * Method: D. M. Pelt, K. J. Batenburg, "A method for locally approximating
+ * regularized iterative tomographic reconstruction methods" (arXiv 1604.02292).
+ * Section 2.1 defines the data p (N_d N_theta line integrals), the image x
+ * (N x N pixels), the projector W, its transpose, and the local / outer
+ * operators W_L = W M_L, W_F = W M_F with W = W_L + W_F (eq. 1, eq. locouter).
+ * Section 2.2 defines FBP(p, h) = W^T C_h p; Section 2.3 the regularised
+ * problem argmin_{x in D} ||p - W x||^2 + lambda g(x) (eq. priorsys), here with
+ * D = {x >= 0} and g = TV.  Section 3.3 pads the local part on each side and
+ * crops the result; Section 5.6 reconstructs independent local parts in
+ * parallel and places them side by side.
+ *
+ * Conventions (all sizes in pixels; FP32 data, row-major, contiguous):
+ *   pixel (r, c) of the N x N grid has centre x = c - (N-1)/2, y = r - (N-1)/2;
+ *   detector bin i has centre s_i = (i - (N_d-1)/2) * det_spacing + det_offset;
+ *   a sinogram is float[N_theta][N_d] (detector index fastest);
+ *   a ray is {x cos(theta) + y sin(theta) = s}.  W uses Joseph interpolation:
+ *   w = max(0, 1 - |s_i - t| / m) / m,  t = x cos + y sin,  m = max(|cos|, |sin|).
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller (e.g. a
+ * torch tensor's data_ptr) unless stated otherwise.  The library allocates no
+ * device memory of its own: all internal state lives in the caller-supplied
+ * workspace given to tomo_create, whose size is also the HBM budget that
+ * admission control in roi_submit works against.
+ *
+ * Streams: calls taking `hip_stream` enqueue on that hipStream_t (NULL = the
+ * null stream) and return before the GPU work is done, unless stated.
+ *
+ * Errors: every call returns a tomo_status; nothing aborts or throws across
+ * the ABI.  The text of the last error on a context is tomo_last_error(ctx).
+ * A context may be used from one host thread at a time; the serving calls
+ * (roi_submit / roi_poll) may be called while the library's own scheduler
+ * thread runs.
+ */
+#ifndef TOMO_H
+#define TOMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TOMO_OK = 0,
+    TOMO_EINVAL = -1,   /* invalid argument (size < 1, rect outside grid, null pointer, ...) */
+    TOMO_ENOMEM = -2,   /* the request cannot fit in the workspace, even when it is empty */
+    TOMO_EHIP = -3,     /* a HIP runtime error; see tomo_last_error */
+    TOMO_EBUSY = -4,    /* the resource is in use (e.g. unregistering a sinogram with live requests) */
+    TOMO_ENOENT = -5,   /* unknown geometry id, sinogram id or ticket */
+    TOMO_EAGAIN = -6,   /* the bounded request queue is full; try again later */
+    TOMO_ESTATE = -7    /* call not valid in this state (e.g. GPU call on a host-only context) */
+} tomo_status;
+
+typedef struct tomo_ctx tomo_ctx;
+
+/* Half-open rectangle of pixels on the global N x N lattice. */
+typedef struct { int32_t row0, col0, rows, cols; } tomo_rect;
+
+/* Create a context on HIP device `device` using the caller's device buffer
+ * `workspace` of `workspace_bytes` bytes (kept alive by the caller until
+ * tomo_destroy).  device = -1 creates a host-only planning context that
+ * accepts tomo_set_geometry / tomo_roi_band / tomo_roi_ext only.
+ * Errors: EINVAL (null out, device < -1, workspace NULL or < 1 MiB on a GPU
+ * context), EHIP. */
+tomo_status tomo_create(int device, void* workspace, size_t workspace_bytes, tomo_ctx** out);
+
+/* Stop the scheduler thread, wait for the GPU work the context issued, free host state.
+ * The workspace is not freed (it belongs to the caller). */
+tomo_status tomo_destroy(tomo_ctx* ctx);
+
+/* Text of the last error on ctx; valid until the next call on ctx.  Never NULL. */
+const char* tomo_last_error(const tomo_ctx* ctx);
+
+/* Define a parallel-beam geometry (Section 2.1): an n x n grid, n_angles angles
+ * (angles = host array of n_angles radians, or NULL for theta_k = k pi / n_angles),
+ * n_det bins of width det_spacing (>= 1 pixel) shifted by det_offset.  The
+ * Joseph branch (|cos| >= |sin|: step along rows) is decided here in FP64.
+ * Returns a geometry id in *geom_id.  Errors: EINVAL. */
+tomo_status tomo_set_geometry(tomo_ctx* ctx, int32_t n, int32_t n_angles, int32_t n_det,
+                              const double* angles, double det_spacing, double det_offset,
+                              int32_t* geom_id);
+
+/* Detector band of a region (the nonzero rows of W_L, Section 2.1, widened by
+ * one bin on each side and NOT clipped to the detector): per angle k the
+ * bins [i0[k], i0[k] + width[k]) may be touched by pixels of `region`.
+ * i0 and width are HOST arrays of n_angles entries.  Errors: EINVAL, ENOENT. */
+tomo_status tomo_roi_band(tomo_ctx* ctx, int32_t geom, tomo_rect region, int32_t* i0,
+                          int32_t* width);
+
+/* Extended local part of Section 3.3: `roi` padded by `margin` on each side and
+ * clipped to the grid, written to *ext (host).  Errors: EINVAL. */
+tomo_status tomo_roi_ext(tomo_ctx* ctx, int32_t geom, tomo_rect roi, int32_t margin,
+                         tomo_rect* ext);
+
+/* Forward projection W_L img = W M_L img (Section 2.1 eq. 1): img is the
+ * region's image float[rows][cols]; sino is float[n_angles][n_det].  With
+ * accumulate = 0 the whole sinogram is overwritten (zero outside the region's
+ * band); with accumulate = 1 the projection is added.  Errors: EINVAL, ENOENT,
+ * ENOMEM (region scratch), EHIP. */
+tomo_status tomo_fp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* img,
+                    float* sino, int accumulate, void* hip_stream);
+
+/* Backprojection W_L^T sino = M_L W^T sino onto `region`: img is
+ * float[rows][cols], overwritten (accumulate = 0) or added to.  Errors as tomo_fp. */
+tomo_status tomo_bp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* sino,
+                    float* img, int accumulate, void* hip_stream);
+
+/* FBP with the Ram-Lak filter (Section 2.2 eq. fbp): img (float[n][n]) =
+ * (pi / n_angles) * det_spacing * W^T (det_spacing * h (*) sino), where h is the
+ * spatial Ram-Lak filter for sampling interval det_spacing and (*) is a linear
+ * (zero-padded) convolution along the detector.  Errors as tomo_fp. */
+tomo_status tomo_fbp_ramlak(tomo_ctx* ctx, int32_t geom, const float* sino, float* img,
+                            void* hip_stream);
+
+/* Exterior subtraction through W = W_L + W_F (eq. locouter): for the extended
+ * local part ext_roi, sino_local = sino - W M_F x_ext on every bin of the
+ * region's band that lies on the detector, and 0 on all other bins.
+ * x_ext is float[n][n]; sino and sino_local are float[n_angles][n_det].
+ * Errors as tomo_fp. */
+tomo_status tomo_exterior_subtract(tomo_ctx* ctx, int32_t geom, tomo_rect ext_roi,
+                                   const float* sino, const float* x_ext, float* sino_local,
+                                   void* hip_stream);
+
+typedef enum {
+    ROI_TV_NONNEG_CP = 0,   /* Chambolle-Pock on ||W_L x - b||^2 + lambda TV(x), x >= 0 */
+    ROI_NONNEG_SIRT = 1     /* x <- max(0, x + alpha W_L^T (b - W_L x)), alpha = 1/(N_theta N_d)
+                               (eq. sirtit with the box of eq. sirtbox, l = 0, r = inf) */
+} roi_method;
+
+enum {
+    ROI_FLAG_HALF_DATA = 1, /* use 1/2 ||W_L x - b||^2 as the data term */
+    ROI_FLAG_ANISO_TV = 2   /* anisotropic TV (sum of |d/dr| + |d/dc|) */
+};
+
+/* One local reconstruction request.  roi: the part the caller wants; margin:
+ * padding on each side (Section 3.3), clipped to the grid; lambda: TV weight;
+ * iters: fixed iteration count (no early stop); sigma, tau: CP step sizes, or
+ * 0 for sigma = tau = 1/sqrt(1.01 * lambda_max(W_L^T W_L - Laplacian))
+ * from a cached power iteration (per geometry and extended shape). */
+typedef struct {
+    tomo_rect roi;
+    int32_t margin;
+    int32_t method;     /* roi_method */
+    float lambda;
+    int32_t iters;
+    float sigma, tau;
+    uint32_t flags;     /* ROI_FLAG_* */
+} roi_params;
+
+/* Solve one ROI: extend, subtract the exterior (x_ext = float[n][n], or NULL to
+ * use the Ram-Lak FBP of sino computed here), run `iters` iterations on the
+ * extended part from x = 0, and write the crop to out (float[roi.rows][roi.cols]).
+ * Stream-ordered on hip_stream.  Errors: EINVAL, ENOENT, ENOMEM, EHIP. */
+tomo_status roi_solve(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                      const roi_params* params, float* out, void* hip_stream);
+
+/* Solve `count` independent ROIs of one sinogram together (Section 5.6: local
+ * parts are independent and can be reconstructed in parallel): every
+ * iteration runs as one launch per operator over the work items of all ROIs.
+ * params and outs are HOST arrays of count entries; outs[i] is a device
+ * pointer to float[roi.rows][roi.cols].  Each result equals the one roi_solve
+ * gives for the same ROI.  Errors as roi_solve. */
+tomo_status roi_solve_batch(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                            int32_t count, const roi_params* params, float* const* outs,
+                            void* hip_stream);
+
+/* The CP step size the library would use for extended region `ext` (host float
+ * out).  Runs the power iteration if the shape is not cached (blocking).
+ * Errors: EINVAL, ENOENT, ENOMEM, EHIP. */
+tomo_status roi_step_size(tomo_ctx* ctx, int32_t geom, tomo_rect ext, float* sigma_tau);
+
+/* Make a sinogram resident for serving: the library computes and keeps its
+ * Ram-Lak FBP exterior estimate x_ext and the residual r = sino - W x_ext in
+ * the workspace (Section 3.3: precompute once, reuse for every local part).
+ * `sino` (float[n_angles][n_det]) is borrowed: it must stay alive and unchanged
+ * until tomo_unregister_sinogram.  Blocking.  Errors: EINVAL, ENOENT, ENOMEM, EHIP. */
+tomo_status tomo_register_sinogram(tomo_ctx* ctx, int32_t geom, const float* sino,
+                                   int32_t* sino_id);
+
+/* Release a registered sinogram.  Errors: ENOENT, EBUSY (requests still queued or running). */
+tomo_status tomo_unregister_sinogram(tomo_ctx* ctx, int32_t sino_id);
+
+/* Submit a request against a registered sinogram.  Never blocks: the request
+ * joins a bounded queue; the scheduler thread admits it into the running batch
+ * when a slot and workspace memory are free (continuous batching), runs it on
+ * its own stream together with the other admitted requests, and writes the
+ * crop into out (device float[roi.rows][roi.cols], kept alive by the caller
+ * until roi_poll reports done).  Errors: EINVAL, ENOENT, ENOMEM (cannot fit even
+ * in an empty workspace), EAGAIN (queue full). */
+tomo_status roi_submit(tomo_ctx* ctx, int32_t sino_id, const roi_params* params, float* out,
+                       uint64_t* ticket);
+
+/* Poll a ticket: *done = 1 once its result is in `out` (then *latency_ms, if
+ * not NULL, is the host-clock time from roi_submit to completion).  A done
+ * ticket is forgotten after the poll that reports it.  Never blocks.
+ * Errors: ENOENT (unknown or already reported ticket), EHIP (the request failed). */
+tomo_status roi_poll(tomo_ctx* ctx, uint64_t ticket, int* done, float* latency_ms);
+
+/* Serving knobs: maximum concurrent slots (default 64) and iterations per
+ * scheduler tick (default 4); 0 leaves a value unchanged. */
+tomo_status tomo_serving_config(tomo_ctx* ctx, int32_t max_slots, int32_t iters_per_tick);
+
+/* Kernel launch shape knobs (autotuner hooks): FP segments per ray (1, 2, 4) and BP angle
+ * groups per pixel (1, 2, 4); 0 = choose automatically from the problem size. */
+tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups);
+
+/* Algorithmic work: the exact number of nonzeros of W_L for `region` (the
+ * pixel-ray pairs with w > 0, counted in FP64 on the host from the entry
+ * formula above), i.e. the updates one forward projection (or one
+ * backprojection) of the region performs.  Works on host-only contexts.
+ * Errors: EINVAL, ENOENT. */
+tomo_status tomo_roi_nnz(tomo_ctx* ctx, int32_t geom, tomo_rect region, int64_t* nnz);
+
+/* Measurement hook: with enable = 1, the solve calls record a HIP event pair on
+ * their stream around every forward-projection (kernel 0) and backprojection
+ * (kernel 1) launch of the iterations.  tomo_kernel_time waits for the recorded
+ * events and returns, per kernel, the number of timed launches and their total
+ * GPU time in milliseconds (host outputs); reset = 1 clears the totals. */
+tomo_status tomo_kernel_timing(tomo_ctx* ctx, int enable);
+tomo_status tomo_kernel_time(tomo_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms,
+                             int reset);
+
+/* Workspace bytes in use now and at peak (host outputs). */
+tomo_status tomo_workspace_usage(tomo_ctx* ctx, size_t* used, size_t* peak);
+
+/* Wait until all GPU work issued by the context's own streams is done. */
+tomo_status tomo_synchronize(tomo_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOMO_H */

@@ -1,0 +1,9 @@
+"""MI355X-native local-ROI regularised tomography (arXiv 1604.02292).
+
+The compute path is the HIP library libtomo.so (C ABI in include/tomo.h);
+`tomo.Context` is its thin Python binding.
+"""
+
+from .tomo import Context, TomoError, make_params  # noqa: F401
+from ._lib import (roi_params, tomo_rect, ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT,  # noqa: F401
+                   ROI_FLAG_HALF_DATA, ROI_FLAG_ANISO_TV)

@@ -1,0 +1,1118 @@
+// C ABI of the local-ROI tomography library (declared in include/tomo.h) and
+// the solve pipeline: exterior estimate (Ram-Lak FBP, Section 2.2), exterior
+// subtraction through W = W_L + W_F (eq. locouter), step sizes, the batched
+// Chambolle-Pock / SIRT iterations on extended local parts (Section 3.3), and
+// the crop.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "tomo_runtime.h"
+#include "tomo_serve.h"
+
+using namespace tomo;
+
+namespace tomo {
+
+static constexpr int kPowerIters = 50;
+
+void bp_tile(int ag, int* th, int* tw) {
+    const int P = 256 / ag;
+    *tw = (ag == 4) ? 8 : 16;
+    *th = P / *tw;
+}
+
+LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels) {
+    LaunchCfg L;
+    // Split rays / pixels across more waves while the whole problem is too small
+    // to fill 256 CUs with at least ~8 waves each.
+    const long long want = 256LL * 8 * 64;
+    L.seg = total_rays >= 4 * want ? 1 : (total_rays >= 2 * want ? 2 : 4);
+    L.ag = total_pixels >= 4 * want ? 1 : (total_pixels >= 2 * want ? 2 : 4);
+    if (ctx->fp_seg) L.seg = ctx->fp_seg;
+    if (ctx->bp_ag) L.ag = ctx->bp_ag;
+    return L;
+}
+
+// Device bytes of one ROI's state: x, xbar ping-pong, xbar^T, z ping-pong, y, b, part.
+size_t state_bytes(const Geom& g, const Plan& p) {
+    const size_t nr = p.reg.rows, nc = p.reg.cols;
+    const size_t tiles = ((nr + 7) / 8) * ((nc + 7) / 8);
+    // 9 sub-arrays, each rounded up to 64 floats by carve_state
+    size_t f = nr * nc + 2 * nr * p.xp + nc * p.tp + 4 * nr * nc + 2 * (size_t)g.na * p.bpitch +
+               tiles + 10 * 64;
+    return f * sizeof(float) + 256;
+}
+
+tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p) {
+    const tomo_rect& r = p.roi;
+    if (r.rows < 1 || r.cols < 1 || r.row0 < 0 || r.col0 < 0 || r.row0 + r.rows > g.n ||
+        r.col0 + r.cols > g.n)
+        return fail(ctx, TOMO_EINVAL, "roi (%d,%d,%d,%d) is empty or outside the %dx%d grid",
+                    r.row0, r.col0, r.rows, r.cols, g.n, g.n);
+    if (p.margin < 0) return fail(ctx, TOMO_EINVAL, "margin < 0");
+    if (p.iters <= 0) return fail(ctx, TOMO_EINVAL, "iters must be > 0");
+    if (!(p.lambda >= 0.f) || !std::isfinite(p.lambda)) return fail(ctx, TOMO_EINVAL, "lambda must be >= 0");
+    if (p.method != ROI_TV_NONNEG_CP && p.method != ROI_NONNEG_SIRT)
+        return fail(ctx, TOMO_EINVAL, "unknown method %d", p.method);
+    if (!(p.sigma >= 0.f) || !(p.tau >= 0.f)) return fail(ctx, TOMO_EINVAL, "negative step size");
+    if (p.flags & ~3u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
+    return TOMO_OK;
+}
+
+Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int ntc) {
+    Job J;
+    std::memset(&J, 0, sizeof J);
+    J.nr = st.ext.rows;
+    J.nc = st.ext.cols;
+    J.xp = st.plan.xp;
+    J.tp = st.plan.tp;
+    J.n_angles = g.na;
+    J.bpitch = st.plan.bpitch;
+    J.n_det = g.nd;
+    J.fp_mode = fp_mode;
+    J.bp_mode = bp_mode;
+    J.flags = (int)st.prm.flags;
+    J.ldx = st.ext.cols;
+    J.ntc = ntc;
+    J.sigma = st.sigma;
+    J.tau = st.tau;
+    J.lam = st.prm.lambda;
+    const bool half = (st.prm.flags & ROI_FLAG_HALF_DATA) != 0;
+    J.dual_div = (float)(1.0 / (1.0 + (half ? (double)st.sigma : 0.5 * (double)st.sigma)));
+    J.alpha = (float)(1.0 / ((double)g.na * (double)g.nd));
+    J.scale = 1.f;
+    J.afp = st.d_afp;
+    J.abp = st.d_abp;
+    J.x = st.x;
+    J.xb[0] = st.xb0;
+    J.xb[1] = st.xb1;
+    J.xt = st.xt;
+    J.z[0] = st.z0;
+    J.z[1] = st.z1;
+    J.y = st.y;
+    J.b = st.b;
+    J.part = st.part;
+    return J;
+}
+
+// Items of the forward projector for job `jj` with tables `afp`.
+void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg) {
+    const int rpb = 256 / seg;
+    for (int k = 0; k < (int)afp.size(); ++k) {
+        const int nch = (afp[k].w + rpb - 1) / rpb;
+        for (int ch = 0; ch < nch; ++ch) out.push_back(Item{jj, k, ch, 0});
+    }
+}
+
+void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag) {
+    int th, tw;
+    bp_tile(ag, &th, &tw);
+    for (int a = 0; a < (nr + th - 1) / th; ++a)
+        for (int b = 0; b < (nc + tw - 1) / tw; ++b) out.push_back(Item{jj, a, b, 0});
+}
+
+
+// Exterior estimate on the whole grid, as padded + transposed + plain images.
+struct ExtSrc {
+    const float* plain = nullptr;   // [n][n]
+    float* xb = nullptr;            // padded [n][xp]
+    float* xt = nullptr;            // padded [n][tp]
+    int xp = 0, tp = 0;
+    std::vector<char*> allocs;
+};
+
+// Ram-Lak FBP of `sino` into (plain, padded, transposed) images of the grid.
+tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, float* xb, float* xt,
+                     const Plan& P, hipStream_t s, std::vector<char*>& allocs, Staging& stg) {
+    const Geom& g = ctx->geoms[gid];
+    if (g.nd > 8192) return fail(ctx, TOMO_EINVAL, "FBP supports at most 8192 detector bins");
+    const size_t band_bytes = (size_t)g.na * P.bpitch * sizeof(float);
+    int th, tw;
+    const LaunchCfg L = choose_launch(ctx, 0, (long long)g.n * g.n);
+    bp_tile(L.ag, &th, &tw);
+    std::vector<Item> items;
+    bp_items(items, 0, g.n, g.n, L.ag);
+    Meta m;
+    const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
+    const size_t o_abp = m.add(P.abp.data(), P.abp.size() * sizeof(AngBP));
+    const size_t o_job = m.reserve(sizeof(Job));
+    const size_t o_it = m.add(items.data(), items.size() * sizeof(Item));
+    char* dm = ctx->arena.alloc(m.buf.size() + band_bytes + 256);
+    if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace too small for the FBP tables");
+    allocs.push_back(dm);
+    float* band = (float*)(dm + align_up(m.buf.size(), 256));
+    Job J;
+    std::memset(&J, 0, sizeof J);
+    J.nr = g.n;
+    J.nc = g.n;
+    J.xp = P.xp;
+    J.tp = P.tp;
+    J.n_angles = g.na;
+    J.bpitch = P.bpitch;
+    J.n_det = g.nd;
+    J.bp_mode = BP_STORE;
+    J.ldx = g.n;
+    J.scale = (float)(M_PI / g.na * g.spacing);
+    J.afp = (const AngFP*)(dm + o_afp);
+    J.abp = (const AngBP*)(dm + o_abp);
+    J.x = plain;
+    J.xb[0] = xb;
+    J.xt = xt;
+    J.y = band;
+    std::memcpy(m.buf.data() + o_job, &J, sizeof J);
+    TOMO_HIP(ctx, stg.upload(dm, m.buf.data(), m.buf.size(), s));
+    TOMO_HIP(ctx, launch_fill(band, (size_t)g.na * P.bpitch, 0.f, s));
+    TOMO_HIP(ctx, launch_ramp(sino, g.na, g.nd, g.d_taps, J.afp, band, P.bpitch, s));
+    TOMO_HIP(ctx, launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
+                            0, L.ag, s));
+    return TOMO_OK;
+}
+
+// x_ext: the caller's image, or the Ram-Lak FBP of sino.
+static tomo_status prepare_exterior(tomo_ctx* ctx, int gid, const float* sino,
+                                    const float* x_ext_user, hipStream_t s, ExtSrc& E) {
+    const Geom& g = ctx->geoms[gid];
+    const Rect full{0, 0, g.n, g.n};
+    const Plan P = make_plan(g, full, full);
+    E.xp = P.xp;
+    E.tp = P.tp;
+    const size_t nb = (size_t)g.n * P.xp, nt = (size_t)g.n * P.tp;
+    const size_t np = x_ext_user ? 0 : (size_t)g.n * g.n;
+    char* blk = ctx->arena.alloc((nb + nt + np) * sizeof(float) + 512);
+    if (!blk) return fail(ctx, TOMO_ENOMEM, "workspace too small for the exterior estimate");
+    E.allocs.push_back(blk);
+    E.xb = (float*)blk;
+    E.xt = E.xb + nb;
+    float* plain = x_ext_user ? nullptr : E.xt + nt;
+    TOMO_HIP(ctx, launch_fill(E.xb, nb + nt, 0.f, s));
+    if (x_ext_user) {
+        E.plain = x_ext_user;
+        TOMO_HIP(ctx, launch_pad_copy(x_ext_user, g.n, 0, 0, g.n, g.n, E.xb, E.xp, E.xt, E.tp,
+                                      nullptr, 0, s));
+        return TOMO_OK;
+    }
+    E.plain = plain;
+    return fbp_into(ctx, gid, sino, plain, E.xb, E.xt, P, s, E.allocs, ctx->staging);
+}
+
+// Carve one ROI's device state out of its block.
+void carve_state(const Geom& g, RoiState& st, char* blk) {
+    const Plan& p = st.plan;
+    const size_t nr = p.reg.rows, nc = p.reg.cols;
+    float* f = (float*)blk;
+    auto take = [&](size_t n) {
+        float* q = f;
+        f += align_up(n, 64);
+        return q;
+    };
+    st.x = take(nr * nc);
+    st.xb0 = take(nr * p.xp);
+    st.xb1 = take(nr * p.xp);
+    st.xt = take(nc * p.tp);
+    st.z0 = take(2 * nr * nc);
+    st.z1 = take(2 * nr * nc);
+    st.y = take((size_t)g.na * p.bpitch);
+    st.state_floats = (size_t)(f - (float*)blk);
+    st.b = take((size_t)g.na * p.bpitch);
+    st.part = take(((nr + 7) / 8) * ((nc + 7) / 8));
+    st.total_floats = (size_t)(f - (float*)blk);
+    st.block = blk;
+}
+
+// Power iteration for lambda_max(W_L^T W_L - Laplacian) on one ROI's buffers
+// (tables already on the device); result cached per (geometry, shape).
+tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, Staging& stg) {
+    if (st.prm.method != ROI_TV_NONNEG_CP) return TOMO_OK;
+    if (st.prm.sigma > 0.f && st.prm.tau > 0.f) {
+        st.sigma = st.prm.sigma;
+        st.tau = st.prm.tau;
+        return TOMO_OK;
+    }
+    const auto key = std::make_tuple(gid, st.ext.rows, st.ext.cols);
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        auto it = ctx->step_cache.find(key);
+        if (it != ctx->step_cache.end()) {
+            st.sigma = st.tau = it->second;
+            return TOMO_OK;
+        }
+    }
+    const Geom& g = ctx->geoms[gid];
+    const int nr = st.ext.rows, nc = st.ext.cols;
+    const LaunchCfg L = choose_launch(ctx, (long long)g.na * st.plan.wmax, (long long)nr * nc);
+    int th, tw;
+    bp_tile(L.ag, &th, &tw);
+    RoiState tmp = st;
+    Job J = make_job(g, tmp, FP_BAND_STORE, BP_POWER, (nc + tw - 1) / tw);
+    std::vector<Item> fi, bi;
+    fp_items(fi, 0, st.plan.afp, L.seg);
+    bp_items(bi, 0, nr, nc, L.ag);
+    const int n_part = (int)bi.size();
+    Meta m;
+    const size_t o_job = m.add(&J, sizeof J);
+    const size_t o_fi = m.add(fi.data(), fi.size() * sizeof(Item));
+    const size_t o_bi = m.add(bi.data(), bi.size() * sizeof(Item));
+    const size_t o_est = m.reserve(64);
+    std::vector<char*> mine;
+    char* dm = ctx->arena.alloc(m.buf.size());
+    if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace too small for the power iteration");
+    mine.push_back(dm);
+    // part[] must hold one entry per BP tile
+    float* part = st.part;
+    const size_t part_cap = ((size_t)(nr + 7) / 8) * ((nc + 7) / 8);
+    if ((size_t)n_part > part_cap) return fail(ctx, TOMO_EINVAL, "internal: partial-sum buffer");
+    J.part = part;
+    std::memcpy(m.buf.data() + o_job, &J, sizeof J);
+    TOMO_HIP(ctx, stg.upload(dm, m.buf.data(), m.buf.size(), s));
+    float* est = (float*)(dm + o_est);
+    TOMO_HIP(ctx, launch_fill(st.block ? (float*)st.block : st.x, st.state_floats, 0.f, s));
+    TOMO_HIP(ctx, launch_fill_padded(st.xb0, st.xt, nr, nc, st.plan.xp, st.plan.tp, 1.f, s));
+    for (int it = 0; it < kPowerIters; ++it) {
+        TOMO_HIP(ctx, launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_fi), (int)fi.size(),
+                                it, L.seg, s));
+        TOMO_HIP(ctx, launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_bi), n_part, it,
+                                L.ag, s));
+        float* nxt = ((it + 1) & 1) ? st.xb1 : st.xb0;
+        TOMO_HIP(ctx, launch_power_normalize(st.x, nc, nr, nc, part, n_part, nxt, st.plan.xp,
+                                             st.xt, st.plan.tp, est, s));
+    }
+    float h_est = 0.f;
+    TOMO_HIP(ctx, hipMemcpyAsync(&h_est, est, sizeof(float), hipMemcpyDeviceToHost, s));
+    TOMO_HIP(ctx, hipStreamSynchronize(s));
+    ctx->arena.free_after(mine, s);
+    if (!(h_est > 0.f) || !std::isfinite(h_est))
+        return fail(ctx, TOMO_EHIP, "power iteration gave a non-positive norm estimate");
+    const float step = (float)(1.0 / std::sqrt(1.01 * (double)h_est));
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        ctx->step_cache[key] = step;
+    }
+    st.sigma = st.tau = step;
+    return TOMO_OK;
+}
+
+// The batched solve (one sinogram, many ROIs).  `reg` (optional) is a
+// registered sinogram whose x_ext and residual r = p - W x_ext are resident.
+tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* x_ext_user,
+                        const SinoState* reg, int count, const roi_params* params,
+                        float* const* outs, hipStream_t s) {
+    const Geom& g = ctx->geoms[gid];
+    const Rect full{0, 0, g.n, g.n};
+    std::vector<RoiState> R(count);
+    long long rays = 0, pix = 0;
+    size_t state_total = 0;
+    for (int i = 0; i < count; ++i) {
+        tomo_status st = validate_params(ctx, g, params[i]);
+        if (st != TOMO_OK) return st;
+        if (!outs[i]) return fail(ctx, TOMO_EINVAL, "null output pointer for ROI %d", i);
+        RoiState& r = R[i];
+        r.prm = params[i];
+        r.roi = Rect{params[i].roi.row0, params[i].roi.col0, params[i].roi.rows, params[i].roi.cols};
+        r.ext = extend_rect(r.roi, params[i].margin, g.n);
+        r.plan = make_plan(g, r.ext, r.ext);
+        r.plan_full = make_plan(g, full, r.ext);
+        rays += (long long)g.na * r.plan.wmax;
+        pix += (long long)r.ext.rows * r.ext.cols;
+        state_total += align_up(state_bytes(g, r.plan), 256);
+    }
+    if (state_total > ctx->arena.capacity())
+        return fail(ctx, TOMO_ENOMEM, "batch needs %zu bytes of state; workspace holds %zu",
+                    state_total, ctx->arena.capacity());
+    std::vector<char*> allocs;
+    auto cleanup = [&]() { ctx->arena.free_after(allocs, s); };
+
+    ExtSrc E;
+    const float* rglob = nullptr;
+    if (reg) {
+        E.plain = reg->x_plain;
+        E.xb = reg->xb;
+        E.xt = reg->xt;
+        E.xp = reg->xp;
+        E.tp = reg->tp;
+        rglob = reg->resid;
+    } else {
+        tomo_status st = prepare_exterior(ctx, gid, sino, x_ext_user, s, E);
+        allocs.insert(allocs.end(), E.allocs.begin(), E.allocs.end());
+        if (st != TOMO_OK) {
+            cleanup();
+            return st;
+        }
+    }
+    // Many ROIs: one global residual r = p - W x_ext is cheaper than a band
+    // projection of the whole grid per ROI (Section 3.3: reuse across local parts).
+    long long band_sum = 0;
+    for (auto& r : R) band_sum += r.plan.wmax;
+    float* rbuf = nullptr;
+    const bool global_resid = !reg && band_sum > g.nd;
+
+    const LaunchCfg L = choose_launch(ctx, rays, pix);
+    int th, tw;
+    bp_tile(L.ag, &th, &tw);
+
+    char* sblk = ctx->arena.alloc(state_total + 256);
+    if (!sblk) {
+        cleanup();
+        return fail(ctx, TOMO_ENOMEM, "workspace too small for %d ROI states (%zu bytes)", count,
+                    state_total);
+    }
+    allocs.push_back(sblk);
+    {
+        char* p = sblk;
+        for (auto& r : R) {
+            carve_state(g, r, p);
+            p += align_up(state_bytes(g, r.plan), 256);
+        }
+    }
+    // Tables, exterior jobs and their work items.
+    Meta m;
+    std::vector<size_t> o_afp(count), o_abp(count), o_afpf(count);
+    for (int i = 0; i < count; ++i) {
+        o_afp[i] = m.add(R[i].plan.afp.data(), R[i].plan.afp.size() * sizeof(AngFP));
+        o_abp[i] = m.add(R[i].plan.abp.data(), R[i].plan.abp.size() * sizeof(AngBP));
+        o_afpf[i] = m.add(R[i].plan_full.afp.data(), R[i].plan_full.afp.size() * sizeof(AngFP));
+    }
+    Plan Pfull;
+    size_t o_afp_glob = 0;
+    if (global_resid) {
+        Pfull = make_plan(g, full, full);
+        o_afp_glob = m.add(Pfull.afp.data(), Pfull.afp.size() * sizeof(AngFP));
+    }
+    const size_t o_jobs_e1 = m.reserve(sizeof(Job) * count);
+    const size_t o_jobs_e2 = m.reserve(sizeof(Job) * count);
+    const size_t o_job_g = m.reserve(sizeof(Job));
+    std::vector<Item> it_e1, it_e2, it_g;
+    for (int i = 0; i < count; ++i) {
+        fp_items(it_e1, i, R[i].plan_full.afp, L.seg);
+        fp_items(it_e2, i, R[i].plan.afp, L.seg);
+    }
+    if (global_resid) fp_items(it_g, 0, Pfull.afp, choose_launch(ctx, (long long)g.na * g.nd, 0).seg);
+    const size_t o_it_e1 = m.add(it_e1.data(), it_e1.size() * sizeof(Item));
+    const size_t o_it_e2 = m.add(it_e2.data(), it_e2.size() * sizeof(Item));
+    const size_t o_it_g = m.add(it_g.data(), it_g.size() * sizeof(Item));
+    const size_t rbytes = global_resid ? (size_t)g.na * g.nd * sizeof(float) : 0;
+    char* dm = ctx->arena.alloc(m.buf.size() + rbytes + 512);
+    if (!dm) {
+        cleanup();
+        return fail(ctx, TOMO_ENOMEM, "workspace too small for the batch tables");
+    }
+    allocs.push_back(dm);
+    if (global_resid) {
+        rbuf = (float*)(dm + align_up(m.buf.size(), 256));
+        rglob = rbuf;
+    }
+    for (int i = 0; i < count; ++i) {
+        R[i].d_afp = (AngFP*)(dm + o_afp[i]);
+        R[i].d_abp = (AngBP*)(dm + o_abp[i]);
+        R[i].d_afp_full = (AngFP*)(dm + o_afpf[i]);
+    }
+    // E1: b = p - W x_ext on the ROI band (full-grid rays), unless r is available.
+    // E2: b += W_L x_ext|L  (or b = r + W_L x_ext|L).
+    for (int i = 0; i < count; ++i) {
+        RoiState& r = R[i];
+        Job J1 = make_job(g, r, FP_BAND_FROM_GLOBAL, BP_STORE, 0);
+        J1.nr = g.n;
+        J1.nc = g.n;
+        J1.xp = E.xp;
+        J1.tp = E.tp;
+        J1.xb[0] = J1.xb[1] = E.xb;
+        J1.xt = E.xt;
+        J1.afp = r.d_afp_full;
+        J1.y = r.b;
+        J1.gbase = sino;
+        J1.scale = -1.f;
+        std::memcpy(m.buf.data() + o_jobs_e1 + i * sizeof(Job), &J1, sizeof J1);
+        Job J2 = make_job(g, r, rglob ? FP_BAND_FROM_GLOBAL : FP_BAND_ADD, BP_STORE, 0);
+        J2.xb[1] = J2.xb[0];
+        J2.y = r.b;
+        J2.gbase = rglob;
+        J2.scale = 1.f;
+        std::memcpy(m.buf.data() + o_jobs_e2 + i * sizeof(Job), &J2, sizeof J2);
+    }
+    if (global_resid) {
+        Job Jg;
+        std::memset(&Jg, 0, sizeof Jg);
+        Jg.nr = g.n;
+        Jg.nc = g.n;
+        Jg.xp = E.xp;
+        Jg.tp = E.tp;
+        Jg.n_angles = g.na;
+        Jg.n_det = g.nd;
+        Jg.fp_mode = FP_RESID;
+        Jg.afp = (const AngFP*)(dm + o_afp_glob);
+        Jg.xb[0] = Jg.xb[1] = E.xb;
+        Jg.xt = E.xt;
+        Jg.gout = rbuf;
+        Jg.gbase = sino;
+        Jg.scale = -1.f;
+        Jg.bpitch = 1;
+        std::memcpy(m.buf.data() + o_job_g, &Jg, sizeof Jg);
+    }
+    hipError_t e = ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, TOMO_EHIP, "upload: %s", hipGetErrorString(e));
+    }
+#define CK(expr)                                                                          \
+    do {                                                                                  \
+        hipError_t e__ = (expr);                                                          \
+        if (e__ != hipSuccess) {                                                          \
+            cleanup();                                                                    \
+            return fail(ctx, TOMO_EHIP, "%s failed: %s", #expr, hipGetErrorString(e__));  \
+        }                                                                                 \
+    } while (0)
+    CK(launch_fill((float*)sblk, state_total / sizeof(float), 0.f, s));
+    if (global_resid)
+        CK(launch_fp((const Job*)(dm + o_job_g), (const Item*)(dm + o_it_g), (int)it_g.size(), 0,
+                     choose_launch(ctx, (long long)g.na * g.nd, 0).seg, s));
+    if (!rglob)
+        CK(launch_fp((const Job*)(dm + o_jobs_e1), (const Item*)(dm + o_it_e1), (int)it_e1.size(),
+                     0, L.seg, s));
+    for (auto& r : R)
+        CK(launch_pad_copy(E.plain, g.n, r.ext.r0, r.ext.c0, r.ext.rows, r.ext.cols, r.xb0,
+                           r.plan.xp, r.xt, r.plan.tp, nullptr, 0, s));
+    CK(launch_fp((const Job*)(dm + o_jobs_e2), (const Item*)(dm + o_it_e2), (int)it_e2.size(), 0,
+                 L.seg, s));
+    // Step sizes (cached per shape; the power iteration reuses the state buffers).
+    for (auto& r : R) {
+        tomo_status st = step_size_for(ctx, gid, r, s, ctx->staging);
+        if (st != TOMO_OK) {
+            cleanup();
+            return st;
+        }
+    }
+    // Zero the iteration state again (x, xbar, xbar^T, z, y; b is kept).
+    for (auto& r : R) CK(launch_fill((float*)r.block, r.state_floats, 0.f, s));
+
+    // Iteration jobs; ROIs ordered by decreasing iteration count so that the
+    // work items of the still-running ROIs always form a prefix of the list.
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return R[a].prm.iters > R[b].prm.iters; });
+    std::vector<Job> jobs(count);
+    std::vector<Item> fi, bi;
+    std::vector<int> fi_end(count), bi_end(count);
+    for (int q = 0; q < count; ++q) {
+        RoiState& r = R[order[q]];
+        const bool cp = r.prm.method == ROI_TV_NONNEG_CP;
+        jobs[q] = make_job(g, r, cp ? FP_CP_DUAL : FP_SIRT, cp ? BP_CP : BP_SIRT,
+                           (r.ext.cols + tw - 1) / tw);
+        fp_items(fi, q, r.plan.afp, L.seg);
+        bp_items(bi, q, r.ext.rows, r.ext.cols, L.ag);
+        fi_end[q] = (int)fi.size();
+        bi_end[q] = (int)bi.size();
+    }
+    Meta m2;
+    const size_t o_jobs = m2.add(jobs.data(), jobs.size() * sizeof(Job));
+    const size_t o_fi = m2.add(fi.data(), fi.size() * sizeof(Item));
+    const size_t o_bi = m2.add(bi.data(), bi.size() * sizeof(Item));
+    char* dm2 = ctx->arena.alloc(m2.buf.size());
+    if (!dm2) {
+        cleanup();
+        return fail(ctx, TOMO_ENOMEM, "workspace too small for the iteration tables");
+    }
+    allocs.push_back(dm2);
+    CK(ctx->staging.upload(dm2, m2.buf.data(), m2.buf.size(), s));
+    const Job* d_jobs = (const Job*)(dm2 + o_jobs);
+    const Item* d_fi = (const Item*)(dm2 + o_fi);
+    const Item* d_bi = (const Item*)(dm2 + o_bi);
+    int active = count;
+    const int max_it = R[order[0]].prm.iters;
+    const bool timed = ctx->timing;
+    for (int it = 0; it < max_it; ++it) {
+        while (active > 0 && R[order[active - 1]].prm.iters <= it) --active;
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+        if (timed) {
+            e0 = timing_event(ctx);
+            e1 = timing_event(ctx);
+            e2 = timing_event(ctx);
+            CK(hipEventRecord(e0, s));
+        }
+        CK(launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, s));
+        if (timed) CK(hipEventRecord(e1, s));
+        CK(launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, s));
+        if (timed) {
+            CK(hipEventRecord(e2, s));
+            ctx->ev_pending.emplace_back(e0, e1, 0);
+            ctx->ev_pending.emplace_back(e1, e2, 1);
+        }
+    }
+    for (int i = 0; i < count; ++i) {
+        const RoiState& r = R[i];
+        CK(launch_crop(r.x, r.ext.cols, r.roi.r0 - r.ext.r0, r.roi.c0 - r.ext.c0, r.roi.rows,
+                       r.roi.cols, outs[i], s));
+    }
+#undef CK
+    cleanup();
+    return TOMO_OK;
+}
+
+hipEvent_t timing_event(tomo_ctx* ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Exact nonzero count of W_L (entry formula in FP64): per angle and pixel, the
+// bins i with |s_i - t| < m.
+long long count_nnz(const Geom& g, const Rect& reg) {
+    const double h = (g.n - 1) / 2.0, hd = (g.nd - 1) / 2.0;
+    long long nnz = 0;
+    for (int k = 0; k < g.na; ++k) {
+        const double c = g.c[k], s = g.s[k], m = g.m[k];
+        for (int r = 0; r < reg.rows; ++r) {
+            const double y = reg.r0 + r - h;
+            for (int q = 0; q < reg.cols; ++q) {
+                const double t = (reg.c0 + q - h) * c + y * s;
+                const double u = (t - g.offset) / g.spacing + hd;
+                const int lo = (int)std::floor(u) - 2;
+                for (int i = lo; i <= lo + 5; ++i) {
+                    if (i < 0 || i >= g.nd) continue;
+                    const double si = (i - hd) * g.spacing + g.offset;
+                    if (std::fabs(si - t) < m) ++nnz;
+                }
+            }
+        }
+    }
+    return nnz;
+}
+
+}  // namespace tomo
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+#define GUARD_BEGIN try {
+#define GUARD_END(ctx)                                                                  \
+    }                                                                                   \
+    catch (const std::bad_alloc&) {                                                     \
+        return fail((ctx), TOMO_ENOMEM, "host allocation failed");                      \
+    }                                                                                   \
+    catch (...) {                                                                       \
+        return fail((ctx), TOMO_EINVAL, "unexpected host exception");                   \
+    }
+
+static tomo_status need_gpu(tomo_ctx* ctx) {
+    if (!ctx) return TOMO_EINVAL;
+    if (ctx->host_only) return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(ctx, TOMO_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+    return TOMO_OK;
+}
+
+static tomo_status get_geom(tomo_ctx* ctx, int32_t gid, const Geom** g) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (gid < 0 || gid >= (int)ctx->geoms.size()) return fail(ctx, TOMO_ENOENT, "unknown geometry %d", gid);
+    *g = &ctx->geoms[gid];
+    return TOMO_OK;
+}
+
+static tomo_status check_rect(tomo_ctx* ctx, const Geom& g, tomo_rect r) {
+    if (r.rows < 1 || r.cols < 1 || r.row0 < 0 || r.col0 < 0 || r.row0 + r.rows > g.n ||
+        r.col0 + r.cols > g.n)
+        return fail(ctx, TOMO_EINVAL, "rect (%d,%d,%d,%d) is empty or outside the %dx%d grid",
+                    r.row0, r.col0, r.rows, r.cols, g.n, g.n);
+    return TOMO_OK;
+}
+
+extern "C" {
+
+tomo_status tomo_create(int device, void* workspace, size_t workspace_bytes, tomo_ctx** out) {
+    if (!out) return TOMO_EINVAL;
+    *out = nullptr;
+    if (device < -1) return TOMO_EINVAL;
+    tomo_ctx* ctx = nullptr;
+    try {
+        ctx = new tomo_ctx();
+    } catch (...) {
+        return TOMO_ENOMEM;
+    }
+    ctx->device = device;
+    ctx->host_only = device < 0;
+    if (!ctx->host_only) {
+        if (!workspace || workspace_bytes < (1u << 20)) {
+            delete ctx;
+            return TOMO_EINVAL;
+        }
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev ||
+            hipSetDevice(device) != hipSuccess) {
+            delete ctx;
+            return TOMO_EHIP;
+        }
+        ctx->ws = (char*)workspace;
+        ctx->ws_bytes = workspace_bytes;
+        ctx->arena.init(ctx->ws, workspace_bytes);
+    }
+    *out = ctx;
+    return TOMO_OK;
+}
+
+tomo_status tomo_destroy(tomo_ctx* ctx) {
+    if (!ctx) return TOMO_EINVAL;
+    if (!ctx->host_only) {
+        (void)hipSetDevice(ctx->device);
+        serve_shutdown(ctx);
+        (void)hipDeviceSynchronize();
+        ctx->arena.reclaim(true);
+        ctx->staging.destroy();
+        std::vector<hipEvent_t> evs = ctx->ev_pool;
+        for (auto& p : ctx->ev_pending) {
+            evs.push_back(std::get<0>(p));
+            evs.push_back(std::get<1>(p));
+        }
+        std::sort(evs.begin(), evs.end());
+        evs.erase(std::unique(evs.begin(), evs.end()), evs.end());
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    }
+    delete ctx;
+    return TOMO_OK;
+}
+
+const char* tomo_last_error(const tomo_ctx* ctx) {
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+tomo_status tomo_set_geometry(tomo_ctx* ctx, int32_t n, int32_t n_angles, int32_t n_det,
+                              const double* angles, double det_spacing, double det_offset,
+                              int32_t* geom_id) {
+    if (!ctx || !geom_id) return TOMO_EINVAL;
+    GUARD_BEGIN
+    if (n < 1 || n_angles < 1 || n_det < 1)
+        return fail(ctx, TOMO_EINVAL, "n, n_angles and n_det must be >= 1");
+    if (n > 65536 || n_det > (1 << 20) || n_angles > (1 << 16))
+        return fail(ctx, TOMO_EINVAL, "sizes too large");
+    if (!(det_spacing >= 1.0) || !std::isfinite(det_spacing) || !std::isfinite(det_offset))
+        return fail(ctx, TOMO_EINVAL, "det_spacing must be a finite value >= 1 pixel");
+    Geom g;
+    g.n = n;
+    g.na = n_angles;
+    g.nd = n_det;
+    g.spacing = det_spacing;
+    g.offset = det_offset;
+    for (int k = 0; k < n_angles; ++k) {
+        const double th = angles ? angles[k] : (double)k * M_PI / (double)n_angles;
+        if (!std::isfinite(th)) return fail(ctx, TOMO_EINVAL, "angle %d is not finite", k);
+        const double c = std::cos(th), s = std::sin(th);
+        g.th.push_back(th);
+        g.c.push_back(c);
+        g.s.push_back(s);
+        const int ys = std::fabs(c) >= std::fabs(s);
+        g.ystep.push_back(ys);
+        g.m.push_back(ys ? std::fabs(c) : std::fabs(s));
+    }
+    if (!ctx->host_only) {
+        tomo_status st = need_gpu(ctx);
+        if (st != TOMO_OK) return st;
+        // Ram-Lak taps for sampling interval = spacing, times the spacing of Q = tau (h * p)
+        std::vector<float> taps(n_det, 0.f);
+        for (int d = 0; d < n_det; ++d) {
+            double h = 0.0;
+            if (d == 0)
+                h = 0.25;
+            else if (d & 1)
+                h = -1.0 / (M_PI * M_PI * (double)d * (double)d);
+            taps[d] = (float)(h / det_spacing);
+        }
+        char* p = ctx->arena.alloc(n_det * sizeof(float));
+        if (!p) return fail(ctx, TOMO_ENOMEM, "workspace too small for the filter taps");
+        TOMO_HIP(ctx, hipMemcpy(p, taps.data(), n_det * sizeof(float), hipMemcpyHostToDevice));
+        g.d_taps = (float*)p;
+    }
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->geoms.push_back(std::move(g));
+    *geom_id = (int32_t)ctx->geoms.size() - 1;
+    return TOMO_OK;
+    GUARD_END(ctx)
+}
+
+tomo_status tomo_roi_band(tomo_ctx* ctx, int32_t geom, tomo_rect region, int32_t* i0,
+                          int32_t* width) {
+    if (!ctx || !i0 || !width) return TOMO_EINVAL;
+    const Geom* g;
+    tomo_status st = get_geom(ctx, geom, &g);
+    if (st != TOMO_OK) return st;
+    st = check_rect(ctx, *g, region);
+    if (st != TOMO_OK) return st;
+    const Rect r{region.row0, region.col0, region.rows, region.cols};
+    for (int k = 0; k < g->na; ++k) band_of(*g, r, k, &i0[k], &width[k]);
+    return TOMO_OK;
+}
+
+tomo_status tomo_roi_ext(tomo_ctx* ctx, int32_t geom, tomo_rect roi, int32_t margin,
+                         tomo_rect* ext) {
+    if (!ctx || !ext) return TOMO_EINVAL;
+    const Geom* g;
+    tomo_status st = get_geom(ctx, geom, &g);
+    if (st != TOMO_OK) return st;
+    st = check_rect(ctx, *g, roi);
+    if (st != TOMO_OK) return st;
+    if (margin < 0) return fail(ctx, TOMO_EINVAL, "margin < 0");
+    const Rect e = extend_rect(Rect{roi.row0, roi.col0, roi.rows, roi.cols}, margin, g->n);
+    *ext = tomo_rect{e.r0, e.c0, e.rows, e.cols};
+    return TOMO_OK;
+}
+
+tomo_status tomo_fp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* img, float* sino,
+                    int accumulate, void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!img || !sino) return fail(ctx, TOMO_EINVAL, "null pointer");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const Geom& g = *gp;
+    if ((st = check_rect(ctx, g, region)) != TOMO_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Rect r{region.row0, region.col0, region.rows, region.cols};
+    const Plan P = make_plan(g, r, r);
+    const LaunchCfg L = choose_launch(ctx, (long long)g.na * P.wmax, 0);
+    std::vector<Item> items;
+    fp_items(items, 0, P.afp, L.seg);
+    Meta m;
+    const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
+    const size_t o_job = m.reserve(sizeof(Job));
+    const size_t o_it = m.add(items.data(), items.size() * sizeof(Item));
+    const size_t nb = (size_t)r.rows * P.xp, nt = (size_t)r.cols * P.tp;
+    char* dm = ctx->arena.alloc(align_up(m.buf.size(), 256) + (nb + nt) * sizeof(float));
+    if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace too small for the region buffers");
+    float* xb = (float*)(dm + align_up(m.buf.size(), 256));
+    float* xt = xb + nb;
+    Job J;
+    std::memset(&J, 0, sizeof J);
+    J.nr = r.rows;
+    J.nc = r.cols;
+    J.xp = P.xp;
+    J.tp = P.tp;
+    J.n_angles = g.na;
+    J.bpitch = P.bpitch;
+    J.n_det = g.nd;
+    J.fp_mode = accumulate ? FP_ACCUM : FP_STORE;
+    J.afp = (const AngFP*)(dm + o_afp);
+    J.xb[0] = J.xb[1] = xb;
+    J.xt = xt;
+    J.gout = sino;
+    std::memcpy(m.buf.data() + o_job, &J, sizeof J);
+    std::vector<char*> allocs{dm};
+    TOMO_HIP(ctx, ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s));
+    TOMO_HIP(ctx, launch_fill(xb, nb + nt, 0.f, s));
+    TOMO_HIP(ctx, launch_pad_copy(img, r.cols, 0, 0, r.rows, r.cols, xb, P.xp, xt, P.tp, nullptr,
+                                  0, s));
+    if (!accumulate) TOMO_HIP(ctx, launch_fill(sino, (size_t)g.na * g.nd, 0.f, s));
+    TOMO_HIP(ctx, launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
+                            0, L.seg, s));
+    ctx->arena.free_after(allocs, s);
+    return TOMO_OK;
+    GUARD_END(ctx)
+}
+
+tomo_status tomo_bp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* sino, float* img,
+                    int accumulate, void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!img || !sino) return fail(ctx, TOMO_EINVAL, "null pointer");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const Geom& g = *gp;
+    if ((st = check_rect(ctx, g, region)) != TOMO_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Rect r{region.row0, region.col0, region.rows, region.cols};
+    const Plan P = make_plan(g, r, r);
+    const LaunchCfg L = choose_launch(ctx, 0, (long long)r.rows * r.cols);
+    std::vector<Item> items;
+    bp_items(items, 0, r.rows, r.cols, L.ag);
+    Meta m;
+    const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
+    const size_t o_abp = m.add(P.abp.data(), P.abp.size() * sizeof(AngBP));
+    const size_t o_job = m.reserve(sizeof(Job));
+    const size_t o_it = m.add(items.data(), items.size() * sizeof(Item));
+    const size_t nband = (size_t)g.na * P.bpitch;
+    char* dm = ctx->arena.alloc(align_up(m.buf.size(), 256) + nband * sizeof(float));
+    if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace too small for the band buffer");
+    float* band = (float*)(dm + align_up(m.buf.size(), 256));
+    Job J;
+    std::memset(&J, 0, sizeof J);
+    J.nr = r.rows;
+    J.nc = r.cols;
+    J.xp = P.xp;
+    J.tp = P.tp;
+    J.n_angles = g.na;
+    J.bpitch = P.bpitch;
+    J.n_det = g.nd;
+    J.bp_mode = accumulate ? BP_ACCUM : BP_STORE;
+    J.ldx = r.cols;
+    J.scale = 1.f;
+    J.afp = (const AngFP*)(dm + o_afp);
+    J.abp = (const AngBP*)(dm + o_abp);
+    J.x = img;
+    J.y = band;
+    std::memcpy(m.buf.data() + o_job, &J, sizeof J);
+    std::vector<char*> allocs{dm};
+    TOMO_HIP(ctx, ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s));
+    TOMO_HIP(ctx, launch_band_gather(sino, g.nd, J.afp, g.na, band, P.bpitch, s));
+    TOMO_HIP(ctx, launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
+                            0, L.ag, s));
+    ctx->arena.free_after(allocs, s);
+    return TOMO_OK;
+    GUARD_END(ctx)
+}
+
+tomo_status tomo_fbp_ramlak(tomo_ctx* ctx, int32_t geom, const float* sino, float* img,
+                            void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!img || !sino) return fail(ctx, TOMO_EINVAL, "null pointer");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const Geom& g = *gp;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Rect full{0, 0, g.n, g.n};
+    const Plan P = make_plan(g, full, full);
+    std::vector<char*> allocs;
+    st = fbp_into(ctx, geom, sino, img, nullptr, nullptr, P, s, allocs, ctx->staging);
+    ctx->arena.free_after(allocs, s);
+    return st;
+    GUARD_END(ctx)
+}
+
+tomo_status tomo_exterior_subtract(tomo_ctx* ctx, int32_t geom, tomo_rect ext_roi,
+                                   const float* sino, const float* x_ext, float* sino_local,
+                                   void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!sino || !x_ext || !sino_local) return fail(ctx, TOMO_EINVAL, "null pointer");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const Geom& g = *gp;
+    if ((st = check_rect(ctx, g, ext_roi)) != TOMO_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Rect full{0, 0, g.n, g.n};
+    RoiState r;
+    std::memset(&r.prm, 0, sizeof r.prm);
+    r.prm.roi = ext_roi;
+    r.prm.iters = 1;
+    r.roi = r.ext = Rect{ext_roi.row0, ext_roi.col0, ext_roi.rows, ext_roi.cols};
+    r.plan = make_plan(g, r.ext, r.ext);
+    r.plan_full = make_plan(g, full, r.ext);
+    std::vector<char*> allocs;
+    ExtSrc E;
+    st = prepare_exterior(ctx, geom, sino, x_ext, s, E);
+    allocs.insert(allocs.end(), E.allocs.begin(), E.allocs.end());
+    if (st != TOMO_OK) {
+        ctx->arena.free_after(allocs, s);
+        return st;
+    }
+    char* blk = ctx->arena.alloc(state_bytes(g, r.plan));
+    if (!blk) {
+        ctx->arena.free_after(allocs, s);
+        return fail(ctx, TOMO_ENOMEM, "workspace too small for the region state");
+    }
+    allocs.push_back(blk);
+    carve_state(g, r, blk);
+    const LaunchCfg L = choose_launch(ctx, (long long)g.na * r.plan.wmax, 0);
+    std::vector<Item> i1, i2;
+    fp_items(i1, 0, r.plan_full.afp, L.seg);
+    fp_items(i2, 1, r.plan.afp, L.seg);
+    Meta m;
+    const size_t o_afp = m.add(r.plan.afp.data(), r.plan.afp.size() * sizeof(AngFP));
+    const size_t o_afpf = m.add(r.plan_full.afp.data(), r.plan_full.afp.size() * sizeof(AngFP));
+    const size_t o_jobs = m.reserve(2 * sizeof(Job));
+    const size_t o_i1 = m.add(i1.data(), i1.size() * sizeof(Item));
+    const size_t o_i2 = m.add(i2.data(), i2.size() * sizeof(Item));
+    char* dm = ctx->arena.alloc(m.buf.size());
+    if (!dm) {
+        ctx->arena.free_after(allocs, s);
+        return fail(ctx, TOMO_ENOMEM, "workspace too small for the tables");
+    }
+    allocs.push_back(dm);
+    r.d_afp = (AngFP*)(dm + o_afp);
+    r.d_afp_full = (AngFP*)(dm + o_afpf);
+    Job J[2];
+    J[0] = make_job(g, r, FP_BAND_FROM_GLOBAL, BP_STORE, 0);
+    J[0].nr = J[0].nc = g.n;
+    J[0].xp = E.xp;
+    J[0].tp = E.tp;
+    J[0].xb[0] = J[0].xb[1] = E.xb;
+    J[0].xt = E.xt;
+    J[0].afp = r.d_afp_full;
+    J[0].gbase = sino;
+    J[0].scale = -1.f;
+    J[1] = make_job(g, r, FP_BAND_ADD, BP_STORE, 0);
+    J[1].xb[1] = J[1].xb[0];
+    J[1].scale = 1.f;
+    J[0].y = J[1].y = r.b;
+    std::memcpy(m.buf.data() + o_jobs, J, sizeof J);
+    auto fin = [&](tomo_status x) {
+        ctx->arena.free_after(allocs, s);
+        return x;
+    };
+    hipError_t e;
+    if ((e = ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s)) != hipSuccess ||
+        (e = launch_fill((float*)blk, r.total_floats, 0.f, s)) != hipSuccess ||
+        (e = launch_fp((const Job*)(dm + o_jobs), (const Item*)(dm + o_i1), (int)i1.size(), 0,
+                       L.seg, s)) != hipSuccess ||
+        (e = launch_pad_copy(E.plain, g.n, r.ext.r0, r.ext.c0, r.ext.rows, r.ext.cols, r.xb0,
+                             r.plan.xp, r.xt, r.plan.tp, nullptr, 0, s)) != hipSuccess ||
+        (e = launch_fp((const Job*)(dm + o_jobs), (const Item*)(dm + o_i2), (int)i2.size(), 0,
+                       L.seg, s)) != hipSuccess ||
+        (e = launch_fill(sino_local, (size_t)g.na * g.nd, 0.f, s)) != hipSuccess ||
+        (e = launch_band_scatter(r.b, r.plan.bpitch, r.d_afp, g.na, sino_local, g.nd, 0, s)) !=
+            hipSuccess)
+        return fin(fail(ctx, TOMO_EHIP, "exterior subtraction: %s", hipGetErrorString(e)));
+    return fin(TOMO_OK);
+    GUARD_END(ctx)
+}
+
+tomo_status roi_solve(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                      const roi_params* params, float* out, void* hip_stream) {
+    if (!params) return ctx ? fail(ctx, TOMO_EINVAL, "null params") : TOMO_EINVAL;
+    float* outs[1] = {out};
+    return roi_solve_batch(ctx, geom, sino, x_ext, 1, params, outs, hip_stream);
+}
+
+tomo_status roi_solve_batch(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                            int32_t count, const roi_params* params, float* const* outs,
+                            void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!sino || !params || !outs || count < 1) return fail(ctx, TOMO_EINVAL, "null pointer or count < 1");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    return solve_batch(ctx, geom, sino, x_ext, nullptr, count, params, outs,
+                       (hipStream_t)hip_stream);
+    GUARD_END(ctx)
+}
+
+tomo_status roi_step_size(tomo_ctx* ctx, int32_t geom, tomo_rect ext, float* sigma_tau) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!sigma_tau) return fail(ctx, TOMO_EINVAL, "null pointer");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const Geom& g = *gp;
+    if ((st = check_rect(ctx, g, ext)) != TOMO_OK) return st;
+    RoiState r;
+    std::memset(&r.prm, 0, sizeof r.prm);
+    r.prm.method = ROI_TV_NONNEG_CP;
+    r.prm.iters = 1;
+    r.roi = r.ext = Rect{ext.row0, ext.col0, ext.rows, ext.cols};
+    r.plan = make_plan(g, r.ext, r.ext);
+    hipStream_t s = nullptr;
+    std::vector<char*> allocs;
+    char* blk = ctx->arena.alloc(state_bytes(g, r.plan));
+    if (!blk) return fail(ctx, TOMO_ENOMEM, "workspace too small");
+    allocs.push_back(blk);
+    carve_state(g, r, blk);
+    Meta m;
+    const size_t o_afp = m.add(r.plan.afp.data(), r.plan.afp.size() * sizeof(AngFP));
+    const size_t o_abp = m.add(r.plan.abp.data(), r.plan.abp.size() * sizeof(AngBP));
+    char* dm = ctx->arena.alloc(m.buf.size());
+    if (!dm) {
+        ctx->arena.free_after(allocs, s);
+        return fail(ctx, TOMO_ENOMEM, "workspace too small");
+    }
+    allocs.push_back(dm);
+    r.d_afp = (AngFP*)(dm + o_afp);
+    r.d_abp = (AngBP*)(dm + o_abp);
+    hipError_t e = ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s);
+    if (e != hipSuccess) {
+        ctx->arena.free_after(allocs, s);
+        return fail(ctx, TOMO_EHIP, "upload: %s", hipGetErrorString(e));
+    }
+    st = step_size_for(ctx, geom, r, s, ctx->staging);
+    ctx->arena.free_after(allocs, s);
+    if (st == TOMO_OK) *sigma_tau = r.sigma;
+    return st;
+    GUARD_END(ctx)
+}
+
+tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups) {
+    if (!ctx) return TOMO_EINVAL;
+    auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
+    if (!ok(fp_segments) || !ok(bp_groups))
+        return fail(ctx, TOMO_EINVAL, "launch knobs must be 0, 1, 2 or 4");
+    ctx->fp_seg = fp_segments;
+    ctx->bp_ag = bp_groups;
+    return TOMO_OK;
+}
+
+tomo_status tomo_roi_nnz(tomo_ctx* ctx, int32_t geom, tomo_rect region, int64_t* nnz) {
+    if (!ctx || !nnz) return TOMO_EINVAL;
+    const Geom* g;
+    tomo_status st = get_geom(ctx, geom, &g);
+    if (st != TOMO_OK) return st;
+    if ((st = check_rect(ctx, *g, region)) != TOMO_OK) return st;
+    *nnz = count_nnz(*g, Rect{region.row0, region.col0, region.rows, region.cols});
+    return TOMO_OK;
+}
+
+tomo_status tomo_kernel_timing(tomo_ctx* ctx, int enable) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    ctx->timing = enable != 0;
+    return TOMO_OK;
+}
+
+tomo_status tomo_kernel_time(tomo_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms,
+                             int reset) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (kernel < 0 || kernel > 1 || !launches || !total_ms)
+        return fail(ctx, TOMO_EINVAL, "kernel must be 0 (fp) or 1 (bp)");
+    for (auto& p : ctx->ev_pending) {
+        float ms = 0.f;
+        TOMO_HIP(ctx, hipEventSynchronize(std::get<1>(p)));
+        TOMO_HIP(ctx, hipEventElapsedTime(&ms, std::get<0>(p), std::get<1>(p)));
+        ctx->t_launches[std::get<2>(p)] += 1;
+        ctx->t_ms[std::get<2>(p)] += ms;
+    }
+    // each FP end event is the BP start event: return every event once
+    std::vector<hipEvent_t> seen;
+    for (auto& p : ctx->ev_pending) {
+        seen.push_back(std::get<0>(p));
+        seen.push_back(std::get<1>(p));
+    }
+    std::sort(seen.begin(), seen.end());
+    seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
+    ctx->ev_pool.insert(ctx->ev_pool.end(), seen.begin(), seen.end());
+    ctx->ev_pending.clear();
+    *launches = ctx->t_launches[kernel];
+    *total_ms = ctx->t_ms[kernel];
+    if (reset) {
+        ctx->t_launches[0] = ctx->t_launches[1] = 0;
+        ctx->t_ms[0] = ctx->t_ms[1] = 0.0;
+    }
+    return TOMO_OK;
+}
+
+tomo_status tomo_workspace_usage(tomo_ctx* ctx, size_t* used, size_t* peak) {
+    if (!ctx || !used || !peak) return TOMO_EINVAL;
+    *used = ctx->arena.used();
+    *peak = ctx->arena.peak();
+    return TOMO_OK;
+}
+
+tomo_status tomo_synchronize(tomo_ctx* ctx) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    serve_drain(ctx);
+    TOMO_HIP(ctx, hipDeviceSynchronize());
+    ctx->arena.reclaim(true);
+    return TOMO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Internal types shared by the HIP kernels and the host runtime.
+//
+// A "job" is one image region with its detector band: the extended local part
+// of one ROI solve, or the whole grid (FBP, exterior projection).  The two
+// batched kernels take an array of jobs and a flat list of work items, so one
+// launch serves any number of ROIs of any size (Section 5.6: independent local
+// parts reconstructed in parallel).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tomo {
+
+// Per (job, angle) table of the ray-driven forward projector (Joseph, Section 2.1).
+// Ray j of the band crosses outer line o (a row, or a column when tr = 1) at the
+// padded inner coordinate  pos = a0 + j * aj + o * step  (inner index + 1).
+struct AngFP {
+    double a0;
+    double aj;
+    double step;
+    float inv_m;      // 1 / max(|cos|, |sin|): path length per outer step
+    int32_t w;        // band width (rays)
+    int32_t i0;       // global bin of band position 0 (may lie off the detector)
+    int32_t tr;       // 1: step along columns, read the transposed image
+    int32_t pad0, pad1;
+};
+static_assert(sizeof(AngFP) == 48, "AngFP layout");
+
+// Per (job, angle) table of the pixel-driven backprojector.  Pixel (r, c) of the
+// region lands at padded band coordinate u = c * cu + r * su + u0 and touches band
+// entries floor(u) and floor(u) + 1 with weights
+//   max(0, A - f B) and max(0, (A - B) + f B),  f = u - floor(u),
+// A = 1/m, B = spacing / m^2: the hat max(0, 1 - |s_i - t| / m) / m.
+struct AngBP {
+    double cu, su, u0;
+    float A, B, AmB, pad;   // AmB = A - B
+};
+static_assert(sizeof(AngBP) == 40, "AngBP layout");
+
+enum FpMode : int32_t {
+    FP_STORE = 0,            // gout[k][i] = fp (on-detector bins of the band)
+    FP_ACCUM = 1,            // gout[k][i] += fp
+    FP_BAND_FROM_GLOBAL = 2, // y[k][j] = gbase[k][i] + scale * fp
+    FP_BAND_ADD = 3,         // y[k][j] += scale * fp
+    FP_CP_DUAL = 4,          // y <- (y + sigma (fp - b)) * dual_div
+    FP_SIRT = 5,             // y <- alpha (b - fp)
+    FP_BAND_STORE = 6,       // y = fp
+    FP_RESID = 7             // gout[k][i] = gbase[k][i] + scale * fp
+};
+
+enum BpMode : int32_t {
+    BP_STORE = 0,   // x = scale * bp   (optional padded copies)
+    BP_ACCUM = 1,   // x += scale * bp
+    BP_CP = 2,      // TV dual + primal prox + extrapolation
+    BP_SIRT = 3,    // x = max(0, x + bp)
+    BP_POWER = 4    // x = bp - div grad v, per-tile sums of x^2
+};
+
+enum JobFlags : int32_t { JF_HALF = 1, JF_ANISO = 2 };
+
+struct Job {
+    int32_t nr, nc;          // region rows, cols
+    int32_t xp, tp;          // pitch of padded xbar [nr][xp] (col c at c+1) and of xbarT [nc][tp]
+    int32_t n_angles;        // band rows
+    int32_t bpitch;          // band pitch (band position j stored at j + 1)
+    int32_t n_det;           // detector bins (off-detector band entries are kept at 0)
+    int32_t fp_mode, bp_mode;
+    int32_t flags;
+    int32_t parity0;         // xbar/z buffer read at launch step s: (s + parity0) & 1
+    int32_t ldx;             // pitch of x
+    int32_t ntc;             // tiles per row of the BP work decomposition
+    int32_t pad0;
+    float sigma, tau, lam, dual_div, alpha, scale;
+    const AngFP* afp;
+    const AngBP* abp;
+    float* x;                // primal / output image [nr][ldx]
+    float* xb[2];            // padded xbar, ping-pong
+    float* xt;               // padded transposed xbar
+    float* z[2];             // TV dual [2][nr][nc], ping-pong
+    float* y;                // band array [n_angles][bpitch] (dual / FP output / BP input)
+    const float* b;          // band data [n_angles][bpitch]
+    float* gout;             // full-detector sinogram output [n_angles][n_det]
+    const float* gbase;      // full-detector sinogram base
+    float* part;             // per-tile partial sums (BP_POWER)
+};
+
+struct Item {
+    int32_t job, a, b, pad;  // FP: angle, ray chunk; BP: tile row, tile col
+};
+
+// Launchers (tomo_kernels.hip).
+hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
+                     hipStream_t s);
+hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
+                     hipStream_t s);
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int tp, float v,
+                              hipStream_t s);
+hipError_t launch_pad_copy(const float* src, int lds, int r0, int c0, int nr, int nc,
+                           float* xb, int xp, float* xt, int tp, float* dst, int ldd,
+                           hipStream_t s);
+hipError_t launch_crop(const float* x, int ldx, int dr, int dc, int rows, int cols, float* out,
+                       hipStream_t s);
+hipError_t launch_band_gather(const float* sino, int n_det, const AngFP* afp, int n_angles,
+                              float* band, int bpitch, hipStream_t s);
+hipError_t launch_band_scatter(const float* band, int bpitch, const AngFP* afp, int n_angles,
+                               float* sino, int n_det, int accumulate, hipStream_t s);
+hipError_t launch_ramp(const float* sino, int n_angles, int n_det, const float* taps,
+                       const AngFP* afp, float* band, int bpitch, hipStream_t s);
+hipError_t launch_power_normalize(const float* w, int ldx, int nr, int nc, const float* part,
+                                  int n_part, float* xb, int xp, float* xt, int tp, float* est,
+                                  hipStream_t s);
+
+}  // namespace tomo

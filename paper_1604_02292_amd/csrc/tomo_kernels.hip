@@ -1,0 +1,666 @@
+// HIP kernels for gfx950 (MI355X): Joseph forward projection, matched
+// backprojection with the fused TV / prox epilogues of the Chambolle-Pock and
+// SIRT iterations, the Ram-Lak filter and small helpers.
+//
+// Operators (paper Section 2.1): W with entries
+//   w[(k,i),(r,c)] = max(0, 1 - |s_i - t_rc| / m_k) / m_k,  t_rc = x_c cos + y_r sin,
+// applied on the fly; local operators W_L = W M_L, W_L^T = M_L W^T.
+// Everything here is FP32 arithmetic except the ray / pixel positions, which
+// are anchored in FP64: a 4096-pixel grid needs more than FP32's 24 bits to
+// place a ray to 1e-5 of a pixel.
+//
+// Nothing here is a dense contraction, so there is no MFMA: the projectors are
+// gathers bound by the vector ALU and the load path, the epilogues by HBM.
+
+#include "tomo_internal.h"
+
+namespace tomo {
+
+namespace {
+
+// Logical work item for hardware block b.  The grid is a multiple of 8 and
+// consecutive blocks are dealt round-robin to the 8 XCDs; this mapping gives
+// each XCD a contiguous range of items, so the items of one ROI (adjacent in
+// the list) share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ int uniform_int(int v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Address-space views: tables and job descriptors are read through the
+// constant space (scalar loads into SGPRs), images and bands through the
+// global space (global_load with a scalar base), not through flat pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CONST_AS __attribute__((address_space(4)))
+#define GLOBAL_AS __attribute__((address_space(1)))
+#else   // the host pass only needs the declarations
+#define CONST_AS
+#define GLOBAL_AS
+#endif
+typedef const GLOBAL_AS float gcfloat;
+
+template <typename T>
+__device__ __forceinline__ const CONST_AS T* cview(const T* p) {
+    return (const CONST_AS T*)(p);
+}
+__device__ __forceinline__ gcfloat* gview(const float* p) { return (gcfloat*)(p); }
+
+// Raw buffer loads: a scalar resource for the whole array, a 32-bit per-lane
+// byte offset and a scalar byte offset for the row.  Word 3 is the raw
+// 32-bit-data format of gfx9-family buffer resources.
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ v2f load2(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+
+// ---------------------------------------------------------------------------
+// Forward projection.  One block = one angle of one job and 256/SEG rays;
+// each ray is split into SEG consecutive segments of outer lines (rows, or
+// columns for |sin| > |cos|) handled by different waves and summed in a fixed
+// order.  A wave's 64 lanes are 64 adjacent rays, so at every outer line they
+// read nearly contiguous pixels of one image row (the transposed copy of the
+// image serves the column-stepping angles, keeping those reads contiguous).
+// ---------------------------------------------------------------------------
+template <int SEG>
+__global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
+                                                 const Item* __restrict__ items, int n_items,
+                                                 int step) {
+    constexpr int SUBS = 4 / SEG;
+    __shared__ float red[SEG > 1 ? 256 : 1];
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    if (bid >= n_items) return;
+    const Item it = cview(items)[bid];
+    const CONST_AS Job* J = cview(jobs) + it.job;
+    const int k = it.a;
+    const AngFP A = cview(J->afp)[k];
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int seg = wave % SEG;
+    const int sub = wave / SEG;
+    const int jfirst = (it.b * SUBS + sub) * 64;
+    const int j = jfirst + lane;
+    const int rpar = (step + J->parity0) & 1;
+    gcfloat* img = gview(A.tr ? J->xt : J->xb[rpar]);
+    const int pitch = A.tr ? J->tp : J->xp;
+    const int n_outer = A.tr ? J->nc : J->nr;
+    const int n_inner = A.tr ? J->nr : J->nc;
+
+    float acc = 0.f;
+    if (jfirst < A.w) {
+        const int jlast = min(jfirst + 63, A.w - 1);
+        // Outer lines where some ray of this wave lies strictly inside the
+        // padded inner range (0, n_inner + 1); outside it every weight is 0.
+        const double pa = A.a0 + (double)jfirst * A.aj;
+        const double pb = A.a0 + (double)jlast * A.aj;
+        const double hi_in = (double)(n_inner + 1);
+        int o_lo = 0, o_hi = 0;
+        if (A.step == 0.0) {
+            const bool any = (fmax(pa, pb) > 0.0) && (fmin(pa, pb) < hi_in);
+            o_hi = any ? n_outer : 0;
+        } else {
+            const double inv = 1.0 / A.step;
+            const double t1 = -pa * inv, t2 = (hi_in - pa) * inv;
+            const double t3 = -pb * inv, t4 = (hi_in - pb) * inv;
+            double lo = fmin(fmin(t1, t2), fmin(t3, t4));
+            double hi = fmax(fmax(t1, t2), fmax(t3, t4));
+            lo = fmin(fmax(lo, -2.0), (double)n_outer + 2.0);
+            hi = fmin(fmax(hi, -2.0), (double)n_outer + 2.0);
+            o_lo = max(0, (int)floor(lo) - 1);
+            o_hi = min(n_outer, (int)ceil(hi) + 2);
+        }
+        o_lo = uniform_int(o_lo);
+        o_hi = uniform_int(o_hi);
+        const int len = max(0, o_hi - o_lo);
+        const int s0 = o_lo + (len * seg) / SEG;
+        const int s1 = o_lo + (len * (seg + 1)) / SEG;
+        const double pj = A.a0 + (double)j * A.aj;
+        const float stepf = (float)A.step;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, (size_t)n_outer * pitch * sizeof(float));
+        const unsigned rowb = (unsigned)pitch * 4u;
+        // 32 outer lines per FP64 anchor: pos = I + loc with |loc| <= 34, so the
+        // FP32 part carries a few 1e-6 of a pixel at any grid size.  loc is kept
+        // shifted by +64 so that truncation is floor and fract gives the weight.
+        for (int oc = s0; oc < s1; oc += 32) {
+            const double p0 = fma((double)oc, A.step, pj);
+            const double fl0 = fmin(fmax(floor(p0), -1.0e6), 1.0e6);
+            const int I = (int)fl0;
+            const float base64 = (float)(p0 - fl0) + 64.f;
+            const float lo = (float)(64 - I);              // padded position 0
+            const float hi = (float)(n_inner + 65 - I);    // padded position n_inner + 1
+            const unsigned ib4 = (unsigned)(I - 64) * 4u;
+            const int cnt = min(32, s1 - oc);
+            unsigned soff = (unsigned)oc * rowb;
+            int q = 0;
+            // 8 lines per step: the 8 paired loads issue before the first is used
+            for (; q + 8 <= cnt; q += 8) {
+                const float b8 = fmaf((float)q, stepf, base64);
+                float f[8];
+                v2f v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float loc = __builtin_amdgcn_fmed3f(fmaf((float)u, stepf, b8), lo, hi);
+                    f[u] = __builtin_amdgcn_fractf(loc);
+                    const unsigned off = ((unsigned)(int)loc << 2) + ib4;   // in [0, 4 (n_inner+1)]
+                    v[u] = load2(rs, off, soff + (unsigned)u * rowb);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += fmaf(f[u], v[u].y - v[u].x, v[u].x);
+                soff += 8u * rowb;
+            }
+            for (; q < cnt; ++q) {
+                const float loc = __builtin_amdgcn_fmed3f(fmaf((float)q, stepf, base64), lo, hi);
+                const float f = __builtin_amdgcn_fractf(loc);
+                const unsigned off = ((unsigned)(int)loc << 2) + ib4;
+                const v2f v = load2(rs, off, soff);
+                acc += fmaf(f, v.y - v.x, v.x);
+                soff += rowb;
+            }
+        }
+    }
+    if (SEG > 1) {
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        if (seg != 0) return;
+        acc = 0.f;
+#pragma unroll
+        for (int q = 0; q < SEG; ++q) acc += red[(sub * SEG + q) * 64 + lane];
+    }
+    if (j >= A.w) return;
+
+    const float fpv = acc * A.inv_m;
+    const int gi = A.i0 + j;
+    const bool ondet = (gi >= 0) && (gi < J->n_det);
+    const size_t bidx = (size_t)k * J->bpitch + 1 + j;
+    const size_t gidx = (size_t)k * J->n_det + gi;
+    float* y = J->y;
+    float* gout = J->gout;
+    switch (J->fp_mode) {
+        case FP_STORE:
+            if (ondet) gout[gidx] = fpv;
+            break;
+        case FP_ACCUM:
+            if (ondet) gout[gidx] += fpv;
+            break;
+        case FP_BAND_FROM_GLOBAL:
+            y[bidx] = ondet ? J->gbase[gidx] + J->scale * fpv : 0.f;
+            break;
+        case FP_BAND_ADD:
+            y[bidx] = ondet ? y[bidx] + J->scale * fpv : 0.f;
+            break;
+        case FP_CP_DUAL:
+            // prox of sigma F1*, F1(v) = ||v - b||^2 (or 1/2 ||v - b||^2)
+            y[bidx] = ondet ? (y[bidx] + J->sigma * (fpv - J->b[bidx])) * J->dual_div : 0.f;
+            break;
+        case FP_SIRT:
+            y[bidx] = ondet ? J->alpha * (J->b[bidx] - fpv) : 0.f;
+            break;
+        case FP_BAND_STORE:
+            y[bidx] = ondet ? fpv : 0.f;
+            break;
+        case FP_RESID:
+            if (ondet) gout[gidx] = J->gbase[gidx] + J->scale * fpv;
+            break;
+        default:
+            break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backprojection (pixel-driven gather: no atomics, bit-reproducible).  One
+// block = one tile of 256/AG pixels of one job; each pixel's angles are split
+// into AG contiguous groups summed in a fixed order.  For the CP mode the block
+// first computes the TV dual update on its tile plus a one-pixel top/left halo
+// (from the previous xbar and z, which are double-buffered so neighbouring
+// tiles never see half-updated values), takes its divergence, then applies
+// the primal prox and the extrapolation to its own pixels.
+// ---------------------------------------------------------------------------
+template <int AG>
+__global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
+                                                 const Item* __restrict__ items, int n_items,
+                                                 int step) {
+    constexpr int P = 256 / AG;
+    constexpr int TW = (AG == 4) ? 8 : 16;
+    constexpr int TH = P / TW;
+    __shared__ float xs[TH + 2][TW + 2];
+    __shared__ float zs0[TH + 1][TW + 1];
+    __shared__ float zs1[TH + 1][TW + 1];
+    __shared__ float red[256];
+
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    if (bid >= n_items) return;
+    const Item it = cview(items)[bid];
+    const CONST_AS Job* J = cview(jobs) + it.job;
+    const int R0 = it.a * TH, C0 = it.b * TW;
+    const int t = threadIdx.x;
+    const int g = uniform_int(t / P);      // P is a multiple of 64: one group per wave
+    const int p = t % P;
+    const int tr = p / TW, tc = p % TW;
+    const int r = R0 + tr, c = C0 + tc;
+    const int nr = J->nr, nc = J->nc;
+    const bool inside = (r < nr) && (c < nc);
+    const int mode = J->bp_mode;
+    const int rpar = (step + J->parity0) & 1, wpar = rpar ^ 1;
+    const bool tv = (mode == BP_CP) || (mode == BP_POWER);
+
+    float divv = 0.f, zn0 = 0.f, zn1 = 0.f;
+    if (tv) {
+        gcfloat* xb = gview(J->xb[rpar]);
+        const int xp = J->xp;
+        for (int q = t; q < (TH + 2) * (TW + 2); q += 256) {
+            const int lr = q / (TW + 2), lc = q % (TW + 2);
+            const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
+            float v = 0.f;
+            if (rr >= 0 && rr < nr && cc >= -1 && cc <= nc) v = xb[(size_t)rr * xp + cc + 1];
+            xs[lr][lc] = v;
+        }
+        __syncthreads();
+        const size_t plane = (size_t)nr * nc;
+        const float lam = J->lam, sigma = J->sigma;
+        const int aniso = J->flags & JF_ANISO;
+        gcfloat* zo = gview(J->z[rpar]);
+        for (int q = t; q < (TH + 1) * (TW + 1); q += 256) {
+            const int lr = q / (TW + 1), lc = q % (TW + 1);
+            const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
+            float q0 = 0.f, q1 = 0.f;
+            if (rr >= 0 && rr < nr && cc >= 0 && cc < nc) {
+                const float xc = xs[lr][lc];
+                // forward differences, zero on the last row / column (Neumann)
+                const float g0 = (rr < nr - 1) ? xs[lr + 1][lc] - xc : 0.f;
+                const float g1 = (cc < nc - 1) ? xs[lr][lc + 1] - xc : 0.f;
+                if (mode == BP_POWER) {
+                    q0 = g0;
+                    q1 = g1;
+                } else {
+                    const size_t zi = (size_t)rr * nc + cc;
+                    q0 = zo[zi] + sigma * g0;
+                    q1 = zo[plane + zi] + sigma * g1;
+                    if (aniso) {
+                        q0 = fminf(fmaxf(q0, -lam), lam);
+                        q1 = fminf(fmaxf(q1, -lam), lam);
+                    } else if (lam > 0.f) {
+                        // projection of each pixel's 2-vector onto the lambda-ball
+                        const float sc = fmaxf(1.f, sqrtf(q0 * q0 + q1 * q1) / lam);
+                        q0 = q0 / sc;
+                        q1 = q1 / sc;
+                    } else {
+                        q0 = 0.f;
+                        q1 = 0.f;
+                    }
+                }
+            }
+            zs0[lr][lc] = q0;
+            zs1[lr][lc] = q1;
+        }
+        __syncthreads();
+        if (inside) {
+            zn0 = zs0[tr + 1][tc + 1];
+            zn1 = zs1[tr + 1][tc + 1];
+            // div = -grad^T (z is 0 outside the region and on its last row/column)
+            divv = (zn0 - zs0[tr][tc + 1]) + (zn1 - zs1[tr + 1][tc]);
+        }
+    }
+
+    float acc = 0.f;
+    if (inside) {
+        const double lcd = (double)c, lrd = (double)r;
+        const int na = J->n_angles;
+        const int k0 = (na * g) / AG, k1 = (na * (g + 1)) / AG;
+        const int bpitch = J->bpitch;
+        const int bpm = bpitch - 2;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(J->y, (size_t)na * bpitch * sizeof(float));
+        const unsigned rowb = (unsigned)bpitch * 4u;
+        const CONST_AS AngBP* tab = cview(J->abp);
+        int k = k0;
+        // 4 angles per step: 4 paired band loads in flight
+        for (; k + 4 <= k1; k += 4) {
+            float f[4];
+            v2f yv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const AngBP a = tab[k + u];
+                const double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
+                // uu >= 1 inside the band; the unsigned clamp keeps any stray
+                // index inside the row (the value would be wrong, never a fault)
+                const unsigned i = min((unsigned)(int)uu, (unsigned)bpm);
+                f[u] = (float)__builtin_amdgcn_fract(uu);
+                yv[u] = load2(rs, i << 2, (unsigned)(k + u) * rowb);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const AngBP a = tab[k + u];
+                const float w0 = fmaxf(0.f, fmaf(-f[u], a.B, a.A));
+                const float w1 = fmaxf(0.f, fmaf(f[u], a.B, a.AmB));
+                acc = fmaf(w0, yv[u].x, acc);
+                acc = fmaf(w1, yv[u].y, acc);
+            }
+        }
+        for (; k < k1; ++k) {
+            const AngBP a = tab[k];
+            const double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
+            const unsigned i = min((unsigned)(int)uu, (unsigned)bpm);
+            const float f = (float)__builtin_amdgcn_fract(uu);
+            const v2f yv = load2(rs, i << 2, (unsigned)k * rowb);
+            const float w0 = fmaxf(0.f, fmaf(-f, a.B, a.A));
+            const float w1 = fmaxf(0.f, fmaf(f, a.B, a.AmB));
+            acc = fmaf(w0, yv.x, acc);
+            acc = fmaf(w1, yv.y, acc);
+        }
+    }
+    if (AG > 1) {
+        red[t] = acc;
+        __syncthreads();
+        acc = 0.f;
+        if (g == 0) {
+#pragma unroll
+            for (int q = 0; q < AG; ++q) acc += red[q * P + p];
+        }
+    }
+
+    float sq = 0.f;
+    if (g == 0 && inside) {
+        const size_t xi = (size_t)r * J->ldx + c;
+        float* x = J->x;
+        switch (mode) {
+            case BP_STORE: {
+                const float v = J->scale * acc;
+                x[xi] = v;
+                float* xb0 = J->xb[0];
+                float* xt = J->xt;
+                if (xb0) xb0[(size_t)r * J->xp + c + 1] = v;
+                if (xt) xt[(size_t)c * J->tp + r + 1] = v;
+            } break;
+            case BP_ACCUM:
+                x[xi] += J->scale * acc;
+                break;
+            case BP_CP: {
+                const float xo = x[xi];
+                const float xn = fmaxf(0.f, xo - J->tau * (acc - divv));
+                x[xi] = xn;
+                const float xbn = 2.f * xn - xo;   // theta = 1
+                float* xbw = J->xb[wpar];
+                float* xt = J->xt;
+                float* zw = J->z[wpar];
+                xbw[(size_t)r * J->xp + c + 1] = xbn;
+                xt[(size_t)c * J->tp + r + 1] = xbn;
+                const size_t zi = (size_t)r * nc + c;
+                zw[zi] = zn0;
+                zw[(size_t)nr * nc + zi] = zn1;
+            } break;
+            case BP_SIRT: {
+                const float xn = fmaxf(0.f, x[xi] + acc);
+                x[xi] = xn;
+                float* xbw = J->xb[wpar];
+                float* xt = J->xt;
+                xbw[(size_t)r * J->xp + c + 1] = xn;
+                xt[(size_t)c * J->tp + r + 1] = xn;
+            } break;
+            case BP_POWER: {
+                const float w = acc - divv;
+                x[xi] = w;
+                sq = w * w;
+            } break;
+            default:
+                break;
+        }
+    }
+    if (mode == BP_POWER) {
+        __syncthreads();
+        red[t] = sq;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) {
+            float* part = J->part;
+            part[it.a * J->ntc + it.b] = red[0];
+        }
+    }
+}
+
+__global__ void fill_kernel(float* __restrict__ p, size_t n, float v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Interior of the padded buffers set to v, padding to 0.
+__global__ void fill_padded_kernel(float* __restrict__ xb, float* __restrict__ xt, int nr, int nc,
+                                   int xp, int tp, float v) {
+    const size_t nb = (size_t)nr * xp, nt = xt ? (size_t)nc * tp : 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb + nt;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (i < nb) {
+            const int cc = (int)(i % xp);
+            xb[i] = (cc >= 1 && cc <= nc) ? v : 0.f;
+        } else {
+            const size_t q = i - nb;
+            const int rr = (int)(q % tp);
+            xt[q] = (rr >= 1 && rr <= nr) ? v : 0.f;
+        }
+    }
+}
+
+// Region [r0, r0+nr) x [c0, c0+nc) of src -> padded xbar (+ transposed, + plain).
+__global__ void pad_copy_kernel(const float* __restrict__ src, int lds, int r0, int c0, int nr,
+                                int nc, float* __restrict__ xb, int xp, float* __restrict__ xt,
+                                int tp, float* __restrict__ dst, int ldd) {
+    __shared__ float tile[32][33];
+    const int bc = blockIdx.x * 32, br = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int q = ty; q < 32; q += 8) {
+        const int rr = br + q, cc = bc + tx;
+        float v = 0.f;
+        if (rr < nr && cc < nc) {
+            v = src[(size_t)(r0 + rr) * lds + c0 + cc];
+            if (xb) xb[(size_t)rr * xp + cc + 1] = v;
+            if (dst) dst[(size_t)rr * ldd + cc] = v;
+        }
+        tile[q][tx] = v;
+    }
+    if (!xt) return;
+    __syncthreads();
+    for (int q = ty; q < 32; q += 8) {
+        const int cc = bc + q, rr = br + tx;
+        if (rr < nr && cc < nc) xt[(size_t)cc * tp + rr + 1] = tile[tx][q];
+    }
+}
+
+__global__ void crop_kernel(const float* __restrict__ x, int ldx, int dr, int dc, int rows,
+                            int cols, float* __restrict__ out) {
+    const size_t n = (size_t)rows * cols;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int rr = (int)(i / cols), cc = (int)(i % cols);
+        out[i] = x[(size_t)(rr + dr) * ldx + cc + dc];
+    }
+}
+
+// Full-detector sinogram rows -> band layout (band position j at j + 1; zeros
+// off the detector and in the padding).
+__global__ void band_gather_kernel(const float* __restrict__ sino, int n_det,
+                                   const AngFP* __restrict__ afp, float* __restrict__ band,
+                                   int bpitch) {
+    const int k = blockIdx.x;
+    const int i0 = afp[k].i0, w = afp[k].w;
+    for (int q = threadIdx.x; q < bpitch; q += blockDim.x) {
+        const int j = q - 1, gi = i0 + j;
+        float v = 0.f;
+        if (j >= 0 && j < w && gi >= 0 && gi < n_det) v = sino[(size_t)k * n_det + gi];
+        band[(size_t)k * bpitch + q] = v;
+    }
+}
+
+__global__ void band_scatter_kernel(const float* __restrict__ band, int bpitch,
+                                    const AngFP* __restrict__ afp, float* __restrict__ sino,
+                                    int n_det, int accumulate) {
+    const int k = blockIdx.x;
+    const int i0 = afp[k].i0, w = afp[k].w;
+    for (int j = threadIdx.x; j < w; j += blockDim.x) {
+        const int gi = i0 + j;
+        if (gi < 0 || gi >= n_det) continue;
+        const float v = band[(size_t)k * bpitch + 1 + j];
+        if (accumulate)
+            sino[(size_t)k * n_det + gi] += v;
+        else
+            sino[(size_t)k * n_det + gi] = v;
+    }
+}
+
+// Ram-Lak filtering of one angle per block: a linear (zero-padded) convolution
+// along the detector, q[i] = taps[0] p[i] + sum_{odd d} taps[d] (p[i-d] + p[i+d]),
+// written into the band layout of the receiving job.
+__global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sino, int n_det,
+                                                   const float* __restrict__ taps,
+                                                   const AngFP* __restrict__ afp,
+                                                   float* __restrict__ band, int bpitch) {
+    extern __shared__ float sh[];
+    float* prow = sh;              // n_det
+    float* htab = sh + n_det;      // n_det
+    const int k = blockIdx.x;
+    for (int i = threadIdx.x; i < n_det; i += blockDim.x) {
+        prow[i] = sino[(size_t)k * n_det + i];
+        htab[i] = taps[i];
+    }
+    __syncthreads();
+    const int i0 = afp[k].i0, w = afp[k].w;
+    for (int i = threadIdx.x; i < n_det; i += blockDim.x) {
+        float acc = htab[0] * prow[i];
+        const int dl = i, dr = n_det - 1 - i, dm = min(dl, dr);
+        int d = 1;
+        for (; d <= dm; d += 2) acc = fmaf(htab[d], prow[i - d] + prow[i + d], acc);
+        for (int e = d; e <= dl; e += 2) acc = fmaf(htab[e], prow[i - e], acc);
+        for (int e = d; e <= dr; e += 2) acc = fmaf(htab[e], prow[i + e], acc);
+        const int j = i - i0;
+        if (j >= 0 && j < w) band[(size_t)k * bpitch + 1 + j] = acc;
+    }
+}
+
+// Power iteration: v = w / ||w||, ||w|| from the per-tile partial sums (summed
+// in the same fixed order by every block), written into the padded buffers.
+__global__ __launch_bounds__(256) void power_normalize_kernel(
+    const float* __restrict__ w, int ldx, int nr, int nc, const float* __restrict__ part,
+    int n_part, float* __restrict__ xb, int xp, float* __restrict__ xt, int tp,
+    float* __restrict__ est) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < n_part; q += 256) s += (double)part[q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double nrm = sqrt(red[0]);
+    const float inv = nrm > 0.0 ? (float)(1.0 / nrm) : 0.f;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *est = (float)nrm;
+    const size_t n = (size_t)nr * nc;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const int rr = (int)(i / nc), cc = (int)(i % nc);
+        const float v = w[(size_t)rr * ldx + cc] * inv;
+        xb[(size_t)rr * xp + cc + 1] = v;
+        xt[(size_t)cc * tp + rr + 1] = v;
+    }
+}
+
+inline unsigned grid_for(size_t n, unsigned block, unsigned cap = 8192) {
+    size_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+inline unsigned pad8(int n) { return (unsigned)((n + 7) & ~7); }
+
+}  // namespace
+
+hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
+                     hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    const dim3 grid(pad8(n_items)), block(256);
+    switch (segments) {
+        case 1: hipLaunchKernelGGL(fp_kernel<1>, grid, block, 0, s, jobs, items, n_items, step); break;
+        case 2: hipLaunchKernelGGL(fp_kernel<2>, grid, block, 0, s, jobs, items, n_items, step); break;
+        default: hipLaunchKernelGGL(fp_kernel<4>, grid, block, 0, s, jobs, items, n_items, step); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
+                     hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    const dim3 grid(pad8(n_items)), block(256);
+    switch (groups) {
+        case 1: hipLaunchKernelGGL(bp_kernel<1>, grid, block, 0, s, jobs, items, n_items, step); break;
+        case 2: hipLaunchKernelGGL(bp_kernel<2>, grid, block, 0, s, jobs, items, n_items, step); break;
+        default: hipLaunchKernelGGL(bp_kernel<4>, grid, block, 0, s, jobs, items, n_items, step); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int tp, float v,
+                              hipStream_t s) {
+    const size_t n = (size_t)nr * xp + (xt ? (size_t)nc * tp : 0);
+    hipLaunchKernelGGL(fill_padded_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, xb, xt, nr,
+                       nc, xp, tp, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_copy(const float* src, int lds, int r0, int c0, int nr, int nc, float* xb,
+                           int xp, float* xt, int tp, float* dst, int ldd, hipStream_t s) {
+    const dim3 grid((nc + 31) / 32, (nr + 31) / 32);
+    hipLaunchKernelGGL(pad_copy_kernel, grid, dim3(256), 0, s, src, lds, r0, c0, nr, nc, xb, xp,
+                       xt, tp, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_crop(const float* x, int ldx, int dr, int dc, int rows, int cols, float* out,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(crop_kernel, dim3(grid_for((size_t)rows * cols, 256)), dim3(256), 0, s, x,
+                       ldx, dr, dc, rows, cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_gather(const float* sino, int n_det, const AngFP* afp, int n_angles,
+                              float* band, int bpitch, hipStream_t s) {
+    hipLaunchKernelGGL(band_gather_kernel, dim3(n_angles), dim3(256), 0, s, sino, n_det, afp,
+                       band, bpitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_scatter(const float* band, int bpitch, const AngFP* afp, int n_angles,
+                               float* sino, int n_det, int accumulate, hipStream_t s) {
+    hipLaunchKernelGGL(band_scatter_kernel, dim3(n_angles), dim3(256), 0, s, band, bpitch, afp,
+                       sino, n_det, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_ramp(const float* sino, int n_angles, int n_det, const float* taps,
+                       const AngFP* afp, float* band, int bpitch, hipStream_t s) {
+    const size_t lds = (size_t)2 * n_det * sizeof(float);
+    hipLaunchKernelGGL(ramp_kernel, dim3(n_angles), dim3(256), lds, s, sino, n_det, taps, afp,
+                       band, bpitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_normalize(const float* w, int ldx, int nr, int nc, const float* part,
+                                  int n_part, float* xb, int xp, float* xt, int tp, float* est,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(power_normalize_kernel, dim3(grid_for((size_t)nr * nc, 256, 256)),
+                       dim3(256), 0, s, w, ldx, nr, nc, part, n_part, xb, xp, xt, tp, est);
+    return hipGetLastError();
+}
+
+}  // namespace tomo

@@ -1,0 +1,191 @@
+// Host runtime internals: geometry, planning tables, the workspace arena and
+// the context.  Shared by the C ABI (tomo_capi.cpp) and the serving scheduler
+// (tomo_serve.cpp).
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/tomo.h"
+#include "tomo_internal.h"
+
+namespace tomo {
+
+struct Rect {
+    int r0, c0, rows, cols;
+};
+
+// Parallel-beam geometry (Section 2.1); the row/column-stepping branch of
+// Joseph's method is decided here, once, in FP64.
+struct Geom {
+    int n = 0, na = 0, nd = 0;
+    double spacing = 1.0, offset = 0.0;
+    std::vector<double> th, c, s, m;
+    std::vector<int> ystep;
+    float* d_taps = nullptr;   // Ram-Lak taps h[0..nd-1] / spacing (device, GPU contexts)
+    size_t taps_off = 0;
+};
+
+// Host tables of one job: an image region and the detector band of a (possibly
+// different) band source region.
+struct Plan {
+    Rect reg{};
+    std::vector<AngFP> afp;
+    std::vector<AngBP> abp;
+    int wmax = 0;
+    int bpitch = 0;
+    int xp = 0, tp = 0;
+};
+
+void band_of(const Geom& g, const Rect& b, int k, int* i0, int* w);
+Plan make_plan(const Geom& g, const Rect& reg, const Rect& band_src);
+Rect extend_rect(const Rect& roi, int margin, int n);
+
+// First-fit allocator over the caller's workspace.  Frees are deferred until
+// an event recorded on the stream that last used the memory has completed, so
+// memory is only reused in stream order.
+class Arena {
+public:
+    void init(char* base, size_t bytes);
+    // Returns nullptr when the request does not fit even after reclaiming all
+    // completed deferred frees (waiting for them when `wait` is true).
+    char* alloc(size_t bytes, bool wait = true);
+    void free_now(char* p);
+    void free_after(std::vector<char*> ps, hipStream_t s);
+    void reclaim(bool wait);
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+    size_t capacity() const { return size_; }
+    size_t largest_free() const;
+
+private:
+    char* base_ = nullptr;
+    size_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    std::map<size_t, size_t> live_;   // offset -> length
+    std::deque<std::pair<hipEvent_t, std::vector<char*>>> pending_;
+    std::recursive_mutex mu_;
+    void release_locked(size_t off);
+};
+
+// Pinned host staging for small uploads (tables, job descriptors, work lists).
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool ev_live = false;
+    hipError_t upload(void* dev, const void* src, size_t bytes, hipStream_t s);
+    void destroy();
+};
+
+struct SinoState;
+struct ServeState;
+
+}  // namespace tomo
+
+struct tomo_ctx {
+    tomo_ctx();
+    ~tomo_ctx();   // defined where the serving state is a complete type
+    int device = -1;
+    bool host_only = true;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    tomo::Arena arena;
+    tomo::Staging staging;
+    std::string err;
+    std::recursive_mutex mu;   // geometry list, caches, registrations
+    std::deque<tomo::Geom> geoms;   // deque: references stay valid while serving reads them
+    std::map<std::tuple<int, int, int>, float> step_cache;
+    int fp_seg = 0, bp_ag = 0;
+    std::map<int, std::unique_ptr<tomo::SinoState>> sinos;
+    int next_sino = 1;
+    std::unique_ptr<tomo::ServeState> serve;
+    // kernel timing (measurement hook)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::tuple<hipEvent_t, hipEvent_t, int>> ev_pending;
+    long long t_launches[2] = {0, 0};
+    double t_ms[2] = {0.0, 0.0};
+};
+
+namespace tomo {
+
+tomo_status fail(tomo_ctx* ctx, tomo_status st, const char* fmt, ...);
+
+#define TOMO_HIP(ctx, expr)                                                                 \
+    do {                                                                                     \
+        hipError_t e__ = (expr);                                                             \
+        if (e__ != hipSuccess)                                                               \
+            return ::tomo::fail((ctx), TOMO_EHIP, "%s failed: %s", #expr, hipGetErrorString(e__)); \
+    } while (0)
+
+// ---- solve pipeline shared by roi_solve, roi_solve_batch and serving ----
+
+struct RoiState {
+    roi_params prm{};
+    Rect roi{}, ext{};
+    Plan plan;            // ext region, ext band
+    Plan plan_full;       // full grid, ext band (exterior projection)
+    // device
+    char* block = nullptr;   // contiguous zero-initialised state
+    size_t state_floats = 0;   // x .. y (re-zeroed before iterating)
+    size_t total_floats = 0;   // x .. part
+    float *x = nullptr, *xb0 = nullptr, *xb1 = nullptr, *xt = nullptr, *z0 = nullptr,
+          *z1 = nullptr, *y = nullptr, *b = nullptr, *part = nullptr;
+    AngFP* d_afp = nullptr;
+    AngBP* d_abp = nullptr;
+    AngFP* d_afp_full = nullptr;
+    float sigma = 0.f, tau = 0.f;
+    int ntr = 0, ntc = 0;
+};
+
+struct LaunchCfg {
+    int seg = 4, ag = 4;
+};
+
+LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels);
+void bp_tile(int ag, int* th, int* tw);
+size_t state_bytes(const Geom& g, const Plan& p);
+tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p);
+hipEvent_t timing_event(tomo_ctx* ctx);
+long long count_nnz(const Geom& g, const Rect& reg);
+tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, Staging& stg);
+Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int ntc);
+void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg);
+void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag);
+void carve_state(const Geom& g, RoiState& st, char* blk);
+tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, float* xb, float* xt,
+                     const Plan& P, hipStream_t s, std::vector<char*>& allocs, Staging& stg);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Packs small host arrays for one upload into one device block.
+struct Meta {
+    std::vector<char> buf;
+    size_t add(const void* p, size_t n) {
+        const size_t off = align_up(buf.size(), 64);
+        buf.resize(off + n);
+        if (n) std::memcpy(buf.data() + off, p, n);
+        return off;
+    }
+    size_t reserve(size_t n) {
+        const size_t off = align_up(buf.size(), 64);
+        buf.resize(off + n);
+        return off;
+    }
+};
+
+}  // namespace tomo

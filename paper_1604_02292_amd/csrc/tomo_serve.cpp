@@ -1,0 +1,525 @@
+// Serving: resident sinograms and a continuous-batching scheduler for ROI solves.
+//
+// Requests join a bounded host queue (roi_submit never blocks).  A scheduler
+// thread owns one HIP stream; at every tick boundary it admits queued requests
+// into free slots while their state fits in the workspace (the HBM budget),
+// prepares them (exterior subtraction from the resident residual, step size),
+// runs a few iterations of *all* admitted slots as one forward-projection and
+// one backprojection launch per iteration, and retires finished slots (crop into
+// the caller's buffer, ticket done).  A slot's arithmetic never depends on the
+// other slots: its work items, reduction order and launch shape are fixed, so a
+// result is bit-identical alone and in any mix.  Independent local parts are
+// the paper's unit of parallel work (Section 5.6).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "tomo_runtime.h"
+#include "tomo_serve.h"
+
+namespace tomo {
+
+namespace {
+thread_local bool t_serve = false;
+thread_local std::string t_err;
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Fixed launch shape for served slots (see the note at the top of the file).
+constexpr int kServeSeg = 2;
+constexpr int kServeAG = 2;
+}  // namespace
+
+bool on_serve_thread() { return t_serve; }
+void set_thread_error(const char* msg) { t_err = msg; }
+
+struct Request {
+    uint64_t ticket = 0;
+    int sino_id = 0;
+    roi_params prm{};
+    float* out = nullptr;
+    double t_submit = 0.0;
+};
+
+struct Slot {
+    Request req;
+    RoiState st;
+    SinoState* sino = nullptr;
+    int it = 0;
+    int parity0 = 0;
+    std::vector<char*> allocs;
+};
+
+struct TicketInfo {
+    int state = 0;   // 0 pending, 1 done, 2 failed
+    float latency_ms = 0.f;
+    std::string err;
+};
+
+struct ServeState {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv, cv_idle;
+    std::deque<Request> queue;
+    size_t queue_cap = 8192;
+    std::map<uint64_t, TicketInfo> tickets;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    bool busy = false;
+    int max_slots = 64;
+    int iters_per_tick = 4;
+    hipStream_t stream = nullptr;
+    Staging staging;
+    long long step = 0;   // global iteration counter of the batch
+};
+
+tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s) {
+    const Geom& g = ctx->geoms[S.gid];
+    const Rect full{0, 0, g.n, g.n};
+    const Plan P = make_plan(g, full, full);
+    S.xp = P.xp;
+    S.tp = P.tp;
+    const size_t nb = (size_t)g.n * P.xp, nt = (size_t)g.n * P.tp, np = (size_t)g.n * g.n;
+    const size_t nr = (size_t)g.na * g.nd;
+    S.block = ctx->arena.alloc((nb + nt + np + nr) * sizeof(float) + 1024);
+    if (!S.block) return fail(ctx, TOMO_ENOMEM, "workspace too small to register the sinogram");
+    S.xb = (float*)S.block;
+    S.xt = S.xb + align_up(nb, 64);
+    S.x_plain = S.xt + align_up(nt, 64);
+    S.resid = S.x_plain + align_up(np, 64);
+    std::vector<char*> allocs;
+    TOMO_HIP(ctx, launch_fill(S.xb, (size_t)(S.resid - S.xb), 0.f, s));
+    tomo_status st = fbp_into(ctx, S.gid, S.sino, S.x_plain, S.xb, S.xt, P, s, allocs, ctx->staging);
+    if (st != TOMO_OK) {
+        ctx->arena.free_after(allocs, s);
+        return st;
+    }
+    // r = p - W x_ext over the whole detector
+    const LaunchCfg L = choose_launch(ctx, (long long)g.na * g.nd, 0);
+    std::vector<Item> items;
+    fp_items(items, 0, P.afp, L.seg);
+    Meta m;
+    const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
+    const size_t o_job = m.reserve(sizeof(Job));
+    const size_t o_it = m.add(items.data(), items.size() * sizeof(Item));
+    char* dm = ctx->arena.alloc(m.buf.size());
+    if (!dm) {
+        ctx->arena.free_after(allocs, s);
+        return fail(ctx, TOMO_ENOMEM, "workspace too small for the residual tables");
+    }
+    allocs.push_back(dm);
+    Job J;
+    std::memset(&J, 0, sizeof J);
+    J.nr = J.nc = g.n;
+    J.xp = P.xp;
+    J.tp = P.tp;
+    J.n_angles = g.na;
+    J.bpitch = P.bpitch;
+    J.n_det = g.nd;
+    J.fp_mode = FP_RESID;
+    J.afp = (const AngFP*)(dm + o_afp);
+    J.xb[0] = J.xb[1] = S.xb;
+    J.xt = S.xt;
+    J.gout = S.resid;
+    J.gbase = S.sino;
+    J.scale = -1.f;
+    std::memcpy(m.buf.data() + o_job, &J, sizeof J);
+    hipError_t e = ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s);
+    if (e == hipSuccess) e = launch_fill(S.resid, nr, 0.f, s);
+    if (e == hipSuccess)
+        e = launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(), 0,
+                      L.seg, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    ctx->arena.free_after(allocs, s);
+    if (e != hipSuccess) return fail(ctx, TOMO_EHIP, "registering: %s", hipGetErrorString(e));
+    return TOMO_OK;
+}
+
+namespace {
+
+// Prepare one admitted slot on the scheduler stream: tables, b = r + W_L x_ext|L,
+// step size, zeroed state.
+tomo_status prepare_slot(tomo_ctx* ctx, ServeState& S, Slot& sl) {
+    const Geom& g = ctx->geoms[sl.sino->gid];
+    RoiState& r = sl.st;
+    hipStream_t s = S.stream;
+    Meta m;
+    const size_t o_afp = m.add(r.plan.afp.data(), r.plan.afp.size() * sizeof(AngFP));
+    const size_t o_abp = m.add(r.plan.abp.data(), r.plan.abp.size() * sizeof(AngBP));
+    const size_t o_job = m.reserve(sizeof(Job));
+    std::vector<Item> items;
+    fp_items(items, 0, r.plan.afp, kServeSeg);
+    const size_t o_it = m.add(items.data(), items.size() * sizeof(Item));
+    char* dm = ctx->arena.alloc(m.buf.size(), false);
+    if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace full");
+    sl.allocs.push_back(dm);
+    r.d_afp = (AngFP*)(dm + o_afp);
+    r.d_abp = (AngBP*)(dm + o_abp);
+    Job J = make_job(g, r, FP_BAND_FROM_GLOBAL, BP_STORE, 0);
+    J.xb[1] = J.xb[0];
+    J.gbase = sl.sino->resid;
+    J.y = r.b;
+    J.scale = 1.f;
+    std::memcpy(m.buf.data() + o_job, &J, sizeof J);
+    TOMO_HIP(ctx, S.staging.upload(dm, m.buf.data(), m.buf.size(), s));
+    TOMO_HIP(ctx, launch_fill((float*)r.block, r.total_floats, 0.f, s));
+    TOMO_HIP(ctx, launch_pad_copy(sl.sino->x_plain, g.n, r.ext.r0, r.ext.c0, r.ext.rows,
+                                  r.ext.cols, r.xb0, r.plan.xp, r.xt, r.plan.tp, nullptr, 0, s));
+    TOMO_HIP(ctx, launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
+                            0, kServeSeg, s));
+    tomo_status st = step_size_for(ctx, sl.sino->gid, r, s, S.staging);
+    if (st != TOMO_OK) return st;
+    TOMO_HIP(ctx, launch_fill((float*)r.block, r.state_floats, 0.f, s));
+    return TOMO_OK;
+}
+
+void finish_ticket(ServeState& S, uint64_t t, int state, float lat, const std::string& err) {
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.tickets.find(t);
+    if (it == S.tickets.end()) return;
+    it->second.state = state;
+    it->second.latency_ms = lat;
+    it->second.err = err;
+}
+
+void scheduler(tomo_ctx* ctx) {
+    t_serve = true;
+    ServeState& S = *ctx->serve;
+    (void)hipSetDevice(ctx->device);
+    std::vector<std::unique_ptr<Slot>> slots;
+    char* d_lists = nullptr;
+    const Job* d_jobs = nullptr;
+    const Item* d_fi = nullptr;
+    const Item* d_bi = nullptr;
+    int n_fi = 0, n_bi = 0;
+    bool changed = false;
+    for (;;) {
+        // ---- admission ----
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            S.busy = !slots.empty() || !S.queue.empty();
+            if (!S.busy) S.cv_idle.notify_all();
+            S.cv.wait(lk, [&] { return S.stop || !S.queue.empty() || !slots.empty(); });
+            if (S.stop && slots.empty()) {
+                // fail whatever is still queued
+                for (auto& q : S.queue) {
+                    auto it = S.tickets.find(q.ticket);
+                    if (it != S.tickets.end()) {
+                        it->second.state = 2;
+                        it->second.err = "context destroyed";
+                    }
+                    auto sit = ctx->sinos.find(q.sino_id);
+                    if (sit != ctx->sinos.end()) sit->second->users--;
+                }
+                S.queue.clear();
+                S.busy = false;
+                S.cv_idle.notify_all();
+                break;
+            }
+            S.busy = true;
+        }
+        for (;;) {
+            Request req;
+            {
+                std::lock_guard<std::mutex> lk(S.mu);
+                if (S.stop || S.queue.empty() || (int)slots.size() >= S.max_slots) break;
+                req = S.queue.front();
+            }
+            auto sl = std::make_unique<Slot>();
+            sl->req = req;
+            {
+                std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+                sl->sino = ctx->sinos.at(req.sino_id).get();
+            }
+            const Geom& g = ctx->geoms[sl->sino->gid];
+            RoiState& r = sl->st;
+            r.prm = req.prm;
+            r.roi = Rect{req.prm.roi.row0, req.prm.roi.col0, req.prm.roi.rows, req.prm.roi.cols};
+            r.ext = extend_rect(r.roi, req.prm.margin, g.n);
+            r.plan = make_plan(g, r.ext, r.ext);
+            char* blk = ctx->arena.alloc(state_bytes(g, r.plan), false);
+            if (!blk && slots.empty()) blk = ctx->arena.alloc(state_bytes(g, r.plan), true);
+            if (!blk) {
+                if (slots.empty()) {   // cannot ever fit: fail it rather than stall
+                    std::lock_guard<std::mutex> lk(S.mu);
+                    S.queue.pop_front();
+                    auto it = S.tickets.find(req.ticket);
+                    if (it != S.tickets.end()) {
+                        it->second.state = 2;
+                        it->second.err = "request does not fit in the workspace";
+                    }
+                    sl->sino->users--;
+                    continue;
+                }
+                break;   // wait for running slots to free memory
+            }
+            {
+                std::lock_guard<std::mutex> lk(S.mu);
+                S.queue.pop_front();
+            }
+            sl->allocs.push_back(blk);
+            carve_state(g, r, blk);
+            t_err.clear();
+            tomo_status st = prepare_slot(ctx, S, *sl);
+            if (st != TOMO_OK) {
+                finish_ticket(S, req.ticket, 2, 0.f, t_err);
+                (void)hipStreamSynchronize(S.stream);
+                ctx->arena.free_after(sl->allocs, S.stream);
+                sl->sino->users--;
+                continue;
+            }
+            sl->parity0 = (int)((2 - (S.step & 1)) & 1);   // (step + parity0) even at it = 0
+            slots.push_back(std::move(sl));
+            changed = true;
+        }
+        if (slots.empty()) continue;
+        // ---- batch lists (rebuilt when membership changes) ----
+        if (changed) {
+            std::vector<Job> jobs;
+            std::vector<Item> fi, bi;
+            int th, tw;
+            bp_tile(kServeAG, &th, &tw);
+            for (size_t q = 0; q < slots.size(); ++q) {
+                Slot& sl = *slots[q];
+                const Geom& g = ctx->geoms[sl.sino->gid];
+                const bool cp = sl.st.prm.method == ROI_TV_NONNEG_CP;
+                Job J = make_job(g, sl.st, cp ? FP_CP_DUAL : FP_SIRT, cp ? BP_CP : BP_SIRT,
+                                 (sl.st.ext.cols + tw - 1) / tw);
+                J.parity0 = sl.parity0;
+                jobs.push_back(J);
+                fp_items(fi, (int)q, sl.st.plan.afp, kServeSeg);
+                bp_items(bi, (int)q, sl.st.ext.rows, sl.st.ext.cols, kServeAG);
+            }
+            Meta m;
+            const size_t o_j = m.add(jobs.data(), jobs.size() * sizeof(Job));
+            const size_t o_f = m.add(fi.data(), fi.size() * sizeof(Item));
+            const size_t o_b = m.add(bi.data(), bi.size() * sizeof(Item));
+            if (d_lists) ctx->arena.free_after({d_lists}, S.stream);
+            d_lists = ctx->arena.alloc(m.buf.size(), true);
+            if (!d_lists ||
+                S.staging.upload(d_lists, m.buf.data(), m.buf.size(), S.stream) != hipSuccess) {
+                for (auto& sl : slots) {
+                    finish_ticket(S, sl->req.ticket, 2, 0.f, "cannot upload the batch lists");
+                    ctx->arena.free_after(sl->allocs, S.stream);
+                    sl->sino->users--;
+                }
+                slots.clear();
+                continue;
+            }
+            d_jobs = (const Job*)(d_lists + o_j);
+            d_fi = (const Item*)(d_lists + o_f);
+            d_bi = (const Item*)(d_lists + o_b);
+            n_fi = (int)fi.size();
+            n_bi = (int)bi.size();
+            changed = false;
+        }
+        // ---- one tick: the same few iterations for every admitted slot ----
+        int tick = S.iters_per_tick;
+        for (auto& sl : slots) tick = std::min(tick, sl->req.prm.iters - sl->it);
+        hipError_t e = hipSuccess;
+        for (int t = 0; t < tick && e == hipSuccess; ++t) {
+            const int stp = (int)(S.step & 0x3fffffff);
+            e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream);
+            if (e == hipSuccess) e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, S.stream);
+            S.step++;
+        }
+        for (auto& sl : slots) sl->it += tick;
+        // ---- retire finished slots ----
+        std::vector<size_t> done;
+        for (size_t q = 0; q < slots.size(); ++q)
+            if (slots[q]->it >= slots[q]->req.prm.iters) done.push_back(q);
+        for (size_t q : done) {
+            const RoiState& r = slots[q]->st;
+            if (e == hipSuccess)
+                e = launch_crop(r.x, r.ext.cols, r.roi.r0 - r.ext.r0, r.roi.c0 - r.ext.c0,
+                                r.roi.rows, r.roi.cols, slots[q]->req.out, S.stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(S.stream);
+        const double tnow = now_ms();
+        if (e != hipSuccess) {
+            for (auto& sl : slots) {
+                finish_ticket(S, sl->req.ticket, 2, 0.f, hipGetErrorString(e));
+                sl->sino->users--;
+            }
+            slots.clear();
+            changed = true;
+            continue;
+        }
+        for (auto qi = done.rbegin(); qi != done.rend(); ++qi) {
+            Slot& sl = *slots[*qi];
+            finish_ticket(S, sl.req.ticket, 1, (float)(tnow - sl.req.t_submit), "");
+            ctx->arena.free_after(sl.allocs, S.stream);
+            sl.sino->users--;
+            slots.erase(slots.begin() + (long)*qi);
+            changed = true;
+        }
+    }
+    if (d_lists) ctx->arena.free_after({d_lists}, S.stream);
+    (void)hipStreamSynchronize(S.stream);
+}
+
+tomo_status ensure_serving(tomo_ctx* ctx) {
+    if (ctx->serve && ctx->serve->th.joinable()) return TOMO_OK;
+    if (!ctx->serve) ctx->serve = std::make_unique<ServeState>();
+    ServeState& S = *ctx->serve;
+    if (!S.stream) TOMO_HIP(ctx, hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
+    S.stop = false;
+    S.th = std::thread(scheduler, ctx);
+    return TOMO_OK;
+}
+
+}  // namespace
+
+void serve_shutdown(tomo_ctx* ctx) {
+    if (!ctx->serve) return;
+    ServeState& S = *ctx->serve;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.stop = true;
+    }
+    S.cv.notify_all();
+    if (S.th.joinable()) S.th.join();
+    S.staging.destroy();
+    if (S.stream) (void)hipStreamDestroy(S.stream);
+    S.stream = nullptr;
+}
+
+void serve_drain(tomo_ctx* ctx) {
+    if (!ctx->serve) return;
+    ServeState& S = *ctx->serve;
+    std::unique_lock<std::mutex> lk(S.mu);
+    S.cv_idle.wait(lk, [&] { return !S.busy && S.queue.empty(); });
+}
+
+}  // namespace tomo
+
+using namespace tomo;
+
+tomo_ctx::tomo_ctx() = default;
+tomo_ctx::~tomo_ctx() = default;
+
+extern "C" {
+
+tomo_status tomo_register_sinogram(tomo_ctx* ctx, int32_t geom, const float* sino,
+                                   int32_t* sino_id) {
+    if (!ctx || !sino || !sino_id) return ctx ? fail(ctx, TOMO_EINVAL, "null pointer") : TOMO_EINVAL;
+    if (ctx->host_only) return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
+    try {
+        if (geom < 0 || geom >= (int)ctx->geoms.size())
+            return fail(ctx, TOMO_ENOENT, "unknown geometry %d", geom);
+        TOMO_HIP(ctx, hipSetDevice(ctx->device));
+        auto S = std::make_unique<SinoState>();
+        S->gid = geom;
+        S->sino = sino;
+        tomo_status st = build_resident(ctx, *S, nullptr);
+        if (st != TOMO_OK) {
+            if (S->block) ctx->arena.free_after({S->block}, nullptr);
+            return st;
+        }
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        const int id = ctx->next_sino++;
+        ctx->sinos[id] = std::move(S);
+        *sino_id = id;
+        return TOMO_OK;
+    } catch (...) {
+        return fail(ctx, TOMO_ENOMEM, "host allocation failed");
+    }
+}
+
+tomo_status tomo_unregister_sinogram(tomo_ctx* ctx, int32_t sino_id) {
+    if (!ctx) return TOMO_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->sinos.find(sino_id);
+    if (it == ctx->sinos.end()) return fail(ctx, TOMO_ENOENT, "unknown sinogram %d", sino_id);
+    if (it->second->users.load() > 0)
+        return fail(ctx, TOMO_EBUSY, "sinogram %d has %d live requests", sino_id,
+                    it->second->users.load());
+    (void)hipSetDevice(ctx->device);
+    ctx->arena.free_after({it->second->block}, nullptr);
+    ctx->sinos.erase(it);
+    return TOMO_OK;
+}
+
+tomo_status roi_submit(tomo_ctx* ctx, int32_t sino_id, const roi_params* params, float* out,
+                       uint64_t* ticket) {
+    if (!ctx || !params || !out || !ticket)
+        return ctx ? fail(ctx, TOMO_EINVAL, "null pointer") : TOMO_EINVAL;
+    if (ctx->host_only) return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
+    try {
+        SinoState* sp = nullptr;
+        {
+            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+            auto it = ctx->sinos.find(sino_id);
+            if (it == ctx->sinos.end()) return fail(ctx, TOMO_ENOENT, "unknown sinogram %d", sino_id);
+            sp = it->second.get();
+        }
+        const Geom& g = ctx->geoms[sp->gid];
+        tomo_status st = validate_params(ctx, g, *params);
+        if (st != TOMO_OK) return st;
+        const Rect roi{params->roi.row0, params->roi.col0, params->roi.rows, params->roi.cols};
+        const Rect ext = extend_rect(roi, params->margin, g.n);
+        const Plan P = make_plan(g, ext, ext);
+        if (state_bytes(g, P) + 64 * 1024 > ctx->arena.capacity())
+            return fail(ctx, TOMO_ENOMEM, "request state (%zu bytes) exceeds the workspace",
+                        state_bytes(g, P));
+        st = ensure_serving(ctx);
+        if (st != TOMO_OK) return st;
+        ServeState& S = *ctx->serve;
+        {
+            std::lock_guard<std::mutex> lk(S.mu);
+            if (S.queue.size() >= S.queue_cap) return fail(ctx, TOMO_EAGAIN, "request queue full");
+            Request r;
+            r.ticket = S.next_ticket++;
+            r.sino_id = sino_id;
+            r.prm = *params;
+            r.out = out;
+            r.t_submit = now_ms();
+            S.tickets[r.ticket] = TicketInfo{};
+            sp->users++;
+            S.queue.push_back(r);
+            *ticket = r.ticket;
+        }
+        S.cv.notify_all();
+        return TOMO_OK;
+    } catch (...) {
+        return fail(ctx, TOMO_ENOMEM, "host allocation failed");
+    }
+}
+
+tomo_status roi_poll(tomo_ctx* ctx, uint64_t ticket, int* done, float* latency_ms) {
+    if (!ctx || !done) return ctx ? fail(ctx, TOMO_EINVAL, "null pointer") : TOMO_EINVAL;
+    *done = 0;
+    if (!ctx->serve) return fail(ctx, TOMO_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    ServeState& S = *ctx->serve;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.tickets.find(ticket);
+    if (it == S.tickets.end())
+        return fail(ctx, TOMO_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second.state == 0) return TOMO_OK;
+    if (it->second.state == 2) {
+        const std::string err = it->second.err;
+        S.tickets.erase(it);
+        return fail(ctx, TOMO_EHIP, "request failed: %s", err.c_str());
+    }
+    *done = 1;
+    if (latency_ms) *latency_ms = it->second.latency_ms;
+    S.tickets.erase(it);
+    return TOMO_OK;
+}
+
+tomo_status tomo_serving_config(tomo_ctx* ctx, int32_t max_slots, int32_t iters_per_tick) {
+    if (!ctx) return TOMO_EINVAL;
+    if (max_slots < 0 || iters_per_tick < 0 || max_slots > 4096 || iters_per_tick > 1000)
+        return fail(ctx, TOMO_EINVAL, "serving knobs out of range");
+    if (!ctx->serve) ctx->serve = std::make_unique<ServeState>();
+    std::lock_guard<std::mutex> lk(ctx->serve->mu);
+    if (max_slots) ctx->serve->max_slots = max_slots;
+    if (iters_per_tick) ctx->serve->iters_per_tick = iters_per_tick;
+    return TOMO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI: the library loads, exports every call of
+include/tomo.h, and its planning logic (bands, extended rects, validation)
+agrees with the oracle.  No GPU is touched (host-only context, device = -1)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_02292_amd import _lib
+from paper_1604_02292_amd.tomo import Context, TomoError
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "tomo.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:tomo|roi)_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_call():
+    lib = _lib.load()
+    names = _header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, n
+
+
+def test_host_context_rejects_gpu_calls():
+    ctx = Context(device=-1)
+    g = ctx.tomo_set_geometry(64, 8, 96)
+    lib = ctx.lib
+    st = lib.tomo_fp(ctx.h, g, _lib.tomo_rect(0, 0, 4, 4), None, None, 0, None)
+    assert st == _lib.TOMO_ESTATE
+    st = lib.tomo_synchronize(ctx.h)
+    assert st == _lib.TOMO_ESTATE
+
+
+@pytest.mark.parametrize("n,na,nd", [(128, 32, 192), (1024, 128, 1536), (2048, 256, 3072),
+                                     (4096, 512, 6144)])
+def test_band_covers_exact_nonzero_rows(n, na, nd):
+    """Every nonzero row of W_L (the oracle's brute-force band) lies inside the
+    library's band, which is at most 2 bins wider on each side."""
+    ctx = Context(device=-1)
+    g = ctx.tomo_set_geometry(n, na, nd)
+    geo = oracle.make_geometry(n, na, nd)
+    rng = np.random.default_rng(n)
+    rects = [(0, 0, 9, 13), (n - 7, n - 11, 7, 11),
+             (int(rng.integers(0, n - 20)), int(rng.integers(0, n - 20)), 20, 17)]
+    for rect in rects:
+        i0, w = ctx.tomo_roi_band(g, rect)
+        exact = oracle.band_exact(geo, rect)
+        for k in range(na):
+            lo, hi = exact[k]
+            assert i0[k] <= lo and hi <= i0[k] + w[k] - 1
+            assert lo - i0[k] <= 3 and (i0[k] + w[k] - 1) - hi <= 3
+
+
+def test_roi_ext_matches_oracle():
+    ctx = Context(device=-1)
+    g = ctx.tomo_set_geometry(128, 4, 192)
+    for roi, m in [((48, 48, 32, 32), 16), ((0, 100, 32, 28), 16), ((0, 0, 128, 128), 16),
+                   ((120, 3, 8, 8), 0)]:
+        assert ctx.tomo_roi_ext(g, roi, m) == oracle.roi_extend(roi, m, 128)
+
+
+def test_argument_validation():
+    ctx = Context(device=-1)
+    with pytest.raises(TomoError) as e:
+        ctx.tomo_set_geometry(0, 8, 8)
+    assert e.value.status == _lib.TOMO_EINVAL
+    with pytest.raises(TomoError) as e:
+        ctx.tomo_set_geometry(64, 8, 96, det_spacing=0.5)
+    assert e.value.status == _lib.TOMO_EINVAL
+    g = ctx.tomo_set_geometry(64, 8, 96)
+    for bad in [(0, 0, 0, 4), (-1, 0, 4, 4), (60, 60, 8, 8)]:
+        with pytest.raises(TomoError) as e:
+            ctx.tomo_roi_band(g, bad)
+        assert e.value.status == _lib.TOMO_EINVAL
+    with pytest.raises(TomoError) as e:
+        ctx.tomo_roi_ext(g, (0, 0, 4, 4), -1)
+    assert e.value.status == _lib.TOMO_EINVAL
+    lib = ctx.lib
+    i0 = (C.c_int32 * 8)()
+    w = (C.c_int32 * 8)()
+    assert lib.tomo_roi_band(ctx.h, 7, _lib.tomo_rect(0, 0, 4, 4), i0, w) == _lib.TOMO_ENOENT
+    assert lib.tomo_create(-2, None, 0, C.byref(C.c_void_p())) == _lib.TOMO_EINVAL
+    assert b"unknown geometry" in lib.tomo_last_error(ctx.h)
+
+
+@pytest.mark.parametrize("n,na,nd,rect", [(128, 32, 192, (32, 32, 64, 64)),
+                                          (64, 45, 90, (0, 10, 20, 33)),
+                                          (1024, 128, 1536, (416, 416, 40, 48))])
+def test_nnz_count_matches_oracle(n, na, nd, rect):
+    """The library's algorithmic update count is the nonzero count of the oracle's W_L."""
+    ctx = Context(device=-1)
+    g = ctx.tomo_set_geometry(n, na, nd)
+    WL = oracle.sparse_local(oracle.make_geometry(n, na, nd), rect)
+    assert ctx.tomo_roi_nnz(g, rect) == WL.nnz
