@@ -204,6 +204,12 @@ tomo_status roi_poll(tomo_ctx* ctx, uint64_t ticket, int* done, float* latency_m
  * scheduler tick (default 4); 0 leaves a value unchanged. */
 tomo_status tomo_serving_config(tomo_ctx* ctx, int32_t max_slots, int32_t iters_per_tick);
 
+/* Iteration graphs: when enabled (the default), the second and later solves
+ * with the same work-list layout replay a captured hipGraph of the whole
+ * iteration loop instead of launching its kernels one by one (same kernels,
+ * same arguments, same results).  enable = 0 always launches eagerly. */
+tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
+
 /* Kernel launch shape knobs (autotuner hooks): FP segments per ray (1, 2, 4) and BP angle
  * groups per pixel (1, 2, 4); 0 = choose automatically from the problem size. */
 tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups);
@@ -215,12 +221,16 @@ tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_group
  * Errors: EINVAL, ENOENT. */
 tomo_status tomo_roi_nnz(tomo_ctx* ctx, int32_t geom, tomo_rect region, int64_t* nnz);
 
-/* Measurement hook: with enable = 1, the solve calls record a HIP event pair on
- * their stream around every forward-projection (kernel 0) and backprojection
- * (kernel 1) launch of the iterations.  tomo_kernel_time waits for the recorded
+/* Measurement hook for the iteration kernels, forward projection (kernel 0)
+ * and backprojection (kernel 1).  mode 1: the solve calls record a HIP event
+ * pair on their stream around every iteration launch.  mode 2: each solve
+ * first runs 50 back-to-back launches of each kernel on its own data, captured
+ * in a hipGraph (no dispatch gaps between them) and bracketed by two HIP events
+ * on the solve's stream, then clears its state and solves as usual (results
+ * are unchanged).  mode 0: off.  tomo_kernel_time waits for the recorded
  * events and returns, per kernel, the number of timed launches and their total
  * GPU time in milliseconds (host outputs); reset = 1 clears the totals. */
-tomo_status tomo_kernel_timing(tomo_ctx* ctx, int enable);
+tomo_status tomo_kernel_timing(tomo_ctx* ctx, int mode);
 tomo_status tomo_kernel_time(tomo_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms,
                              int reset);
 

@@ -54,6 +54,7 @@ SIGNATURES = {
     "roi_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_float)]),
     "tomo_serving_config": (C.c_int, [_P, _I, _I]),
     "tomo_set_launch": (C.c_int, [_P, _I, _I]),
+    "tomo_set_graphs": (C.c_int, [_P, C.c_int]),
     "tomo_roi_nnz": (C.c_int, [_P, _I, tomo_rect, C.POINTER(C.c_int64)]),
     "tomo_kernel_timing": (C.c_int, [_P, C.c_int]),
     "tomo_kernel_time": (C.c_int, [_P, _I, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int]),

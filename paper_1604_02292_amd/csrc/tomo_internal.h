@@ -85,9 +85,15 @@ struct Job {
     float* part;             // per-tile partial sums (BP_POWER)
 };
 
+// One block's work.  `tab` points at the block's table (FP: the AngFP entry of
+// its angle; BP: the job's AngBP array) so the kernel can fetch the job
+// descriptor and the table at the same time.
 struct Item {
     int32_t job, a, b, pad;  // FP: angle, ray chunk; BP: tile row, tile col
+    const void* tab;
+    int64_t pad2;
 };
+static_assert(sizeof(Item) == 32, "Item layout");
 
 // Launchers (tomo_kernels.hip).
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,

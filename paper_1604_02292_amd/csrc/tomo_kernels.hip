@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
     const Item it = cview(items)[bid];
     const CONST_AS Job* J = cview(jobs) + it.job;
     const int k = it.a;
-    const AngFP A = cview(J->afp)[k];
+    const AngFP A = *cview((const AngFP*)it.tab);
     const int lane = threadIdx.x & 63;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int seg = wave % SEG;
@@ -90,6 +90,26 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
     const int pitch = A.tr ? J->tp : J->xp;
     const int n_outer = A.tr ? J->nc : J->nr;
     const int n_inner = A.tr ? J->nr : J->nc;
+
+    // Epilogue operands are independent of the ray sum: fetch them first so
+    // their memory latency overlaps the loop.
+    const int mode = J->fp_mode;
+    const int gi = A.i0 + j;
+    const bool ondet = (gi >= 0) && (gi < J->n_det);
+    const size_t bidx = (size_t)k * J->bpitch + 1 + j;
+    const size_t gidx = (size_t)k * J->n_det + gi;
+    float pre0 = 0.f, pre1 = 0.f;
+    if (seg == 0 && j < A.w && ondet) {
+        switch (mode) {
+            case FP_ACCUM: pre0 = J->gout[gidx]; break;
+            case FP_BAND_FROM_GLOBAL:
+            case FP_RESID: pre0 = J->gbase[gidx]; break;
+            case FP_BAND_ADD: pre0 = J->y[bidx]; break;
+            case FP_CP_DUAL: pre0 = J->y[bidx]; pre1 = J->b[bidx]; break;
+            case FP_SIRT: pre1 = J->b[bidx]; break;
+            default: break;
+        }
+    }
 
     float acc = 0.f;
     if (jfirst < A.w) {
@@ -137,7 +157,21 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
             const int cnt = min(32, s1 - oc);
             unsigned soff = (unsigned)oc * rowb;
             int q = 0;
-            // 8 lines per step: the 8 paired loads issue before the first is used
+            if (cnt == 32) {
+                // a full chunk: all 32 paired loads issue before the first is used
+                float f[32];
+                v2f v[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) {
+                    const float loc = __builtin_amdgcn_fmed3f(fmaf((float)u, stepf, base64), lo, hi);
+                    f[u] = __builtin_amdgcn_fractf(loc);
+                    const unsigned off = ((unsigned)(int)loc << 2) + ib4;   // in [0, 4 (n_inner+1)]
+                    v[u] = load2(rs, off, soff + (unsigned)u * rowb);
+                }
+#pragma unroll
+                for (int u = 0; u < 32; ++u) acc += fmaf(f[u], v[u].y - v[u].x, v[u].x);
+                q = 32;
+            }
             for (; q + 8 <= cnt; q += 8) {
                 const float b8 = fmaf((float)q, stepf, base64);
                 float f[8];
@@ -146,7 +180,7 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
                 for (int u = 0; u < 8; ++u) {
                     const float loc = __builtin_amdgcn_fmed3f(fmaf((float)u, stepf, b8), lo, hi);
                     f[u] = __builtin_amdgcn_fractf(loc);
-                    const unsigned off = ((unsigned)(int)loc << 2) + ib4;   // in [0, 4 (n_inner+1)]
+                    const unsigned off = ((unsigned)(int)loc << 2) + ib4;
                     v[u] = load2(rs, off, soff + (unsigned)u * rowb);
                 }
 #pragma unroll
@@ -174,37 +208,33 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
     if (j >= A.w) return;
 
     const float fpv = acc * A.inv_m;
-    const int gi = A.i0 + j;
-    const bool ondet = (gi >= 0) && (gi < J->n_det);
-    const size_t bidx = (size_t)k * J->bpitch + 1 + j;
-    const size_t gidx = (size_t)k * J->n_det + gi;
     float* y = J->y;
     float* gout = J->gout;
-    switch (J->fp_mode) {
+    switch (mode) {
         case FP_STORE:
             if (ondet) gout[gidx] = fpv;
             break;
         case FP_ACCUM:
-            if (ondet) gout[gidx] += fpv;
+            if (ondet) gout[gidx] = pre0 + fpv;
             break;
         case FP_BAND_FROM_GLOBAL:
-            y[bidx] = ondet ? J->gbase[gidx] + J->scale * fpv : 0.f;
+            y[bidx] = ondet ? pre0 + J->scale * fpv : 0.f;
             break;
         case FP_BAND_ADD:
-            y[bidx] = ondet ? y[bidx] + J->scale * fpv : 0.f;
+            y[bidx] = ondet ? pre0 + J->scale * fpv : 0.f;
             break;
         case FP_CP_DUAL:
             // prox of sigma F1*, F1(v) = ||v - b||^2 (or 1/2 ||v - b||^2)
-            y[bidx] = ondet ? (y[bidx] + J->sigma * (fpv - J->b[bidx])) * J->dual_div : 0.f;
+            y[bidx] = ondet ? (pre0 + J->sigma * (fpv - pre1)) * J->dual_div : 0.f;
             break;
         case FP_SIRT:
-            y[bidx] = ondet ? J->alpha * (J->b[bidx] - fpv) : 0.f;
+            y[bidx] = ondet ? J->alpha * (pre1 - fpv) : 0.f;
             break;
         case FP_BAND_STORE:
             y[bidx] = ondet ? fpv : 0.f;
             break;
         case FP_RESID:
-            if (ondet) gout[gidx] = J->gbase[gidx] + J->scale * fpv;
+            if (ondet) gout[gidx] = pre0 + J->scale * fpv;
             break;
         default:
             break;
@@ -248,10 +278,34 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     const int rpar = (step + J->parity0) & 1, wpar = rpar ^ 1;
     const bool tv = (mode == BP_CP) || (mode == BP_POWER);
 
+    // Every load that does not depend on another one is issued here, before the
+    // first barrier: the primal value of the own pixel, the xbar tile with its
+    // halo, and the old TV dual of the tile plus top/left halo.
+    const size_t xi = (size_t)r * J->ldx + c;
+    float xo = 0.f;
+    if (inside && (mode == BP_CP || mode == BP_SIRT || mode == BP_ACCUM)) xo = J->x[xi];
+    constexpr int NZ = ((TH + 1) * (TW + 1) + 255) / 256;
+    float zq0[NZ], zq1[NZ];
     float divv = 0.f, zn0 = 0.f, zn1 = 0.f;
     if (tv) {
         gcfloat* xb = gview(J->xb[rpar]);
         const int xp = J->xp;
+        const size_t plane = (size_t)nr * nc;
+        gcfloat* zo = gview(J->z[rpar]);
+#pragma unroll
+        for (int u = 0; u < NZ; ++u) {
+            const int q = t + 256 * u;
+            const int lr = q / (TW + 1), lc = q % (TW + 1);
+            const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
+            zq0[u] = 0.f;
+            zq1[u] = 0.f;
+            if (mode == BP_CP && q < (TH + 1) * (TW + 1) && rr >= 0 && rr < nr && cc >= 0 &&
+                cc < nc) {
+                const size_t zi = (size_t)rr * nc + cc;
+                zq0[u] = zo[zi];
+                zq1[u] = zo[plane + zi];
+            }
+        }
         for (int q = t; q < (TH + 2) * (TW + 2); q += 256) {
             const int lr = q / (TW + 2), lc = q % (TW + 2);
             const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
@@ -260,11 +314,12 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
             xs[lr][lc] = v;
         }
         __syncthreads();
-        const size_t plane = (size_t)nr * nc;
         const float lam = J->lam, sigma = J->sigma;
         const int aniso = J->flags & JF_ANISO;
-        gcfloat* zo = gview(J->z[rpar]);
-        for (int q = t; q < (TH + 1) * (TW + 1); q += 256) {
+#pragma unroll
+        for (int u = 0; u < NZ; ++u) {
+            const int q = t + 256 * u;
+            if (q >= (TH + 1) * (TW + 1)) break;
             const int lr = q / (TW + 1), lc = q % (TW + 1);
             const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
             float q0 = 0.f, q1 = 0.f;
@@ -277,9 +332,8 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                     q0 = g0;
                     q1 = g1;
                 } else {
-                    const size_t zi = (size_t)rr * nc + cc;
-                    q0 = zo[zi] + sigma * g0;
-                    q1 = zo[plane + zi] + sigma * g1;
+                    q0 = zq0[u] + sigma * g0;
+                    q1 = zq1[u] + sigma * g1;
                     if (aniso) {
                         q0 = fminf(fmaxf(q0, -lam), lam);
                         q1 = fminf(fmaxf(q1, -lam), lam);
@@ -315,14 +369,14 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         const int bpm = bpitch - 2;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(J->y, (size_t)na * bpitch * sizeof(float));
         const unsigned rowb = (unsigned)bpitch * 4u;
-        const CONST_AS AngBP* tab = cview(J->abp);
+        const CONST_AS AngBP* tab = cview((const AngBP*)it.tab);
         int k = k0;
-        // 4 angles per step: 4 paired band loads in flight
-        for (; k + 4 <= k1; k += 4) {
-            float f[4];
-            v2f yv[4];
+        // 16 angles per step: 16 paired band loads in flight
+        for (; k + 16 <= k1; k += 16) {
+            float f[16];
+            v2f yv[16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const AngBP a = tab[k + u];
                 const double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
                 // uu >= 1 inside the band; the unsigned clamp keeps any stray
@@ -332,7 +386,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                 yv[u] = load2(rs, i << 2, (unsigned)(k + u) * rowb);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const AngBP a = tab[k + u];
                 const float w0 = fmaxf(0.f, fmaf(-f[u], a.B, a.A));
                 const float w1 = fmaxf(0.f, fmaf(f[u], a.B, a.AmB));
@@ -364,7 +418,6 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
 
     float sq = 0.f;
     if (g == 0 && inside) {
-        const size_t xi = (size_t)r * J->ldx + c;
         float* x = J->x;
         switch (mode) {
             case BP_STORE: {
@@ -376,10 +429,9 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                 if (xt) xt[(size_t)c * J->tp + r + 1] = v;
             } break;
             case BP_ACCUM:
-                x[xi] += J->scale * acc;
+                x[xi] = xo + J->scale * acc;
                 break;
             case BP_CP: {
-                const float xo = x[xi];
                 const float xn = fmaxf(0.f, xo - J->tau * (acc - divv));
                 x[xi] = xn;
                 const float xbn = 2.f * xn - xo;   // theta = 1
@@ -393,7 +445,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                 zw[(size_t)nr * nc + zi] = zn1;
             } break;
             case BP_SIRT: {
-                const float xn = fmaxf(0.f, x[xi] + acc);
+                const float xn = fmaxf(0.f, xo + acc);
                 x[xi] = xn;
                 float* xbw = J->xb[wpar];
                 float* xt = J->xt;
@@ -513,9 +565,10 @@ __global__ void band_scatter_kernel(const float* __restrict__ band, int bpitch,
     }
 }
 
-// Ram-Lak filtering of one angle per block: a linear (zero-padded) convolution
-// along the detector, q[i] = taps[0] p[i] + sum_{odd d} taps[d] (p[i-d] + p[i+d]),
-// written into the band layout of the receiving job.
+// Ram-Lak filtering: block (chunk, angle) produces 256 consecutive outputs of
+// one detector row as a linear (zero-padded) convolution along the detector,
+// q[i] = taps[0] p[i] + sum_{odd d} taps[d] (p[i-d] + p[i+d]), written into
+// the band layout of the receiving job.
 __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sino, int n_det,
                                                    const float* __restrict__ taps,
                                                    const AngFP* __restrict__ afp,
@@ -523,23 +576,23 @@ __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sin
     extern __shared__ float sh[];
     float* prow = sh;              // n_det
     float* htab = sh + n_det;      // n_det
-    const int k = blockIdx.x;
+    const int k = blockIdx.y;
     for (int i = threadIdx.x; i < n_det; i += blockDim.x) {
         prow[i] = sino[(size_t)k * n_det + i];
         htab[i] = taps[i];
     }
     __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_det) return;
     const int i0 = afp[k].i0, w = afp[k].w;
-    for (int i = threadIdx.x; i < n_det; i += blockDim.x) {
-        float acc = htab[0] * prow[i];
-        const int dl = i, dr = n_det - 1 - i, dm = min(dl, dr);
-        int d = 1;
-        for (; d <= dm; d += 2) acc = fmaf(htab[d], prow[i - d] + prow[i + d], acc);
-        for (int e = d; e <= dl; e += 2) acc = fmaf(htab[e], prow[i - e], acc);
-        for (int e = d; e <= dr; e += 2) acc = fmaf(htab[e], prow[i + e], acc);
-        const int j = i - i0;
-        if (j >= 0 && j < w) band[(size_t)k * bpitch + 1 + j] = acc;
-    }
+    float acc = htab[0] * prow[i];
+    const int dl = i, dr = n_det - 1 - i, dm = min(dl, dr);
+    int d = 1;
+    for (; d <= dm; d += 2) acc = fmaf(htab[d], prow[i - d] + prow[i + d], acc);
+    for (int e = d; e <= dl; e += 2) acc = fmaf(htab[e], prow[i - e], acc);
+    for (int e = d; e <= dr; e += 2) acc = fmaf(htab[e], prow[i + e], acc);
+    const int j = i - i0;
+    if (j >= 0 && j < w) band[(size_t)k * bpitch + 1 + j] = acc;
 }
 
 // Power iteration: v = w / ||w||, ||w|| from the per-tile partial sums (summed
@@ -650,8 +703,8 @@ hipError_t launch_band_scatter(const float* band, int bpitch, const AngFP* afp, 
 hipError_t launch_ramp(const float* sino, int n_angles, int n_det, const float* taps,
                        const AngFP* afp, float* band, int bpitch, hipStream_t s) {
     const size_t lds = (size_t)2 * n_det * sizeof(float);
-    hipLaunchKernelGGL(ramp_kernel, dim3(n_angles), dim3(256), lds, s, sino, n_det, taps, afp,
-                       band, bpitch);
+    hipLaunchKernelGGL(ramp_kernel, dim3((n_det + 255) / 256, n_angles), dim3(256), lds, s, sino,
+                       n_det, taps, afp, band, bpitch);
     return hipGetLastError();
 }
 

@@ -94,6 +94,19 @@ struct Staging {
 struct SinoState;
 struct ServeState;
 
+// A captured hipGraph of a whole iteration loop (all FP / BP launches of a
+// solve), replayed for later solves with the same work-list layout.  Its job
+// and item arrays live in `dbuf` (owned by the entry); each solve uploads its
+// own descriptors there before replaying.
+struct GraphEntry {
+    char* dbuf = nullptr;
+    size_t bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t last = nullptr;
+    long long stamp = 0;
+};
+
 }  // namespace tomo
 
 struct tomo_ctx {
@@ -113,8 +126,14 @@ struct tomo_ctx {
     std::map<int, std::unique_ptr<tomo::SinoState>> sinos;
     int next_sino = 1;
     std::unique_ptr<tomo::ServeState> serve;
+    // cached iteration graphs, keyed by the work-list layout
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::vector<long long>, tomo::GraphEntry> graphs;
+    std::map<std::vector<long long>, int> graph_seen;
+    long long graph_clock = 0;
     // kernel timing (measurement hook)
-    bool timing = false;
+    int timing_mode = 0;   // 0 off, 1 events around every launch, 2 graph-bracketed pass
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::tuple<hipEvent_t, hipEvent_t, int>> ev_pending;
     long long t_launches[2] = {0, 0};
@@ -164,8 +183,12 @@ hipEvent_t timing_event(tomo_ctx* ctx);
 long long count_nnz(const Geom& g, const Rect& reg);
 tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, Staging& stg);
 Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int ntc);
-void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg);
-void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag);
+// Work items; the device table pointers must already be known (items store them).
+void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg,
+              const AngFP* d_afp);
+void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag, const AngBP* d_abp);
+size_t count_fp_items(const std::vector<AngFP>& afp, int seg);
+size_t count_bp_items(int nr, int nc, int ag);
 void carve_state(const Geom& g, RoiState& st, char* blk);
 tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, float* xb, float* xt,
                      const Plan& P, hipStream_t s, std::vector<char*>& allocs, Staging& stg);
@@ -185,6 +208,9 @@ struct Meta {
         const size_t off = align_up(buf.size(), 64);
         buf.resize(off + n);
         return off;
+    }
+    void put(size_t off, const void* p, size_t n) {
+        if (n) std::memcpy(buf.data() + off, p, n);
     }
 };
 

@@ -101,17 +101,18 @@ tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s) {
     // r = p - W x_ext over the whole detector
     const LaunchCfg L = choose_launch(ctx, (long long)g.na * g.nd, 0);
     std::vector<Item> items;
-    fp_items(items, 0, P.afp, L.seg);
     Meta m;
     const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
     const size_t o_job = m.reserve(sizeof(Job));
-    const size_t o_it = m.add(items.data(), items.size() * sizeof(Item));
+    const size_t o_it = m.reserve(count_fp_items(P.afp, L.seg) * sizeof(Item));
     char* dm = ctx->arena.alloc(m.buf.size());
     if (!dm) {
         ctx->arena.free_after(allocs, s);
         return fail(ctx, TOMO_ENOMEM, "workspace too small for the residual tables");
     }
     allocs.push_back(dm);
+    fp_items(items, 0, P.afp, L.seg, (const AngFP*)(dm + o_afp));
+    m.put(o_it, items.data(), items.size() * sizeof(Item));
     Job J;
     std::memset(&J, 0, sizeof J);
     J.nr = J.nc = g.n;
@@ -152,13 +153,14 @@ tomo_status prepare_slot(tomo_ctx* ctx, ServeState& S, Slot& sl) {
     const size_t o_abp = m.add(r.plan.abp.data(), r.plan.abp.size() * sizeof(AngBP));
     const size_t o_job = m.reserve(sizeof(Job));
     std::vector<Item> items;
-    fp_items(items, 0, r.plan.afp, kServeSeg);
-    const size_t o_it = m.add(items.data(), items.size() * sizeof(Item));
+    const size_t o_it = m.reserve(count_fp_items(r.plan.afp, kServeSeg) * sizeof(Item));
     char* dm = ctx->arena.alloc(m.buf.size(), false);
     if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace full");
     sl.allocs.push_back(dm);
     r.d_afp = (AngFP*)(dm + o_afp);
     r.d_abp = (AngBP*)(dm + o_abp);
+    fp_items(items, 0, r.plan.afp, kServeSeg, r.d_afp);
+    m.put(o_it, items.data(), items.size() * sizeof(Item));
     Job J = make_job(g, r, FP_BAND_FROM_GLOBAL, BP_STORE, 0);
     J.xb[1] = J.xb[0];
     J.gbase = sl.sino->resid;
@@ -291,8 +293,8 @@ void scheduler(tomo_ctx* ctx) {
                                  (sl.st.ext.cols + tw - 1) / tw);
                 J.parity0 = sl.parity0;
                 jobs.push_back(J);
-                fp_items(fi, (int)q, sl.st.plan.afp, kServeSeg);
-                bp_items(bi, (int)q, sl.st.ext.rows, sl.st.ext.cols, kServeAG);
+                fp_items(fi, (int)q, sl.st.plan.afp, kServeSeg, sl.st.d_afp);
+                bp_items(bi, (int)q, sl.st.ext.rows, sl.st.ext.cols, kServeAG, sl.st.d_abp);
             }
             Meta m;
             const size_t o_j = m.add(jobs.data(), jobs.size() * sizeof(Job));

@@ -198,13 +198,16 @@ class Context:
     def tomo_set_launch(self, fp_segments=0, bp_groups=0):
         self._check(self.lib.tomo_set_launch(self.h, int(fp_segments), int(bp_groups)))
 
+    def tomo_set_graphs(self, enable=True):
+        self._check(self.lib.tomo_set_graphs(self.h, int(bool(enable))))
+
     def tomo_roi_nnz(self, geom, region):
         v = C.c_int64()
         self._check(self.lib.tomo_roi_nnz(self.h, geom, _rect(region), C.byref(v)))
         return v.value
 
-    def tomo_kernel_timing(self, enable=True):
-        self._check(self.lib.tomo_kernel_timing(self.h, int(bool(enable))))
+    def tomo_kernel_timing(self, mode=1):
+        self._check(self.lib.tomo_kernel_timing(self.h, int(mode)))
 
     def tomo_kernel_time(self, kernel, reset=False):
         n, ms = C.c_int64(), C.c_double()

@@ -1,0 +1,156 @@
+"""Serving: resident sinograms, roi_submit / roi_poll with continuous batching.
+
+Each request's result must be the same alone and in a mix (bit-identical:
+a slot's arithmetic never depends on the other slots), agree with roi_solve
+on the same request (up to FP32 rounding of the exterior data), and match the
+FP64 oracle at the 1e-3 reconstruction bar.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def wait_all(ctx, tickets, timeout=120.0):
+    lat = {}
+    t0 = time.time()
+    pending = set(tickets)
+    while pending:
+        for t in list(pending):
+            done, ms = ctx.roi_poll(t)
+            if done:
+                lat[t] = ms
+                pending.discard(t)
+        if time.time() - t0 > timeout:
+            raise AssertionError(f"{len(pending)} requests not done after {timeout}s")
+        time.sleep(0.0005)
+    return lat
+
+
+@pytest.fixture(scope="module")
+def served():
+    from paper_1604_02292_amd import Context
+    ctx = Context(0, workspace_bytes=2 << 30)
+    d = synth.make_inputs("c1")
+    cfg = d["cfg"]
+    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    p32 = d["sino"].astype(np.float32)
+    sino = dev(p32)
+    sid = ctx.tomo_register_sinogram(g, sino)
+    yield ctx, g, sid, sino, p32, cfg
+    ctx.tomo_synchronize()
+    ctx.tomo_unregister_sinogram(sid)
+    ctx.close()
+
+
+REQS = [((48, 48, 32, 32), 16, "cp", 0.05, 100), ((0, 0, 24, 40), 6, "sirt", 0.0, 60),
+        ((90, 10, 30, 30), 8, "cp", 5.0, 77), ((60, 100, 16, 20), 4, "cp", 0.05, 33),
+        ((5, 90, 40, 36), 10, "sirt", 0.0, 120), ((64, 64, 64, 64), 16, "cp", 0.05, 51)]
+
+
+def test_alone_equals_mix_and_matches_roi_solve(served):
+    from paper_1604_02292_amd import make_params
+    ctx, g, sid, sino, p32, cfg = served
+    params = [make_params(r, m, meth, lam, it) for r, m, meth, lam, it in REQS]
+    alone = []
+    for p in params:
+        o = torch.empty((p.roi.rows, p.roi.cols), device="cuda")
+        wait_all(ctx, [ctx.roi_submit(sid, p, o)])
+        alone.append(o.clone())
+    outs = [torch.empty((p.roi.rows, p.roi.cols), device="cuda") for p in params]
+    tickets = [ctx.roi_submit(sid, p, o) for p, o in zip(params, outs)]
+    lat = wait_all(ctx, tickets)
+    assert all(v is not None and v > 0 for v in lat.values())
+    torch.cuda.synchronize()
+    for a, b in zip(alone, outs):
+        assert torch.equal(a, b)
+    # permuted submission order
+    perm = [5, 2, 0, 4, 1, 3]
+    outs2 = [None] * len(params)
+    tickets = []
+    for i in perm:
+        outs2[i] = torch.empty((params[i].roi.rows, params[i].roi.cols), device="cuda")
+        tickets.append(ctx.roi_submit(sid, params[i], outs2[i]))
+    wait_all(ctx, tickets)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, outs2):
+        assert torch.equal(a, b)
+    # same requests through roi_solve (FBP exterior recomputed there)
+    for p, a in zip(params, alone):
+        o = torch.empty((p.roi.rows, p.roi.cols), device="cuda")
+        ctx.roi_solve(g, sino, p, o)
+        torch.cuda.synchronize()
+        assert rel(o.double().cpu().numpy(), a.double().cpu().numpy()) <= 1e-5
+
+
+def test_served_matches_oracle(served):
+    from paper_1604_02292_amd import make_params
+    ctx, g, sid, sino, p32, cfg = served
+    geo = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    for (roi, m, meth, lam, it) in [REQS[0], REQS[1], REQS[2]]:
+        ref = oracle.local_solve(geo, p32.astype(np.float64), roi, m, method=meth, lam=lam,
+                                 iters=it, full=True)
+        s = ref["sigma"] if meth == "cp" else 0.0
+        p = make_params(roi, m, meth, lam, it, s, s)
+        o = torch.empty((roi[2], roi[3]), device="cuda")
+        wait_all(ctx, [ctx.roi_submit(sid, p, o)])
+        e = rel(o.double().cpu().numpy(), ref["x"])
+        print(f"[serve] {roi} {meth} rel {e:.2e}", flush=True)
+        assert e <= 1e-3
+
+
+def test_admission_errors(served):
+    from paper_1604_02292_amd import Context, TomoError, make_params, _lib
+    ctx, g, sid, sino, p32, cfg = served
+    # unknown sinogram / ticket
+    p = make_params((0, 0, 8, 8), 2, "cp", 0.05, 10)
+    o = torch.empty((8, 8), device="cuda")
+    with pytest.raises(TomoError) as e:
+        ctx.roi_submit(999, p, o)
+    assert e.value.status == _lib.TOMO_ENOENT
+    with pytest.raises(TomoError) as e:
+        ctx.roi_poll(123456789)
+    assert e.value.status == _lib.TOMO_ENOENT
+    # invalid request
+    o16 = torch.empty((16, 16), device="cuda")
+    with pytest.raises(TomoError) as e:
+        ctx.roi_submit(sid, make_params((120, 120, 16, 16), 2, "cp", 0.05, 10), o16)
+    assert e.value.status == _lib.TOMO_EINVAL
+    # busy: unregister while requests are queued
+    outs = [torch.empty((32, 32), device="cuda") for _ in range(16)]
+    tickets = [ctx.roi_submit(sid, make_params((40, 40, 32, 32), 16, "cp", 0.05, 200), q)
+               for q in outs]
+    with pytest.raises(TomoError) as e:
+        ctx.tomo_unregister_sinogram(sid)
+    assert e.value.status == _lib.TOMO_EBUSY
+    wait_all(ctx, tickets)
+    # a request larger than the whole workspace is refused at submission
+    small = Context(0, workspace_bytes=24 << 20)
+    try:
+        g2 = small.tomo_set_geometry(1024, 128, 1536)
+        s2 = torch.zeros((128, 1536), device="cuda")
+        sid2 = small.tomo_register_sinogram(g2, s2)
+        big = torch.empty((1024, 1024), device="cuda")
+        with pytest.raises(TomoError) as e:
+            small.roi_submit(sid2, make_params((0, 0, 1024, 1024), 0, "cp", 0.02, 5), big)
+        assert e.value.status == _lib.TOMO_ENOMEM
+        small.tomo_unregister_sinogram(sid2)
+    finally:
+        small.close()
