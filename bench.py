@@ -74,12 +74,143 @@ def cpu_baseline(d, cfg, roi, margin):
                       f"(measured {t_fbp + t_ext + t_step + t_10:.1f}s)"}
 
 
+def batched_leg(torch, reps=3):
+    """64 uneven ROIs (sides 32..256, margin side/4) on a 2048^2 grid, 256 angles,
+    3072 bins, 200 CP-TV iterations: one roi_solve_batch call vs the same ROIs
+    solved one at a time, both from the same precomputed FBP exterior."""
+    import synth
+    from paper_1604_02292_amd import Context, make_params
+    d = synth.make_inputs("c3", with_image=False)
+    cfg = d["cfg"]
+    ctx = Context(0, workspace_bytes=8 << 30)
+    try:
+        g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+        sino = torch.from_numpy(d["sino"].astype(np.float32)).cuda()
+        xe = torch.empty((cfg["n"], cfg["n"]), dtype=torch.float32, device="cuda")
+        ctx.tomo_fbp_ramlak(g, sino, xe)
+        rois = synth.roi_list("c3")
+        params = [make_params(r[:4], r[4], "cp", cfg["lam"], cfg["iters"]) for r in rois]
+        outs = [torch.empty((r[2], r[3]), dtype=torch.float32, device="cuda") for r in rois]
+        updates = 2 * cfg["iters"] * sum(ctx.tomo_roi_nnz(g, ctx.tomo_roi_ext(g, r[:4], r[4]))
+                                          for r in rois)
+        for _ in range(2):   # step sizes, then the graph capture
+            ctx.roi_solve_batch(g, sino, params, outs, x_ext=xe)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.roi_solve_batch(g, sino, params, outs, x_ext=xe)
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / reps
+        one = [torch.empty_like(o) for o in outs]
+        for p, o in zip(params, one):   # warm shapes
+            ctx.roi_solve(g, sino, p, o, x_ext=xe)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p, o in zip(params, one):
+            ctx.roi_solve(g, sino, p, o, x_ext=xe)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        diff = max(float((a - b).abs().max() / (b.abs().max() + 1e-30)) for a, b in zip(outs, one))
+        log(f"batched: 64 ROIs {1e3 * t_batch:.1f} ms per batch; one at a time {1e3 * t_seq:.1f} ms; "
+            f"{updates / t_batch / 1e9:.0f} Gupd/s")
+        return {"workload": "batch64-n2048-a256: 64 ROIs, sides {32,64,128,256}, margin side/4, "
+                            "256 angles, 3072 bins, CP-TV 200 its",
+                "roi_solves_per_s": len(rois) / t_batch, "ms_per_batch": 1e3 * t_batch,
+                "one_at_a_time_roi_solves_per_s": len(rois) / t_seq,
+                "speedup_vs_one_at_a_time": t_seq / t_batch,
+                "updates_per_s": updates / t_batch,
+                "max_rel_diff_batch_vs_single": diff}
+    finally:
+        ctx.close()
+
+
+def serving_leg(torch, n_req=200, n_warm=64):
+    """64 resident 2048^2 slices (512 angles x 3072 bins); requests with side
+    U{32..512}, margin ceil(side/4), 80% CP-TV / 20% nonnegative SIRT, 100-300
+    iterations.  Capacity = completion rate with all requests queued at once;
+    latency = submit-to-done at Poisson arrivals of half that rate; plain =
+    the same requests solved one at a time with roi_solve."""
+    import synth
+    from paper_1604_02292_amd import Context, make_params
+    cfg = synth.workload("c5")
+    slices = synth.make_slices("c5")
+    ctx = Context(0, workspace_bytes=12 << 30)
+    try:
+        g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+        sinos = [torch.from_numpy(s_.astype(np.float32)).cuda() for s_ in slices]
+        t0 = time.perf_counter()
+        sids = [ctx.tomo_register_sinogram(g, s_) for s_ in sinos]
+        t_reg = time.perf_counter() - t0
+
+        def prm(r):
+            return make_params(r["rect"], r["margin"], r["method"], r["lam"], r["iters"])
+
+        def run(reqs, open_loop):
+            outs = [torch.empty((r["rect"][2], r["rect"][3]), device="cuda") for r in reqs]
+            lat, pend = [], {}
+            i = 0
+            t_start = time.perf_counter()
+            while i < len(reqs) or pend:
+                now = time.perf_counter() - t_start
+                while i < len(reqs) and (not open_loop or reqs[i]["t"] <= now):
+                    t = ctx.roi_submit(sids[reqs[i]["slice"]], prm(reqs[i]), outs[i])
+                    pend[t] = i
+                    i += 1
+                for t in list(pend):
+                    done, ms = ctx.roi_poll(t)
+                    if done:
+                        lat.append(ms)
+                        del pend[t]
+                time.sleep(0.0002)
+            return time.perf_counter() - t_start, lat, outs
+
+        run(synth.serving_requests(n_warm, 1.0, seed_offset=1), False)
+        reqs = synth.serving_requests(n_req, 1.0, seed_offset=2)
+        t_cap, lat_cap, outs = run(reqs, False)
+        cap = n_req / t_cap
+        qps = 0.5 * cap
+        reqs_open = synth.serving_requests(n_req, qps, seed_offset=3)
+        t_open, lat_open, _ = run(reqs_open, True)
+        # plain one-at-a-time solves of the capacity requests (same exterior estimates)
+        xes = {}
+        for r in reqs:
+            if r["slice"] not in xes:
+                xe = torch.empty((cfg["n"], cfg["n"]), device="cuda")
+                ctx.tomo_fbp_ramlak(g, sinos[r["slice"]], xe)
+                xes[r["slice"]] = xe
+        torch.cuda.synchronize()
+        plain_outs = [torch.empty_like(o) for o in outs]
+        t0 = time.perf_counter()
+        for r, o in zip(reqs, plain_outs):
+            ctx.roi_solve(g, sinos[r["slice"]], prm(r), o, x_ext=xes[r["slice"]])
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        diff = max(float((a - b).abs().max() / (b.abs().max() + 1e-30))
+                   for a, b in zip(outs, plain_outs))
+        log(f"serving: register {t_reg:.2f}s; capacity {cap:.1f} req/s; open loop at {qps:.1f} "
+            f"req/s: p50 {np.percentile(lat_open, 50):.1f} ms p99 {np.percentile(lat_open, 99):.1f} "
+            f"ms; plain {n_req / t_plain:.1f} req/s")
+        return {"workload": "serve-64x2048-a512: 64 resident slices, side U{32..512}, 80% CP-TV / "
+                            "20% SIRT, 100-300 its",
+                "capacity_solves_per_s": cap, "offered_qps": qps,
+                "p50_ms": float(np.percentile(lat_open, 50)),
+                "p99_ms": float(np.percentile(lat_open, 99)),
+                "saturated_p50_ms": float(np.percentile(lat_cap, 50)),
+                "saturated_p99_ms": float(np.percentile(lat_cap, 99)),
+                "one_at_a_time_solves_per_s": n_req / t_plain,
+                "requests": n_req, "max_rel_diff_served_vs_plain": diff}
+    finally:
+        ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--skip-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -161,9 +292,19 @@ def main():
         "fp_updates_per_s": fp_rate, "bp_updates_per_s": bp_rate,
         "roofline": roofline,
     }
+    ctx.close()
+    if not args.skip_batch:
+        try:
+            res["batched"] = batched_leg(torch)
+        except Exception as e:   # the headline line must still print
+            res["batched"] = {"error": repr(e)}
+    if not args.skip_serve:
+        try:
+            res["serving"] = serving_leg(torch)
+        except Exception as e:
+            res["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(d, cfg, roi, margin)
-    ctx.close()
     print(json.dumps(res), flush=True)
 
 

@@ -16,11 +16,11 @@ Shared conventions (parallel-beam geometry, pixel units):
 from .phantom import (Ellipses, random_ellipses, texture_ellipses, concat_ellipses,
                       raster, analytic_sinogram, add_gaussian_noise, add_poisson_noise,
                       disc_sinogram, angles_uniform, bin_centres)
-from .configs import WORKLOADS, workload, make_inputs, roi_list, serving_requests
+from .configs import WORKLOADS, workload, make_inputs, make_slices, roi_list, serving_requests
 
 __all__ = [
     "Ellipses", "random_ellipses", "texture_ellipses", "concat_ellipses", "raster",
     "analytic_sinogram", "add_gaussian_noise", "add_poisson_noise", "disc_sinogram",
     "angles_uniform", "bin_centres", "WORKLOADS", "workload", "make_inputs", "roi_list",
-    "serving_requests",
+    "serving_requests", "make_slices",
 ]

@@ -48,11 +48,19 @@ def _streams(cfg_id):
     return ss.spawn(4)   # phantom, noise, rois, arrivals
 
 
-def make_inputs(name, subrays=4, with_image=True, slice_index=None, supersample=1):
+def _workers():
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def make_inputs(name, subrays=4, with_image=True, slice_index=None, supersample=1,
+                workers=None):
     """Phantom ellipses, ground-truth raster and noisy FP32-ready sinogram (float64).
 
-    For the serving workload pass slice_index (0..63) to get one slice.
+    For the serving workload pass slice_index (0..63) to get one slice.  The
+    result does not depend on `workers` (processes used for the line integrals).
     """
+    workers = _workers() if workers is None else workers
     cfg = workload(name)
     ph_ss, no_ss, _, _ = _streams(cfg["id"])
     if slice_index is not None:
@@ -63,7 +71,8 @@ def make_inputs(name, subrays=4, with_image=True, slice_index=None, supersample=
     ell = random_ellipses(rng, n, cfg["n_ellipses"])
     if cfg.get("texture"):
         ell = concat_ellipses(ell, texture_ellipses(rng, n, cfg["n_texture"], cfg["texture"]))
-    clean = analytic_sinogram(ell, cfg["n_angles"], cfg["n_det"], subrays=subrays)
+    clean = analytic_sinogram(ell, cfg["n_angles"], cfg["n_det"], subrays=subrays,
+                              workers=workers)
     nrng = np.random.default_rng(no_ss)
     kind, level = cfg["noise"]
     if kind == "gauss":
@@ -74,6 +83,25 @@ def make_inputs(name, subrays=4, with_image=True, slice_index=None, supersample=
     if with_image:
         out["image"] = raster(ell, n, supersample)
     return out
+
+
+def _slice_job(args):
+    name, k, subrays = args
+    return make_inputs(name, subrays=subrays, with_image=False, slice_index=k, workers=1)["sino"]
+
+
+def make_slices(name="c5", indices=None, subrays=4, workers=None):
+    """Noisy sinograms of the serving workload's slices (float64 [N_theta, N_d] each),
+    generated in parallel; identical to make_inputs(..., slice_index=k)["sino"]."""
+    cfg = workload(name)
+    indices = list(range(cfg["n_slices"])) if indices is None else list(indices)
+    workers = _workers() if workers is None else workers
+    jobs = [(name, k, subrays) for k in indices]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+            return pool.map(_slice_job, jobs)
+    return [_slice_job(j) for j in jobs]
 
 
 def roi_list(name):

@@ -117,24 +117,18 @@ def raster(ell, n, supersample=1):
     return img
 
 
-def analytic_sinogram(ell, n_angles, n_det, spacing=1.0, offset=0.0, subrays=4,
-                      angles=None):
-    """Exact line integrals of the additive ellipse phantom, shape [N_theta, N_d].
+_CHUNK = 16   # ellipses per partial sum (fixed, so results do not depend on `workers`)
 
-    Each bin is the mean over `subrays` parallel rays at offsets
-    ((q + 1/2)/subrays - 1/2) * spacing from the bin centre (for 4 sub-rays:
-    +-1/8 and +-3/8 of a bin).  The line integral of an ellipse of value v
-    along {x cos t + y sin t = s} is v * 2ab sqrt(r^2 - s'^2) / r^2 with
-    s' = s - (cx cos t + cy sin t) and r^2 = a^2 cos^2(t-phi) + b^2 sin^2(t-phi).
-    """
-    th = angles_uniform(n_angles) if angles is None else np.asarray(angles, np.float64)
+
+def _sino_chunk(args):
+    ell, idx, th, n_det, spacing, offset, subrays = args
     n_angles = len(th)
     ct, st = np.cos(th), np.sin(th)
     q = (np.arange(subrays) + 0.5) / subrays - 0.5
     centre = (n_det - 1) / 2.0
     flat = np.zeros(n_angles * n_det, dtype=np.float64)
     kk = np.arange(n_angles)
-    for e in range(len(ell)):
+    for e in idx:
         cx, cy, a, b, phi, v = (ell.cx[e], ell.cy[e], ell.a[e], ell.b[e], ell.phi[e], ell.v[e])
         proj = cx * ct + cy * st                      # centre's detector coordinate
         al = th - phi
@@ -142,18 +136,44 @@ def analytic_sinogram(ell, n_angles, n_det, spacing=1.0, offset=0.0, subrays=4,
         rmax = max(a, b)
         width = int(np.ceil(2 * rmax / spacing)) + 4
         i_start = np.floor((proj - rmax - offset) / spacing + centre).astype(np.int64) - 1
-        idx = i_start[:, None] + np.arange(width)[None, :]          # [angles, width]
-        s_bin = (idx - centre) * spacing + offset
-        val = np.zeros(idx.shape)
+        ii = i_start[:, None] + np.arange(width)[None, :]          # [angles, width]
+        s_bin = (ii - centre) * spacing + offset
+        val = np.zeros(ii.shape)
         for qq in q:
             sp = s_bin + qq * spacing - proj[:, None]
             d = r2[:, None] - sp * sp
             val += np.where(d > 0, np.sqrt(np.maximum(d, 0.0)), 0.0)
         val *= (2.0 * a * b * v / subrays) / r2[:, None]
-        ok = (idx >= 0) & (idx < n_det) & (val != 0)
-        flat += np.bincount((kk[:, None] * n_det + idx)[ok], weights=val[ok],
+        ok = (ii >= 0) & (ii < n_det) & (val != 0)
+        flat += np.bincount((kk[:, None] * n_det + ii)[ok], weights=val[ok],
                             minlength=n_angles * n_det)
-    return flat.reshape(n_angles, n_det)
+    return flat
+
+
+def analytic_sinogram(ell, n_angles, n_det, spacing=1.0, offset=0.0, subrays=4,
+                      angles=None, workers=1):
+    """Exact line integrals of the additive ellipse phantom, shape [N_theta, N_d].
+
+    Each bin is the mean over `subrays` parallel rays at offsets
+    ((q + 1/2)/subrays - 1/2) * spacing from the bin centre (for 4 sub-rays:
+    +-1/8 and +-3/8 of a bin).  The line integral of an ellipse of value v
+    along {x cos t + y sin t = s} is v * 2ab sqrt(r^2 - s'^2) / r^2 with
+    s' = s - (cx cos t + cy sin t) and r^2 = a^2 cos^2(t-phi) + b^2 sin^2(t-phi).
+    Ellipses are summed in fixed chunks, in order, whatever `workers` is.
+    """
+    th = angles_uniform(n_angles) if angles is None else np.asarray(angles, np.float64)
+    chunks = [range(i, min(i + _CHUNK, len(ell))) for i in range(0, len(ell), _CHUNK)]
+    jobs = [(ell, c, th, n_det, spacing, offset, subrays) for c in chunks]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+            parts = pool.map(_sino_chunk, jobs)
+    else:
+        parts = [_sino_chunk(j) for j in jobs]
+    flat = np.zeros(len(th) * n_det)
+    for part in parts:
+        flat += part
+    return flat.reshape(len(th), n_det)
 
 
 def disc_sinogram(radius, value, n_angles, n_det, spacing=1.0, offset=0.0, cx=0.0, cy=0.0,

@@ -1,0 +1,76 @@
+"""Batched solves at full size: 64 uneven ROIs on a 2048^2 grid (256 angles, 3072
+bins, 200 iterations) and the 16 x 16 tiling of a 4096^2 grid (512 angles, 6144
+bins, 200 iterations), each in one roi_solve_batch call.  Sampled ROIs / tiles
+are compared with stored oracle results (tests/golden/make_golden.py) at the
+1e-3 reconstruction bar; the sampled requests carry the oracle's step sizes.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", f"{name}_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result for {name}")
+    return np.load(path)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1604_02292_amd import Context
+    c = Context(0, workspace_bytes=8 << 30)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("name", ["c3", "c4"])
+def test_batched_workload_sampled_parity(ctx, name):
+    from paper_1604_02292_amd import make_params
+    gold = _golden(name)
+    print(f"[batch {name}] generating inputs", flush=True)
+    d = synth.make_inputs(name, with_image=False)
+    cfg = d["cfg"]
+    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    rois = synth.roi_list(name)
+    sampled = {int(k.split("_")[1]) for k in gold.files if k.startswith("x_")}
+    params, outs = [], []
+    for i, (r0, c0, rr, cc, m) in enumerate(rois):
+        s = float(gold[f"sigma_{i}"]) if i in sampled else 0.0
+        params.append(make_params((r0, c0, rr, cc), m, "cp", cfg["lam"], cfg["iters"], s, s))
+        outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
+    sino = torch.from_numpy(d["sino"].astype(np.float32)).cuda()
+    print(f"[batch {name}] solving {len(rois)} ROIs in one batch", flush=True)
+    ctx.roi_solve_batch(g, sino, params, outs)
+    torch.cuda.synchronize()
+    for i in sorted(sampled):
+        assert tuple(gold[f"rect_{i}"][:4]) == tuple(rois[i][:4])
+        e = rel(outs[i].double().cpu().numpy(), gold[f"x_{i}"])
+        print(f"    roi {i} {rois[i]} rel {e:.2e}", flush=True)
+        assert e <= 1e-3
+    for o in outs:
+        assert torch.isfinite(o).all()
+        assert (o >= 0).all()
+    if name == "c4":
+        # the stitched tiles cover the whole grid without overlap (no blending)
+        full = torch.zeros((cfg["n"], cfg["n"]), device="cuda")
+        cover = torch.zeros((cfg["n"], cfg["n"]), device="cuda")
+        for (r0, c0, rr, cc, m), o in zip(rois, outs):
+            full[r0:r0 + rr, c0:c0 + cc] = o
+            cover[r0:r0 + rr, c0:c0 + cc] += 1
+        assert bool((cover == 1).all())
