@@ -74,13 +74,12 @@ def cpu_baseline(d, cfg, roi, margin):
                       f"(measured {t_fbp + t_ext + t_step + t_10:.1f}s)"}
 
 
-def batched_leg(torch, reps=3):
+def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
     """64 uneven ROIs (sides 32..256, margin side/4) on a 2048^2 grid, 256 angles,
     3072 bins, 200 CP-TV iterations: one roi_solve_batch call vs the same ROIs
     solved one at a time, both from the same precomputed FBP exterior."""
     import synth
     from paper_1604_02292_amd import Context, make_params
-    d = synth.make_inputs("c3", with_image=False)
     cfg = d["cfg"]
     ctx = Context(0, workspace_bytes=8 << 30)
     try:
@@ -89,9 +88,12 @@ def batched_leg(torch, reps=3):
         xe = torch.empty((cfg["n"], cfg["n"]), dtype=torch.float32, device="cuda")
         ctx.tomo_fbp_ramlak(g, sino, xe)
         rois = synth.roi_list("c3")
-        params = [make_params(r[:4], r[4], "cp", cfg["lam"], cfg["iters"]) for r in rois]
+        its = iters or cfg["iters"]
+        params = [make_params(r[:4], r[4], "cp", cfg["lam"], its, fixed_step, fixed_step)
+                  for r in rois]
         outs = [torch.empty((r[2], r[3]), dtype=torch.float32, device="cuda") for r in rois]
-        updates = 2 * cfg["iters"] * sum(ctx.tomo_roi_nnz(g, ctx.tomo_roi_ext(g, r[:4], r[4]))
+        log(f"batched: inputs ready, {len(rois)} ROIs, {its} iterations")
+        updates = 2 * its * sum(ctx.tomo_roi_nnz(g, ctx.tomo_roi_ext(g, r[:4], r[4]))
                                           for r in rois)
         for _ in range(2):   # step sizes, then the graph capture
             ctx.roi_solve_batch(g, sino, params, outs, x_ext=xe)
@@ -101,6 +103,9 @@ def batched_leg(torch, reps=3):
             ctx.roi_solve_batch(g, sino, params, outs, x_ext=xe)
         torch.cuda.synchronize()
         t_batch = (time.perf_counter() - t0) / reps
+        if not compare:
+            return {"roi_solves_per_s": len(rois) / t_batch, "ms_per_batch": 1e3 * t_batch,
+                    "updates_per_s": updates / t_batch}
         one = [torch.empty_like(o) for o in outs]
         for p, o in zip(params, one):   # warm shapes
             ctx.roi_solve(g, sino, p, o, x_ext=xe)
@@ -124,7 +129,7 @@ def batched_leg(torch, reps=3):
         ctx.close()
 
 
-def serving_leg(torch, n_req=200, n_warm=64):
+def serving_leg(torch, slices, n_req=200, n_warm=64):
     """64 resident 2048^2 slices (512 angles x 3072 bins); requests with side
     U{32..512}, margin ceil(side/4), 80% CP-TV / 20% nonnegative SIRT, 100-300
     iterations.  Capacity = completion rate with all requests queued at once;
@@ -133,7 +138,6 @@ def serving_leg(torch, n_req=200, n_warm=64):
     import synth
     from paper_1604_02292_amd import Context, make_params
     cfg = synth.workload("c5")
-    slices = synth.make_slices("c5")
     ctx = Context(0, workspace_bytes=12 << 30)
     try:
         g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
@@ -211,6 +215,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--only", choices=["batch", "serve"], default=None,
+                    help="run only one secondary leg (for profiling) and print its JSON")
+    ap.add_argument("--iters", type=int, default=None,
+                    help="override the iteration count of --only legs (profiling runs)")
+    ap.add_argument("--fixed-step", type=float, default=0.0,
+                    help="explicit CP step for --only legs, skipping the power iteration")
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="processes for input generation (0 = one per core, at most 16)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -218,11 +230,27 @@ def main():
               "per-iteration communication, but no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import synth
+    gw = args.gen_workers or None
+    # all inputs are generated before the GPU is initialised (the generator forks)
+    d3 = slices = None
+    if args.only != "serve" and not (args.only is None and args.skip_batch):
+        d3 = synth.make_inputs("c3", with_image=False, workers=gw)
+    if args.only != "batch" and not (args.only is None and args.skip_serve):
+        slices = synth.make_slices("c5", workers=gw)
+    log("inputs generated")
+    import torch
     from paper_1604_02292_amd import Context, make_params
 
-    d = synth.make_inputs("c2", with_image=False)
+    if args.only == "batch":
+        print(json.dumps(batched_leg(torch, d3, reps=args.steps, compare=False, iters=args.iters,
+                                     fixed_step=args.fixed_step)), flush=True)
+        return
+    if args.only == "serve":
+        print(json.dumps(serving_leg(torch, slices)), flush=True)
+        return
+
+    d = synth.make_inputs("c2", with_image=False, workers=1)
     cfg = d["cfg"]
     r0, c0, rr, cc, margin = synth.roi_list("c2")[0]
     roi = (r0, c0, rr, cc)
@@ -295,12 +323,12 @@ def main():
     ctx.close()
     if not args.skip_batch:
         try:
-            res["batched"] = batched_leg(torch)
+            res["batched"] = batched_leg(torch, d3)
         except Exception as e:   # the headline line must still print
             res["batched"] = {"error": repr(e)}
     if not args.skip_serve:
         try:
-            res["serving"] = serving_leg(torch)
+            res["serving"] = serving_leg(torch, slices)
         except Exception as e:
             res["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:

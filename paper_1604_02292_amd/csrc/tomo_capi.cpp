@@ -17,10 +17,10 @@ namespace tomo {
 
 static constexpr int kPowerIters = 50;
 
-void bp_tile(int ag, int* th, int* tw) {
+void bp_tile(int ag, int ppt, int* th, int* tw) {
     const int P = 256 / ag;
     *tw = (ag == 4) ? 8 : 16;
-    *th = P / *tw;
+    *th = (P / *tw) * ppt;
 }
 
 LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels) {
@@ -30,8 +30,12 @@ LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long tot
     const long long want = 256LL * 8 * 64;
     L.seg = total_rays >= 4 * want ? 1 : (total_rays >= 2 * want ? 2 : 4);
     L.ag = total_pixels >= 4 * want ? 1 : (total_pixels >= 2 * want ? 2 : 4);
+    // two pixels per thread share the per-angle position work once the problem
+    // is large enough that halving the thread count still fills the chip
+    L.ppt = total_pixels >= 8 * want ? 2 : 1;
     if (ctx->fp_seg) L.seg = ctx->fp_seg;
     if (ctx->bp_ag) L.ag = ctx->bp_ag;
+    if (ctx->bp_ppt) L.ppt = ctx->bp_ppt;
     return L;
 }
 
@@ -114,15 +118,16 @@ size_t count_fp_items(const std::vector<AngFP>& afp, int seg) {
     return n;
 }
 
-size_t count_bp_items(int nr, int nc, int ag) {
+size_t count_bp_items(int nr, int nc, int ag, int ppt) {
     int th, tw;
-    bp_tile(ag, &th, &tw);
+    bp_tile(ag, ppt, &th, &tw);
     return (size_t)((nr + th - 1) / th) * (size_t)((nc + tw - 1) / tw);
 }
 
-void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag, const AngBP* d_abp) {
+void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag, int ppt,
+              const AngBP* d_abp) {
     int th, tw;
-    bp_tile(ag, &th, &tw);
+    bp_tile(ag, ppt, &th, &tw);
     for (int a = 0; a < (nr + th - 1) / th; ++a)
         for (int b = 0; b < (nc + tw - 1) / tw; ++b) out.push_back(Item{jj, a, b, 0, d_abp, 0});
 }
@@ -145,17 +150,17 @@ tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, fl
     const size_t band_bytes = (size_t)g.na * P.bpitch * sizeof(float);
     int th, tw;
     const LaunchCfg L = choose_launch(ctx, 0, (long long)g.n * g.n);
-    bp_tile(L.ag, &th, &tw);
+    bp_tile(L.ag, L.ppt, &th, &tw);
     std::vector<Item> items;
     Meta m;
     const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
     const size_t o_abp = m.add(P.abp.data(), P.abp.size() * sizeof(AngBP));
     const size_t o_job = m.reserve(sizeof(Job));
-    const size_t o_it = m.reserve(count_bp_items(g.n, g.n, L.ag) * sizeof(Item));
+    const size_t o_it = m.reserve(count_bp_items(g.n, g.n, L.ag, L.ppt) * sizeof(Item));
     char* dm = ctx->arena.alloc(m.buf.size() + band_bytes + 256);
     if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace too small for the FBP tables");
     allocs.push_back(dm);
-    bp_items(items, 0, g.n, g.n, L.ag, (const AngBP*)(dm + o_abp));
+    bp_items(items, 0, g.n, g.n, L.ag, L.ppt, (const AngBP*)(dm + o_abp));
     m.put(o_it, items.data(), items.size() * sizeof(Item));
     float* band = (float*)(dm + align_up(m.buf.size(), 256));
     Job J;
@@ -181,7 +186,7 @@ tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, fl
     TOMO_HIP(ctx, launch_fill(band, (size_t)g.na * P.bpitch, 0.f, s));
     TOMO_HIP(ctx, launch_ramp(sino, g.na, g.nd, g.d_taps, J.afp, band, P.bpitch, s));
     TOMO_HIP(ctx, launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
-                            0, L.ag, s));
+                            0, L.ag, L.ppt, s));
     return TOMO_OK;
 }
 
@@ -267,7 +272,7 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     pr.plan = make_plan(g, pr.ext, pr.ext);
     const LaunchCfg L = choose_launch(ctx, (long long)g.na * pr.plan.wmax, (long long)nr * nc);
     int th, tw;
-    bp_tile(L.ag, &th, &tw);
+    bp_tile(L.ag, L.ppt, &th, &tw);
     std::vector<char*> mine;
     char* blk = ctx->arena.alloc(state_bytes(g, pr.plan));
     if (!blk) return fail(ctx, TOMO_ENOMEM, "workspace too small for the power iteration");
@@ -278,7 +283,7 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     const size_t o_abp = m.add(pr.plan.abp.data(), pr.plan.abp.size() * sizeof(AngBP));
     const size_t o_job = m.reserve(sizeof(Job));
     const size_t o_fi = m.reserve(count_fp_items(pr.plan.afp, L.seg) * sizeof(Item));
-    const size_t o_bi = m.reserve(count_bp_items(nr, nc, L.ag) * sizeof(Item));
+    const size_t o_bi = m.reserve(count_bp_items(nr, nc, L.ag, L.ppt) * sizeof(Item));
     const size_t o_est = m.reserve(64);
     char* dm = ctx->arena.alloc(m.buf.size());
     if (!dm) {
@@ -290,7 +295,7 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     pr.d_abp = (AngBP*)(dm + o_abp);
     std::vector<Item> fi, bi;
     fp_items(fi, 0, pr.plan.afp, L.seg, pr.d_afp);
-    bp_items(bi, 0, nr, nc, L.ag, pr.d_abp);
+    bp_items(bi, 0, nr, nc, L.ag, L.ppt, pr.d_abp);
     const int n_part = (int)bi.size();
     Job J = make_job(g, pr, FP_BAND_STORE, BP_POWER, (nc + tw - 1) / tw);
     m.put(o_job, &J, sizeof J);
@@ -309,7 +314,7 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
         e = launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_fi), (int)fi.size(), it,
                       L.seg, s);
         if (e == hipSuccess)
-            e = launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_bi), n_part, it, L.ag, s);
+            e = launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_bi), n_part, it, L.ag, L.ppt, s);
         float* nxt = ((it + 1) & 1) ? pr.xb1 : pr.xb0;
         if (e == hipSuccess)
             e = launch_power_normalize(pr.x, nc, nr, nc, pr.part, n_part, nxt, pr.plan.xp, pr.xt,
@@ -386,7 +391,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
 
     const LaunchCfg L = choose_launch(ctx, rays, pix);
     int th, tw;
-    bp_tile(L.ag, &th, &tw);
+    bp_tile(L.ag, L.ppt, &th, &tw);
 
     char* sblk = ctx->arena.alloc(state_total + 256);
     if (!sblk) {
@@ -545,7 +550,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         jobs[q] = make_job(g, r, cp ? FP_CP_DUAL : FP_SIRT, cp ? BP_CP : BP_SIRT,
                            (r.ext.cols + tw - 1) / tw);
         fp_items(fi, q, r.plan.afp, L.seg, r.d_afp);
-        bp_items(bi, q, r.ext.rows, r.ext.cols, L.ag, r.d_abp);
+        bp_items(bi, q, r.ext.rows, r.ext.cols, L.ag, L.ppt, r.d_abp);
         fi_end[q] = (int)fi.size();
         bi_end[q] = (int)bi.size();
     }
@@ -573,7 +578,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
             }
             if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, st)) != hipSuccess) return e;
             if (timed && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
-            if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, st)) != hipSuccess) return e;
+            if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, st)) != hipSuccess) return e;
             if (timed) {
                 if ((e = hipEventRecord(e2, st)) != hipSuccess) return e;
                 ctx->ev_pending.emplace_back(e0, e1, 0);
@@ -604,7 +609,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
                 le = kind == 0 ? launch_fp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_fi),
                                            fi_end[count - 1], q, L.seg, ctx->cap_stream)
                                : launch_bp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_bi),
-                                           bi_end[count - 1], q, L.ag, ctx->cap_stream);
+                                           bi_end[count - 1], q, L.ag, L.ppt, ctx->cap_stream);
             const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &gr);
             CK(le);
             CK(ce);
@@ -995,11 +1000,11 @@ tomo_status tomo_bp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
     const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
     const size_t o_abp = m.add(P.abp.data(), P.abp.size() * sizeof(AngBP));
     const size_t o_job = m.reserve(sizeof(Job));
-    const size_t o_it = m.reserve(count_bp_items(r.rows, r.cols, L.ag) * sizeof(Item));
+    const size_t o_it = m.reserve(count_bp_items(r.rows, r.cols, L.ag, L.ppt) * sizeof(Item));
     const size_t nband = (size_t)g.na * P.bpitch;
     char* dm = ctx->arena.alloc(align_up(m.buf.size(), 256) + nband * sizeof(float));
     if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace too small for the band buffer");
-    bp_items(items, 0, r.rows, r.cols, L.ag, (const AngBP*)(dm + o_abp));
+    bp_items(items, 0, r.rows, r.cols, L.ag, L.ppt, (const AngBP*)(dm + o_abp));
     m.put(o_it, items.data(), items.size() * sizeof(Item));
     float* band = (float*)(dm + align_up(m.buf.size(), 256));
     Job J;
@@ -1023,7 +1028,7 @@ tomo_status tomo_bp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
     TOMO_HIP(ctx, ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s));
     TOMO_HIP(ctx, launch_band_gather(sino, g.nd, J.afp, g.na, band, P.bpitch, s));
     TOMO_HIP(ctx, launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
-                            0, L.ag, s));
+                            0, L.ag, L.ppt, s));
     ctx->arena.free_after(allocs, s);
     return TOMO_OK;
     GUARD_END(ctx)
@@ -1204,13 +1209,15 @@ tomo_status roi_step_size(tomo_ctx* ctx, int32_t geom, tomo_rect ext, float* sig
     GUARD_END(ctx)
 }
 
-tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups) {
+tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups,
+                            int32_t bp_pixels_per_thread) {
     if (!ctx) return TOMO_EINVAL;
     auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
-    if (!ok(fp_segments) || !ok(bp_groups))
-        return fail(ctx, TOMO_EINVAL, "launch knobs must be 0, 1, 2 or 4");
+    if (!ok(fp_segments) || !ok(bp_groups) || bp_pixels_per_thread < 0 || bp_pixels_per_thread > 2)
+        return fail(ctx, TOMO_EINVAL, "launch knobs: segments/groups in {0,1,2,4}, pixels in {0,1,2}");
     ctx->fp_seg = fp_segments;
     ctx->bp_ag = bp_groups;
+    ctx->bp_ppt = bp_pixels_per_thread;
     return TOMO_OK;
 }
 

@@ -23,20 +23,23 @@ struct AngFP {
     int32_t w;        // band width (rays)
     int32_t i0;       // global bin of band position 0 (may lie off the detector)
     int32_t tr;       // 1: step along columns, read the transposed image
-    int32_t pad0, pad1;
+    float bscale;     // B = spacing / m^2: band arrays read by the backprojector hold B * y
+    int32_t pad1;
 };
 static_assert(sizeof(AngFP) == 48, "AngFP layout");
 
 // Per (job, angle) table of the pixel-driven backprojector.  Pixel (r, c) of the
 // region lands at padded band coordinate u = c * cu + r * su + u0 and touches band
-// entries floor(u) and floor(u) + 1 with weights
-//   max(0, A - f B) and max(0, (A - B) + f B),  f = u - floor(u),
-// A = 1/m, B = spacing / m^2: the hat max(0, 1 - |s_i - t| / m) / m.
+// entries floor(u) and floor(u) + 1.  With f = u - floor(u), A = 1/m and
+// B = spacing / m^2, the hat max(0, 1 - |s_i - t| / m) / m gives the weights
+//   max(0, A - f B) = B max(0, r - f)   and   max(0, (A - B) + f B) = B max(0, f + r - 1),
+// r = A / B = m / spacing.  Band arrays read by the backprojector store B * y, so
+// the kernel only evaluates max(0, r - f) and max(0, f + rm1), rm1 = r - 1.
 struct AngBP {
     double cu, su, u0;
-    float A, B, AmB, pad;   // AmB = A - B
+    float r, rm1;
 };
-static_assert(sizeof(AngBP) == 40, "AngBP layout");
+static_assert(sizeof(AngBP) == 32, "AngBP layout");
 
 enum FpMode : int32_t {
     FP_STORE = 0,            // gout[k][i] = fp (on-detector bins of the band)
@@ -99,7 +102,7 @@ static_assert(sizeof(Item) == 32, "Item layout");
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
                      hipStream_t s);
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
-                     hipStream_t s);
+                     int ppt, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int tp, float v,
                               hipStream_t s);

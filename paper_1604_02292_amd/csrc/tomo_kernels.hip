@@ -224,14 +224,14 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
             y[bidx] = ondet ? pre0 + J->scale * fpv : 0.f;
             break;
         case FP_CP_DUAL:
-            // prox of sigma F1*, F1(v) = ||v - b||^2 (or 1/2 ||v - b||^2)
-            y[bidx] = ondet ? (pre0 + J->sigma * (fpv - pre1)) * J->dual_div : 0.f;
+            // prox of sigma F1*, F1(v) = ||v - b||^2 (or 1/2 ||v - b||^2), on B * y
+            y[bidx] = ondet ? (pre0 + (J->sigma * A.bscale) * (fpv - pre1)) * J->dual_div : 0.f;
             break;
         case FP_SIRT:
-            y[bidx] = ondet ? J->alpha * (pre1 - fpv) : 0.f;
+            y[bidx] = ondet ? (J->alpha * A.bscale) * (pre1 - fpv) : 0.f;
             break;
         case FP_BAND_STORE:
-            y[bidx] = ondet ? fpv : 0.f;
+            y[bidx] = ondet ? A.bscale * fpv : 0.f;
             break;
         case FP_RESID:
             if (ondet) gout[gidx] = pre0 + J->scale * fpv;
@@ -243,24 +243,25 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
 
 // ---------------------------------------------------------------------------
 // Backprojection (pixel-driven gather: no atomics, bit-reproducible).  One
-// block = one tile of 256/AG pixels of one job; each pixel's angles are split
-// into AG contiguous groups summed in a fixed order.  For the CP mode the block
-// first computes the TV dual update on its tile plus a one-pixel top/left halo
-// (from the previous xbar and z, which are double-buffered so neighbouring
-// tiles never see half-updated values), takes its divergence, then applies
-// the primal prox and the extrapolation to its own pixels.
+// block = one tile of 256/AG threads of one job, each thread owning PPT
+// vertically adjacent pixels; each pixel's angles are split into AG contiguous
+// groups summed in a fixed order.  For the CP mode the block first computes
+// the TV dual update on its tile plus a one-pixel top/left halo (from the
+// previous xbar and z, which are double-buffered so neighbouring tiles never
+// see half-updated values), takes its divergence, then applies the primal
+// prox and the extrapolation to its own pixels.
 // ---------------------------------------------------------------------------
-template <int AG>
+template <int AG, int PPT>
 __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
                                                  int step) {
-    constexpr int P = 256 / AG;
+    constexpr int P = 256 / AG;              // threads per angle group (a multiple of 64)
     constexpr int TW = (AG == 4) ? 8 : 16;
-    constexpr int TH = P / TW;
+    constexpr int TH = (P / TW) * PPT;       // pixel rows of the tile
     __shared__ float xs[TH + 2][TW + 2];
     __shared__ float zs0[TH + 1][TW + 1];
     __shared__ float zs1[TH + 1][TW + 1];
-    __shared__ float red[256];
+    __shared__ float red[PPT][256];
 
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     if (bid >= n_items) return;
@@ -270,23 +271,31 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     const int t = threadIdx.x;
     const int g = uniform_int(t / P);      // P is a multiple of 64: one group per wave
     const int p = t % P;
-    const int tr = p / TW, tc = p % TW;
-    const int r = R0 + tr, c = C0 + tc;
+    const int tr = (p / TW) * PPT, tc = p % TW;   // first own pixel in the tile
+    const int c = C0 + tc;
     const int nr = J->nr, nc = J->nc;
-    const bool inside = (r < nr) && (c < nc);
     const int mode = J->bp_mode;
     const int rpar = (step + J->parity0) & 1, wpar = rpar ^ 1;
     const bool tv = (mode == BP_CP) || (mode == BP_POWER);
+    bool inside[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) inside[q] = (R0 + tr + q < nr) && (c < nc);
 
     // Every load that does not depend on another one is issued here, before the
-    // first barrier: the primal value of the own pixel, the xbar tile with its
+    // first barrier: the primal values of the own pixels, the xbar tile with its
     // halo, and the old TV dual of the tile plus top/left halo.
-    const size_t xi = (size_t)r * J->ldx + c;
-    float xo = 0.f;
-    if (inside && (mode == BP_CP || mode == BP_SIRT || mode == BP_ACCUM)) xo = J->x[xi];
+    float xo[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        xo[q] = 0.f;
+        if (inside[q] && (mode == BP_CP || mode == BP_SIRT || mode == BP_ACCUM))
+            xo[q] = J->x[(size_t)(R0 + tr + q) * J->ldx + c];
+    }
     constexpr int NZ = ((TH + 1) * (TW + 1) + 255) / 256;
     float zq0[NZ], zq1[NZ];
-    float divv = 0.f, zn0 = 0.f, zn1 = 0.f;
+    float divv[PPT], zn0[PPT], zn1[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) divv[q] = zn0[q] = zn1[q] = 0.f;
     if (tv) {
         gcfloat* xb = gview(J->xb[rpar]);
         const int xp = J->xp;
@@ -352,126 +361,152 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
             zs1[lr][lc] = q1;
         }
         __syncthreads();
-        if (inside) {
-            zn0 = zs0[tr + 1][tc + 1];
-            zn1 = zs1[tr + 1][tc + 1];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            if (!inside[q]) continue;
+            const int lr = tr + q + 1, lc = tc + 1;
+            zn0[q] = zs0[lr][lc];
+            zn1[q] = zs1[lr][lc];
             // div = -grad^T (z is 0 outside the region and on its last row/column)
-            divv = (zn0 - zs0[tr][tc + 1]) + (zn1 - zs1[tr + 1][tc]);
+            divv[q] = (zn0[q] - zs0[lr - 1][lc]) + (zn1[q] - zs1[lr][lc - 1]);
         }
     }
 
-    float acc = 0.f;
-    if (inside) {
-        const double lcd = (double)c, lrd = (double)r;
+    float acc[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) acc[q] = 0.f;
+    if (inside[0]) {
+        const double lcd = (double)c, lrd = (double)(R0 + tr);
         const int na = J->n_angles;
         const int k0 = (na * g) / AG, k1 = (na * (g + 1)) / AG;
         const int bpitch = J->bpitch;
-        const int bpm = bpitch - 2;
+        const unsigned bpm = (unsigned)(bpitch - 2);
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(J->y, (size_t)na * bpitch * sizeof(float));
         const unsigned rowb = (unsigned)bpitch * 4u;
         const CONST_AS AngBP* tab = cview((const AngBP*)it.tab);
+        constexpr int UA = 16 / PPT;   // angles per step: 16 paired band loads in flight
         int k = k0;
-        // 16 angles per step: 16 paired band loads in flight
-        for (; k + 16 <= k1; k += 16) {
-            float f[16];
-            v2f yv[16];
+        for (; k + UA <= k1; k += UA) {
+            float f[UA][PPT];
+            v2f yv[UA][PPT];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < UA; ++u) {
                 const AngBP a = tab[k + u];
-                const double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
-                // uu >= 1 inside the band; the unsigned clamp keeps any stray
-                // index inside the row (the value would be wrong, never a fault)
-                const unsigned i = min((unsigned)(int)uu, (unsigned)bpm);
-                f[u] = (float)__builtin_amdgcn_fract(uu);
-                yv[u] = load2(rs, i << 2, (unsigned)(k + u) * rowb);
+                double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    if (q) uu += a.su;
+                    // uu >= 1 inside the band; the unsigned clamp keeps any stray
+                    // index inside the row (a wrong value, never a fault)
+                    const unsigned i = min((unsigned)(int)uu, bpm);
+                    f[u][q] = (float)__builtin_amdgcn_fract(uu);
+                    yv[u][q] = load2(rs, i << 2, (unsigned)(k + u) * rowb);
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < UA; ++u) {
                 const AngBP a = tab[k + u];
-                const float w0 = fmaxf(0.f, fmaf(-f[u], a.B, a.A));
-                const float w1 = fmaxf(0.f, fmaf(f[u], a.B, a.AmB));
-                acc = fmaf(w0, yv[u].x, acc);
-                acc = fmaf(w1, yv[u].y, acc);
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    const float w0 = fmaxf(0.f, a.r - f[u][q]);
+                    const float w1 = fmaxf(0.f, f[u][q] + a.rm1);
+                    acc[q] = fmaf(w0, yv[u][q].x, acc[q]);
+                    acc[q] = fmaf(w1, yv[u][q].y, acc[q]);
+                }
             }
         }
         for (; k < k1; ++k) {
             const AngBP a = tab[k];
-            const double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
-            const unsigned i = min((unsigned)(int)uu, (unsigned)bpm);
-            const float f = (float)__builtin_amdgcn_fract(uu);
-            const v2f yv = load2(rs, i << 2, (unsigned)k * rowb);
-            const float w0 = fmaxf(0.f, fmaf(-f, a.B, a.A));
-            const float w1 = fmaxf(0.f, fmaf(f, a.B, a.AmB));
-            acc = fmaf(w0, yv.x, acc);
-            acc = fmaf(w1, yv.y, acc);
+            double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                if (q) uu += a.su;
+                const unsigned i = min((unsigned)(int)uu, bpm);
+                const float f = (float)__builtin_amdgcn_fract(uu);
+                const v2f yv = load2(rs, i << 2, (unsigned)k * rowb);
+                const float w0 = fmaxf(0.f, a.r - f);
+                const float w1 = fmaxf(0.f, f + a.rm1);
+                acc[q] = fmaf(w0, yv.x, acc[q]);
+                acc[q] = fmaf(w1, yv.y, acc[q]);
+            }
         }
     }
     if (AG > 1) {
-        red[t] = acc;
-        __syncthreads();
-        acc = 0.f;
-        if (g == 0) {
 #pragma unroll
-            for (int q = 0; q < AG; ++q) acc += red[q * P + p];
+        for (int q = 0; q < PPT; ++q) red[q][t] = acc[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            acc[q] = 0.f;
+            if (g == 0) {
+#pragma unroll
+                for (int h = 0; h < AG; ++h) acc[q] += red[q][h * P + p];
+            }
         }
     }
 
     float sq = 0.f;
-    if (g == 0 && inside) {
+    if (g == 0) {
         float* x = J->x;
-        switch (mode) {
-            case BP_STORE: {
-                const float v = J->scale * acc;
-                x[xi] = v;
-                float* xb0 = J->xb[0];
-                float* xt = J->xt;
-                if (xb0) xb0[(size_t)r * J->xp + c + 1] = v;
-                if (xt) xt[(size_t)c * J->tp + r + 1] = v;
-            } break;
-            case BP_ACCUM:
-                x[xi] = xo + J->scale * acc;
-                break;
-            case BP_CP: {
-                const float xn = fmaxf(0.f, xo - J->tau * (acc - divv));
-                x[xi] = xn;
-                const float xbn = 2.f * xn - xo;   // theta = 1
-                float* xbw = J->xb[wpar];
-                float* xt = J->xt;
-                float* zw = J->z[wpar];
-                xbw[(size_t)r * J->xp + c + 1] = xbn;
-                xt[(size_t)c * J->tp + r + 1] = xbn;
-                const size_t zi = (size_t)r * nc + c;
-                zw[zi] = zn0;
-                zw[(size_t)nr * nc + zi] = zn1;
-            } break;
-            case BP_SIRT: {
-                const float xn = fmaxf(0.f, xo + acc);
-                x[xi] = xn;
-                float* xbw = J->xb[wpar];
-                float* xt = J->xt;
-                xbw[(size_t)r * J->xp + c + 1] = xn;
-                xt[(size_t)c * J->tp + r + 1] = xn;
-            } break;
-            case BP_POWER: {
-                const float w = acc - divv;
-                x[xi] = w;
-                sq = w * w;
-            } break;
-            default:
-                break;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            if (!inside[q]) continue;
+            const int r = R0 + tr + q;
+            const size_t xi = (size_t)r * J->ldx + c;
+            switch (mode) {
+                case BP_STORE: {
+                    const float v = J->scale * acc[q];
+                    x[xi] = v;
+                    float* xb0 = J->xb[0];
+                    float* xt = J->xt;
+                    if (xb0) xb0[(size_t)r * J->xp + c + 1] = v;
+                    if (xt) xt[(size_t)c * J->tp + r + 1] = v;
+                } break;
+                case BP_ACCUM:
+                    x[xi] = xo[q] + J->scale * acc[q];
+                    break;
+                case BP_CP: {
+                    const float xn = fmaxf(0.f, xo[q] - J->tau * (acc[q] - divv[q]));
+                    x[xi] = xn;
+                    const float xbn = 2.f * xn - xo[q];   // theta = 1
+                    float* xbw = J->xb[wpar];
+                    float* xt = J->xt;
+                    float* zw = J->z[wpar];
+                    xbw[(size_t)r * J->xp + c + 1] = xbn;
+                    xt[(size_t)c * J->tp + r + 1] = xbn;
+                    const size_t zi = (size_t)r * nc + c;
+                    zw[zi] = zn0[q];
+                    zw[(size_t)nr * nc + zi] = zn1[q];
+                } break;
+                case BP_SIRT: {
+                    const float xn = fmaxf(0.f, xo[q] + acc[q]);
+                    x[xi] = xn;
+                    float* xbw = J->xb[wpar];
+                    float* xt = J->xt;
+                    xbw[(size_t)r * J->xp + c + 1] = xn;
+                    xt[(size_t)c * J->tp + r + 1] = xn;
+                } break;
+                case BP_POWER: {
+                    const float w = acc[q] - divv[q];
+                    x[xi] = w;
+                    sq += w * w;
+                } break;
+                default:
+                    break;
+            }
         }
     }
     if (mode == BP_POWER) {
         __syncthreads();
-        red[t] = sq;
+        red[0][t] = sq;
         __syncthreads();
         for (int h = 128; h > 0; h >>= 1) {
-            if (t < h) red[t] += red[t + h];
+            if (t < h) red[0][t] += red[0][t + h];
             __syncthreads();
         }
         if (t == 0) {
             float* part = J->part;
-            part[it.a * J->ntc + it.b] = red[0];
+            part[it.a * J->ntc + it.b] = red[0][0];
         }
     }
 }
@@ -534,17 +569,19 @@ __global__ void crop_kernel(const float* __restrict__ x, int ldx, int dr, int dc
     }
 }
 
-// Full-detector sinogram rows -> band layout (band position j at j + 1; zeros
-// off the detector and in the padding).
+// Full-detector sinogram rows -> band layout for the backprojector (band
+// position j at j + 1, scaled by the angle's B; zeros off the detector and in
+// the padding).
 __global__ void band_gather_kernel(const float* __restrict__ sino, int n_det,
                                    const AngFP* __restrict__ afp, float* __restrict__ band,
                                    int bpitch) {
     const int k = blockIdx.x;
     const int i0 = afp[k].i0, w = afp[k].w;
+    const float bs = afp[k].bscale;
     for (int q = threadIdx.x; q < bpitch; q += blockDim.x) {
         const int j = q - 1, gi = i0 + j;
         float v = 0.f;
-        if (j >= 0 && j < w && gi >= 0 && gi < n_det) v = sino[(size_t)k * n_det + gi];
+        if (j >= 0 && j < w && gi >= 0 && gi < n_det) v = bs * sino[(size_t)k * n_det + gi];
         band[(size_t)k * bpitch + q] = v;
     }
 }
@@ -567,8 +604,8 @@ __global__ void band_scatter_kernel(const float* __restrict__ band, int bpitch,
 
 // Ram-Lak filtering: block (chunk, angle) produces 256 consecutive outputs of
 // one detector row as a linear (zero-padded) convolution along the detector,
-// q[i] = taps[0] p[i] + sum_{odd d} taps[d] (p[i-d] + p[i+d]), written into
-// the band layout of the receiving job.
+// q[i] = taps[0] p[i] + sum_{odd d} taps[d] (p[i-d] + p[i+d]), written (times
+// the angle's B) into the band layout of the receiving backprojection.
 __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sino, int n_det,
                                                    const float* __restrict__ taps,
                                                    const AngFP* __restrict__ afp,
@@ -592,7 +629,7 @@ __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sin
     for (int e = d; e <= dl; e += 2) acc = fmaf(htab[e], prow[i - e], acc);
     for (int e = d; e <= dr; e += 2) acc = fmaf(htab[e], prow[i + e], acc);
     const int j = i - i0;
-    if (j >= 0 && j < w) band[(size_t)k * bpitch + 1 + j] = acc;
+    if (j >= 0 && j < w) band[(size_t)k * bpitch + 1 + j] = afp[k].bscale * acc;
 }
 
 // Power iteration: v = w / ||w||, ||w|| from the per-tile partial sums (summed
@@ -646,14 +683,25 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
 }
 
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
-                     hipStream_t s) {
+                     int ppt, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items)), block(256);
-    switch (groups) {
-        case 1: hipLaunchKernelGGL(bp_kernel<1>, grid, block, 0, s, jobs, items, n_items, step); break;
-        case 2: hipLaunchKernelGGL(bp_kernel<2>, grid, block, 0, s, jobs, items, n_items, step); break;
-        default: hipLaunchKernelGGL(bp_kernel<4>, grid, block, 0, s, jobs, items, n_items, step); break;
+#define TOMO_BP(AGV, PPTV) \
+    hipLaunchKernelGGL((bp_kernel<AGV, PPTV>), grid, block, 0, s, jobs, items, n_items, step)
+    if (ppt == 2) {
+        switch (groups) {
+            case 1: TOMO_BP(1, 2); break;
+            case 2: TOMO_BP(2, 2); break;
+            default: TOMO_BP(4, 2); break;
+        }
+    } else {
+        switch (groups) {
+            case 1: TOMO_BP(1, 1); break;
+            case 2: TOMO_BP(2, 1); break;
+            default: TOMO_BP(4, 1); break;
+        }
     }
+#undef TOMO_BP
     return hipGetLastError();
 }
 

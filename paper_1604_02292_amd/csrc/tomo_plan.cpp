@@ -81,14 +81,13 @@ Plan make_plan(const Geom& g, const Rect& reg, const Rect& bsrc) {
         a.inv_m = (float)(1.0 / m);
         a.w = w;
         a.i0 = i0;
+        a.bscale = (float)(sp / (m * m));
         AngBP& bp = P.abp[k];
         bp.cu = c / sp;
         bp.su = s / sp;
         bp.u0 = -D / sp + 1.0;
-        bp.A = (float)(1.0 / m);
-        bp.B = (float)(sp / (m * m));
-        bp.AmB = (float)(1.0 / m - sp / (m * m));
-        bp.pad = 0.f;
+        bp.r = (float)(m / sp);
+        bp.rm1 = (float)(m / sp - 1.0);
         P.wmax = std::max(P.wmax, w);
     }
     P.bpitch = round_up(P.wmax + 3, 4);

@@ -122,7 +122,7 @@ struct tomo_ctx {
     std::recursive_mutex mu;   // geometry list, caches, registrations
     std::deque<tomo::Geom> geoms;   // deque: references stay valid while serving reads them
     std::map<std::tuple<int, int, int>, float> step_cache;
-    int fp_seg = 0, bp_ag = 0;
+    int fp_seg = 0, bp_ag = 0, bp_ppt = 0;
     std::map<int, std::unique_ptr<tomo::SinoState>> sinos;
     int next_sino = 1;
     std::unique_ptr<tomo::ServeState> serve;
@@ -172,11 +172,11 @@ struct RoiState {
 };
 
 struct LaunchCfg {
-    int seg = 4, ag = 4;
+    int seg = 4, ag = 4, ppt = 1;
 };
 
 LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels);
-void bp_tile(int ag, int* th, int* tw);
+void bp_tile(int ag, int ppt, int* th, int* tw);
 size_t state_bytes(const Geom& g, const Plan& p);
 tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p);
 hipEvent_t timing_event(tomo_ctx* ctx);
@@ -186,9 +186,10 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
 // Work items; the device table pointers must already be known (items store them).
 void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg,
               const AngFP* d_afp);
-void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag, const AngBP* d_abp);
+void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag, int ppt,
+              const AngBP* d_abp);
 size_t count_fp_items(const std::vector<AngFP>& afp, int seg);
-size_t count_bp_items(int nr, int nc, int ag);
+size_t count_bp_items(int nr, int nc, int ag, int ppt);
 void carve_state(const Geom& g, RoiState& st, char* blk);
 tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, float* xb, float* xt,
                      const Plan& P, hipStream_t s, std::vector<char*>& allocs, Staging& stg);

@@ -32,6 +32,7 @@ double now_ms() {
 // Fixed launch shape for served slots (see the note at the top of the file).
 constexpr int kServeSeg = 2;
 constexpr int kServeAG = 2;
+constexpr int kServePPT = 2;
 }  // namespace
 
 bool on_serve_thread() { return t_serve; }
@@ -284,7 +285,7 @@ void scheduler(tomo_ctx* ctx) {
             std::vector<Job> jobs;
             std::vector<Item> fi, bi;
             int th, tw;
-            bp_tile(kServeAG, &th, &tw);
+            bp_tile(kServeAG, kServePPT, &th, &tw);
             for (size_t q = 0; q < slots.size(); ++q) {
                 Slot& sl = *slots[q];
                 const Geom& g = ctx->geoms[sl.sino->gid];
@@ -294,7 +295,8 @@ void scheduler(tomo_ctx* ctx) {
                 J.parity0 = sl.parity0;
                 jobs.push_back(J);
                 fp_items(fi, (int)q, sl.st.plan.afp, kServeSeg, sl.st.d_afp);
-                bp_items(bi, (int)q, sl.st.ext.rows, sl.st.ext.cols, kServeAG, sl.st.d_abp);
+                bp_items(bi, (int)q, sl.st.ext.rows, sl.st.ext.cols, kServeAG, kServePPT,
+                         sl.st.d_abp);
             }
             Meta m;
             const size_t o_j = m.add(jobs.data(), jobs.size() * sizeof(Job));
@@ -326,7 +328,7 @@ void scheduler(tomo_ctx* ctx) {
         for (int t = 0; t < tick && e == hipSuccess; ++t) {
             const int stp = (int)(S.step & 0x3fffffff);
             e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream);
-            if (e == hipSuccess) e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, S.stream);
+            if (e == hipSuccess) e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, kServePPT, S.stream);
             S.step++;
         }
         for (auto& sl : slots) sl->it += tick;
