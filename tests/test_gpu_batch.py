@@ -6,6 +6,8 @@ are compared with stored oracle results (tests/golden/make_golden.py) at the
 """
 
 import os
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -31,6 +33,17 @@ def _golden(name):
     return np.load(path)
 
 
+def _sino_in_subprocess(name, tmpdir):
+    """Generate the workload's sinogram in a fresh process (the generator forks
+    worker processes, which must not inherit this process's GPU state)."""
+    path = os.path.join(str(tmpdir), f"{name}_sino.npy")
+    code = ("import sys, numpy; sys.path.insert(0, %r); import synth; "
+            "numpy.save(%r, synth.make_inputs(%r, with_image=False)['sino'])"
+            % (os.path.dirname(HERE), path, name))
+    subprocess.run([sys.executable, "-c", code], check=True, timeout=600)
+    return np.load(path)
+
+
 @pytest.fixture(scope="module")
 def ctx():
     from paper_1604_02292_amd import Context
@@ -40,21 +53,21 @@ def ctx():
 
 
 @pytest.mark.parametrize("name", ["c3", "c4"])
-def test_batched_workload_sampled_parity(ctx, name):
+def test_batched_workload_sampled_parity(ctx, name, tmp_path_factory):
     from paper_1604_02292_amd import make_params
     gold = _golden(name)
     print(f"[batch {name}] generating inputs", flush=True)
-    d = synth.make_inputs(name, with_image=False)
-    cfg = d["cfg"]
+    sino_np = _sino_in_subprocess(name, tmp_path_factory.mktemp(name))
+    cfg = synth.workload(name)
     g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
     rois = synth.roi_list(name)
-    sampled = {int(k.split("_")[1]) for k in gold.files if k.startswith("x_")}
+    sampled = {int(k[2:]) for k in gold.files if k.startswith("x_") and k[2:].isdigit()}
     params, outs = [], []
     for i, (r0, c0, rr, cc, m) in enumerate(rois):
         s = float(gold[f"sigma_{i}"]) if i in sampled else 0.0
         params.append(make_params((r0, c0, rr, cc), m, "cp", cfg["lam"], cfg["iters"], s, s))
         outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
-    sino = torch.from_numpy(d["sino"].astype(np.float32)).cuda()
+    sino = torch.from_numpy(sino_np.astype(np.float32)).cuda()
     print(f"[batch {name}] solving {len(rois)} ROIs in one batch", flush=True)
     ctx.roi_solve_batch(g, sino, params, outs)
     torch.cuda.synchronize()
