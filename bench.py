@@ -223,7 +223,19 @@ def main():
                     help="explicit CP step for --only legs, skipping the power iteration")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes for input generation (0 = one per core, at most 16)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 5 times (the "
+                         "reference kernel for scaling HBM traffic counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "ROI solves are independent and would be sharded across GPUs without "

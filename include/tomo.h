@@ -211,10 +211,12 @@ tomo_status tomo_serving_config(tomo_ctx* ctx, int32_t max_slots, int32_t iters_
 tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
 
 /* Kernel launch shape knobs (autotuner hooks): FP segments per ray (1, 2, 4), BP angle
- * groups per pixel (1, 2, 4) and BP pixels per thread (1, 2); 0 = choose automatically
- * from the problem size.  Results agree to FP32 rounding across shapes. */
+ * groups per pixel (1, 2, 4), BP pixels per thread (1, 2) and the order in which
+ * work items are dealt to the chip's 8 XCDs (1: one contiguous eighth of the
+ * item list per XCD, 2: round-robin); 0 = choose automatically from the problem.
+ * Results agree to FP32 rounding across shapes.  Errors: EINVAL. */
 tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups,
-                            int32_t bp_pixels_per_thread);
+                            int32_t bp_pixels_per_thread, int32_t xcd_order);
 
 /* Algorithmic work: the exact number of nonzeros of W_L for `region` (the
  * pixel-ray pairs with w > 0, counted in FP64 on the host from the entry

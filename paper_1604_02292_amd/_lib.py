@@ -53,7 +53,7 @@ SIGNATURES = {
     "roi_submit": (C.c_int, [_P, _I, C.POINTER(roi_params), _P, C.POINTER(C.c_uint64)]),
     "roi_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_float)]),
     "tomo_serving_config": (C.c_int, [_P, _I, _I]),
-    "tomo_set_launch": (C.c_int, [_P, _I, _I, _I]),
+    "tomo_set_launch": (C.c_int, [_P, _I, _I, _I, _I]),
     "tomo_set_graphs": (C.c_int, [_P, C.c_int]),
     "tomo_roi_nnz": (C.c_int, [_P, _I, tomo_rect, C.POINTER(C.c_int64)]),
     "tomo_kernel_timing": (C.c_int, [_P, C.c_int]),

@@ -36,6 +36,7 @@ LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long tot
     if (ctx->fp_seg) L.seg = ctx->fp_seg;
     if (ctx->bp_ag) L.ag = ctx->bp_ag;
     if (ctx->bp_ppt) L.ppt = ctx->bp_ppt;
+    if (ctx->xcd_order) L.contig = ctx->xcd_order == 1;
     return L;
 }
 
@@ -389,7 +390,11 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     float* rbuf = nullptr;
     const bool global_resid = !reg && band_sum > g.nd;
 
-    const LaunchCfg L = choose_launch(ctx, rays, pix);
+    LaunchCfg L = choose_launch(ctx, rays, pix);
+    // Many jobs of uneven cost: deal items round-robin over the XCDs so every
+    // XCD gets an equal share of each job (contiguous eighths of the item list
+    // can differ in cost by half).
+    if (!ctx->xcd_order && count > 1) L.contig = 0;
     int th, tw;
     bp_tile(L.ag, L.ppt, &th, &tw);
 
@@ -536,11 +541,14 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     for (auto& r : R) CK(launch_fill((float*)r.block, r.state_floats, 0.f, s));
 
     // Iteration jobs; ROIs ordered by decreasing iteration count so that the
-    // work items of the still-running ROIs always form a prefix of the list.
+    // work items of the still-running ROIs always form a prefix of the list,
+    // and larger regions first within a count (their longer items start early).
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return R[a].prm.iters > R[b].prm.iters; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (R[a].prm.iters != R[b].prm.iters) return R[a].prm.iters > R[b].prm.iters;
+        return (long long)R[a].ext.rows * R[a].ext.cols > (long long)R[b].ext.rows * R[b].ext.cols;
+    });
     std::vector<Job> jobs(count);
     std::vector<Item> fi, bi;
     std::vector<int> fi_end(count), bi_end(count);
@@ -576,9 +584,12 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
                 e2 = timing_event(ctx);
                 if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
             }
-            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, st)) != hipSuccess) return e;
+            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, st, L.contig)) != hipSuccess)
+                return e;
             if (timed && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
-            if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, st)) != hipSuccess) return e;
+            if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, st, L.contig)) !=
+                hipSuccess)
+                return e;
             if (timed) {
                 if ((e = hipEventRecord(e2, st)) != hipSuccess) return e;
                 ctx->ev_pending.emplace_back(e0, e1, 0);
@@ -607,9 +618,10 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
             hipError_t le = hipSuccess;
             for (int q = 0; q < kReps && le == hipSuccess; ++q)
                 le = kind == 0 ? launch_fp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_fi),
-                                           fi_end[count - 1], q, L.seg, ctx->cap_stream)
+                                           fi_end[count - 1], q, L.seg, ctx->cap_stream, L.contig)
                                : launch_bp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_bi),
-                                           bi_end[count - 1], q, L.ag, L.ppt, ctx->cap_stream);
+                                           bi_end[count - 1], q, L.ag, L.ppt, ctx->cap_stream,
+                                           L.contig);
             const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &gr);
             CK(le);
             CK(ce);
@@ -1210,14 +1222,17 @@ tomo_status roi_step_size(tomo_ctx* ctx, int32_t geom, tomo_rect ext, float* sig
 }
 
 tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups,
-                            int32_t bp_pixels_per_thread) {
+                            int32_t bp_pixels_per_thread, int32_t xcd_order) {
     if (!ctx) return TOMO_EINVAL;
     auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
-    if (!ok(fp_segments) || !ok(bp_groups) || bp_pixels_per_thread < 0 || bp_pixels_per_thread > 2)
-        return fail(ctx, TOMO_EINVAL, "launch knobs: segments/groups in {0,1,2,4}, pixels in {0,1,2}");
+    if (!ok(fp_segments) || !ok(bp_groups) || bp_pixels_per_thread < 0 ||
+        bp_pixels_per_thread > 2 || xcd_order < 0 || xcd_order > 2)
+        return fail(ctx, TOMO_EINVAL, "launch knobs: segments/groups in {0,1,2,4}, pixels in "
+                    "{0,1,2}, xcd order in {0,1,2}");
     ctx->fp_seg = fp_segments;
     ctx->bp_ag = bp_groups;
     ctx->bp_ppt = bp_pixels_per_thread;
+    ctx->xcd_order = xcd_order;
     return TOMO_OK;
 }
 

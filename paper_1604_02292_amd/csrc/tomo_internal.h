@@ -35,11 +35,14 @@ static_assert(sizeof(AngFP) == 48, "AngFP layout");
 //   max(0, A - f B) = B max(0, r - f)   and   max(0, (A - B) + f B) = B max(0, f + r - 1),
 // r = A / B = m / spacing.  Band arrays read by the backprojector store B * y, so
 // the kernel only evaluates max(0, r - f) and max(0, f + rm1), rm1 = r - 1.
+// The FP64 terms place a tile's reference point; the FP32 copies of cu and su
+// carry the small offsets of the tile's pixels from it.
 struct AngBP {
-    double cu, su, u0;
-    float r, rm1;
+    float cu, su, r, rm1;     // FP32: read as one 16-byte scalar load per angle
+    double cud, sud, u0;      // FP64: per-tile anchors
+    double pad;
 };
-static_assert(sizeof(AngBP) == 32, "AngBP layout");
+static_assert(sizeof(AngBP) == 48, "AngBP layout");
 
 enum FpMode : int32_t {
     FP_STORE = 0,            // gout[k][i] = fp (on-detector bins of the band)
@@ -99,10 +102,12 @@ struct Item {
 static_assert(sizeof(Item) == 32, "Item layout");
 
 // Launchers (tomo_kernels.hip).
+// contiguous = 1: each XCD runs one contiguous eighth of the items (L2
+// locality for many small jobs); 0: item b runs on XCD b mod 8 (balanced).
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
-                     hipStream_t s);
+                     hipStream_t s, int contiguous = 1);
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
-                     int ppt, hipStream_t s);
+                     int ppt, hipStream_t s, int contiguous = 1);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int tp, float v,
                               hipStream_t s);

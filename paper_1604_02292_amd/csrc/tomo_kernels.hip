@@ -19,11 +19,12 @@ namespace tomo {
 namespace {
 
 // Logical work item for hardware block b.  The grid is a multiple of 8 and
-// consecutive blocks are dealt round-robin to the 8 XCDs; this mapping gives
-// each XCD a contiguous range of items, so the items of one ROI (adjacent in
-// the list) share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int G) {
-    return (b & 7) * (G >> 3) + (b >> 3);
+// consecutive blocks are dealt round-robin to the 8 XCDs.  With `contiguous`
+// set, XCD x gets the x-th eighth of the item list, so the items of one ROI
+// (adjacent in the list) share that XCD's L2; otherwise item b runs on XCD
+// b mod 8, which balances the XCDs for any mix of item costs.
+__device__ __forceinline__ int xcd_remap(int b, int G, int contiguous) {
+    return contiguous ? (b & 7) * (G >> 3) + (b >> 3) : b;
 }
 
 __device__ __forceinline__ int uniform_int(int v) {
@@ -52,9 +53,21 @@ __device__ __forceinline__ gcfloat* gview(const float* p) { return (gcfloat*)(p)
 // byte offset and a scalar byte offset for the row.  Word 3 is the raw
 // 32-bit-data format of gfx9-family buffer resources.
 typedef float v2f __attribute__((ext_vector_type(2)));
+
+// A tile's per-angle anchor in LDS: FP32 fraction (+ shift) and the integer
+// part as a byte offset into the band row.
+struct Anchor {
+    float f;
+    unsigned i4;
+};
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, size_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
 }
+#if defined(__HIP_DEVICE_COMPILE__)   // distinct from const float* only in the device pass
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(gcfloat* p, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+#endif
 __device__ __forceinline__ v2f load2(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
 }
@@ -70,10 +83,10 @@ __device__ __forceinline__ v2f load2(__amdgpu_buffer_rsrc_t rs, unsigned voff, u
 template <int SEG>
 __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
-                                                 int step) {
+                                                 int step, int contiguous) {
     constexpr int SUBS = 4 / SEG;
     __shared__ float red[SEG > 1 ? 256 : 1];
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
     if (bid >= n_items) return;
     const Item it = cview(items)[bid];
     const CONST_AS Job* J = cview(jobs) + it.job;
@@ -141,21 +154,23 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
         const int s1 = o_lo + (len * (seg + 1)) / SEG;
         const double pj = A.a0 + (double)j * A.aj;
         const float stepf = (float)A.step;
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, (size_t)n_outer * pitch * sizeof(float));
         const unsigned rowb = (unsigned)pitch * 4u;
-        // 32 outer lines per FP64 anchor: pos = I + loc with |loc| <= 34, so the
-        // FP32 part carries a few 1e-6 of a pixel at any grid size.  loc is kept
-        // shifted by +64 so that truncation is floor and fract gives the weight.
+        // Each outer line is read through its own buffer resource whose range is
+        // that line: a lane whose position falls off the padded line gets 0 from
+        // the hardware range check, and the line's first and last entries are
+        // zero padding, so no position clamp is needed.
+        // 32 outer lines per FP64 anchor: pos = I + loc with loc within 64 +- 34,
+        // so the FP32 part carries a few 1e-6 of a pixel at any grid size; the
+        // +64 shift makes truncation a floor and fract the interpolation weight.
         for (int oc = s0; oc < s1; oc += 32) {
             const double p0 = fma((double)oc, A.step, pj);
             const double fl0 = fmin(fmax(floor(p0), -1.0e6), 1.0e6);
             const int I = (int)fl0;
             const float base64 = (float)(p0 - fl0) + 64.f;
-            const float lo = (float)(64 - I);              // padded position 0
-            const float hi = (float)(n_inner + 65 - I);    // padded position n_inner + 1
-            const unsigned ib4 = (unsigned)(I - 64) * 4u;
+            unsigned ib4 = (unsigned)(I - 64) * 4u;
+            asm("" : "+v"(ib4));   // keeps (index << 2) + ib4 a single shift-add
             const int cnt = min(32, s1 - oc);
-            unsigned soff = (unsigned)oc * rowb;
+            gcfloat* line = img + (size_t)oc * pitch;
             int q = 0;
             if (cnt == 32) {
                 // a full chunk: all 32 paired loads issue before the first is used
@@ -163,10 +178,10 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
                 v2f v[32];
 #pragma unroll
                 for (int u = 0; u < 32; ++u) {
-                    const float loc = __builtin_amdgcn_fmed3f(fmaf((float)u, stepf, base64), lo, hi);
+                    const float loc = fmaf((float)u, stepf, base64);
                     f[u] = __builtin_amdgcn_fractf(loc);
-                    const unsigned off = ((unsigned)(int)loc << 2) + ib4;   // in [0, 4 (n_inner+1)]
-                    v[u] = load2(rs, off, soff + (unsigned)u * rowb);
+                    const unsigned off = ((unsigned)loc << 2) + ib4;
+                    v[u] = load2(make_rsrc(line + (size_t)u * pitch, rowb), off, 0);
                 }
 #pragma unroll
                 for (int u = 0; u < 32; ++u) acc += fmaf(f[u], v[u].y - v[u].x, v[u].x);
@@ -178,22 +193,20 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
                 v2f v[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const float loc = __builtin_amdgcn_fmed3f(fmaf((float)u, stepf, b8), lo, hi);
+                    const float loc = fmaf((float)u, stepf, b8);
                     f[u] = __builtin_amdgcn_fractf(loc);
-                    const unsigned off = ((unsigned)(int)loc << 2) + ib4;
-                    v[u] = load2(rs, off, soff + (unsigned)u * rowb);
+                    const unsigned off = ((unsigned)loc << 2) + ib4;
+                    v[u] = load2(make_rsrc(line + (size_t)(q + u) * pitch, rowb), off, 0);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) acc += fmaf(f[u], v[u].y - v[u].x, v[u].x);
-                soff += 8u * rowb;
             }
             for (; q < cnt; ++q) {
-                const float loc = __builtin_amdgcn_fmed3f(fmaf((float)q, stepf, base64), lo, hi);
+                const float loc = fmaf((float)q, stepf, base64);
                 const float f = __builtin_amdgcn_fractf(loc);
-                const unsigned off = ((unsigned)(int)loc << 2) + ib4;
-                const v2f v = load2(rs, off, soff);
+                const unsigned off = ((unsigned)loc << 2) + ib4;
+                const v2f v = load2(make_rsrc(line + (size_t)q * pitch, rowb), off, 0);
                 acc += fmaf(f, v.y - v.x, v.x);
-                soff += rowb;
             }
         }
     }
@@ -254,7 +267,7 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
 template <int AG, int PPT>
 __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
-                                                 int step) {
+                                                 int step, int contiguous) {
     constexpr int P = 256 / AG;              // threads per angle group (a multiple of 64)
     constexpr int TW = (AG == 4) ? 8 : 16;
     constexpr int TH = (P / TW) * PPT;       // pixel rows of the tile
@@ -262,8 +275,12 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     __shared__ float zs0[TH + 1][TW + 1];
     __shared__ float zs1[TH + 1][TW + 1];
     __shared__ float red[PPT][256];
+    // Per-angle anchors of the tile, ANC per pass (AG groups x PA angles).
+    constexpr int ANC = 1024, PA = ANC / AG;
+    constexpr int SHIFT = TW > TH ? TW : TH;
+    __shared__ Anchor anc[ANC];
 
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
     if (bid >= n_items) return;
     const Item it = cview(items)[bid];
     const CONST_AS Job* J = cview(jobs) + it.job;
@@ -280,6 +297,29 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     bool inside[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) inside[q] = (R0 + tr + q < nr) && (c < nc);
+
+    // Tile anchors (FP64): the padded band coordinate of the tile's reference
+    // point (C0 + TW/2, R0 + TH/2) for each angle, split into an integer part kept
+    // as a byte offset and a fraction + SHIFT in FP32.  A pixel's coordinate is
+    // the anchor plus its offset inside the tile, |offset| <= max(TW, TH)/2 * sqrt 2
+    // < SHIFT, so the FP32 value stays positive (truncation = floor) and small.
+    const int na = J->n_angles;
+    const CONST_AS AngBP* tab = cview((const AngBP*)it.tab);
+    const int npass = ((na + AG - 1) / AG + PA - 1) / PA;
+    auto fill_anchors = [&](int pass) {
+        for (int e = t; e < ANC; e += 256) {
+            const int gg = e / PA;
+            const int kk = (na * gg) / AG + pass * PA + e % PA;
+            if (kk < (na * (gg + 1)) / AG) {
+                const double T = fma((double)C0 + 0.5 * TW, tab[kk].cud,
+                                     fma((double)R0 + 0.5 * TH, tab[kk].sud, tab[kk].u0));
+                const double fl = fmin(fmax(floor(T), -1.0e6), 1.0e6);
+                anc[e].f = (float)(T - fl) + (float)SHIFT;
+                anc[e].i4 = (unsigned)((int)fl - SHIFT) * 4u;
+            }
+        }
+    };
+    fill_anchors(0);
 
     // Every load that does not depend on another one is issued here, before the
     // first barrier: the primal values of the own pixels, the xbar tile with its
@@ -372,60 +412,69 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         }
     }
 
+    if (!tv) __syncthreads();   // anchors of the first pass
+
     float acc[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) acc[q] = 0.f;
-    if (inside[0]) {
-        const double lcd = (double)c, lrd = (double)(R0 + tr);
-        const int na = J->n_angles;
-        const int k0 = (na * g) / AG, k1 = (na * (g + 1)) / AG;
-        const int bpitch = J->bpitch;
-        const unsigned bpm = (unsigned)(bpitch - 2);
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(J->y, (size_t)na * bpitch * sizeof(float));
-        const unsigned rowb = (unsigned)bpitch * 4u;
-        const CONST_AS AngBP* tab = cview((const AngBP*)it.tab);
+    const int kg0 = (na * g) / AG, kg1 = (na * (g + 1)) / AG;
+    const int bpitch = J->bpitch;
+    const unsigned rowb = (unsigned)bpitch * 4u;
+    gcfloat* yband = gview(J->y);
+    const float dcf = (float)(tc - TW / 2), drf = (float)(tr - TH / 2);
+    for (int pass = 0; pass < npass; ++pass) {
+        if (pass > 0) {
+            __syncthreads();
+            fill_anchors(pass);
+            __syncthreads();
+        }
+        const int ka = kg0 + pass * PA, kb = min(kg1, ka + PA);
+        const Anchor* an = anc + g * PA - ka;
+        if (!inside[0]) continue;
+        // Each band row is read through its own buffer resource whose range is
+        // that row, so a stray coordinate reads 0 instead of a neighbouring row.
         constexpr int UA = 16 / PPT;   // angles per step: 16 paired band loads in flight
-        int k = k0;
-        for (; k + UA <= k1; k += UA) {
+        int k = ka;
+        for (; k + UA <= kb; k += UA) {
             float f[UA][PPT];
             v2f yv[UA][PPT];
 #pragma unroll
             for (int u = 0; u < UA; ++u) {
-                const AngBP a = tab[k + u];
-                double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
+                const Anchor A = an[k + u];
+                const __amdgpu_buffer_rsrc_t rs = make_rsrc(yband + (size_t)(k + u) * bpitch, rowb);
+                float loc = fmaf(dcf, tab[k + u].cu, fmaf(drf, tab[k + u].su, A.f));
 #pragma unroll
                 for (int q = 0; q < PPT; ++q) {
-                    if (q) uu += a.su;
-                    // uu >= 1 inside the band; the unsigned clamp keeps any stray
-                    // index inside the row (a wrong value, never a fault)
-                    const unsigned i = min((unsigned)(int)uu, bpm);
-                    f[u][q] = (float)__builtin_amdgcn_fract(uu);
-                    yv[u][q] = load2(rs, i << 2, (unsigned)(k + u) * rowb);
+                    if (q) loc += tab[k + u].su;
+                    f[u][q] = __builtin_amdgcn_fractf(loc);
+                    yv[u][q] = load2(rs, ((unsigned)loc << 2) + A.i4, 0);
                 }
             }
 #pragma unroll
             for (int u = 0; u < UA; ++u) {
-                const AngBP a = tab[k + u];
+                const float r = tab[k + u].r, rm1 = tab[k + u].rm1;
 #pragma unroll
                 for (int q = 0; q < PPT; ++q) {
-                    const float w0 = fmaxf(0.f, a.r - f[u][q]);
-                    const float w1 = fmaxf(0.f, f[u][q] + a.rm1);
+                    // clamp to [0, 1] == max(0, .) here: r <= 1 and f >= 0
+                    const float w0 = __builtin_amdgcn_fmed3f(r - f[u][q], 0.f, 1.f);
+                    const float w1 = __builtin_amdgcn_fmed3f(f[u][q] + rm1, 0.f, 1.f);
                     acc[q] = fmaf(w0, yv[u][q].x, acc[q]);
                     acc[q] = fmaf(w1, yv[u][q].y, acc[q]);
                 }
             }
         }
-        for (; k < k1; ++k) {
-            const AngBP a = tab[k];
-            double uu = fma(lcd, a.cu, fma(lrd, a.su, a.u0));
+        for (; k < kb; ++k) {
+            const Anchor A = an[k];
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(yband + (size_t)k * bpitch, rowb);
+            const float r = tab[k].r, rm1 = tab[k].rm1;
+            float loc = fmaf(dcf, tab[k].cu, fmaf(drf, tab[k].su, A.f));
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
-                if (q) uu += a.su;
-                const unsigned i = min((unsigned)(int)uu, bpm);
-                const float f = (float)__builtin_amdgcn_fract(uu);
-                const v2f yv = load2(rs, i << 2, (unsigned)k * rowb);
-                const float w0 = fmaxf(0.f, a.r - f);
-                const float w1 = fmaxf(0.f, f + a.rm1);
+                if (q) loc += tab[k].su;
+                const float f = __builtin_amdgcn_fractf(loc);
+                const v2f yv = load2(rs, ((unsigned)loc << 2) + A.i4, 0);
+                const float w0 = __builtin_amdgcn_fmed3f(r - f, 0.f, 1.f);
+                const float w1 = __builtin_amdgcn_fmed3f(f + rm1, 0.f, 1.f);
                 acc[q] = fmaf(w0, yv.x, acc[q]);
                 acc[q] = fmaf(w1, yv.y, acc[q]);
             }
@@ -671,23 +720,24 @@ inline unsigned pad8(int n) { return (unsigned)((n + 7) & ~7); }
 }  // namespace
 
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
-                     hipStream_t s) {
+                     hipStream_t s, int contiguous) {
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items)), block(256);
     switch (segments) {
-        case 1: hipLaunchKernelGGL(fp_kernel<1>, grid, block, 0, s, jobs, items, n_items, step); break;
-        case 2: hipLaunchKernelGGL(fp_kernel<2>, grid, block, 0, s, jobs, items, n_items, step); break;
-        default: hipLaunchKernelGGL(fp_kernel<4>, grid, block, 0, s, jobs, items, n_items, step); break;
+        case 1: hipLaunchKernelGGL(fp_kernel<1>, grid, block, 0, s, jobs, items, n_items, step, contiguous); break;
+        case 2: hipLaunchKernelGGL(fp_kernel<2>, grid, block, 0, s, jobs, items, n_items, step, contiguous); break;
+        default: hipLaunchKernelGGL(fp_kernel<4>, grid, block, 0, s, jobs, items, n_items, step, contiguous); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
-                     int ppt, hipStream_t s) {
+                     int ppt, hipStream_t s, int contiguous) {
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items)), block(256);
 #define TOMO_BP(AGV, PPTV) \
-    hipLaunchKernelGGL((bp_kernel<AGV, PPTV>), grid, block, 0, s, jobs, items, n_items, step)
+    hipLaunchKernelGGL((bp_kernel<AGV, PPTV>), grid, block, 0, s, jobs, items, n_items, step, \
+                       contiguous)
     if (ppt == 2) {
         switch (groups) {
             case 1: TOMO_BP(1, 2); break;

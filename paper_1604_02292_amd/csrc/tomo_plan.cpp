@@ -83,9 +83,12 @@ Plan make_plan(const Geom& g, const Rect& reg, const Rect& bsrc) {
         a.i0 = i0;
         a.bscale = (float)(sp / (m * m));
         AngBP& bp = P.abp[k];
-        bp.cu = c / sp;
-        bp.su = s / sp;
+        std::memset(&bp, 0, sizeof bp);
+        bp.cud = c / sp;
+        bp.sud = s / sp;
         bp.u0 = -D / sp + 1.0;
+        bp.cu = (float)bp.cud;
+        bp.su = (float)bp.sud;
         bp.r = (float)(m / sp);
         bp.rm1 = (float)(m / sp - 1.0);
         P.wmax = std::max(P.wmax, w);

@@ -122,7 +122,7 @@ struct tomo_ctx {
     std::recursive_mutex mu;   // geometry list, caches, registrations
     std::deque<tomo::Geom> geoms;   // deque: references stay valid while serving reads them
     std::map<std::tuple<int, int, int>, float> step_cache;
-    int fp_seg = 0, bp_ag = 0, bp_ppt = 0;
+    int fp_seg = 0, bp_ag = 0, bp_ppt = 0, xcd_order = 0;
     std::map<int, std::unique_ptr<tomo::SinoState>> sinos;
     int next_sino = 1;
     std::unique_ptr<tomo::ServeState> serve;
@@ -173,6 +173,7 @@ struct RoiState {
 
 struct LaunchCfg {
     int seg = 4, ag = 4, ppt = 1;
+    int contig = 1;   // 1: contiguous item ranges per XCD, 0: round-robin items
 };
 
 LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels);

@@ -327,8 +327,10 @@ void scheduler(tomo_ctx* ctx) {
         hipError_t e = hipSuccess;
         for (int t = 0; t < tick && e == hipSuccess; ++t) {
             const int stp = (int)(S.step & 0x3fffffff);
-            e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream);
-            if (e == hipSuccess) e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, kServePPT, S.stream);
+            // slots of uneven size: items dealt round-robin over the XCDs
+            e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream, 0);
+            if (e == hipSuccess)
+                e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, kServePPT, S.stream, 0);
             S.step++;
         }
         for (auto& sl : slots) sl->it += tick;

@@ -195,9 +195,9 @@ class Context:
     def tomo_serving_config(self, max_slots=0, iters_per_tick=0):
         self._check(self.lib.tomo_serving_config(self.h, int(max_slots), int(iters_per_tick)))
 
-    def tomo_set_launch(self, fp_segments=0, bp_groups=0, bp_pixels_per_thread=0):
+    def tomo_set_launch(self, fp_segments=0, bp_groups=0, bp_pixels_per_thread=0, xcd_order=0):
         self._check(self.lib.tomo_set_launch(self.h, int(fp_segments), int(bp_groups),
-                                             int(bp_pixels_per_thread)))
+                                             int(bp_pixels_per_thread), int(xcd_order)))
 
     def tomo_set_graphs(self, enable=True):
         self._check(self.lib.tomo_set_graphs(self.h, int(bool(enable))))
