@@ -35,8 +35,40 @@ PEAK_UPDATES = VALU_LANE_OPS / OPS_PER_UPDATE
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1604_02292_amd", "csrc", "tomo_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def profiled_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summaries (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    reading of the same counter for a plain device copy of known size), or None
+    when no summary matches the kernel source as it is now."""
+    if not os.path.isdir(PROFILES):
+        return None
+    want = kernel_source_hash()
+    for fn in sorted(os.listdir(PROFILES)):
+        if not fn.endswith(".md"):
+            continue
+        with open(os.path.join(PROFILES, fn)) as f:
+            for line in f:
+                if not line.startswith("traffic-json: "):
+                    continue
+                rec = json.loads(line[len("traffic-json: "):])
+                if (rec.get("workload") == workload and rec.get("kernel") == kernel and
+                        rec.get("kernel_source_sha256") == want):
+                    return rec["bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(d, cfg, roi, margin):
@@ -93,8 +125,10 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
                   for r in rois]
         outs = [torch.empty((r[2], r[3]), dtype=torch.float32, device="cuda") for r in rois]
         log(f"batched: inputs ready, {len(rois)} ROIs, {its} iterations")
-        updates = 2 * its * sum(ctx.tomo_roi_nnz(g, ctx.tomo_roi_ext(g, r[:4], r[4]))
-                                          for r in rois)
+        nnz = sum(ctx.tomo_roi_nnz(g, ctx.tomo_roi_ext(g, r[:4], r[4])) for r in rois)
+        updates = 2 * its * nnz
+        best, t_fp, t_bp = ctx.tomo_autotune(g, sino, params, outs, x_ext=xe)
+        log(f"batched: autotune {best} (fp {1e3 * t_fp:.1f} us, bp {1e3 * t_bp:.1f} us per launch)")
         for _ in range(2):   # step sizes, then the graph capture
             ctx.roi_solve_batch(g, sino, params, outs, x_ext=xe)
         torch.cuda.synchronize()
@@ -103,9 +137,11 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
             ctx.roi_solve_batch(g, sino, params, outs, x_ext=xe)
         torch.cuda.synchronize()
         t_batch = (time.perf_counter() - t0) / reps
+        kern = {"launch": best, "fp_us": 1e3 * t_fp, "bp_us": 1e3 * t_bp,
+                "fp_updates_per_s": nnz / (t_fp * 1e-3), "bp_updates_per_s": nnz / (t_bp * 1e-3)}
         if not compare:
             return {"roi_solves_per_s": len(rois) / t_batch, "ms_per_batch": 1e3 * t_batch,
-                    "updates_per_s": updates / t_batch}
+                    "updates_per_s": updates / t_batch, **kern}
         one = [torch.empty_like(o) for o in outs]
         for p, o in zip(params, one):   # warm shapes
             ctx.roi_solve(g, sino, p, o, x_ext=xe)
@@ -124,57 +160,68 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
                 "one_at_a_time_roi_solves_per_s": len(rois) / t_seq,
                 "speedup_vs_one_at_a_time": t_seq / t_batch,
                 "updates_per_s": updates / t_batch,
-                "max_rel_diff_batch_vs_single": diff}
+                "max_rel_diff_batch_vs_single": diff, **kern}
     finally:
         ctx.close()
 
 
-def serving_leg(torch, slices, n_req=200, n_warm=64):
+def serving_leg(torch, slices, n_req=200, n_warm=64, fractions=(0.25, 0.5, 0.75, 0.9)):
     """64 resident 2048^2 slices (512 angles x 3072 bins); requests with side
     U{32..512}, margin ceil(side/4), 80% CP-TV / 20% nonnegative SIRT, 100-300
     iterations.  Capacity = completion rate with all requests queued at once;
-    latency = submit-to-done at Poisson arrivals of half that rate; plain =
-    the same requests solved one at a time with roi_solve."""
+    latency = submit-to-done at Poisson arrivals of the given fractions of that
+    rate; plain = the same requests solved one at a time with roi_solve; small
+    budget = the capacity run again with a workspace that holds only a few
+    slots next to two resident slices, so admission by HBM budget binds."""
     import synth
     from paper_1604_02292_amd import Context, make_params
     cfg = synth.workload("c5")
+
+    def prm(r):
+        return make_params(r["rect"], r["margin"], r["method"], r["lam"], r["iters"])
+
+    def run(ctx, sids, reqs, open_loop):
+        outs = [torch.empty((r["rect"][2], r["rect"][3]), device="cuda") for r in reqs]
+        lat, pend = [], {}
+        i = 0
+        t_start = time.perf_counter()
+        while i < len(reqs) or pend:
+            now = time.perf_counter() - t_start
+            while i < len(reqs) and (not open_loop or reqs[i]["t"] <= now):
+                t = ctx.roi_submit(sids[reqs[i]["slice"] % len(sids)], prm(reqs[i]), outs[i])
+                pend[t] = i
+                i += 1
+            for t in list(pend):
+                done, ms = ctx.roi_poll(t)
+                if done:
+                    lat.append(ms)
+                    del pend[t]
+            time.sleep(0.0002)
+        return time.perf_counter() - t_start, lat, outs
+
+    def pct(v, q):
+        return float(np.percentile(v, q))
+
+    sinos = [torch.from_numpy(s_.astype(np.float32)).cuda() for s_ in slices]
     ctx = Context(0, workspace_bytes=12 << 30)
     try:
         g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
-        sinos = [torch.from_numpy(s_.astype(np.float32)).cuda() for s_ in slices]
         t0 = time.perf_counter()
         sids = [ctx.tomo_register_sinogram(g, s_) for s_ in sinos]
         t_reg = time.perf_counter() - t0
-
-        def prm(r):
-            return make_params(r["rect"], r["margin"], r["method"], r["lam"], r["iters"])
-
-        def run(reqs, open_loop):
-            outs = [torch.empty((r["rect"][2], r["rect"][3]), device="cuda") for r in reqs]
-            lat, pend = [], {}
-            i = 0
-            t_start = time.perf_counter()
-            while i < len(reqs) or pend:
-                now = time.perf_counter() - t_start
-                while i < len(reqs) and (not open_loop or reqs[i]["t"] <= now):
-                    t = ctx.roi_submit(sids[reqs[i]["slice"]], prm(reqs[i]), outs[i])
-                    pend[t] = i
-                    i += 1
-                for t in list(pend):
-                    done, ms = ctx.roi_poll(t)
-                    if done:
-                        lat.append(ms)
-                        del pend[t]
-                time.sleep(0.0002)
-            return time.perf_counter() - t_start, lat, outs
-
-        run(synth.serving_requests(n_warm, 1.0, seed_offset=1), False)
+        run(ctx, sids, synth.serving_requests(n_warm, 1.0, seed_offset=1), False)
         reqs = synth.serving_requests(n_req, 1.0, seed_offset=2)
-        t_cap, lat_cap, outs = run(reqs, False)
+        t_cap, lat_cap, outs = run(ctx, sids, reqs, False)
         cap = n_req / t_cap
-        qps = 0.5 * cap
-        reqs_open = synth.serving_requests(n_req, qps, seed_offset=3)
-        t_open, lat_open, _ = run(reqs_open, True)
+        sweep = []
+        for k, fr in enumerate(fractions):
+            reqs_open = synth.serving_requests(n_req, fr * cap, seed_offset=3 + k)
+            t_open, lat_open, _ = run(ctx, sids, reqs_open, True)
+            sweep.append({"fraction_of_capacity": fr, "offered_qps": fr * cap,
+                          "achieved_qps": n_req / t_open, "p50_ms": pct(lat_open, 50),
+                          "p99_ms": pct(lat_open, 99)})
+            log(f"serving: {fr:.2f} x capacity ({fr * cap:.1f} req/s): p50 {pct(lat_open, 50):.1f} "
+                f"ms p99 {pct(lat_open, 99):.1f} ms")
         # plain one-at-a-time solves of the capacity requests (same exterior estimates)
         xes = {}
         for r in reqs:
@@ -191,20 +238,34 @@ def serving_leg(torch, slices, n_req=200, n_warm=64):
         t_plain = time.perf_counter() - t0
         diff = max(float((a - b).abs().max() / (b.abs().max() + 1e-30))
                    for a, b in zip(outs, plain_outs))
-        log(f"serving: register {t_reg:.2f}s; capacity {cap:.1f} req/s; open loop at {qps:.1f} "
-            f"req/s: p50 {np.percentile(lat_open, 50):.1f} ms p99 {np.percentile(lat_open, 99):.1f} "
-            f"ms; plain {n_req / t_plain:.1f} req/s")
-        return {"workload": "serve-64x2048-a512: 64 resident slices, side U{32..512}, 80% CP-TV / "
-                            "20% SIRT, 100-300 its",
-                "capacity_solves_per_s": cap, "offered_qps": qps,
-                "p50_ms": float(np.percentile(lat_open, 50)),
-                "p99_ms": float(np.percentile(lat_open, 99)),
-                "saturated_p50_ms": float(np.percentile(lat_cap, 50)),
-                "saturated_p99_ms": float(np.percentile(lat_cap, 99)),
-                "one_at_a_time_solves_per_s": n_req / t_plain,
-                "requests": n_req, "max_rel_diff_served_vs_plain": diff}
+        del xes
     finally:
         ctx.close()
+    # small HBM budget: two resident slices plus room for a few slots
+    small = (2 * 60 << 20) + (96 << 20)
+    ctx = Context(0, workspace_bytes=small)
+    try:
+        g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+        sids = [ctx.tomo_register_sinogram(g, s_) for s_ in sinos[:2]]
+        reqs_small = synth.serving_requests(n_req // 2, 1.0, seed_offset=9)
+        t_small, lat_small, _ = run(ctx, sids, reqs_small, False)
+        peak = ctx.tomo_workspace_usage()
+    finally:
+        ctx.close()
+    mid = sweep[min(1, len(sweep) - 1)]
+    log(f"serving: register {t_reg:.2f}s; capacity {cap:.1f} req/s; plain {n_req / t_plain:.1f} "
+        f"req/s; {small >> 20} MiB budget: {len(reqs_small) / t_small:.1f} req/s")
+    return {"workload": "serve-64x2048-a512: 64 resident slices, side U{32..512}, 80% CP-TV / "
+                        "20% SIRT, 100-300 its",
+            "capacity_solves_per_s": cap, "offered_qps": mid["offered_qps"],
+            "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "latency_sweep": sweep,
+            "saturated_p50_ms": pct(lat_cap, 50), "saturated_p99_ms": pct(lat_cap, 99),
+            "one_at_a_time_solves_per_s": n_req / t_plain,
+            "requests": n_req, "max_rel_diff_served_vs_plain": diff,
+            "small_budget": {"workspace_mib": small >> 20, "resident_slices": 2,
+                             "capacity_solves_per_s": len(reqs_small) / t_small,
+                             "p50_ms": pct(lat_small, 50), "p99_ms": pct(lat_small, 99),
+                             "workspace_usage": peak}}
 
 
 def main():
@@ -274,6 +335,10 @@ def main():
     ext = ctx.tomo_roi_ext(g, roi, margin)
     nnz = ctx.tomo_roi_nnz(g, ext)
 
+    # one-time plan step (like an FFT plan): time every launch shape of the two
+    # projector kernels on this problem and keep the fastest for its class
+    best, t_fp, t_bp = ctx.tomo_autotune(g, sino, [prm], [torch.empty_like(out)])
+    log(f"autotune: {best} (fp {1e3 * t_fp:.2f} us, bp {1e3 * t_bp:.2f} us per launch)")
     for _ in range(max(2, args.warmup)):   # the second solve captures the iteration graph
         ctx.roi_solve(g, sino, prm, out)
     torch.cuda.synchronize()
@@ -315,9 +380,11 @@ def main():
         f"({bp_rate / 1e9:.1f} Gupd/s); nnz/launch {nnz}")
     dom_bp = ms_bp >= ms_fp
     rate = bp_rate if dom_bp else fp_rate
-    roofline = {"bound": "alu", "kernel": "bp_kernel" if dom_bp else "fp_kernel",
+    kname = "bp_kernel" if dom_bp else "fp_kernel"
+    roofline = {"bound": "alu", "kernel": kname,
                 "achieved": rate / 1e9, "peak": PEAK_UPDATES / 1e9, "unit": "Gupdate/s",
-                "frac": rate / PEAK_UPDATES, "traffic": None,
+                "frac": rate / PEAK_UPDATES,
+                "traffic": profiled_traffic("single-roi-1024", kname),
                 "avg_launch_us": bp_us if dom_bp else fp_us, "updates_per_launch": nnz}
     res = {
         "metric": "ROI solves/s (single 128^2 ROI, 300 CP-TV iterations, FBP exterior)",
@@ -327,7 +394,7 @@ def main():
         "data": "synthetic (seeded random-ellipse phantom, exact line integrals, Poisson noise)",
         "config": {"workload": "single-roi-1024: 1024^2 grid, 128 angles, 1536 bins, "
                                "128^2 ROI + 32 px margin, CP-TV lambda 0.02 + nonneg, 300 its",
-                   "extended_roi": list(ext)},
+                   "extended_roi": list(ext), "launch": best},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "fp_updates_per_s": fp_rate, "bp_updates_per_s": bp_rate,
         "roofline": roofline,

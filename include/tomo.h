@@ -210,13 +210,46 @@ tomo_status tomo_serving_config(tomo_ctx* ctx, int32_t max_slots, int32_t iters_
  * same arguments, same results).  enable = 0 always launches eagerly. */
 tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
 
-/* Kernel launch shape knobs (autotuner hooks): FP segments per ray (1, 2, 4), BP angle
- * groups per pixel (1, 2, 4), BP pixels per thread (1, 2) and the order in which
- * work items are dealt to the chip's 8 XCDs (1: one contiguous eighth of the
- * item list per XCD, 2: round-robin); 0 = choose automatically from the problem.
- * Results agree to FP32 rounding across shapes.  Errors: EINVAL. */
-tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups,
-                            int32_t bp_pixels_per_thread, int32_t xcd_order);
+/* Kernel launch shape of the two projector kernels.  Every field 0 = choose
+ * automatically (from an autotuned entry for the problem's shape class when
+ * tomo_autotune has measured one, else from the problem size).
+ *   fp_segments           forward projector: waves per ray, 1, 2 or 4
+ *   fp_xcd_order          order in which forward-projector work items are dealt
+ *                         to the chip's 8 XCDs: 1 = one contiguous eighth of the
+ *                         item list per XCD (L2 locality), 2 = round-robin
+ *   bp_variant            backprojector: 1 = direct band reads from memory,
+ *                         2 = band windows staged in LDS per block of angles
+ *   bp_groups             backprojector angle groups per pixel, 1, 2 or 4
+ *                         (variant 2 always uses 1)
+ *   bp_pixels_per_thread  1 or 2
+ *   bp_xcd_order          as fp_xcd_order, for the backprojector
+ * Results agree to FP32 rounding across shapes; the two variants give
+ * identical results for the same groups and pixels per thread. */
+typedef struct {
+    int32_t fp_segments, fp_xcd_order;
+    int32_t bp_variant, bp_groups, bp_pixels_per_thread, bp_xcd_order;
+} tomo_launch;
+
+/* Force a launch shape for every later call on ctx (NULL = all automatic).
+ * Errors: EINVAL (a field outside the values above). */
+tomo_status tomo_set_launch(tomo_ctx* ctx, const tomo_launch* cfg);
+/* The shape last set with tomo_set_launch.  Errors: EINVAL. */
+tomo_status tomo_get_launch(tomo_ctx* ctx, tomo_launch* cfg);
+
+/* Autotuner: times every forward-projector shape (segments x XCD order) and
+ * every backprojector shape (variant x groups x pixels per thread x XCD
+ * order) on this batch of ROI solves, one iteration each with HIP events
+ * around back-to-back launches, and records the fastest of each for the
+ * batch's shape class (geometry, total extended pixels to within a factor
+ * of 2, one ROI or many).  Later roi_solve / roi_solve_batch calls of that
+ * class use it unless tomo_set_launch forces a shape.  Arguments as for
+ * roi_solve_batch (outs receive the one-iteration results and are then
+ * undefined); best (nullable, host) receives the chosen shape and ms
+ * (nullable, host, 2 floats) the chosen FP and BP launch times in ms.
+ * Synchronizes `hip_stream`.  Errors: as roi_solve_batch. */
+tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                          int32_t count, const roi_params* params, float* const* outs,
+                          void* hip_stream, tomo_launch* best, float* ms);
 
 /* Algorithmic work: the exact number of nonzeros of W_L for `region` (the
  * pixel-ray pairs with w > 0, counted in FP64 on the host from the entry

@@ -30,6 +30,12 @@ class roi_params(C.Structure):
                 ("tau", C.c_float), ("flags", C.c_uint32)]
 
 
+class tomo_launch(C.Structure):
+    _fields_ = [("fp_segments", C.c_int32), ("fp_xcd_order", C.c_int32),
+                ("bp_variant", C.c_int32), ("bp_groups", C.c_int32),
+                ("bp_pixels_per_thread", C.c_int32), ("bp_xcd_order", C.c_int32)]
+
+
 # name -> (restype, argtypes), mirroring include/tomo.h
 _P = C.c_void_p
 _I = C.c_int32
@@ -53,7 +59,10 @@ SIGNATURES = {
     "roi_submit": (C.c_int, [_P, _I, C.POINTER(roi_params), _P, C.POINTER(C.c_uint64)]),
     "roi_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_float)]),
     "tomo_serving_config": (C.c_int, [_P, _I, _I]),
-    "tomo_set_launch": (C.c_int, [_P, _I, _I, _I, _I]),
+    "tomo_set_launch": (C.c_int, [_P, C.POINTER(tomo_launch)]),
+    "tomo_get_launch": (C.c_int, [_P, C.POINTER(tomo_launch)]),
+    "tomo_autotune": (C.c_int, [_P, _I, _P, _P, _I, C.POINTER(roi_params), C.POINTER(_P), _P,
+                                C.POINTER(tomo_launch), C.POINTER(C.c_float)]),
     "tomo_set_graphs": (C.c_int, [_P, C.c_int]),
     "tomo_roi_nnz": (C.c_int, [_P, _I, tomo_rect, C.POINTER(C.c_int64)]),
     "tomo_kernel_timing": (C.c_int, [_P, C.c_int]),

@@ -23,6 +23,17 @@ void bp_tile(int ag, int ppt, int* th, int* tw) {
     *th = (P / *tw) * ppt;
 }
 
+// Overwrite the non-zero fields of k onto L.
+static void apply_knobs(LaunchCfg& L, const tomo_launch& k) {
+    if (k.fp_segments) L.seg = k.fp_segments;
+    if (k.fp_xcd_order) L.cfp = k.fp_xcd_order == 1;
+    if (k.bp_variant) L.staged = k.bp_variant == 2;
+    if (k.bp_groups) L.ag = k.bp_groups;
+    if (k.bp_pixels_per_thread) L.ppt = k.bp_pixels_per_thread;
+    if (k.bp_xcd_order) L.cbp = k.bp_xcd_order == 1;
+    if (L.staged) L.ag = 1;
+}
+
 LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels) {
     LaunchCfg L;
     // Split rays / pixels across more waves while the whole problem is too small
@@ -33,10 +44,35 @@ LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long tot
     // two pixels per thread share the per-angle position work once the problem
     // is large enough that halving the thread count still fills the chip
     L.ppt = total_pixels >= 8 * want ? 2 : 1;
-    if (ctx->fp_seg) L.seg = ctx->fp_seg;
-    if (ctx->bp_ag) L.ag = ctx->bp_ag;
-    if (ctx->bp_ppt) L.ppt = ctx->bp_ppt;
-    if (ctx->xcd_order) L.contig = ctx->xcd_order == 1;
+    // Large problems are bound by the rate of vector-memory gathers: stage the
+    // band in LDS (one angle group, two pixels per thread).  Small ones are
+    // latency-bound: read the band directly, angles split over groups.
+    L.staged = total_pixels >= 4 * want;
+    if (L.staged) {
+        L.ag = 1;
+        L.ppt = 2;
+    }
+    apply_knobs(L, ctx->knobs);
+    return L;
+}
+
+std::tuple<int, int, int> tune_key(int gid, int jobs, long long total_pixels) {
+    int lg = 0;
+    while ((2LL << lg) <= total_pixels) ++lg;   // floor(log2(pixels))
+    return std::make_tuple(gid, lg, jobs > 1 ? 1 : 0);
+}
+
+LaunchCfg choose_launch_for(tomo_ctx* ctx, int gid, int jobs, long long total_rays,
+                            long long total_pixels) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    LaunchCfg L = choose_launch(ctx, total_rays, total_pixels);
+    // Many jobs of uneven cost: deal items round-robin over the XCDs so every
+    // XCD gets an equal share of each job (contiguous eighths of the item list
+    // can differ in cost by half).
+    if (jobs > 1) L.cfp = L.cbp = 0;
+    auto it = ctx->tuned.find(tune_key(gid, jobs, total_pixels));
+    if (it != ctx->tuned.end()) apply_knobs(L, it->second);
+    apply_knobs(L, ctx->knobs);   // forced fields win
     return L;
 }
 
@@ -147,10 +183,16 @@ struct ExtSrc {
 tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, float* xb, float* xt,
                      const Plan& P, hipStream_t s, std::vector<char*>& allocs, Staging& stg) {
     const Geom& g = ctx->geoms[gid];
-    if (g.nd > 8192) return fail(ctx, TOMO_EINVAL, "FBP supports at most 8192 detector bins");
+    if (g.nd > 16384) return fail(ctx, TOMO_EINVAL, "FBP supports at most 16384 detector bins");
     const size_t band_bytes = (size_t)g.na * P.bpitch * sizeof(float);
     int th, tw;
-    const LaunchCfg L = choose_launch(ctx, 0, (long long)g.n * g.n);
+    // the filtered backprojection sums cancel to values far below their terms:
+    // one fixed shape (LDS-staged, one angle group, two pixels per thread) with
+    // compensated sums over the angles
+    LaunchCfg L = choose_launch(ctx, 0, (long long)g.n * g.n);
+    L.staged = 1;
+    L.ag = 1;
+    L.ppt = 2;
     bp_tile(L.ag, L.ppt, &th, &tw);
     std::vector<Item> items;
     Meta m;
@@ -187,7 +229,7 @@ tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, fl
     TOMO_HIP(ctx, launch_fill(band, (size_t)g.na * P.bpitch, 0.f, s));
     TOMO_HIP(ctx, launch_ramp(sino, g.na, g.nd, g.d_taps, J.afp, band, P.bpitch, s));
     TOMO_HIP(ctx, launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
-                            0, L.ag, L.ppt, s));
+                            0, L.ag, L.ppt, s, L.cbp, 1, 1));
     return TOMO_OK;
 }
 
@@ -315,7 +357,8 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
         e = launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_fi), (int)fi.size(), it,
                       L.seg, s);
         if (e == hipSuccess)
-            e = launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_bi), n_part, it, L.ag, L.ppt, s);
+            e = launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_bi), n_part, it, L.ag, L.ppt, s,
+                          L.cbp, L.staged);
         float* nxt = ((it + 1) & 1) ? pr.xb1 : pr.xb0;
         if (e == hipSuccess)
             e = launch_power_normalize(pr.x, nc, nr, nc, pr.part, n_part, nxt, pr.plan.xp, pr.xt,
@@ -334,6 +377,24 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     }
     st.sigma = st.tau = stp;
     return done(TOMO_OK);
+}
+
+// Workspace bytes step_size_for will allocate for st (0 when the step is given
+// or cached): the power iteration's temporary state, tables and item lists.
+size_t step_size_scratch_bytes(tomo_ctx* ctx, int gid, const RoiState& st) {
+    if (st.prm.method != ROI_TV_NONNEG_CP) return 0;
+    if (st.prm.sigma > 0.f && st.prm.tau > 0.f) return 0;
+    const Geom& g = ctx->geoms[gid];
+    const int nr = std::min(g.n, (st.ext.rows + 15) / 16 * 16);
+    const int nc = std::min(g.n, (st.ext.cols + 15) / 16 * 16);
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        if (ctx->step_cache.count(std::make_tuple(gid, nr, nc))) return 0;
+    }
+    const Plan p = make_plan(g, Rect{0, 0, nr, nc}, Rect{0, 0, nr, nc});
+    const size_t tables = (size_t)g.na * (sizeof(AngFP) + sizeof(AngBP)) + sizeof(Job) + 64;
+    const size_t items = (count_fp_items(p.afp, 1) + count_bp_items(nr, nc, 1, 1)) * sizeof(Item);
+    return state_bytes(g, p) + tables + items + 4096;
 }
 
 // The batched solve (one sinogram, many ROIs).  `reg` (optional) is a
@@ -390,11 +451,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     float* rbuf = nullptr;
     const bool global_resid = !reg && band_sum > g.nd;
 
-    LaunchCfg L = choose_launch(ctx, rays, pix);
-    // Many jobs of uneven cost: deal items round-robin over the XCDs so every
-    // XCD gets an equal share of each job (contiguous eighths of the item list
-    // can differ in cost by half).
-    if (!ctx->xcd_order && count > 1) L.contig = 0;
+    const LaunchCfg L = choose_launch_for(ctx, gid, count, rays, pix);
     int th, tw;
     bp_tile(L.ag, L.ppt, &th, &tw);
 
@@ -584,10 +641,11 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
                 e2 = timing_event(ctx);
                 if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
             }
-            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, st, L.contig)) != hipSuccess)
+            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, st, L.cfp)) != hipSuccess)
                 return e;
             if (timed && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
-            if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, st, L.contig)) !=
+            if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, st, L.cbp,
+                               L.staged)) !=
                 hipSuccess)
                 return e;
             if (timed) {
@@ -618,10 +676,10 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
             hipError_t le = hipSuccess;
             for (int q = 0; q < kReps && le == hipSuccess; ++q)
                 le = kind == 0 ? launch_fp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_fi),
-                                           fi_end[count - 1], q, L.seg, ctx->cap_stream, L.contig)
+                                           fi_end[count - 1], q, L.seg, ctx->cap_stream, L.cfp)
                                : launch_bp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_bi),
                                            bi_end[count - 1], q, L.ag, L.ppt, ctx->cap_stream,
-                                           L.contig);
+                                           L.cbp, L.staged);
             const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &gr);
             CK(le);
             CK(ce);
@@ -890,19 +948,23 @@ tomo_status tomo_set_geometry(tomo_ctx* ctx, int32_t n, int32_t n_angles, int32_
     if (!ctx->host_only) {
         tomo_status st = need_gpu(ctx);
         if (st != TOMO_OK) return st;
-        // Ram-Lak taps for sampling interval = spacing, times the spacing of Q = tau (h * p)
-        std::vector<float> taps(n_det, 0.f);
+        // Ram-Lak taps for sampling interval = spacing, times the spacing of Q = tau (h * p),
+        // each as an FP32 pair hi + lo (the FP32 rounding of the tap, then of its
+        // remainder), so the FP32 filter carries the taps to about 1e-14.
+        std::vector<float> taps(2 * (size_t)n_det, 0.f);
         for (int d = 0; d < n_det; ++d) {
             double h = 0.0;
             if (d == 0)
                 h = 0.25;
             else if (d & 1)
                 h = -1.0 / (M_PI * M_PI * (double)d * (double)d);
-            taps[d] = (float)(h / det_spacing);
+            h /= det_spacing;
+            taps[2 * d] = (float)h;
+            taps[2 * d + 1] = (float)(h - (double)taps[2 * d]);
         }
-        char* p = ctx->arena.alloc(n_det * sizeof(float));
+        char* p = ctx->arena.alloc(taps.size() * sizeof(float));
         if (!p) return fail(ctx, TOMO_ENOMEM, "workspace too small for the filter taps");
-        TOMO_HIP(ctx, hipMemcpy(p, taps.data(), n_det * sizeof(float), hipMemcpyHostToDevice));
+        TOMO_HIP(ctx, hipMemcpy(p, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice));
         g.d_taps = (float*)p;
     }
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -1040,7 +1102,7 @@ tomo_status tomo_bp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
     TOMO_HIP(ctx, ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s));
     TOMO_HIP(ctx, launch_band_gather(sino, g.nd, J.afp, g.na, band, P.bpitch, s));
     TOMO_HIP(ctx, launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
-                            0, L.ag, L.ppt, s));
+                            0, L.ag, L.ppt, s, L.cbp, L.staged));
     ctx->arena.free_after(allocs, s);
     return TOMO_OK;
     GUARD_END(ctx)
@@ -1177,6 +1239,103 @@ tomo_status roi_solve_batch(tomo_ctx* ctx, int32_t geom, const float* sino, cons
     GUARD_END(ctx)
 }
 
+tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                          int32_t count, const roi_params* params, float* const* outs,
+                          void* hip_stream, tomo_launch* best, float* ms) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!sino || !params || !outs || count < 1) return fail(ctx, TOMO_EINVAL, "null pointer or count < 1");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<roi_params> p1(params, params + count);
+    long long pix = 0;
+    for (auto& q : p1) {
+        if ((st = validate_params(ctx, *gp, q)) != TOMO_OK) return st;
+        q.iters = 1;
+        const Rect e = extend_rect(Rect{q.roi.row0, q.roi.col0, q.roi.rows, q.roi.cols}, q.margin, gp->n);
+        pix += (long long)e.rows * e.cols;
+    }
+    // Candidates.  Each measurement run times one FP shape and one BP shape
+    // (timing mode 2: 50 back-to-back launches in a graph between two events).
+    std::vector<tomo_launch> fpc, bpc;
+    for (int xo = 1; xo <= 2; ++xo)
+        for (int sg : {1, 2, 4}) {
+            tomo_launch k{};
+            k.fp_segments = sg;
+            k.fp_xcd_order = xo;
+            fpc.push_back(k);
+        }
+    for (int xo = 1; xo <= 2; ++xo) {
+        for (int pp : {1, 2}) {
+            tomo_launch k{};
+            k.bp_variant = 2;
+            k.bp_groups = 1;
+            k.bp_pixels_per_thread = pp;
+            k.bp_xcd_order = xo;
+            bpc.push_back(k);
+            for (int ag : {1, 2, 4}) {
+                k.bp_variant = 1;
+                k.bp_groups = ag;
+                bpc.push_back(k);
+            }
+        }
+    }
+    const tomo_launch saved = ctx->knobs;
+    const int saved_mode = ctx->timing_mode;
+    double best_fp = 1e30, best_bp = 1e30;
+    tomo_launch bf{}, bb{};
+    const size_t runs = std::max(fpc.size(), bpc.size());
+    for (size_t i = 0; i < runs && st == TOMO_OK; ++i) {
+        const tomo_launch& f = fpc[i % fpc.size()];
+        const tomo_launch& b = bpc[i % bpc.size()];
+        tomo_launch k = b;
+        k.fp_segments = f.fp_segments;
+        k.fp_xcd_order = f.fp_xcd_order;
+        ctx->knobs = k;
+        ctx->timing_mode = 2;
+        ctx->t_launches[0] = ctx->t_launches[1] = 0;
+        ctx->t_ms[0] = ctx->t_ms[1] = 0.0;
+        st = solve_batch(ctx, geom, sino, x_ext, nullptr, count, p1.data(), outs, s);
+        if (st == TOMO_OK) {
+            const hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = fail(ctx, TOMO_EHIP, "autotune: %s", hipGetErrorString(e));
+        }
+        if (st != TOMO_OK || ctx->t_launches[0] == 0 || ctx->t_launches[1] == 0) break;
+        const double fms = ctx->t_ms[0] / (double)ctx->t_launches[0];
+        const double bms = ctx->t_ms[1] / (double)ctx->t_launches[1];
+        if (fms < best_fp) {
+            best_fp = fms;
+            bf = f;
+        }
+        if (bms < best_bp) {
+            best_bp = bms;
+            bb = b;
+        }
+    }
+    ctx->knobs = saved;
+    ctx->timing_mode = saved_mode;
+    ctx->t_launches[0] = ctx->t_launches[1] = 0;
+    ctx->t_ms[0] = ctx->t_ms[1] = 0.0;
+    if (st != TOMO_OK) return st;
+    if (best_fp >= 1e30 || best_bp >= 1e30) return fail(ctx, TOMO_EHIP, "autotune: no timing recorded");
+    tomo_launch r = bb;
+    r.fp_segments = bf.fp_segments;
+    r.fp_xcd_order = bf.fp_xcd_order;
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        ctx->tuned[tune_key(geom, count, pix)] = r;
+    }
+    if (best) *best = r;
+    if (ms) {
+        ms[0] = (float)best_fp;
+        ms[1] = (float)best_bp;
+    }
+    return TOMO_OK;
+    GUARD_END(ctx)
+}
+
 tomo_status roi_step_size(tomo_ctx* ctx, int32_t geom, tomo_rect ext, float* sigma_tau) {
     tomo_status st = need_gpu(ctx);
     if (st != TOMO_OK) return st;
@@ -1221,18 +1380,25 @@ tomo_status roi_step_size(tomo_ctx* ctx, int32_t geom, tomo_rect ext, float* sig
     GUARD_END(ctx)
 }
 
-tomo_status tomo_set_launch(tomo_ctx* ctx, int32_t fp_segments, int32_t bp_groups,
-                            int32_t bp_pixels_per_thread, int32_t xcd_order) {
+tomo_status tomo_set_launch(tomo_ctx* ctx, const tomo_launch* cfg) {
     if (!ctx) return TOMO_EINVAL;
+    tomo_launch k{};
+    if (cfg) k = *cfg;
     auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
-    if (!ok(fp_segments) || !ok(bp_groups) || bp_pixels_per_thread < 0 ||
-        bp_pixels_per_thread > 2 || xcd_order < 0 || xcd_order > 2)
+    auto in012 = [](int v) { return v >= 0 && v <= 2; };
+    if (!ok(k.fp_segments) || !ok(k.bp_groups) || !in012(k.bp_pixels_per_thread) ||
+        !in012(k.bp_variant) || !in012(k.fp_xcd_order) || !in012(k.bp_xcd_order))
         return fail(ctx, TOMO_EINVAL, "launch knobs: segments/groups in {0,1,2,4}, pixels in "
-                    "{0,1,2}, xcd order in {0,1,2}");
-    ctx->fp_seg = fp_segments;
-    ctx->bp_ag = bp_groups;
-    ctx->bp_ppt = bp_pixels_per_thread;
-    ctx->xcd_order = xcd_order;
+                    "{0,1,2}, variant and xcd order in {0,1,2}");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->knobs = k;
+    return TOMO_OK;
+}
+
+tomo_status tomo_get_launch(tomo_ctx* ctx, tomo_launch* cfg) {
+    if (!ctx || !cfg) return TOMO_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    *cfg = ctx->knobs;
     return TOMO_OK;
 }
 

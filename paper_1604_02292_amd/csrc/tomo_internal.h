@@ -106,8 +106,13 @@ static_assert(sizeof(Item) == 32, "Item layout");
 // locality for many small jobs); 0: item b runs on XCD b mod 8 (balanced).
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
                      hipStream_t s, int contiguous = 1);
+// staged = 1: band windows staged in LDS (one angle group; throughput shape),
+// 0: direct band reads (any group count; latency shape).  Same results.
+// compensated = 1: compensated sums over angles, staged, groups 1, ppt 2 only
+// (the items must be built for that tiling).
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
-                     int ppt, hipStream_t s, int contiguous = 1);
+                     int ppt, hipStream_t s, int contiguous = 1, int staged = 0,
+                     int compensated = 0);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int tp, float v,
                               hipStream_t s);

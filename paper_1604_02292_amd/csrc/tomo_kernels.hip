@@ -27,6 +27,21 @@ __device__ __forceinline__ int xcd_remap(int b, int G, int contiguous) {
     return contiguous ? (b & 7) * (G >> 3) + (b >> 3) : b;
 }
 
+// Smallest s with s * s > v (compile time).
+constexpr int isqrt_above(int v) {
+    int s = 0;
+    while (s * s <= v) ++s;
+    return s;
+}
+
+// Neumaier's compensated sum: s + c carries s + t with the rounding error of
+// the FP32 addition kept in c (Neumaier 1974, improved Kahan-Babuska sum).
+__device__ __forceinline__ void comp_add(float& s, float& c, float t) {
+    const float u = s + t;
+    c += (fabsf(s) >= fabsf(t)) ? ((s - u) + t) : ((t - u) + s);
+    s = u;
+}
+
 __device__ __forceinline__ int uniform_int(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
@@ -37,9 +52,11 @@ __device__ __forceinline__ int uniform_int(int v) {
 #if defined(__HIP_DEVICE_COMPILE__)
 #define CONST_AS __attribute__((address_space(4)))
 #define GLOBAL_AS __attribute__((address_space(1)))
+#define LDS_AS __attribute__((address_space(3)))
 #else   // the host pass only needs the declarations
 #define CONST_AS
 #define GLOBAL_AS
+#define LDS_AS
 #endif
 typedef const GLOBAL_AS float gcfloat;
 
@@ -54,11 +71,17 @@ __device__ __forceinline__ gcfloat* gview(const float* p) { return (gcfloat*)(p)
 // 32-bit-data format of gfx9-family buffer resources.
 typedef float v2f __attribute__((ext_vector_type(2)));
 
-// A tile's per-angle anchor in LDS: FP32 fraction (+ shift) and the integer
-// part as a byte offset into the band row.
+// A tile's per-angle anchor in LDS: FP32 fraction (+ shift PSH) and the
+// integer part I as the byte offset 4 (I - PSH).
 struct Anchor {
     float f;
-    unsigned i4;
+    int i4;
+};
+// A staged band window in LDS: the anchor fraction (+ shift) and the LDS byte
+// address that band coordinate (integer part of the anchor - shift) maps to.
+struct WinMeta {
+    float f;
+    unsigned base;
 };
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, size_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
@@ -171,6 +194,9 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
             asm("" : "+v"(ib4));   // keeps (index << 2) + ib4 a single shift-add
             const int cnt = min(32, s1 - oc);
             gcfloat* line = img + (size_t)oc * pitch;
+            // two-level sum: the chunk's terms first, then the chunk into the ray
+            // (long rays of a large grid keep a few ulp of the full sum)
+            float cs = 0.f;
             int q = 0;
             if (cnt == 32) {
                 // a full chunk: all 32 paired loads issue before the first is used
@@ -184,7 +210,7 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
                     v[u] = load2(make_rsrc(line + (size_t)u * pitch, rowb), off, 0);
                 }
 #pragma unroll
-                for (int u = 0; u < 32; ++u) acc += fmaf(f[u], v[u].y - v[u].x, v[u].x);
+                for (int u = 0; u < 32; ++u) cs += fmaf(f[u], v[u].y - v[u].x, v[u].x);
                 q = 32;
             }
             for (; q + 8 <= cnt; q += 8) {
@@ -199,15 +225,16 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
                     v[u] = load2(make_rsrc(line + (size_t)(q + u) * pitch, rowb), off, 0);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc += fmaf(f[u], v[u].y - v[u].x, v[u].x);
+                for (int u = 0; u < 8; ++u) cs += fmaf(f[u], v[u].y - v[u].x, v[u].x);
             }
             for (; q < cnt; ++q) {
                 const float loc = fmaf((float)q, stepf, base64);
                 const float f = __builtin_amdgcn_fractf(loc);
                 const unsigned off = ((unsigned)loc << 2) + ib4;
                 const v2f v = load2(make_rsrc(line + (size_t)q * pitch, rowb), off, 0);
-                acc += fmaf(f, v.y - v.x, v.x);
+                cs += fmaf(f, v.y - v.x, v.x);
             }
+            acc += cs;
         }
     }
     if (SEG > 1) {
@@ -264,7 +291,7 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
 // see half-updated values), takes its divergence, then applies the primal
 // prox and the extrapolation to its own pixels.
 // ---------------------------------------------------------------------------
-template <int AG, int PPT>
+template <int AG, int PPT, bool STAGED, bool COMP>
 __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
                                                  int step, int contiguous) {
@@ -277,8 +304,22 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     __shared__ float red[PPT][256];
     // Per-angle anchors of the tile, ANC per pass (AG groups x PA angles).
     constexpr int ANC = 1024, PA = ANC / AG;
-    constexpr int SHIFT = TW > TH ? TW : TH;
+    // Staged band windows: WS entries per angle starting SHIFT below the
+    // anchor; a pixel's offset from the anchor is at most
+    // sqrt((TW/2)^2 + (TH/2)^2) <= 18 bins, so its pair lies inside the window.
+    // In FP32 the anchor fraction carries the smaller shift PSH (> that offset),
+    // which keeps the coordinate positive and its rounding error small.
+    constexpr int SHIFT = 32, WS = 64;
+    constexpr int PSH = isqrt_above((TW / 2) * (TW / 2) + (TH / 2) * (TH / 2)) + 1;
+    static_assert(PSH <= SHIFT, "pixel offsets exceed the window");
+    constexpr int KA = 32 / AG, NW = AG * KA, WPW = NW / 4;   // per stage: angles per group,
+                                                              // windows, windows per wave
+    static_assert(TW * TW + TH * TH <= 36 * 36, "tile too large for the band window");
     __shared__ Anchor anc[ANC];
+    // [guard][buffer 0: NW windows][buffer 1][guard]: stray lanes of ragged tiles
+    // stay inside the guards
+    __shared__ float win[STAGED ? (2 * NW + 2) * WS : 1];
+    __shared__ WinMeta wmeta[2][STAGED ? NW : 1];
 
     const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
     if (bid >= n_items) return;
@@ -300,9 +341,9 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
 
     // Tile anchors (FP64): the padded band coordinate of the tile's reference
     // point (C0 + TW/2, R0 + TH/2) for each angle, split into an integer part kept
-    // as a byte offset and a fraction + SHIFT in FP32.  A pixel's coordinate is
+    // and a fraction + PSH in FP32.  A pixel's coordinate is
     // the anchor plus its offset inside the tile, |offset| <= max(TW, TH)/2 * sqrt 2
-    // < SHIFT, so the FP32 value stays positive (truncation = floor) and small.
+    // < PSH, so the FP32 value stays positive (truncation = floor) and small.
     const int na = J->n_angles;
     const CONST_AS AngBP* tab = cview((const AngBP*)it.tab);
     const int npass = ((na + AG - 1) / AG + PA - 1) / PA;
@@ -314,8 +355,8 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                 const double T = fma((double)C0 + 0.5 * TW, tab[kk].cud,
                                      fma((double)R0 + 0.5 * TH, tab[kk].sud, tab[kk].u0));
                 const double fl = fmin(fmax(floor(T), -1.0e6), 1.0e6);
-                anc[e].f = (float)(T - fl) + (float)SHIFT;
-                anc[e].i4 = (unsigned)((int)fl - SHIFT) * 4u;
+                anc[e].f = (float)(T - fl) + (float)PSH;
+                anc[e].i4 = ((int)fl - PSH) * 4;
             }
         }
     };
@@ -414,14 +455,27 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
 
     if (!tv) __syncthreads();   // anchors of the first pass
 
-    float acc[PPT];
+    float acc[PPT], cacc[PPT];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) acc[q] = 0.f;
-    const int kg0 = (na * g) / AG, kg1 = (na * (g + 1)) / AG;
+    for (int q = 0; q < PPT; ++q) acc[q] = cacc[q] = 0.f;
+    // one pixel-angle term w0 y0 + w1 y1; COMP keeps the sum compensated (the
+    // filtered-backprojection sums cancel to values far below their terms)
+    auto accum = [&](int q, float w0, float y0, float w1, float y1) {
+        if constexpr (COMP) {
+            comp_add(acc[q], cacc[q], fmaf(w0, y0, w1 * y1));
+        } else {
+            acc[q] = fmaf(w0, y0, acc[q]);
+            acc[q] = fmaf(w1, y1, acc[q]);
+        }
+    };
+    const int kg0 = (na * g) / AG, kg1 = (na * (g + 1)) / AG;   // this group's angles
+    const float dcf = (float)(tc - TW / 2), drf = (float)(tr - TH / 2);
+    if constexpr (!STAGED) {
+    // ---- backprojection, direct: every pixel reads its band pair from global
+    // memory (fewest dependent steps: the latency-bound shape) ----
     const int bpitch = J->bpitch;
     const unsigned rowb = (unsigned)bpitch * 4u;
     gcfloat* yband = gview(J->y);
-    const float dcf = (float)(tc - TW / 2), drf = (float)(tr - TH / 2);
     for (int pass = 0; pass < npass; ++pass) {
         if (pass > 0) {
             __syncthreads();
@@ -447,7 +501,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                 for (int q = 0; q < PPT; ++q) {
                     if (q) loc += tab[k + u].su;
                     f[u][q] = __builtin_amdgcn_fractf(loc);
-                    yv[u][q] = load2(rs, ((unsigned)loc << 2) + A.i4, 0);
+                    yv[u][q] = load2(rs, ((unsigned)loc << 2) + (unsigned)A.i4, 0);
                 }
             }
 #pragma unroll
@@ -458,8 +512,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                     // clamp to [0, 1] == max(0, .) here: r <= 1 and f >= 0
                     const float w0 = __builtin_amdgcn_fmed3f(r - f[u][q], 0.f, 1.f);
                     const float w1 = __builtin_amdgcn_fmed3f(f[u][q] + rm1, 0.f, 1.f);
-                    acc[q] = fmaf(w0, yv[u][q].x, acc[q]);
-                    acc[q] = fmaf(w1, yv[u][q].y, acc[q]);
+                    accum(q, w0, yv[u][q].x, w1, yv[u][q].y);
                 }
             }
         }
@@ -472,13 +525,155 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
             for (int q = 0; q < PPT; ++q) {
                 if (q) loc += tab[k].su;
                 const float f = __builtin_amdgcn_fractf(loc);
-                const v2f yv = load2(rs, ((unsigned)loc << 2) + A.i4, 0);
+                const v2f yv = load2(rs, ((unsigned)loc << 2) + (unsigned)A.i4, 0);
                 const float w0 = __builtin_amdgcn_fmed3f(r - f, 0.f, 1.f);
                 const float w1 = __builtin_amdgcn_fmed3f(f + rm1, 0.f, 1.f);
-                acc[q] = fmaf(w0, yv.x, acc[q]);
-                acc[q] = fmaf(w1, yv.y, acc[q]);
+                accum(q, w0, yv.x, w1, yv.y);
             }
         }
+    }
+    } else {
+    // ---- backprojection, staged: band windows in LDS, KA angles per group per
+    // stage, double-buffered; each window is one coalesced 64-entry row read,
+    // and every pixel-angle reads its pair from LDS (the throughput shape) ----
+    const int wv = uniform_int(t >> 6), lane = t & 63;
+    const int bpitch = J->bpitch;
+    const int wsmax = bpitch - WS;           // bpitch >= WS by construction
+    const unsigned rowb = (unsigned)bpitch * 4u;
+    gcfloat* yband = gview(J->y);
+    const __amdgpu_buffer_rsrc_t rs_band = make_rsrc(yband, (size_t)na * bpitch * sizeof(float));
+    LDS_AS float* const wl = (LDS_AS float*)win + WS;
+    const unsigned wl_bytes = (unsigned)(size_t)wl;
+    for (int pass = 0; pass < npass; ++pass) {
+        if (pass > 0) {
+            __syncthreads();
+            fill_anchors(pass);
+            __syncthreads();
+        }
+        // angles of group gg in this pass: [lo(gg), hi(gg)); stage s covers
+        // lo + s KA .. lo + s KA + KA - 1
+        const int span = min(PA, (na + AG - 1) / AG - pass * PA);   // upper bound over groups
+        const int nst = (max(span, 0) + KA - 1) / KA;
+        // Window w of stage st holds angle slot w % KA of group w / KA.  Only the
+        // staged values stay live across a stage; the rest is recomputed at
+        // store time from the anchors (read together, before any is used).
+        auto win_kk = [&](int st, int w, bool* ok) {
+            const int gg = w / KA, j = w % KA;
+            const int lo = (na * gg) / AG + pass * PA;
+            const int hi = min((na * (gg + 1)) / AG, lo + PA);
+            *ok = lo + st * KA + j < hi;
+            return lo + st * KA + j;
+        };
+        auto win_anchors = [&](int st, Anchor* A) {
+#pragma unroll
+            for (int i = 0; i < WPW; ++i) {
+                const int w = wv * WPW + i;
+                A[i] = anc[min((w / KA) * PA + st * KA + w % KA, ANC - 1)];
+            }
+        };
+        float sv[WPW];
+        auto stage_load = [&](int st) {
+            Anchor A[WPW];
+            win_anchors(st, A);
+#pragma unroll
+            for (int i = 0; i < WPW; ++i) {
+                bool ok;
+                const int kk = win_kk(st, wv * WPW + i, &ok);
+                sv[i] = 0.f;
+                if (ok) {   // the window lies inside its band row: ws in [0, bpitch - WS]
+                    const int ws = min(max((uniform_int(A[i].i4) >> 2) + PSH - SHIFT, 0), wsmax);
+                    sv[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                         rs_band, (unsigned)lane * 4u,
+                                                         (unsigned)kk * rowb + (unsigned)ws * 4u, 0));
+                }
+            }
+        };
+        auto stage_store = [&](int st, int buf) {
+            Anchor A[WPW];
+            win_anchors(st, A);
+#pragma unroll
+            for (int i = 0; i < WPW; ++i) {
+                const int w = wv * WPW + i;
+                bool ok;
+                (void)win_kk(st, w, &ok);
+                if (!ok) continue;
+                const int I = (uniform_int(A[i].i4) >> 2) + PSH;
+                const int ws = min(max(I - SHIFT, 0), wsmax);
+                const int slot = (buf * NW + w) * WS;
+                wl[slot + lane] = sv[i];
+                if (lane == 0) {
+                    wmeta[buf][w].f = A[i].f;
+                    wmeta[buf][w].base = wl_bytes + (unsigned)(slot + I - PSH - ws) * 4u;
+                }
+            }
+        };
+        if (nst > 0) {
+            stage_load(0);
+            stage_store(0, 0);
+        }
+        __syncthreads();
+        for (int st = 0; st < nst; ++st) {
+            const int buf = st & 1;
+            if (st + 1 < nst) stage_load(st + 1);   // in flight while this stage computes
+            const int kfirst = kg0 + pass * PA + st * KA;
+            const int nj = max(0, min(KA, min(kg1, kg0 + pass * PA + PA) - kfirst));
+            if (inside[0]) {
+                const WinMeta* wm = wmeta[buf] + g * KA;
+                constexpr int UA = 8 / PPT;   // LDS latency is short: 8 pair reads in flight
+                int j = 0;
+                for (; j + UA <= nj; j += UA) {
+                    float f[UA][PPT];
+                    v2f yv[UA][PPT];
+#pragma unroll
+                    for (int u = 0; u < UA; ++u) {
+                        const WinMeta M = wm[j + u];
+                        const AngBP a = tab[kfirst + j + u];
+                        float loc = fmaf(dcf, a.cu, fmaf(drf, a.su, M.f));
+#pragma unroll
+                        for (int q = 0; q < PPT; ++q) {
+                            if (q) loc += a.su;
+                            f[u][q] = __builtin_amdgcn_fractf(loc);
+                            const LDS_AS float* pp =
+                                (const LDS_AS float*)(size_t)(((unsigned)loc << 2) + M.base);
+                            yv[u][q] = v2f{pp[0], pp[1]};
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < UA; ++u) {
+                        const float r = tab[kfirst + j + u].r, rm1 = tab[kfirst + j + u].rm1;
+#pragma unroll
+                        for (int q = 0; q < PPT; ++q) {
+                            // clamp to [0, 1] == max(0, .) here: r <= 1 and f >= 0
+                            const float w0 = __builtin_amdgcn_fmed3f(r - f[u][q], 0.f, 1.f);
+                            const float w1 = __builtin_amdgcn_fmed3f(f[u][q] + rm1, 0.f, 1.f);
+                            accum(q, w0, yv[u][q].x, w1, yv[u][q].y);
+                        }
+                    }
+                }
+                for (; j < nj; ++j) {
+                    const WinMeta M = wm[j];
+                    const AngBP a = tab[kfirst + j];
+                    float loc = fmaf(dcf, a.cu, fmaf(drf, a.su, M.f));
+#pragma unroll
+                    for (int q = 0; q < PPT; ++q) {
+                        if (q) loc += a.su;
+                        const float f = __builtin_amdgcn_fractf(loc);
+                        const LDS_AS float* pp =
+                            (const LDS_AS float*)(size_t)(((unsigned)loc << 2) + M.base);
+                        const float w0 = __builtin_amdgcn_fmed3f(a.r - f, 0.f, 1.f);
+                        const float w1 = __builtin_amdgcn_fmed3f(f + a.rm1, 0.f, 1.f);
+                        accum(q, w0, pp[0], w1, pp[1]);
+                    }
+                }
+            }
+            if (st + 1 < nst) stage_store(st + 1, (st + 1) & 1);
+            __syncthreads();
+        }
+    }
+    }
+    if constexpr (COMP) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) acc[q] += cacc[q];
     }
     if (AG > 1) {
 #pragma unroll
@@ -655,30 +850,48 @@ __global__ void band_scatter_kernel(const float* __restrict__ band, int bpitch,
 // one detector row as a linear (zero-padded) convolution along the detector,
 // q[i] = taps[0] p[i] + sum_{odd d} taps[d] (p[i-d] + p[i+d]), written (times
 // the angle's B) into the band layout of the receiving backprojection.
+// Ram-Lak filter of one sinogram row, linear (zero outside the detector).  The
+// centre tap and the negative odd taps cancel to a small filtered value, so
+// the sum is compensated and the taps are FP32 pairs hi + lo: the FP32 result
+// then agrees with an exact convolution of the FP32 data to a few ulp.
 __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sino, int n_det,
                                                    const float* __restrict__ taps,
                                                    const AngFP* __restrict__ afp,
                                                    float* __restrict__ band, int bpitch) {
-    extern __shared__ float sh[];
-    float* prow = sh;              // n_det
-    float* htab = sh + n_det;      // n_det
+    extern __shared__ float prow[];   // n_det
     const int k = blockIdx.y;
-    for (int i = threadIdx.x; i < n_det; i += blockDim.x) {
-        prow[i] = sino[(size_t)k * n_det + i];
-        htab[i] = taps[i];
-    }
+    for (int i = threadIdx.x; i < n_det; i += blockDim.x) prow[i] = sino[(size_t)k * n_det + i];
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_det) return;
+    const CONST_AS float* h = cview(taps);   // tap index is uniform: scalar loads
     const int i0 = afp[k].i0, w = afp[k].w;
-    float acc = htab[0] * prow[i];
+    float s = h[0] * prow[i], c = fmaf(h[1], prow[i], fmaf(h[0], prow[i], -s));
+    float lo = 0.f;
     const int dl = i, dr = n_det - 1 - i, dm = min(dl, dr);
     int d = 1;
-    for (; d <= dm; d += 2) acc = fmaf(htab[d], prow[i - d] + prow[i + d], acc);
-    for (int e = d; e <= dl; e += 2) acc = fmaf(htab[e], prow[i - e], acc);
-    for (int e = d; e <= dr; e += 2) acc = fmaf(htab[e], prow[i + e], acc);
+    for (; d <= dm; d += 2) {
+        const float P = prow[i - d] + prow[i + d];
+        const float t = h[2 * d] * P;
+        comp_add(s, c, t);
+        c += fmaf(h[2 * d], P, -t);        // rounding of the product
+        lo = fmaf(h[2 * d + 1], P, lo);    // the taps' low parts
+    }
+    for (int e = d; e <= dl; e += 2) {
+        const float t = h[2 * e] * prow[i - e];
+        comp_add(s, c, t);
+        c += fmaf(h[2 * e], prow[i - e], -t);
+        lo = fmaf(h[2 * e + 1], prow[i - e], lo);
+    }
+    for (int e = d; e <= dr; e += 2) {
+        const float t = h[2 * e] * prow[i + e];
+        comp_add(s, c, t);
+        c += fmaf(h[2 * e], prow[i + e], -t);
+        lo = fmaf(h[2 * e + 1], prow[i + e], lo);
+    }
+    const float q = s + (c + lo);
     const int j = i - i0;
-    if (j >= 0 && j < w) band[(size_t)k * bpitch + 1 + j] = afp[k].bscale * acc;
+    if (j >= 0 && j < w) band[(size_t)k * bpitch + 1 + j] = afp[k].bscale * q;
 }
 
 // Power iteration: v = w / ||w||, ||w|| from the per-tile partial sums (summed
@@ -732,23 +945,28 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
 }
 
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
-                     int ppt, hipStream_t s, int contiguous) {
+                     int ppt, hipStream_t s, int contiguous, int staged, int compensated) {
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items)), block(256);
-#define TOMO_BP(AGV, PPTV) \
-    hipLaunchKernelGGL((bp_kernel<AGV, PPTV>), grid, block, 0, s, jobs, items, n_items, step, \
-                       contiguous)
-    if (ppt == 2) {
+#define TOMO_BP(AGV, PPTV, ST, CO)                                                              \
+    hipLaunchKernelGGL((bp_kernel<AGV, PPTV, ST, CO>), grid, block, 0, s, jobs, items, n_items, \
+                       step, contiguous)
+    if (compensated) {   // one shape only: staged, one group, two pixels per thread
+        TOMO_BP(1, 2, true, true);
+    } else if (staged) {   // one angle group: a stage's windows serve the whole tile
+        if (ppt == 2) TOMO_BP(1, 2, true, false);
+        else TOMO_BP(1, 1, true, false);
+    } else if (ppt == 2) {
         switch (groups) {
-            case 1: TOMO_BP(1, 2); break;
-            case 2: TOMO_BP(2, 2); break;
-            default: TOMO_BP(4, 2); break;
+            case 1: TOMO_BP(1, 2, false, false); break;
+            case 2: TOMO_BP(2, 2, false, false); break;
+            default: TOMO_BP(4, 2, false, false); break;
         }
     } else {
         switch (groups) {
-            case 1: TOMO_BP(1, 1); break;
-            case 2: TOMO_BP(2, 1); break;
-            default: TOMO_BP(4, 1); break;
+            case 1: TOMO_BP(1, 1, false, false); break;
+            case 2: TOMO_BP(2, 1, false, false); break;
+            default: TOMO_BP(4, 1, false, false); break;
         }
     }
 #undef TOMO_BP
@@ -800,7 +1018,7 @@ hipError_t launch_band_scatter(const float* band, int bpitch, const AngFP* afp, 
 
 hipError_t launch_ramp(const float* sino, int n_angles, int n_det, const float* taps,
                        const AngFP* afp, float* band, int bpitch, hipStream_t s) {
-    const size_t lds = (size_t)2 * n_det * sizeof(float);
+    const size_t lds = (size_t)n_det * sizeof(float);
     hipLaunchKernelGGL(ramp_kernel, dim3((n_det + 255) / 256, n_angles), dim3(256), lds, s, sino,
                        n_det, taps, afp, band, bpitch);
     return hipGetLastError();

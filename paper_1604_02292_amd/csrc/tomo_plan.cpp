@@ -93,7 +93,8 @@ Plan make_plan(const Geom& g, const Rect& reg, const Rect& bsrc) {
         bp.rm1 = (float)(m / sp - 1.0);
         P.wmax = std::max(P.wmax, w);
     }
-    P.bpitch = round_up(P.wmax + 3, 4);
+    // at least 64 entries: the backprojector stages 64-entry windows of each row
+    P.bpitch = std::max(64, round_up(P.wmax + 3, 4));
     P.xp = round_up(reg.cols + 3, 4);
     P.tp = round_up(reg.rows + 3, 4);
     return P;

@@ -35,7 +35,8 @@ struct Geom {
     double spacing = 1.0, offset = 0.0;
     std::vector<double> th, c, s, m;
     std::vector<int> ystep;
-    float* d_taps = nullptr;   // Ram-Lak taps h[0..nd-1] / spacing (device, GPU contexts)
+    float* d_taps = nullptr;   // Ram-Lak taps h[d] / spacing as FP32 pairs (hi, lo), d < nd
+                               // (device, GPU contexts)
     size_t taps_off = 0;
 };
 
@@ -122,7 +123,8 @@ struct tomo_ctx {
     std::recursive_mutex mu;   // geometry list, caches, registrations
     std::deque<tomo::Geom> geoms;   // deque: references stay valid while serving reads them
     std::map<std::tuple<int, int, int>, float> step_cache;
-    int fp_seg = 0, bp_ag = 0, bp_ppt = 0, xcd_order = 0;
+    tomo_launch knobs{};   // launch shape forced by the user; 0 fields = automatic
+    std::map<std::tuple<int, int, int>, tomo_launch> tuned;   // autotuner results by class
     std::map<int, std::unique_ptr<tomo::SinoState>> sinos;
     int next_sino = 1;
     std::unique_ptr<tomo::ServeState> serve;
@@ -173,15 +175,21 @@ struct RoiState {
 
 struct LaunchCfg {
     int seg = 4, ag = 4, ppt = 1;
-    int contig = 1;   // 1: contiguous item ranges per XCD, 0: round-robin items
+    int cfp = 1, cbp = 1;   // XCD order of FP / BP items: 1 contiguous, 0 round-robin
+    int staged = 0;         // backprojector variant: 1 = LDS-staged band windows
 };
 
 LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels);
+// As choose_launch, preferring an autotuned shape for (geometry, pixels, jobs).
+LaunchCfg choose_launch_for(tomo_ctx* ctx, int gid, int jobs, long long total_rays,
+                            long long total_pixels);
+std::tuple<int, int, int> tune_key(int gid, int jobs, long long total_pixels);
 void bp_tile(int ag, int ppt, int* th, int* tw);
 size_t state_bytes(const Geom& g, const Plan& p);
 tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p);
 hipEvent_t timing_event(tomo_ctx* ctx);
 long long count_nnz(const Geom& g, const Rect& reg);
+size_t step_size_scratch_bytes(tomo_ctx* ctx, int gid, const RoiState& st);
 tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, Staging& stg);
 Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int ntc);
 // Work items; the device table pointers must already be known (items store them).

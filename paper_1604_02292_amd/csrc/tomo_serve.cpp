@@ -30,9 +30,12 @@ double now_ms() {
 }
 
 // Fixed launch shape for served slots (see the note at the top of the file).
+// The backprojector variant (direct or LDS-staged) may change with the mix:
+// for one group and pixel count per thread both give the same bits.
 constexpr int kServeSeg = 2;
-constexpr int kServeAG = 2;
+constexpr int kServeAG = 1;
 constexpr int kServePPT = 2;
+constexpr long long kServeStagedPixels = 1LL << 19;   // staged once the mix is this large
 }  // namespace
 
 bool on_serve_thread() { return t_serve; }
@@ -199,6 +202,7 @@ void scheduler(tomo_ctx* ctx) {
     const Item* d_fi = nullptr;
     const Item* d_bi = nullptr;
     int n_fi = 0, n_bi = 0;
+    bool staged = false;
     bool changed = false;
     for (;;) {
         // ---- admission ----
@@ -244,8 +248,20 @@ void scheduler(tomo_ctx* ctx) {
             r.roi = Rect{req.prm.roi.row0, req.prm.roi.col0, req.prm.roi.rows, req.prm.roi.cols};
             r.ext = extend_rect(r.roi, req.prm.margin, g.n);
             r.plan = make_plan(g, r.ext, r.ext);
+            // the slot's state, plus room for its step-size power iteration when
+            // the step is not cached yet (probed now, released just before use)
+            const size_t scratch = step_size_scratch_bytes(ctx, sl->sino->gid, r);
             char* blk = ctx->arena.alloc(state_bytes(g, r.plan), false);
             if (!blk && slots.empty()) blk = ctx->arena.alloc(state_bytes(g, r.plan), true);
+            char* probe = nullptr;
+            if (blk && scratch) {
+                probe = ctx->arena.alloc(scratch, false);
+                if (!probe && slots.empty()) probe = ctx->arena.alloc(scratch, true);
+                if (!probe) {
+                    ctx->arena.free_now(blk);
+                    blk = nullptr;
+                }
+            }
             if (!blk) {
                 if (slots.empty()) {   // cannot ever fit: fail it rather than stall
                     std::lock_guard<std::mutex> lk(S.mu);
@@ -266,6 +282,7 @@ void scheduler(tomo_ctx* ctx) {
             }
             sl->allocs.push_back(blk);
             carve_state(g, r, blk);
+            if (probe) ctx->arena.free_now(probe);
             t_err.clear();
             tomo_status st = prepare_slot(ctx, S, *sl);
             if (st != TOMO_OK) {
@@ -319,6 +336,9 @@ void scheduler(tomo_ctx* ctx) {
             d_bi = (const Item*)(d_lists + o_b);
             n_fi = (int)fi.size();
             n_bi = (int)bi.size();
+            long long pix = 0;
+            for (auto& sl : slots) pix += (long long)sl->st.ext.rows * sl->st.ext.cols;
+            staged = pix >= kServeStagedPixels;
             changed = false;
         }
         // ---- one tick: the same few iterations for every admitted slot ----
@@ -330,7 +350,7 @@ void scheduler(tomo_ctx* ctx) {
             // slots of uneven size: items dealt round-robin over the XCDs
             e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream, 0);
             if (e == hipSuccess)
-                e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, kServePPT, S.stream, 0);
+                e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, kServePPT, S.stream, 0, staged);
             S.step++;
         }
         for (auto& sl : slots) sl->it += tick;
@@ -468,10 +488,15 @@ tomo_status roi_submit(tomo_ctx* ctx, int32_t sino_id, const roi_params* params,
         if (st != TOMO_OK) return st;
         const Rect roi{params->roi.row0, params->roi.col0, params->roi.rows, params->roi.cols};
         const Rect ext = extend_rect(roi, params->margin, g.n);
-        const Plan P = make_plan(g, ext, ext);
-        if (state_bytes(g, P) + 64 * 1024 > ctx->arena.capacity())
-            return fail(ctx, TOMO_ENOMEM, "request state (%zu bytes) exceeds the workspace",
-                        state_bytes(g, P));
+        RoiState probe;
+        probe.prm = *params;
+        probe.roi = roi;
+        probe.ext = ext;
+        probe.plan = make_plan(g, ext, ext);
+        const size_t need = state_bytes(g, probe.plan) + step_size_scratch_bytes(ctx, sp->gid, probe);
+        if (need + 64 * 1024 > ctx->arena.capacity())
+            return fail(ctx, TOMO_ENOMEM, "request needs %zu bytes; the workspace holds %zu", need,
+                        ctx->arena.capacity());
         st = ensure_serving(ctx);
         if (st != TOMO_OK) return st;
         ServeState& S = *ctx->serve;

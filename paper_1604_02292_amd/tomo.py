@@ -8,7 +8,7 @@ stream, and nothing here computes on the data.
 import ctypes as C
 
 from . import _lib
-from ._lib import tomo_rect, roi_params, ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT
+from ._lib import tomo_rect, roi_params, tomo_launch, ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT
 
 
 class TomoError(RuntimeError):
@@ -195,9 +195,30 @@ class Context:
     def tomo_serving_config(self, max_slots=0, iters_per_tick=0):
         self._check(self.lib.tomo_serving_config(self.h, int(max_slots), int(iters_per_tick)))
 
-    def tomo_set_launch(self, fp_segments=0, bp_groups=0, bp_pixels_per_thread=0, xcd_order=0):
-        self._check(self.lib.tomo_set_launch(self.h, int(fp_segments), int(bp_groups),
-                                             int(bp_pixels_per_thread), int(xcd_order)))
+    def tomo_set_launch(self, fp_segments=0, fp_xcd_order=0, bp_variant=0, bp_groups=0,
+                        bp_pixels_per_thread=0, bp_xcd_order=0):
+        k = tomo_launch(int(fp_segments), int(fp_xcd_order), int(bp_variant), int(bp_groups),
+                        int(bp_pixels_per_thread), int(bp_xcd_order))
+        self._check(self.lib.tomo_set_launch(self.h, C.byref(k)))
+
+    def tomo_get_launch(self):
+        k = tomo_launch()
+        self._check(self.lib.tomo_get_launch(self.h, C.byref(k)))
+        return {f: getattr(k, f) for f, _ in tomo_launch._fields_}
+
+    def tomo_autotune(self, geom, sino, params, outs, x_ext=None, stream=None):
+        """Time every launch shape on this batch; returns (shape dict, fp_ms, bp_ms)."""
+        n, na, nd = self.geoms[geom]
+        cnt = len(params)
+        parr = (roi_params * cnt)(*params)
+        oarr = (C.c_void_p * cnt)(*[_ptr(o, (p.roi.rows, p.roi.cols), "out").value
+                                    for o, p in zip(outs, params)])
+        best = tomo_launch()
+        ms = (C.c_float * 2)()
+        self._check(self.lib.tomo_autotune(self.h, geom, _ptr(sino, (na, nd), "sino"),
+                                           _ptr(x_ext, (n, n), "x_ext"), cnt, parr, oarr,
+                                           _stream(stream), C.byref(best), ms))
+        return {f: getattr(best, f) for f, _ in tomo_launch._fields_}, ms[0], ms[1]
 
     def tomo_set_graphs(self, enable=True):
         self._check(self.lib.tomo_set_graphs(self.h, int(bool(enable))))

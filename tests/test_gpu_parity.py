@@ -88,6 +88,77 @@ def test_fp_bp_parity(ctx, gname, rect):
     assert abs(lhs - rhs) <= PROJ_TOL * abs(lhs)
 
 
+SHAPES_BP = [dict(bp_variant=1, bp_groups=a, bp_pixels_per_thread=q) for a in (1, 2, 4)
+             for q in (1, 2)] + [dict(bp_variant=2, bp_pixels_per_thread=q) for q in (1, 2)]
+
+
+@pytest.mark.parametrize("gname,rect", [("c1", (0, 100, 40, 28)), ("c2", (416, 416, 192, 192)),
+                                        ("c4", (1000, 37, 300, 261)), ("odd", (3, 5, 31, 77))])
+def test_every_launch_shape_matches_oracle(ctx, gname, rect):
+    """Every forward-projector and backprojector launch shape (segments, XCD
+    order, direct or LDS-staged band reads, groups, pixels per thread) agrees
+    with the oracle; the staged and direct backprojectors give identical bits
+    for the same groups and pixels per thread."""
+    n, na, nd = GEOMS[gname]
+    g = ctx.tomo_set_geometry(n, na, nd)
+    geo = oracle.make_geometry(n, na, nd)
+    rng = np.random.default_rng(7 + sum(rect))
+    img = rng.random((rect[2], rect[3])).astype(np.float32)
+    y = (rng.random((na, nd)) - 0.3).astype(np.float32)
+    ref_fp = oracle.fp_ray(geo, img.astype(np.float64), rect)
+    ref_bp = oracle.bp_pixel(geo, y.astype(np.float64), rect)
+    try:
+        for seg in (1, 2, 4):
+            for xo in (1, 2):
+                ctx.tomo_set_launch(fp_segments=seg, fp_xcd_order=xo)
+                sino = torch.empty((na, nd), dtype=torch.float32, device="cuda")
+                ctx.tomo_fp(g, rect, dev(img), sino)
+                e = rel(host(sino), ref_fp)
+                say(f"    {gname} {rect} fp seg {seg} xcd {xo}: {e:.2e}")
+                assert e <= PROJ_TOL
+        got = {}
+        for shp in SHAPES_BP:
+            for xo in (1, 2):
+                ctx.tomo_set_launch(bp_xcd_order=xo, **shp)
+                b = torch.empty((rect[2], rect[3]), dtype=torch.float32, device="cuda")
+                ctx.tomo_bp(g, rect, dev(y), b)
+                e = rel(host(b), ref_bp)
+                say(f"    {gname} {rect} bp {shp} xcd {xo}: {e:.2e}")
+                assert e <= PROJ_TOL
+                key = (shp.get("bp_groups", 1), shp["bp_pixels_per_thread"])
+                if key in got:
+                    assert torch.equal(got[key], b)
+                got[key] = b
+    finally:
+        ctx.tomo_set_launch()
+
+
+def test_autotune_picks_a_valid_shape(ctx):
+    """The autotuner times every shape on a batch, returns the fastest pair and
+    later solves of that shape class use it; results stay within rounding of the
+    untuned solve."""
+    from paper_1604_02292_amd import make_params
+    d, cfg, geo, p32 = _c1_problem()
+    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    rois = [((48, 48, 32, 32), 16), ((0, 0, 16, 24), 4), ((100, 90, 28, 38), 7)]
+    params = [make_params(r, m, "cp", cfg["lam"], 30) for r, m in rois]
+    sino = dev(p32)
+    before = [torch.empty((p.roi.rows, p.roi.cols), device="cuda") for p in params]
+    ctx.roi_solve_batch(g, sino, params, before)
+    scratch = [torch.empty_like(o) for o in before]
+    best, fp_ms, bp_ms = ctx.tomo_autotune(g, sino, params, scratch)
+    say(f"    tuned {best} fp {fp_ms * 1e3:.1f} us bp {bp_ms * 1e3:.1f} us")
+    assert best["fp_segments"] in (1, 2, 4) and best["fp_xcd_order"] in (1, 2)
+    assert best["bp_variant"] in (1, 2) and best["bp_pixels_per_thread"] in (1, 2)
+    assert best["bp_groups"] in (1, 2, 4) and best["bp_xcd_order"] in (1, 2)
+    assert 0 < fp_ms < 10 and 0 < bp_ms < 10
+    after = [torch.empty_like(o) for o in before]
+    ctx.roi_solve_batch(g, sino, params, after)
+    torch.cuda.synchronize()
+    for a, b in zip(before, after):
+        assert rel(host(a), host(b)) <= 1e-5
+
+
 def test_fp_accumulate_and_phantom(ctx):
     n, na, nd = GEOMS["c1"]
     g = ctx.tomo_set_geometry(n, na, nd)
@@ -228,7 +299,7 @@ def test_batch_equals_single_and_is_deterministic(ctx):
             ((100, 90, 28, 38), 7, "sirt", 50), ((10, 70, 8, 8), 2, "cp", 60)]
     params = [make_params(r, m, meth, cfg["lam"], it) for r, m, meth, it in rois]
     sino = dev(p32)
-    ctx.tomo_set_launch(2, 2)
+    ctx.tomo_set_launch(fp_segments=2, bp_variant=1, bp_groups=2, bp_pixels_per_thread=1)
     try:
         outs = [torch.empty((p.roi.rows, p.roi.cols), device="cuda") for p in params]
         ctx.roi_solve_batch(g, sino, params, outs)
@@ -246,7 +317,7 @@ def test_batch_equals_single_and_is_deterministic(ctx):
             # computes one global residual: equal up to FP32 rounding of b
             assert rel(host(a), host(b)) <= 1e-5
     finally:
-        ctx.tomo_set_launch(0, 0)
+        ctx.tomo_set_launch()
 
 
 def test_graph_replay_equals_eager(ctx):

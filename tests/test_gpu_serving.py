@@ -154,3 +154,32 @@ def test_admission_errors(served):
         small.tomo_unregister_sinogram(sid2)
     finally:
         small.close()
+
+
+def test_small_budget_admission(served):
+    """With a workspace that holds the resident sinogram and only about one
+    slot (state plus its step-size power iteration), requests of shapes whose
+    step size is not cached yet are admitted one or two at a time and all
+    complete with the same results as roi_solve."""
+    from paper_1604_02292_amd import Context, make_params
+    ctx, g, sid, sino, p32, cfg = served
+    small = Context(0, workspace_bytes=1 << 20)
+    try:
+        g2 = small.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+        sid2 = small.tomo_register_sinogram(g2, sino)
+        rects = [(40 + k, 36 + 2 * k, 24 + 3 * k, 20 + 5 * k) for k in range(6)]
+        params = [make_params(r, 8 + k, "cp", cfg["lam"], 40) for k, r in enumerate(rects)]
+        outs = [torch.empty((r[2], r[3]), device="cuda") for r in rects]
+        tickets = [small.roi_submit(sid2, p, o) for p, o in zip(params, outs)]
+        wait_all(small, tickets)
+        used, peak = small.tomo_workspace_usage()
+        assert peak <= 1 << 20
+        torch.cuda.synchronize()
+        for p, o in zip(params, outs):
+            ref = torch.empty_like(o)
+            ctx.roi_solve(g, sino, p, ref)
+            torch.cuda.synchronize()
+            assert rel(o.double().cpu().numpy(), ref.double().cpu().numpy()) <= 1e-5
+        small.tomo_unregister_sinogram(sid2)
+    finally:
+        small.close()
