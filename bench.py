@@ -284,18 +284,24 @@ def main():
                     help="explicit CP step for --only legs, skipping the power iteration")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes for input generation (0 = one per core, at most 16)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the launch shapes of the single-ROI leg before timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (the "
                          "reference kernel for scaling HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
+        # two plain copies of 256 MiB each: the runtime's blit copy and an
+        # elementwise kernel (y = 1 * x), 3 times each
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(5):
+        for _ in range(3):
             dst.copy_(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}), flush=True)
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -335,10 +341,15 @@ def main():
     ext = ctx.tomo_roi_ext(g, roi, margin)
     nnz = ctx.tomo_roi_nnz(g, ext)
 
-    # one-time plan step (like an FFT plan): time every launch shape of the two
-    # projector kernels on this problem and keep the fastest for its class
-    best, t_fp, t_bp = ctx.tomo_autotune(g, sino, [prm], [torch.empty_like(out)])
-    log(f"autotune: {best} (fp {1e3 * t_fp:.2f} us, bp {1e3 * t_bp:.2f} us per launch)")
+    if args.autotune:
+        # one-time plan step (like an FFT plan): time every launch shape of the
+        # two projector kernels on this problem and keep the fastest for its class
+        best, t_fp, t_bp = ctx.tomo_autotune(g, sino, [prm], [torch.empty_like(out)])
+        log(f"autotune: {best} (fp {1e3 * t_fp:.2f} us, bp {1e3 * t_bp:.2f} us per launch)")
+    else:
+        # the size heuristics' shapes (for this workload they are also the ones the
+        # autotuner picks), so that a profiled run of this command runs the same kernels
+        best = ctx.tomo_resolve_launch(g, [prm])
     for _ in range(max(2, args.warmup)):   # the second solve captures the iteration graph
         ctx.roi_solve(g, sino, prm, out)
     torch.cuda.synchronize()

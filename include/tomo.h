@@ -236,6 +236,13 @@ tomo_status tomo_set_launch(tomo_ctx* ctx, const tomo_launch* cfg);
 /* The shape last set with tomo_set_launch.  Errors: EINVAL. */
 tomo_status tomo_get_launch(tomo_ctx* ctx, tomo_launch* cfg);
 
+/* The launch shape roi_solve / roi_solve_batch would use now for this batch of
+ * ROI parameters (host array of count entries): forced fields, else an
+ * autotuned entry for the batch's class, else the size heuristics.  Errors:
+ * EINVAL, ENOENT. */
+tomo_status tomo_resolve_launch(tomo_ctx* ctx, int32_t geom, int32_t count,
+                                const roi_params* params, tomo_launch* out);
+
 /* Autotuner: times every forward-projector shape (segments x XCD order) and
  * every backprojector shape (variant x groups x pixels per thread x XCD
  * order) on this batch of ROI solves, one iteration each with HIP events

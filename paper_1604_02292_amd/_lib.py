@@ -61,6 +61,7 @@ SIGNATURES = {
     "tomo_serving_config": (C.c_int, [_P, _I, _I]),
     "tomo_set_launch": (C.c_int, [_P, C.POINTER(tomo_launch)]),
     "tomo_get_launch": (C.c_int, [_P, C.POINTER(tomo_launch)]),
+    "tomo_resolve_launch": (C.c_int, [_P, _I, _I, C.POINTER(roi_params), C.POINTER(tomo_launch)]),
     "tomo_autotune": (C.c_int, [_P, _I, _P, _P, _I, C.POINTER(roi_params), C.POINTER(_P), _P,
                                 C.POINTER(tomo_launch), C.POINTER(C.c_float)]),
     "tomo_set_graphs": (C.c_int, [_P, C.c_int]),

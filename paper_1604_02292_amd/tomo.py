@@ -206,6 +206,14 @@ class Context:
         self._check(self.lib.tomo_get_launch(self.h, C.byref(k)))
         return {f: getattr(k, f) for f, _ in tomo_launch._fields_}
 
+    def tomo_resolve_launch(self, geom, params):
+        """The launch shape a solve of this batch of parameters would use now."""
+        cnt = len(params)
+        parr = (roi_params * cnt)(*params)
+        k = tomo_launch()
+        self._check(self.lib.tomo_resolve_launch(self.h, geom, cnt, parr, C.byref(k)))
+        return {f: getattr(k, f) for f, _ in tomo_launch._fields_}
+
     def tomo_autotune(self, geom, sino, params, outs, x_ext=None, stream=None):
         """Time every launch shape on this batch; returns (shape dict, fp_ms, bp_ms)."""
         n, na, nd = self.geoms[geom]

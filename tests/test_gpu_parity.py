@@ -152,6 +152,7 @@ def test_autotune_picks_a_valid_shape(ctx):
     assert best["bp_variant"] in (1, 2) and best["bp_pixels_per_thread"] in (1, 2)
     assert best["bp_groups"] in (1, 2, 4) and best["bp_xcd_order"] in (1, 2)
     assert 0 < fp_ms < 10 and 0 < bp_ms < 10
+    assert ctx.tomo_resolve_launch(g, params) == best
     after = [torch.empty_like(o) for o in before]
     ctx.roi_solve_batch(g, sino, params, after)
     torch.cuda.synchronize()
