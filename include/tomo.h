@@ -214,6 +214,9 @@ tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
  * automatically (from an autotuned entry for the problem's shape class when
  * tomo_autotune has measured one, else from the problem size).
  *   fp_segments           forward projector: waves per ray, 1, 2 or 4
+ *   fp_rays_per_lane      1, or 2 (with one segment): each lane projects two
+ *                         adjacent rays from 4-pixel reads (detector spacing
+ *                         below sqrt 2 pixels; otherwise 1 is used)
  *   fp_xcd_order          order in which forward-projector work items are dealt
  *                         to the chip's 8 XCDs: 1 = one contiguous eighth of the
  *                         item list per XCD (L2 locality), 2 = round-robin
@@ -226,7 +229,7 @@ tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
  * Results agree to FP32 rounding across shapes; the two variants give
  * identical results for the same groups and pixels per thread. */
 typedef struct {
-    int32_t fp_segments, fp_xcd_order;
+    int32_t fp_segments, fp_rays_per_lane, fp_xcd_order;
     int32_t bp_variant, bp_groups, bp_pixels_per_thread, bp_xcd_order;
 } tomo_launch;
 

@@ -31,7 +31,8 @@ class roi_params(C.Structure):
 
 
 class tomo_launch(C.Structure):
-    _fields_ = [("fp_segments", C.c_int32), ("fp_xcd_order", C.c_int32),
+    _fields_ = [("fp_segments", C.c_int32), ("fp_rays_per_lane", C.c_int32),
+                ("fp_xcd_order", C.c_int32),
                 ("bp_variant", C.c_int32), ("bp_groups", C.c_int32),
                 ("bp_pixels_per_thread", C.c_int32), ("bp_xcd_order", C.c_int32)]
 

@@ -26,12 +26,14 @@ void bp_tile(int ag, int ppt, int* th, int* tw) {
 // Overwrite the non-zero fields of k onto L.
 static void apply_knobs(LaunchCfg& L, const tomo_launch& k) {
     if (k.fp_segments) L.seg = k.fp_segments;
+    if (k.fp_rays_per_lane) L.rp = k.fp_rays_per_lane;
     if (k.fp_xcd_order) L.cfp = k.fp_xcd_order == 1;
     if (k.bp_variant) L.staged = k.bp_variant == 2;
     if (k.bp_groups) L.ag = k.bp_groups;
     if (k.bp_pixels_per_thread) L.ppt = k.bp_pixels_per_thread;
     if (k.bp_xcd_order) L.cbp = k.bp_xcd_order == 1;
     if (L.staged) L.ag = 1;
+    if (L.seg != 1) L.rp = 1;
 }
 
 LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels) {
@@ -48,6 +50,9 @@ LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long tot
     // band in LDS (one angle group, two pixels per thread).  Small ones are
     // latency-bound: read the band directly, angles split over groups.
     L.staged = total_pixels >= 4 * want;
+    // one segment per ray: two rays per lane from 4-pixel reads (half the
+    // gathers, the rate that bounds large forward projections)
+    L.rp = L.seg == 1 ? 2 : 1;
     if (L.staged) {
         L.ag = 1;
         L.ppt = 2;
@@ -139,17 +144,17 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
 }
 
 // Items of the forward projector for job `jj` with tables `afp`.
-void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg,
+void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg, int rp,
               const AngFP* d_afp) {
-    const int rpb = 256 / seg;
+    const int rpb = 256 * rp / seg;
     for (int k = 0; k < (int)afp.size(); ++k) {
         const int nch = (afp[k].w + rpb - 1) / rpb;
         for (int ch = 0; ch < nch; ++ch) out.push_back(Item{jj, k, ch, 0, d_afp + k, 0});
     }
 }
 
-size_t count_fp_items(const std::vector<AngFP>& afp, int seg) {
-    const int rpb = 256 / seg;
+size_t count_fp_items(const std::vector<AngFP>& afp, int seg, int rp) {
+    const int rpb = 256 * rp / seg;
     size_t n = 0;
     for (const AngFP& a : afp) n += (size_t)((a.w + rpb - 1) / rpb);
     return n;
@@ -325,7 +330,7 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     const size_t o_afp = m.add(pr.plan.afp.data(), pr.plan.afp.size() * sizeof(AngFP));
     const size_t o_abp = m.add(pr.plan.abp.data(), pr.plan.abp.size() * sizeof(AngBP));
     const size_t o_job = m.reserve(sizeof(Job));
-    const size_t o_fi = m.reserve(count_fp_items(pr.plan.afp, L.seg) * sizeof(Item));
+    const size_t o_fi = m.reserve(count_fp_items(pr.plan.afp, L.seg, L.rp) * sizeof(Item));
     const size_t o_bi = m.reserve(count_bp_items(nr, nc, L.ag, L.ppt) * sizeof(Item));
     const size_t o_est = m.reserve(64);
     char* dm = ctx->arena.alloc(m.buf.size());
@@ -337,7 +342,7 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     pr.d_afp = (AngFP*)(dm + o_afp);
     pr.d_abp = (AngBP*)(dm + o_abp);
     std::vector<Item> fi, bi;
-    fp_items(fi, 0, pr.plan.afp, L.seg, pr.d_afp);
+    fp_items(fi, 0, pr.plan.afp, L.seg, L.rp, pr.d_afp);
     bp_items(bi, 0, nr, nc, L.ag, L.ppt, pr.d_abp);
     const int n_part = (int)bi.size();
     Job J = make_job(g, pr, FP_BAND_STORE, BP_POWER, (nc + tw - 1) / tw);
@@ -355,7 +360,7 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     float* est = (float*)(dm + o_est);
     for (int it = 0; it < kPowerIters && e == hipSuccess; ++it) {
         e = launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_fi), (int)fi.size(), it,
-                      L.seg, s);
+                      L.seg, s, L.cfp, L.rp);
         if (e == hipSuccess)
             e = launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_bi), n_part, it, L.ag, L.ppt, s,
                           L.cbp, L.staged);
@@ -393,7 +398,7 @@ size_t step_size_scratch_bytes(tomo_ctx* ctx, int gid, const RoiState& st) {
     }
     const Plan p = make_plan(g, Rect{0, 0, nr, nc}, Rect{0, 0, nr, nc});
     const size_t tables = (size_t)g.na * (sizeof(AngFP) + sizeof(AngBP)) + sizeof(Job) + 64;
-    const size_t items = (count_fp_items(p.afp, 1) + count_bp_items(nr, nc, 1, 1)) * sizeof(Item);
+    const size_t items = (count_fp_items(p.afp, 1, 1) + count_bp_items(nr, nc, 1, 1)) * sizeof(Item);
     return state_bytes(g, p) + tables + items + 4096;
 }
 
@@ -487,13 +492,13 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     const size_t o_jobs_e2 = m.reserve(sizeof(Job) * count);
     const size_t o_job_g = m.reserve(sizeof(Job));
     std::vector<Item> it_e1, it_e2, it_g;
-    const int seg_g = choose_launch(ctx, (long long)g.na * g.nd, 0).seg;
+    const LaunchCfg Lg = choose_launch(ctx, (long long)g.na * g.nd, 0);
     size_t n_e1 = 0, n_e2 = 0, n_g = 0;
     for (int i = 0; i < count; ++i) {
-        n_e1 += count_fp_items(R[i].plan_full.afp, L.seg);
-        n_e2 += count_fp_items(R[i].plan.afp, L.seg);
+        n_e1 += count_fp_items(R[i].plan_full.afp, L.seg, L.rp);
+        n_e2 += count_fp_items(R[i].plan.afp, L.seg, L.rp);
     }
-    if (global_resid) n_g = count_fp_items(Pfull.afp, seg_g);
+    if (global_resid) n_g = count_fp_items(Pfull.afp, Lg.seg, Lg.rp);
     const size_t o_it_e1 = m.reserve(n_e1 * sizeof(Item));
     const size_t o_it_e2 = m.reserve(n_e2 * sizeof(Item));
     const size_t o_it_g = m.reserve(n_g * sizeof(Item));
@@ -512,10 +517,10 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         R[i].d_afp = (AngFP*)(dm + o_afp[i]);
         R[i].d_abp = (AngBP*)(dm + o_abp[i]);
         R[i].d_afp_full = (AngFP*)(dm + o_afpf[i]);
-        fp_items(it_e1, i, R[i].plan_full.afp, L.seg, R[i].d_afp_full);
-        fp_items(it_e2, i, R[i].plan.afp, L.seg, R[i].d_afp);
+        fp_items(it_e1, i, R[i].plan_full.afp, L.seg, L.rp, R[i].d_afp_full);
+        fp_items(it_e2, i, R[i].plan.afp, L.seg, L.rp, R[i].d_afp);
     }
-    if (global_resid) fp_items(it_g, 0, Pfull.afp, seg_g, (const AngFP*)(dm + o_afp_glob));
+    if (global_resid) fp_items(it_g, 0, Pfull.afp, Lg.seg, Lg.rp, (const AngFP*)(dm + o_afp_glob));
     m.put(o_it_e1, it_e1.data(), it_e1.size() * sizeof(Item));
     m.put(o_it_e2, it_e2.data(), it_e2.size() * sizeof(Item));
     m.put(o_it_g, it_g.data(), it_g.size() * sizeof(Item));
@@ -577,15 +582,15 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     CK(launch_fill((float*)sblk, state_total / sizeof(float), 0.f, s));
     if (global_resid)
         CK(launch_fp((const Job*)(dm + o_job_g), (const Item*)(dm + o_it_g), (int)it_g.size(), 0,
-                     seg_g, s));
+                     Lg.seg, s, Lg.cfp, Lg.rp));
     if (!rglob)
         CK(launch_fp((const Job*)(dm + o_jobs_e1), (const Item*)(dm + o_it_e1), (int)it_e1.size(),
-                     0, L.seg, s));
+                     0, L.seg, s, L.cfp, L.rp));
     for (auto& r : R)
         CK(launch_pad_copy(E.plain, g.n, r.ext.r0, r.ext.c0, r.ext.rows, r.ext.cols, r.xb0,
                            r.plan.xp, r.xt, r.plan.tp, nullptr, 0, s));
     CK(launch_fp((const Job*)(dm + o_jobs_e2), (const Item*)(dm + o_it_e2), (int)it_e2.size(), 0,
-                 L.seg, s));
+                 L.seg, s, L.cfp, L.rp));
     // Step sizes (cached per shape; the power iteration reuses the state buffers).
     for (auto& r : R) {
         tomo_status st = step_size_for(ctx, gid, r, s, ctx->staging);
@@ -614,7 +619,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         const bool cp = r.prm.method == ROI_TV_NONNEG_CP;
         jobs[q] = make_job(g, r, cp ? FP_CP_DUAL : FP_SIRT, cp ? BP_CP : BP_SIRT,
                            (r.ext.cols + tw - 1) / tw);
-        fp_items(fi, q, r.plan.afp, L.seg, r.d_afp);
+        fp_items(fi, q, r.plan.afp, L.seg, L.rp, r.d_afp);
         bp_items(bi, q, r.ext.rows, r.ext.cols, L.ag, L.ppt, r.d_abp);
         fi_end[q] = (int)fi.size();
         bi_end[q] = (int)bi.size();
@@ -641,7 +646,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
                 e2 = timing_event(ctx);
                 if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
             }
-            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, st, L.cfp)) != hipSuccess)
+            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, st, L.cfp, L.rp)) != hipSuccess)
                 return e;
             if (timed && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
             if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, st, L.cbp,
@@ -676,7 +681,8 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
             hipError_t le = hipSuccess;
             for (int q = 0; q < kReps && le == hipSuccess; ++q)
                 le = kind == 0 ? launch_fp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_fi),
-                                           fi_end[count - 1], q, L.seg, ctx->cap_stream, L.cfp)
+                                           fi_end[count - 1], q, L.seg, ctx->cap_stream, L.cfp,
+                                           L.rp)
                                : launch_bp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_bi),
                                            bi_end[count - 1], q, L.ag, L.ppt, ctx->cap_stream,
                                            L.cbp, L.staged);
@@ -1019,11 +1025,11 @@ tomo_status tomo_fp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
     Meta m;
     const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
     const size_t o_job = m.reserve(sizeof(Job));
-    const size_t o_it = m.reserve(count_fp_items(P.afp, L.seg) * sizeof(Item));
+    const size_t o_it = m.reserve(count_fp_items(P.afp, L.seg, L.rp) * sizeof(Item));
     const size_t nb = (size_t)r.rows * P.xp, nt = (size_t)r.cols * P.tp;
     char* dm = ctx->arena.alloc(align_up(m.buf.size(), 256) + (nb + nt) * sizeof(float));
     if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace too small for the region buffers");
-    fp_items(items, 0, P.afp, L.seg, (const AngFP*)(dm + o_afp));
+    fp_items(items, 0, P.afp, L.seg, L.rp, (const AngFP*)(dm + o_afp));
     m.put(o_it, items.data(), items.size() * sizeof(Item));
     float* xb = (float*)(dm + align_up(m.buf.size(), 256));
     float* xt = xb + nb;
@@ -1049,7 +1055,7 @@ tomo_status tomo_fp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
                                   0, s));
     if (!accumulate) TOMO_HIP(ctx, launch_fill(sino, (size_t)g.na * g.nd, 0.f, s));
     TOMO_HIP(ctx, launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
-                            0, L.seg, s));
+                            0, L.seg, s, L.cfp, L.rp));
     ctx->arena.free_after(allocs, s);
     return TOMO_OK;
     GUARD_END(ctx)
@@ -1168,8 +1174,8 @@ tomo_status tomo_exterior_subtract(tomo_ctx* ctx, int32_t geom, tomo_rect ext_ro
     const size_t o_afp = m.add(r.plan.afp.data(), r.plan.afp.size() * sizeof(AngFP));
     const size_t o_afpf = m.add(r.plan_full.afp.data(), r.plan_full.afp.size() * sizeof(AngFP));
     const size_t o_jobs = m.reserve(2 * sizeof(Job));
-    const size_t o_i1 = m.reserve(count_fp_items(r.plan_full.afp, L.seg) * sizeof(Item));
-    const size_t o_i2 = m.reserve(count_fp_items(r.plan.afp, L.seg) * sizeof(Item));
+    const size_t o_i1 = m.reserve(count_fp_items(r.plan_full.afp, L.seg, L.rp) * sizeof(Item));
+    const size_t o_i2 = m.reserve(count_fp_items(r.plan.afp, L.seg, L.rp) * sizeof(Item));
     char* dm = ctx->arena.alloc(m.buf.size());
     if (!dm) {
         ctx->arena.free_after(allocs, s);
@@ -1178,8 +1184,8 @@ tomo_status tomo_exterior_subtract(tomo_ctx* ctx, int32_t geom, tomo_rect ext_ro
     allocs.push_back(dm);
     r.d_afp = (AngFP*)(dm + o_afp);
     r.d_afp_full = (AngFP*)(dm + o_afpf);
-    fp_items(i1, 0, r.plan_full.afp, L.seg, r.d_afp_full);
-    fp_items(i2, 1, r.plan.afp, L.seg, r.d_afp);
+    fp_items(i1, 0, r.plan_full.afp, L.seg, L.rp, r.d_afp_full);
+    fp_items(i2, 1, r.plan.afp, L.seg, L.rp, r.d_afp);
     m.put(o_i1, i1.data(), i1.size() * sizeof(Item));
     m.put(o_i2, i2.data(), i2.size() * sizeof(Item));
     Job J[2];
@@ -1205,11 +1211,11 @@ tomo_status tomo_exterior_subtract(tomo_ctx* ctx, int32_t geom, tomo_rect ext_ro
     if ((e = ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s)) != hipSuccess ||
         (e = launch_fill((float*)blk, r.total_floats, 0.f, s)) != hipSuccess ||
         (e = launch_fp((const Job*)(dm + o_jobs), (const Item*)(dm + o_i1), (int)i1.size(), 0,
-                       L.seg, s)) != hipSuccess ||
+                       L.seg, s, L.cfp, L.rp)) != hipSuccess ||
         (e = launch_pad_copy(E.plain, g.n, r.ext.r0, r.ext.c0, r.ext.rows, r.ext.cols, r.xb0,
                              r.plan.xp, r.xt, r.plan.tp, nullptr, 0, s)) != hipSuccess ||
         (e = launch_fp((const Job*)(dm + o_jobs), (const Item*)(dm + o_i2), (int)i2.size(), 0,
-                       L.seg, s)) != hipSuccess ||
+                       L.seg, s, L.cfp, L.rp)) != hipSuccess ||
         (e = launch_fill(sino_local, (size_t)g.na * g.nd, 0.f, s)) != hipSuccess ||
         (e = launch_band_scatter(r.b, r.plan.bpitch, r.d_afp, g.na, sino_local, g.nd, 0, s)) !=
             hipSuccess)
@@ -1242,6 +1248,7 @@ tomo_status roi_solve_batch(tomo_ctx* ctx, int32_t geom, const float* sino, cons
 static tomo_launch to_knobs(const LaunchCfg& L) {
     tomo_launch d{};
     d.fp_segments = L.seg;
+    d.fp_rays_per_lane = L.rp;
     d.fp_xcd_order = L.cfp ? 1 : 2;
     d.bp_variant = L.staged ? 2 : 1;
     d.bp_groups = L.staged ? 1 : L.ag;
@@ -1300,12 +1307,14 @@ tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const 
     // (timing mode 2: 50 back-to-back launches in a graph between two events).
     std::vector<tomo_launch> fpc, bpc;
     for (int xo = 1; xo <= 2; ++xo)
-        for (int sg : {1, 2, 4}) {
-            tomo_launch k{};
-            k.fp_segments = sg;
-            k.fp_xcd_order = xo;
-            fpc.push_back(k);
-        }
+        for (int sg : {1, 2, 4})
+            for (int rp = 1; rp <= (sg == 1 ? 2 : 1); ++rp) {
+                tomo_launch k{};
+                k.fp_segments = sg;
+                k.fp_rays_per_lane = rp;
+                k.fp_xcd_order = xo;
+                fpc.push_back(k);
+            }
     for (int xo = 1; xo <= 2; ++xo) {
         for (int pp : {1, 2}) {
             tomo_launch k{};
@@ -1344,6 +1353,7 @@ tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const 
         const tomo_launch& b = bpc[i % bpc.size()];
         tomo_launch k = b;
         k.fp_segments = f.fp_segments;
+        k.fp_rays_per_lane = f.fp_rays_per_lane;
         k.fp_xcd_order = f.fp_xcd_order;
         ctx->knobs = k;
         ctx->timing_mode = 2;
@@ -1376,6 +1386,7 @@ tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const 
     if (best_fp >= 1e30 || best_bp >= 1e30) return fail(ctx, TOMO_EHIP, "autotune: no timing recorded");
     tomo_launch r = bb;
     r.fp_segments = bf.fp_segments;
+    r.fp_rays_per_lane = bf.fp_rays_per_lane;
     r.fp_xcd_order = bf.fp_xcd_order;
     {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -1441,6 +1452,7 @@ tomo_status tomo_set_launch(tomo_ctx* ctx, const tomo_launch* cfg) {
     auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
     auto in012 = [](int v) { return v >= 0 && v <= 2; };
     if (!ok(k.fp_segments) || !ok(k.bp_groups) || !in012(k.bp_pixels_per_thread) ||
+        !in012(k.fp_rays_per_lane) ||
         !in012(k.bp_variant) || !in012(k.fp_xcd_order) || !in012(k.bp_xcd_order))
         return fail(ctx, TOMO_EINVAL, "launch knobs: segments/groups in {0,1,2,4}, pixels in "
                     "{0,1,2}, variant and xcd order in {0,1,2}");

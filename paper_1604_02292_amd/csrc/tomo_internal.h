@@ -12,9 +12,15 @@
 
 namespace tomo {
 
+// Padded image layout (xbar [n_r][xp], xbar^T [n_c][tp]): column c of a row is
+// stored at c + kLpad, with zeros before it and at least two zeros after the
+// last column, so an interpolation read that starts up to 3 entries left of
+// the first column stays inside the row.
+constexpr int kLpad = 4;
+
 // Per (job, angle) table of the ray-driven forward projector (Joseph, Section 2.1).
 // Ray j of the band crosses outer line o (a row, or a column when tr = 1) at the
-// padded inner coordinate  pos = a0 + j * aj + o * step  (inner index + 1).
+// storage coordinate  pos = a0 + j * aj + o * step  (inner index + kLpad).
 struct AngFP {
     double a0;
     double aj;
@@ -104,8 +110,10 @@ static_assert(sizeof(Item) == 32, "Item layout");
 // Launchers (tomo_kernels.hip).
 // contiguous = 1: each XCD runs one contiguous eighth of the items (L2
 // locality for many small jobs); 0: item b runs on XCD b mod 8 (balanced).
+// rays_per_lane = 2: each lane projects two adjacent rays from 4-pixel reads
+// (segments must be 1; the items must be built for 512 rays per block).
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
-                     hipStream_t s, int contiguous = 1);
+                     hipStream_t s, int contiguous = 1, int rays_per_lane = 1);
 // staged = 1: band windows staged in LDS (one angle group; throughput shape),
 // 0: direct band reads (any group count; latency shape).  Same results.
 // compensated = 1: compensated sums over angles, staged, groups 1, ppt 2 only

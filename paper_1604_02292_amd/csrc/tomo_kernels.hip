@@ -94,6 +94,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(gcfloat* p, size_t b
 __device__ __forceinline__ v2f load2(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
 }
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4f load4(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+}
 
 // ---------------------------------------------------------------------------
 // Forward projection.  One block = one angle of one job and 256/SEG rays;
@@ -103,12 +107,12 @@ __device__ __forceinline__ v2f load2(__amdgpu_buffer_rsrc_t rs, unsigned voff, u
 // read nearly contiguous pixels of one image row (the transposed copy of the
 // image serves the column-stepping angles, keeping those reads contiguous).
 // ---------------------------------------------------------------------------
-template <int SEG>
+template <int SEG, int RP>
 __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
                                                  int step, int contiguous) {
     constexpr int SUBS = 4 / SEG;
-    __shared__ float red[SEG > 1 ? 256 : 1];
+    __shared__ float red[SEG > 1 ? RP * 256 : 1];
     const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
     if (bid >= n_items) return;
     const Item it = cview(items)[bid];
@@ -119,50 +123,57 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
     const int wave = uniform_int(threadIdx.x >> 6);
     const int seg = wave % SEG;
     const int sub = wave / SEG;
-    const int jfirst = (it.b * SUBS + sub) * 64;
-    const int j = jfirst + lane;
+    const int jfirst = (it.b * SUBS + sub) * 64 * RP;   // a wave: 64 RP adjacent rays
+    const int j0 = jfirst + RP * lane;                  // this lane: rays j0 .. j0 + RP - 1
     const int rpar = (step + J->parity0) & 1;
     gcfloat* img = gview(A.tr ? J->xt : J->xb[rpar]);
     const int pitch = A.tr ? J->tp : J->xp;
     const int n_outer = A.tr ? J->nc : J->nr;
     const int n_inner = A.tr ? J->nr : J->nc;
 
-    // Epilogue operands are independent of the ray sum: fetch them first so
+    // Epilogue operands are independent of the ray sums: fetch them first so
     // their memory latency overlaps the loop.
     const int mode = J->fp_mode;
-    const int gi = A.i0 + j;
-    const bool ondet = (gi >= 0) && (gi < J->n_det);
-    const size_t bidx = (size_t)k * J->bpitch + 1 + j;
-    const size_t gidx = (size_t)k * J->n_det + gi;
-    float pre0 = 0.f, pre1 = 0.f;
-    if (seg == 0 && j < A.w && ondet) {
-        switch (mode) {
-            case FP_ACCUM: pre0 = J->gout[gidx]; break;
-            case FP_BAND_FROM_GLOBAL:
-            case FP_RESID: pre0 = J->gbase[gidx]; break;
-            case FP_BAND_ADD: pre0 = J->y[bidx]; break;
-            case FP_CP_DUAL: pre0 = J->y[bidx]; pre1 = J->b[bidx]; break;
-            case FP_SIRT: pre1 = J->b[bidx]; break;
-            default: break;
+    float pre0[RP], pre1[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+        const int j = j0 + r;
+        const int gi = A.i0 + j;
+        pre0[r] = pre1[r] = 0.f;
+        if (seg == 0 && j < A.w && gi >= 0 && gi < J->n_det) {
+            const size_t bidx = (size_t)k * J->bpitch + 1 + j;
+            const size_t gidx = (size_t)k * J->n_det + gi;
+            switch (mode) {
+                case FP_ACCUM: pre0[r] = J->gout[gidx]; break;
+                case FP_BAND_FROM_GLOBAL:
+                case FP_RESID: pre0[r] = J->gbase[gidx]; break;
+                case FP_BAND_ADD: pre0[r] = J->y[bidx]; break;
+                case FP_CP_DUAL: pre0[r] = J->y[bidx]; pre1[r] = J->b[bidx]; break;
+                case FP_SIRT: pre1[r] = J->b[bidx]; break;
+                default: break;
+            }
         }
     }
 
-    float acc = 0.f;
+    float acc[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) acc[r] = 0.f;
     if (jfirst < A.w) {
-        const int jlast = min(jfirst + 63, A.w - 1);
-        // Outer lines where some ray of this wave lies strictly inside the
-        // padded inner range (0, n_inner + 1); outside it every weight is 0.
+        const int jlast = min(jfirst + 64 * RP - 1, A.w - 1);
+        // Outer lines where some ray of this wave lies strictly inside the image
+        // columns' interpolation range (kLpad - 1, n_inner + kLpad) of storage
+        // coordinates; outside it every weight is 0.
         const double pa = A.a0 + (double)jfirst * A.aj;
         const double pb = A.a0 + (double)jlast * A.aj;
-        const double hi_in = (double)(n_inner + 1);
+        const double lo_in = (double)(kLpad - 1), hi_in = (double)(n_inner + kLpad);
         int o_lo = 0, o_hi = 0;
         if (A.step == 0.0) {
-            const bool any = (fmax(pa, pb) > 0.0) && (fmin(pa, pb) < hi_in);
+            const bool any = (fmax(pa, pb) > lo_in) && (fmin(pa, pb) < hi_in);
             o_hi = any ? n_outer : 0;
         } else {
             const double inv = 1.0 / A.step;
-            const double t1 = -pa * inv, t2 = (hi_in - pa) * inv;
-            const double t3 = -pb * inv, t4 = (hi_in - pb) * inv;
+            const double t1 = (lo_in - pa) * inv, t2 = (hi_in - pa) * inv;
+            const double t3 = (lo_in - pb) * inv, t4 = (hi_in - pb) * inv;
             double lo = fmin(fmin(t1, t2), fmin(t3, t4));
             double hi = fmax(fmax(t1, t2), fmax(t3, t4));
             lo = fmin(fmax(lo, -2.0), (double)n_outer + 2.0);
@@ -175,109 +186,214 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
         const int len = max(0, o_hi - o_lo);
         const int s0 = o_lo + (len * seg) / SEG;
         const int s1 = o_lo + (len * (seg + 1)) / SEG;
-        const double pj = A.a0 + (double)j * A.aj;
         const float stepf = (float)A.step;
         const unsigned rowb = (unsigned)pitch * 4u;
         // Each outer line is read through its own buffer resource whose range is
-        // that line: a lane whose position falls off the padded line gets 0 from
-        // the hardware range check, and the line's first and last entries are
-        // zero padding, so no position clamp is needed.
+        // that line: a read past its end returns 0 per element from the hardware
+        // range check, and the line holds kLpad zeros before its first pixel
+        // (so no read starts before it), so no position clamp is needed.
         // 32 outer lines per FP64 anchor: pos = I + loc with loc within 64 +- 34,
         // so the FP32 part carries a few 1e-6 of a pixel at any grid size; the
         // +64 shift makes truncation a floor and fract the interpolation weight.
-        for (int oc = s0; oc < s1; oc += 32) {
-            const double p0 = fma((double)oc, A.step, pj);
-            const double fl0 = fmin(fmax(floor(p0), -1.0e6), 1.0e6);
-            const int I = (int)fl0;
-            const float base64 = (float)(p0 - fl0) + 64.f;
-            unsigned ib4 = (unsigned)(I - 64) * 4u;
-            asm("" : "+v"(ib4));   // keeps (index << 2) + ib4 a single shift-add
-            const int cnt = min(32, s1 - oc);
-            gcfloat* line = img + (size_t)oc * pitch;
-            // two-level sum: the chunk's terms first, then the chunk into the ray
-            // (long rays of a large grid keep a few ulp of the full sum)
-            float cs = 0.f;
-            int q = 0;
-            if (cnt == 32) {
-                // a full chunk: all 32 paired loads issue before the first is used
-                float f[32];
-                v2f v[32];
+        if constexpr (RP == 1) {
+            const double pj = A.a0 + (double)j0 * A.aj;
+            for (int oc = s0; oc < s1; oc += 32) {
+                const double p0 = fma((double)oc, A.step, pj);
+                const double fl0 = fmin(fmax(floor(p0), -1.0e6), 1.0e6);
+                const float base64 = (float)(p0 - fl0) + 64.f;
+                unsigned ib4 = (unsigned)((int)fl0 - 64) * 4u;
+                asm("" : "+v"(ib4));   // keeps (index << 2) + ib4 a single shift-add
+                const int cnt = min(32, s1 - oc);
+                gcfloat* line = img + (size_t)oc * pitch;
+                // two-level sum: the chunk's terms first, then the chunk into the ray
+                // (long rays of a large grid keep a few ulp of the full sum)
+                float cs = 0.f;
+                int q = 0;
+                if (cnt == 32) {
+                    // a full chunk: all 32 paired loads issue before the first is used
+                    float f[32];
+                    v2f v[32];
 #pragma unroll
-                for (int u = 0; u < 32; ++u) {
-                    const float loc = fmaf((float)u, stepf, base64);
-                    f[u] = __builtin_amdgcn_fractf(loc);
-                    const unsigned off = ((unsigned)loc << 2) + ib4;
-                    v[u] = load2(make_rsrc(line + (size_t)u * pitch, rowb), off, 0);
+                    for (int u = 0; u < 32; ++u) {
+                        const float loc = fmaf((float)u, stepf, base64);
+                        f[u] = __builtin_amdgcn_fractf(loc);
+                        const unsigned off = ((unsigned)loc << 2) + ib4;
+                        v[u] = load2(make_rsrc(line + (size_t)u * pitch, rowb), off, 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) cs += fmaf(f[u], v[u].y - v[u].x, v[u].x);
+                    q = 32;
                 }
+                for (; q + 8 <= cnt; q += 8) {
+                    const float b8 = fmaf((float)q, stepf, base64);
+                    float f[8];
+                    v2f v[8];
 #pragma unroll
-                for (int u = 0; u < 32; ++u) cs += fmaf(f[u], v[u].y - v[u].x, v[u].x);
-                q = 32;
-            }
-            for (; q + 8 <= cnt; q += 8) {
-                const float b8 = fmaf((float)q, stepf, base64);
-                float f[8];
-                v2f v[8];
+                    for (int u = 0; u < 8; ++u) {
+                        const float loc = fmaf((float)u, stepf, b8);
+                        f[u] = __builtin_amdgcn_fractf(loc);
+                        const unsigned off = ((unsigned)loc << 2) + ib4;
+                        v[u] = load2(make_rsrc(line + (size_t)(q + u) * pitch, rowb), off, 0);
+                    }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const float loc = fmaf((float)u, stepf, b8);
-                    f[u] = __builtin_amdgcn_fractf(loc);
-                    const unsigned off = ((unsigned)loc << 2) + ib4;
-                    v[u] = load2(make_rsrc(line + (size_t)(q + u) * pitch, rowb), off, 0);
+                    for (int u = 0; u < 8; ++u) cs += fmaf(f[u], v[u].y - v[u].x, v[u].x);
                 }
+                for (; q < cnt; ++q) {
+                    const float loc = fmaf((float)q, stepf, base64);
+                    const float f = __builtin_amdgcn_fractf(loc);
+                    const unsigned off = ((unsigned)loc << 2) + ib4;
+                    const v2f v = load2(make_rsrc(line + (size_t)q * pitch, rowb), off, 0);
+                    cs += fmaf(f, v.y - v.x, v.x);
+                }
+                acc[0] += cs;
+            }
+        } else if (fabs(A.aj) >= 2.0) {
+            // detector spacing of sqrt 2 pixels or more: the two rays are too far
+            // apart for one 4-pixel read, so each reads its own pairs
 #pragma unroll
-                for (int u = 0; u < 8; ++u) cs += fmaf(f[u], v[u].y - v[u].x, v[u].x);
+            for (int r = 0; r < 2; ++r) {
+                const double pj = A.a0 + (double)(j0 + r) * A.aj;
+                for (int oc = s0; oc < s1; oc += 32) {
+                    const double p0 = fma((double)oc, A.step, pj);
+                    const double fl0 = fmin(fmax(floor(p0), -1.0e6), 1.0e6);
+                    const float base64 = (float)(p0 - fl0) + 64.f;
+                    const unsigned ib4 = (unsigned)((int)fl0 - 64) * 4u;
+                    const int cnt = min(32, s1 - oc);
+                    gcfloat* line = img + (size_t)oc * pitch;
+                    float cs = 0.f;
+                    for (int q = 0; q < cnt; ++q) {
+                        const float loc = fmaf((float)q, stepf, base64);
+                        const float f = __builtin_amdgcn_fractf(loc);
+                        const unsigned off = ((unsigned)loc << 2) + ib4;
+                        const v2f v = load2(make_rsrc(line + (size_t)q * pitch, rowb), off, 0);
+                        cs += fmaf(f, v.y - v.x, v.x);
+                    }
+                    acc[r] += cs;
+                }
             }
-            for (; q < cnt; ++q) {
-                const float loc = fmaf((float)q, stepf, base64);
-                const float f = __builtin_amdgcn_fractf(loc);
-                const unsigned off = ((unsigned)loc << 2) + ib4;
-                const v2f v = load2(make_rsrc(line + (size_t)q * pitch, rowb), off, 0);
-                cs += fmaf(f, v.y - v.x, v.x);
+        } else {
+            // Two adjacent rays per lane from one 4-pixel read: at every line the
+            // lower-positioned ray sits at loc (pixels i, i+1 of the read) and the
+            // other at loc + |aj|, 1 <= |aj| < 2 bins apart, i.e. at t = f + |aj| - 1
+            // in [0, 2) from pixel i+1: the piecewise-linear interpolation
+            // v1 + clamp(t)(v2 - v1) + clamp(t - 1)(v3 - v2) over the same read.
+            const int lo_r = A.aj < 0.0 ? 1 : 0;      // which of the two is lower
+            const double pj = A.a0 + (double)(j0 + lo_r) * A.aj;
+            const float c1 = (float)(fabs(A.aj) - 1.0);
+            const float c2 = (float)(fabs(A.aj) - 2.0);
+            float cl = 0.f, ch = 0.f;
+            for (int oc = s0; oc < s1; oc += 32) {
+                const double p0 = fma((double)oc, A.step, pj);
+                const double fl0 = fmin(fmax(floor(p0), -1.0e6), 1.0e6);
+                const float base64 = (float)(p0 - fl0) + 64.f;
+                unsigned ib4 = (unsigned)((int)fl0 - 64) * 4u;
+                asm("" : "+v"(ib4));
+                const int cnt = min(32, s1 - oc);
+                gcfloat* line = img + (size_t)oc * pitch;
+                float sl = 0.f, sh = 0.f;
+                int q = 0;
+                auto term = [&](float f, v4f v) {
+                    sl += fmaf(f, v.y - v.x, v.x);
+                    const float w1 = __builtin_amdgcn_fmed3f(f + c1, 0.f, 1.f);
+                    const float w2 = __builtin_amdgcn_fmed3f(f + c2, 0.f, 1.f);
+                    sh += v.y;
+                    sh = fmaf(w1, v.z - v.y, sh);
+                    sh = fmaf(w2, v.w - v.z, sh);
+                };
+                if (cnt == 32) {
+                    float f[32];
+                    v4f v[32];
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) {
+                        const float loc = fmaf((float)u, stepf, base64);
+                        f[u] = __builtin_amdgcn_fractf(loc);
+                        const unsigned off = ((unsigned)loc << 2) + ib4;
+                        v[u] = load4(make_rsrc(line + (size_t)u * pitch, rowb), off, 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) term(f[u], v[u]);
+                    q = 32;
+                }
+                for (; q + 8 <= cnt; q += 8) {
+                    const float b8 = fmaf((float)q, stepf, base64);
+                    float f[8];
+                    v4f v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const float loc = fmaf((float)u, stepf, b8);
+                        f[u] = __builtin_amdgcn_fractf(loc);
+                        const unsigned off = ((unsigned)loc << 2) + ib4;
+                        v[u] = load4(make_rsrc(line + (size_t)(q + u) * pitch, rowb), off, 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) term(f[u], v[u]);
+                }
+                for (; q < cnt; ++q) {
+                    const float loc = fmaf((float)q, stepf, base64);
+                    const unsigned off = ((unsigned)loc << 2) + ib4;
+                    term(__builtin_amdgcn_fractf(loc),
+                         load4(make_rsrc(line + (size_t)q * pitch, rowb), off, 0));
+                }
+                cl += sl;
+                ch += sh;
             }
-            acc += cs;
+            acc[lo_r] = cl;
+            acc[1 - lo_r] = ch;
         }
     }
     if (SEG > 1) {
-        red[threadIdx.x] = acc;
+#pragma unroll
+        for (int r = 0; r < RP; ++r) red[r * 256 + threadIdx.x] = acc[r];
         __syncthreads();
         if (seg != 0) return;
-        acc = 0.f;
 #pragma unroll
-        for (int q = 0; q < SEG; ++q) acc += red[(sub * SEG + q) * 64 + lane];
+        for (int r = 0; r < RP; ++r) {
+            acc[r] = 0.f;
+#pragma unroll
+            for (int q = 0; q < SEG; ++q) acc[r] += red[r * 256 + (sub * SEG + q) * 64 + lane];
+        }
     }
-    if (j >= A.w) return;
 
-    const float fpv = acc * A.inv_m;
     float* y = J->y;
     float* gout = J->gout;
-    switch (mode) {
-        case FP_STORE:
-            if (ondet) gout[gidx] = fpv;
-            break;
-        case FP_ACCUM:
-            if (ondet) gout[gidx] = pre0 + fpv;
-            break;
-        case FP_BAND_FROM_GLOBAL:
-            y[bidx] = ondet ? pre0 + J->scale * fpv : 0.f;
-            break;
-        case FP_BAND_ADD:
-            y[bidx] = ondet ? pre0 + J->scale * fpv : 0.f;
-            break;
-        case FP_CP_DUAL:
-            // prox of sigma F1*, F1(v) = ||v - b||^2 (or 1/2 ||v - b||^2), on B * y
-            y[bidx] = ondet ? (pre0 + (J->sigma * A.bscale) * (fpv - pre1)) * J->dual_div : 0.f;
-            break;
-        case FP_SIRT:
-            y[bidx] = ondet ? (J->alpha * A.bscale) * (pre1 - fpv) : 0.f;
-            break;
-        case FP_BAND_STORE:
-            y[bidx] = ondet ? A.bscale * fpv : 0.f;
-            break;
-        case FP_RESID:
-            if (ondet) gout[gidx] = pre0 + J->scale * fpv;
-            break;
-        default:
-            break;
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+        const int j = j0 + r;
+        if (j >= A.w) break;
+        const int gi = A.i0 + j;
+        const bool ondet = (gi >= 0) && (gi < J->n_det);
+        const size_t bidx = (size_t)k * J->bpitch + 1 + j;
+        const size_t gidx = (size_t)k * J->n_det + gi;
+        const float fpv = acc[r] * A.inv_m;
+        switch (mode) {
+            case FP_STORE:
+                if (ondet) gout[gidx] = fpv;
+                break;
+            case FP_ACCUM:
+                if (ondet) gout[gidx] = pre0[r] + fpv;
+                break;
+            case FP_BAND_FROM_GLOBAL:
+                y[bidx] = ondet ? pre0[r] + J->scale * fpv : 0.f;
+                break;
+            case FP_BAND_ADD:
+                y[bidx] = ondet ? pre0[r] + J->scale * fpv : 0.f;
+                break;
+            case FP_CP_DUAL:
+                // prox of sigma F1*, F1(v) = ||v - b||^2 (or 1/2 ||v - b||^2), on B * y
+                y[bidx] = ondet ? (pre0[r] + (J->sigma * A.bscale) * (fpv - pre1[r])) * J->dual_div : 0.f;
+                break;
+            case FP_SIRT:
+                y[bidx] = ondet ? (J->alpha * A.bscale) * (pre1[r] - fpv) : 0.f;
+                break;
+            case FP_BAND_STORE:
+                y[bidx] = ondet ? A.bscale * fpv : 0.f;
+                break;
+            case FP_RESID:
+                if (ondet) gout[gidx] = pre0[r] + J->scale * fpv;
+                break;
+            default:
+                break;
+        }
     }
 }
 
@@ -400,7 +516,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
             const int lr = q / (TW + 2), lc = q % (TW + 2);
             const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
             float v = 0.f;
-            if (rr >= 0 && rr < nr && cc >= -1 && cc <= nc) v = xb[(size_t)rr * xp + cc + 1];
+            if (rr >= 0 && rr < nr && cc >= -1 && cc <= nc) v = xb[(size_t)rr * xp + cc + kLpad];
             xs[lr][lc] = v;
         }
         __syncthreads();
@@ -703,8 +819,8 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                     x[xi] = v;
                     float* xb0 = J->xb[0];
                     float* xt = J->xt;
-                    if (xb0) xb0[(size_t)r * J->xp + c + 1] = v;
-                    if (xt) xt[(size_t)c * J->tp + r + 1] = v;
+                    if (xb0) xb0[(size_t)r * J->xp + c + kLpad] = v;
+                    if (xt) xt[(size_t)c * J->tp + r + kLpad] = v;
                 } break;
                 case BP_ACCUM:
                     x[xi] = xo[q] + J->scale * acc[q];
@@ -716,8 +832,8 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                     float* xbw = J->xb[wpar];
                     float* xt = J->xt;
                     float* zw = J->z[wpar];
-                    xbw[(size_t)r * J->xp + c + 1] = xbn;
-                    xt[(size_t)c * J->tp + r + 1] = xbn;
+                    xbw[(size_t)r * J->xp + c + kLpad] = xbn;
+                    xt[(size_t)c * J->tp + r + kLpad] = xbn;
                     const size_t zi = (size_t)r * nc + c;
                     zw[zi] = zn0[q];
                     zw[(size_t)nr * nc + zi] = zn1[q];
@@ -727,8 +843,8 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                     x[xi] = xn;
                     float* xbw = J->xb[wpar];
                     float* xt = J->xt;
-                    xbw[(size_t)r * J->xp + c + 1] = xn;
-                    xt[(size_t)c * J->tp + r + 1] = xn;
+                    xbw[(size_t)r * J->xp + c + kLpad] = xn;
+                    xt[(size_t)c * J->tp + r + kLpad] = xn;
                 } break;
                 case BP_POWER: {
                     const float w = acc[q] - divv[q];
@@ -769,11 +885,11 @@ __global__ void fill_padded_kernel(float* __restrict__ xb, float* __restrict__ x
          i += (size_t)gridDim.x * blockDim.x) {
         if (i < nb) {
             const int cc = (int)(i % xp);
-            xb[i] = (cc >= 1 && cc <= nc) ? v : 0.f;
+            xb[i] = (cc >= kLpad && cc < nc + kLpad) ? v : 0.f;
         } else {
             const size_t q = i - nb;
             const int rr = (int)(q % tp);
-            xt[q] = (rr >= 1 && rr <= nr) ? v : 0.f;
+            xt[q] = (rr >= kLpad && rr < nr + kLpad) ? v : 0.f;
         }
     }
 }
@@ -790,7 +906,7 @@ __global__ void pad_copy_kernel(const float* __restrict__ src, int lds, int r0, 
         float v = 0.f;
         if (rr < nr && cc < nc) {
             v = src[(size_t)(r0 + rr) * lds + c0 + cc];
-            if (xb) xb[(size_t)rr * xp + cc + 1] = v;
+            if (xb) xb[(size_t)rr * xp + cc + kLpad] = v;
             if (dst) dst[(size_t)rr * ldd + cc] = v;
         }
         tile[q][tx] = v;
@@ -799,7 +915,7 @@ __global__ void pad_copy_kernel(const float* __restrict__ src, int lds, int r0, 
     __syncthreads();
     for (int q = ty; q < 32; q += 8) {
         const int cc = bc + q, rr = br + tx;
-        if (rr < nr && cc < nc) xt[(size_t)cc * tp + rr + 1] = tile[tx][q];
+        if (rr < nr && cc < nc) xt[(size_t)cc * tp + rr + kLpad] = tile[tx][q];
     }
 }
 
@@ -916,8 +1032,8 @@ __global__ __launch_bounds__(256) void power_normalize_kernel(
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
         const int rr = (int)(i / nc), cc = (int)(i % nc);
         const float v = w[(size_t)rr * ldx + cc] * inv;
-        xb[(size_t)rr * xp + cc + 1] = v;
-        xt[(size_t)cc * tp + rr + 1] = v;
+        xb[(size_t)rr * xp + cc + kLpad] = v;
+        xt[(size_t)cc * tp + rr + kLpad] = v;
     }
 }
 
@@ -933,14 +1049,21 @@ inline unsigned pad8(int n) { return (unsigned)((n + 7) & ~7); }
 }  // namespace
 
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
-                     hipStream_t s, int contiguous) {
+                     hipStream_t s, int contiguous, int rays_per_lane) {
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items)), block(256);
-    switch (segments) {
-        case 1: hipLaunchKernelGGL(fp_kernel<1>, grid, block, 0, s, jobs, items, n_items, step, contiguous); break;
-        case 2: hipLaunchKernelGGL(fp_kernel<2>, grid, block, 0, s, jobs, items, n_items, step, contiguous); break;
-        default: hipLaunchKernelGGL(fp_kernel<4>, grid, block, 0, s, jobs, items, n_items, step, contiguous); break;
+#define TOMO_FP(SG, R) \
+    hipLaunchKernelGGL((fp_kernel<SG, R>), grid, block, 0, s, jobs, items, n_items, step, contiguous)
+    if (rays_per_lane == 2) {   // one segment per ray
+        TOMO_FP(1, 2);
+    } else {
+        switch (segments) {
+            case 1: TOMO_FP(1, 1); break;
+            case 2: TOMO_FP(2, 1); break;
+            default: TOMO_FP(4, 1); break;
+        }
     }
+#undef TOMO_FP
     return hipGetLastError();
 }
 

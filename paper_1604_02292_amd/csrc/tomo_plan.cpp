@@ -68,12 +68,12 @@ Plan make_plan(const Geom& g, const Rect& reg, const Rect& bsrc) {
         AngFP& a = P.afp[k];
         std::memset(&a, 0, sizeof a);
         if (g.ystep[k]) {   // ray j meets row r at column (D + j sp - r s) / c
-            a.a0 = D / c + 1.0;
+            a.a0 = D / c + kLpad;
             a.aj = sp / c;
             a.step = -s / c;
             a.tr = 0;
         } else {            // ray j meets column q at row (D + j sp - q c) / s
-            a.a0 = D / s + 1.0;
+            a.a0 = D / s + kLpad;
             a.aj = sp / s;
             a.step = -c / s;
             a.tr = 1;
@@ -95,8 +95,8 @@ Plan make_plan(const Geom& g, const Rect& reg, const Rect& bsrc) {
     }
     // at least 64 entries: the backprojector stages 64-entry windows of each row
     P.bpitch = std::max(64, round_up(P.wmax + 3, 4));
-    P.xp = round_up(reg.cols + 3, 4);
-    P.tp = round_up(reg.rows + 3, 4);
+    P.xp = round_up(reg.cols + kLpad + 2, 4);
+    P.tp = round_up(reg.rows + kLpad + 2, 4);
     return P;
 }
 

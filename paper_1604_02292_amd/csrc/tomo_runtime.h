@@ -175,6 +175,7 @@ struct RoiState {
 
 struct LaunchCfg {
     int seg = 4, ag = 4, ppt = 1;
+    int rp = 1;             // forward projector rays per lane (2 only with seg 1)
     int cfp = 1, cbp = 1;   // XCD order of FP / BP items: 1 contiguous, 0 round-robin
     int staged = 0;         // backprojector variant: 1 = LDS-staged band windows
 };
@@ -193,11 +194,11 @@ size_t step_size_scratch_bytes(tomo_ctx* ctx, int gid, const RoiState& st);
 tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, Staging& stg);
 Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int ntc);
 // Work items; the device table pointers must already be known (items store them).
-void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg,
+void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg, int rp,
               const AngFP* d_afp);
 void bp_items(std::vector<Item>& out, int jj, int nr, int nc, int ag, int ppt,
               const AngBP* d_abp);
-size_t count_fp_items(const std::vector<AngFP>& afp, int seg);
+size_t count_fp_items(const std::vector<AngFP>& afp, int seg, int rp = 1);
 size_t count_bp_items(int nr, int nc, int ag, int ppt);
 void carve_state(const Geom& g, RoiState& st, char* blk);
 tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, float* xb, float* xt,

@@ -108,14 +108,14 @@ tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s) {
     Meta m;
     const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
     const size_t o_job = m.reserve(sizeof(Job));
-    const size_t o_it = m.reserve(count_fp_items(P.afp, L.seg) * sizeof(Item));
+    const size_t o_it = m.reserve(count_fp_items(P.afp, L.seg, L.rp) * sizeof(Item));
     char* dm = ctx->arena.alloc(m.buf.size());
     if (!dm) {
         ctx->arena.free_after(allocs, s);
         return fail(ctx, TOMO_ENOMEM, "workspace too small for the residual tables");
     }
     allocs.push_back(dm);
-    fp_items(items, 0, P.afp, L.seg, (const AngFP*)(dm + o_afp));
+    fp_items(items, 0, P.afp, L.seg, L.rp, (const AngFP*)(dm + o_afp));
     m.put(o_it, items.data(), items.size() * sizeof(Item));
     Job J;
     std::memset(&J, 0, sizeof J);
@@ -137,7 +137,7 @@ tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s) {
     if (e == hipSuccess) e = launch_fill(S.resid, nr, 0.f, s);
     if (e == hipSuccess)
         e = launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(), 0,
-                      L.seg, s);
+                      L.seg, s, L.cfp, L.rp);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     ctx->arena.free_after(allocs, s);
     if (e != hipSuccess) return fail(ctx, TOMO_EHIP, "registering: %s", hipGetErrorString(e));
@@ -157,13 +157,13 @@ tomo_status prepare_slot(tomo_ctx* ctx, ServeState& S, Slot& sl) {
     const size_t o_abp = m.add(r.plan.abp.data(), r.plan.abp.size() * sizeof(AngBP));
     const size_t o_job = m.reserve(sizeof(Job));
     std::vector<Item> items;
-    const size_t o_it = m.reserve(count_fp_items(r.plan.afp, kServeSeg) * sizeof(Item));
+    const size_t o_it = m.reserve(count_fp_items(r.plan.afp, kServeSeg, 1) * sizeof(Item));
     char* dm = ctx->arena.alloc(m.buf.size(), false);
     if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace full");
     sl.allocs.push_back(dm);
     r.d_afp = (AngFP*)(dm + o_afp);
     r.d_abp = (AngBP*)(dm + o_abp);
-    fp_items(items, 0, r.plan.afp, kServeSeg, r.d_afp);
+    fp_items(items, 0, r.plan.afp, kServeSeg, 1, r.d_afp);
     m.put(o_it, items.data(), items.size() * sizeof(Item));
     Job J = make_job(g, r, FP_BAND_FROM_GLOBAL, BP_STORE, 0);
     J.xb[1] = J.xb[0];
@@ -311,7 +311,7 @@ void scheduler(tomo_ctx* ctx) {
                                  (sl.st.ext.cols + tw - 1) / tw);
                 J.parity0 = sl.parity0;
                 jobs.push_back(J);
-                fp_items(fi, (int)q, sl.st.plan.afp, kServeSeg, sl.st.d_afp);
+                fp_items(fi, (int)q, sl.st.plan.afp, kServeSeg, 1, sl.st.d_afp);
                 bp_items(bi, (int)q, sl.st.ext.rows, sl.st.ext.cols, kServeAG, kServePPT,
                          sl.st.d_abp);
             }

@@ -195,10 +195,11 @@ class Context:
     def tomo_serving_config(self, max_slots=0, iters_per_tick=0):
         self._check(self.lib.tomo_serving_config(self.h, int(max_slots), int(iters_per_tick)))
 
-    def tomo_set_launch(self, fp_segments=0, fp_xcd_order=0, bp_variant=0, bp_groups=0,
-                        bp_pixels_per_thread=0, bp_xcd_order=0):
-        k = tomo_launch(int(fp_segments), int(fp_xcd_order), int(bp_variant), int(bp_groups),
-                        int(bp_pixels_per_thread), int(bp_xcd_order))
+    def tomo_set_launch(self, fp_segments=0, fp_rays_per_lane=0, fp_xcd_order=0, bp_variant=0,
+                        bp_groups=0, bp_pixels_per_thread=0, bp_xcd_order=0):
+        k = tomo_launch(int(fp_segments), int(fp_rays_per_lane), int(fp_xcd_order),
+                        int(bp_variant), int(bp_groups), int(bp_pixels_per_thread),
+                        int(bp_xcd_order))
         self._check(self.lib.tomo_set_launch(self.h, C.byref(k)))
 
     def tomo_get_launch(self):
