@@ -417,9 +417,9 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     __shared__ float xs[TH + 2][TW + 2];
     __shared__ float zs0[TH + 1][TW + 1];
     __shared__ float zs1[TH + 1][TW + 1];
-    __shared__ float red[PPT][256];
+    __shared__ float red[PPT][AG > 1 ? 256 : 1];   // group partial sums (and the power sums)
     // Per-angle anchors of the tile, ANC per pass (AG groups x PA angles).
-    constexpr int ANC = 1024, PA = ANC / AG;
+    constexpr int ANC = STAGED ? 256 : 512, PA = ANC / AG;   // (sized for LDS occupancy)
     // Staged band windows: WS entries per angle starting SHIFT below the
     // anchor; a pixel's offset from the anchor is at most
     // sqrt((TW/2)^2 + (TH/2)^2) <= 18 bins, so its pair lies inside the window.
@@ -857,16 +857,19 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         }
     }
     if (mode == BP_POWER) {
+        // block sum of the squares, in the anchor table's LDS (no longer needed)
+        static_assert(sizeof(anc) >= 256 * sizeof(float), "anchor table too small to reuse");
+        float* psum = (float*)anc;
         __syncthreads();
-        red[0][t] = sq;
+        psum[t] = sq;
         __syncthreads();
         for (int h = 128; h > 0; h >>= 1) {
-            if (t < h) red[0][t] += red[0][t + h];
+            if (t < h) psum[t] += psum[t + h];
             __syncthreads();
         }
         if (t == 0) {
             float* part = J->part;
-            part[it.a * J->ntc + it.b] = red[0][0];
+            part[it.a * J->ntc + it.b] = psum[0];
         }
     }
 }
