@@ -21,6 +21,9 @@ Contents and the passages they follow:
              power iteration for the CP step size
   local      extended local part (Section 3.3), exterior subtraction via W = W_L + W_F
              (eq. locouter), the local solve, crop and stitch (Section 5.6)
+  filters    SIRT-approximating FBP filters (Alg. 1, eq. filtcalc, eq. sirtapp), the
+             per-angle detector convolution C_u, and the paper's local method
+             (eq. localmethod, Alg. 2) with the box prior of eq. sirtbox
 
 Every function is pinned by tests in tests/test_oracle_*.py against facts the paper
 or mathematics fixes (adjoint identity between two independent projector codes,
@@ -36,11 +39,14 @@ from .fbp import ramlak_taps, ramp_filter, fbp_ramlak
 from .tv import grad, div, tv_iso, tv_aniso
 from .solvers import (cp_tv_nonneg, sirt_nonneg, power_norm_sq, cp_objective, cp_steps)
 from .local import exterior_subtract, local_solve, crop, stitch
+from .filters import (sirt_filters, filter_centres, filter_apply, fbp_filter, sirt_iterates,
+                      local_method_box)
 
 __all__ = [
     "Geometry", "make_geometry", "roi_extend", "band_exact", "hat_weight", "fp_ray",
     "bp_pixel", "sparse_local", "dense_matrix_hat", "dense_matrix_ray", "ramlak_taps",
     "ramp_filter", "fbp_ramlak", "grad", "div", "tv_iso", "tv_aniso", "cp_tv_nonneg",
     "sirt_nonneg", "power_norm_sq", "cp_objective", "cp_steps", "exterior_subtract",
-    "local_solve", "crop", "stitch",
+    "local_solve", "crop", "stitch", "sirt_filters", "filter_centres", "filter_apply",
+    "fbp_filter", "sirt_iterates", "local_method_box",
 ]
