@@ -127,20 +127,27 @@ tomo_status tomo_exterior_subtract(tomo_ctx* ctx, int32_t geom, tomo_rect ext_ro
 
 typedef enum {
     ROI_TV_NONNEG_CP = 0,   /* Chambolle-Pock on ||W_L x - b||^2 + lambda TV(x), x >= 0 */
-    ROI_NONNEG_SIRT = 1     /* x <- max(0, x + alpha W_L^T (b - W_L x)), alpha = 1/(N_theta N_d)
-                               (eq. sirtit with the box of eq. sirtbox, l = 0, r = inf) */
+    ROI_NONNEG_SIRT = 1,    /* x <- P(x + alpha W_L^T (b - W_L x)), alpha = 1/(N_theta N_d),
+                               P the box of eq. sirtbox: [0, inf), or [box_lo, box_hi] with
+                               ROI_FLAG_BOX (eq. sirtit) */
+    ROI_LOCAL_SIRT = 2      /* the paper's local method (Section 3.2, eq. localmethod, Alg. 2)
+                               for SIRT with the box prior of eq. sirtbox; only through
+                               roi_solve_local */
 } roi_method;
 
 enum {
     ROI_FLAG_HALF_DATA = 1, /* use 1/2 ||W_L x - b||^2 as the data term */
-    ROI_FLAG_ANISO_TV = 2   /* anisotropic TV (sum of |d/dr| + |d/dc|) */
+    ROI_FLAG_ANISO_TV = 2,  /* anisotropic TV (sum of |d/dr| + |d/dc|) */
+    ROI_FLAG_BOX = 4        /* SIRT-type methods: box [box_lo, box_hi] instead of [0, inf) */
 };
 
 /* One local reconstruction request.  roi: the part the caller wants; margin:
  * padding on each side (Section 3.3), clipped to the grid; lambda: TV weight;
  * iters: fixed iteration count (no early stop); sigma, tau: CP step sizes, or
  * 0 for sigma = tau = 1/sqrt(1.01 * lambda_max(W_L^T W_L - Laplacian))
- * from a cached power iteration (per geometry and extended shape). */
+ * from a cached power iteration (per geometry and extended shape); box_lo,
+ * box_hi: the box of SIRT-type methods when flags has ROI_FLAG_BOX (box_lo may
+ * be -inf, box_hi +inf; box_lo <= box_hi; not accepted for CP). */
 typedef struct {
     tomo_rect roi;
     int32_t margin;
@@ -149,6 +156,7 @@ typedef struct {
     int32_t iters;
     float sigma, tau;
     uint32_t flags;     /* ROI_FLAG_* */
+    float box_lo, box_hi;
 } roi_params;
 
 /* Solve one ROI: extend, subtract the exterior (x_ext = float[n][n], or NULL to
@@ -165,6 +173,45 @@ tomo_status roi_solve(tomo_ctx* ctx, int32_t geom, const float* sino, const floa
  * pointer to float[roi.rows][roi.cols].  Each result equals the one roi_solve
  * gives for the same ROI.  Errors as roi_solve. */
 tomo_status roi_solve_batch(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                            int32_t count, const roi_params* params, float* const* outs,
+                            void* hip_stream);
+
+/* SIRT-approximating FBP filters (Section 3.1: eq. filtcalc, eq. sirtapp, Alg. 1).
+ * filters: device float[iters][n_angles][n_det], caller-owned; plane k - 1
+ * receives u_k = alpha W q_k with q_k = sum_{j<k} A^j e, A = I - alpha W^T W,
+ * alpha = 1/(n_angles n_det) and e the unit image at pixel (n/2, n/2) (the grid
+ * centre for odd n).  One projection and one backprojection of the whole grid per
+ * filter, each from the previous one, in FP32; the filters depend only on the
+ * geometry.  Stream-ordered on hip_stream.
+ * Errors: EINVAL (iters < 1, null pointer), ENOENT, ENOMEM, EHIP. */
+tomo_status tomo_sirt_filters(tomo_ctx* ctx, int32_t geom, int32_t iters, float* filters,
+                              void* hip_stream);
+
+/* Filtered data of the local method (Section 3.1 eq. sirtapp; Section 3.3: computed
+ * once per sinogram and shared by all local parts): for k < count,
+ *   out[k][a][i] = sum_j filters[k][a][i - j + c_a] sino[a][j],
+ * terms with an index outside [0, n_det) being zero, where c_a is the bin nearest
+ * the projection of pixel (n/2, n/2) at angle a (the filters' zero lag), decided
+ * in FP64.  filters, sino (float[n_angles][n_det]) and out (float[count][n_angles]
+ * [n_det]) are caller-owned device arrays.  Computed by FFT in FP32; n_det <= 8192.
+ * Stream-ordered.  Errors: EINVAL (count < 1, n_det > 8192, null), ENOENT,
+ * ENOMEM, EHIP. */
+tomo_status tomo_sirt_filter_sino(tomo_ctx* ctx, int32_t geom, const float* filters,
+                                  int32_t count, const float* sino, float* out,
+                                  void* hip_stream);
+
+/* The paper's local method (Section 3.2: eq. localmethod, Alg. 2) with SIRT and the
+ * box prior of eq. sirtbox, for `count` independent ROIs together.  On the extended
+ * part L of each ROI, from v = 0, for k = 1..iters:
+ *   x = P(v + W_L^T (d_k - alpha W_L v)),   v <- x - W_L^T d_k,
+ * with d_k = filtered[k - 1] (tomo_sirt_filter_sino: W_L^T d_k is the local SIRT
+ * approximation FBP_L(p, u_k)), alpha = 1/(n_angles n_det) and P the box of the
+ * request; the crop of x is written to outs[i] (float[roi.rows][roi.cols], device).
+ * filtered: device float[planes][n_angles][n_det]; params and outs are host
+ * arrays of count entries; every params[i].method is ROI_LOCAL_SIRT with
+ * iters <= planes (lambda, sigma, tau are ignored).  Stream-ordered.
+ * Errors: EINVAL, ENOENT, ENOMEM, EHIP. */
+tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, int32_t planes,
                             int32_t count, const roi_params* params, float* const* outs,
                             void* hip_stream);
 
@@ -222,6 +269,7 @@ tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
  *                         item list per XCD (L2 locality), 2 = round-robin
  *   bp_variant            backprojector: 1 = direct band reads from memory,
  *                         2 = band windows staged in LDS per block of angles
+ *                         (roi_solve_local always reads directly)
  *   bp_groups             backprojector angle groups per pixel, 1, 2 or 4
  *                         (variant 2 always uses 1)
  *   bp_pixels_per_thread  1 or 2

@@ -15,8 +15,8 @@ TOMO_OK, TOMO_EINVAL, TOMO_ENOMEM, TOMO_EHIP, TOMO_EBUSY, TOMO_ENOENT, TOMO_EAGA
 STATUS_NAMES = {0: "TOMO_OK", -1: "TOMO_EINVAL", -2: "TOMO_ENOMEM", -3: "TOMO_EHIP",
                 -4: "TOMO_EBUSY", -5: "TOMO_ENOENT", -6: "TOMO_EAGAIN", -7: "TOMO_ESTATE"}
 
-ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT = 0, 1
-ROI_FLAG_HALF_DATA, ROI_FLAG_ANISO_TV = 1, 2
+ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT, ROI_LOCAL_SIRT = 0, 1, 2
+ROI_FLAG_HALF_DATA, ROI_FLAG_ANISO_TV, ROI_FLAG_BOX = 1, 2, 4
 
 
 class tomo_rect(C.Structure):
@@ -27,7 +27,8 @@ class tomo_rect(C.Structure):
 class roi_params(C.Structure):
     _fields_ = [("roi", tomo_rect), ("margin", C.c_int32), ("method", C.c_int32),
                 ("lambda_", C.c_float), ("iters", C.c_int32), ("sigma", C.c_float),
-                ("tau", C.c_float), ("flags", C.c_uint32)]
+                ("tau", C.c_float), ("flags", C.c_uint32), ("box_lo", C.c_float),
+                ("box_hi", C.c_float)]
 
 
 class tomo_launch(C.Structure):
@@ -55,6 +56,9 @@ SIGNATURES = {
     "roi_solve": (C.c_int, [_P, _I, _P, _P, C.POINTER(roi_params), _P, _P]),
     "roi_solve_batch": (C.c_int, [_P, _I, _P, _P, _I, C.POINTER(roi_params), C.POINTER(_P), _P]),
     "roi_step_size": (C.c_int, [_P, _I, tomo_rect, C.POINTER(C.c_float)]),
+    "tomo_sirt_filters": (C.c_int, [_P, _I, _I, _P, _P]),
+    "tomo_sirt_filter_sino": (C.c_int, [_P, _I, _P, _I, _P, _P, _P]),
+    "roi_solve_local": (C.c_int, [_P, _I, _P, _I, _I, C.POINTER(roi_params), C.POINTER(_P), _P]),
     "tomo_register_sinogram": (C.c_int, [_P, _I, _P, C.POINTER(_I)]),
     "tomo_unregister_sinogram": (C.c_int, [_P, _I]),
     "roi_submit": (C.c_int, [_P, _I, C.POINTER(roi_params), _P, C.POINTER(C.c_uint64)]),

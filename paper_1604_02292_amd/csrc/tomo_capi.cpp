@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 
 #include "tomo_runtime.h"
 #include "tomo_serve.h"
@@ -100,10 +101,15 @@ tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p) {
     if (p.margin < 0) return fail(ctx, TOMO_EINVAL, "margin < 0");
     if (p.iters <= 0) return fail(ctx, TOMO_EINVAL, "iters must be > 0");
     if (!(p.lambda >= 0.f) || !std::isfinite(p.lambda)) return fail(ctx, TOMO_EINVAL, "lambda must be >= 0");
-    if (p.method != ROI_TV_NONNEG_CP && p.method != ROI_NONNEG_SIRT)
+    if (p.method != ROI_TV_NONNEG_CP && p.method != ROI_NONNEG_SIRT && p.method != ROI_LOCAL_SIRT)
         return fail(ctx, TOMO_EINVAL, "unknown method %d", p.method);
     if (!(p.sigma >= 0.f) || !(p.tau >= 0.f)) return fail(ctx, TOMO_EINVAL, "negative step size");
-    if (p.flags & ~3u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & ~7u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & ROI_FLAG_BOX) {
+        if (p.method == ROI_TV_NONNEG_CP)
+            return fail(ctx, TOMO_EINVAL, "ROI_FLAG_BOX applies to the SIRT-type methods only");
+        if (!(p.box_lo <= p.box_hi)) return fail(ctx, TOMO_EINVAL, "box needs box_lo <= box_hi");
+    }
     return TOMO_OK;
 }
 
@@ -129,6 +135,9 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
     J.dual_div = (float)(1.0 / (1.0 + (half ? (double)st.sigma : 0.5 * (double)st.sigma)));
     J.alpha = (float)(1.0 / ((double)g.na * (double)g.nd));
     J.scale = 1.f;
+    const bool box = (st.prm.flags & ROI_FLAG_BOX) != 0;
+    J.lo = box ? st.prm.box_lo : 0.f;
+    J.hi = box ? st.prm.box_hi : INFINITY;
     J.afp = st.d_afp;
     J.abp = st.d_abp;
     J.x = st.x;
@@ -402,6 +411,73 @@ size_t step_size_scratch_bytes(tomo_ctx* ctx, int gid, const RoiState& st) {
     return state_bytes(g, p) + tables + items + 4096;
 }
 
+// Launches an iteration loop: replays the cached graph of `key` (a work-list
+// layout) when there is one, captures it on the key's second use, and launches
+// eagerly otherwise.  `enqueue` issues the whole loop on a stream, reading the
+// descriptors of m2 from a device copy at the given base.
+tomo_status run_loop(tomo_ctx* ctx, const std::vector<long long>& key, const Meta& m2,
+                     const std::function<hipError_t(char*, hipStream_t)>& enqueue, hipStream_t s,
+                     std::vector<char*>& allocs) {
+    GraphEntry* ge = nullptr;
+    if (ctx->use_graphs) {
+        auto git = ctx->graphs.find(key);
+        if (git != ctx->graphs.end()) {
+            ge = &git->second;
+        } else if (++ctx->graph_seen[key] >= 2) {
+            // second solve with this layout: capture the loop once and keep it
+            if (ctx->graphs.size() >= 32) {   // evict the least recently used entry
+                auto old = ctx->graphs.begin();
+                for (auto q = ctx->graphs.begin(); q != ctx->graphs.end(); ++q)
+                    if (q->second.stamp < old->second.stamp) old = q;
+                GraphEntry& o = old->second;
+                if (o.last) (void)hipEventSynchronize(o.last);
+                if (o.exec) (void)hipGraphExecDestroy(o.exec);
+                if (o.graph) (void)hipGraphDestroy(o.graph);
+                if (o.last) (void)hipEventDestroy(o.last);
+                ctx->arena.free_now(o.dbuf);
+                ctx->graphs.erase(old);
+            }
+            GraphEntry E2;
+            E2.bytes = m2.buf.size();
+            E2.dbuf = ctx->arena.alloc(E2.bytes);
+            bool ok = E2.dbuf != nullptr;
+            if (ok && !ctx->cap_stream)
+                ok = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
+            if (ok) ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) ==
+                         hipSuccess;
+            if (ok) {
+                const hipError_t le = enqueue(E2.dbuf, ctx->cap_stream);
+                const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &E2.graph);
+                ok = le == hipSuccess && ce == hipSuccess && E2.graph;
+            }
+            if (ok) ok = hipGraphInstantiate(&E2.exec, E2.graph, nullptr, nullptr, 0) == hipSuccess;
+            if (ok) ok = hipEventCreateWithFlags(&E2.last, hipEventDisableTiming) == hipSuccess;
+            if (ok) {
+                ge = &(ctx->graphs[key] = E2);
+            } else {   // fall back to eager launches
+                (void)hipGetLastError();
+                if (E2.exec) (void)hipGraphExecDestroy(E2.exec);
+                if (E2.graph) (void)hipGraphDestroy(E2.graph);
+                if (E2.dbuf) ctx->arena.free_now(E2.dbuf);
+            }
+        }
+    }
+    if (ge) {
+        ge->stamp = ++ctx->graph_clock;
+        TOMO_HIP(ctx, hipStreamWaitEvent(s, ge->last, 0));
+        TOMO_HIP(ctx, ctx->staging.upload(ge->dbuf, m2.buf.data(), m2.buf.size(), s));
+        TOMO_HIP(ctx, hipGraphLaunch(ge->exec, s));
+        TOMO_HIP(ctx, hipEventRecord(ge->last, s));
+        return TOMO_OK;
+    }
+    char* dm2 = ctx->arena.alloc(m2.buf.size());
+    if (!dm2) return fail(ctx, TOMO_ENOMEM, "workspace too small for the iteration tables");
+    allocs.push_back(dm2);
+    TOMO_HIP(ctx, ctx->staging.upload(dm2, m2.buf.data(), m2.buf.size(), s));
+    TOMO_HIP(ctx, enqueue(dm2, s));
+    return TOMO_OK;
+}
+
 // The batched solve (one sinogram, many ROIs).  `reg` (optional) is a
 // registered sinogram whose x_ext and residual r = p - W x_ext are resident.
 tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* x_ext_user,
@@ -415,6 +491,8 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     for (int i = 0; i < count; ++i) {
         tomo_status st = validate_params(ctx, g, params[i]);
         if (st != TOMO_OK) return st;
+        if (params[i].method == ROI_LOCAL_SIRT)
+            return fail(ctx, TOMO_EINVAL, "ROI_LOCAL_SIRT requests go through roi_solve_local");
         if (!outs[i]) return fail(ctx, TOMO_EINVAL, "null output pointer for ROI %d", i);
         RoiState& r = R[i];
         r.prm = params[i];
@@ -707,62 +785,19 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         }
         for (auto& r : R) CK(launch_fill((float*)r.block, r.state_floats, 0.f, s));
     }
-    GraphEntry* ge = nullptr;
-    if (ctx->use_graphs && !timed) {
-        std::vector<long long> key = {max_it, L.seg, L.ag, count, (long long)m2.buf.size()};
+    if (!timed) {
+        std::vector<long long> key = {0,     max_it, L.seg, L.ag,  L.ppt, L.rp,
+                                      L.staged, L.cfp, L.cbp, count, (long long)m2.buf.size()};
         for (int q = 0; q < count; ++q) {
             key.push_back(R[order[q]].prm.iters);
             key.push_back(fi_end[q]);
             key.push_back(bi_end[q]);
         }
-        auto git = ctx->graphs.find(key);
-        if (git != ctx->graphs.end()) {
-            ge = &git->second;
-        } else if (++ctx->graph_seen[key] >= 2) {
-            // second solve with this layout: capture the loop once and keep it
-            if (ctx->graphs.size() >= 32) {   // evict the least recently used entry
-                auto old = ctx->graphs.begin();
-                for (auto q = ctx->graphs.begin(); q != ctx->graphs.end(); ++q)
-                    if (q->second.stamp < old->second.stamp) old = q;
-                GraphEntry& o = old->second;
-                if (o.last) (void)hipEventSynchronize(o.last);
-                if (o.exec) (void)hipGraphExecDestroy(o.exec);
-                if (o.graph) (void)hipGraphDestroy(o.graph);
-                if (o.last) (void)hipEventDestroy(o.last);
-                ctx->arena.free_now(o.dbuf);
-                ctx->graphs.erase(old);
-            }
-            GraphEntry E2;
-            E2.bytes = m2.buf.size();
-            E2.dbuf = ctx->arena.alloc(E2.bytes);
-            bool ok = E2.dbuf != nullptr;
-            if (ok && !ctx->cap_stream)
-                ok = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
-            if (ok) ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) ==
-                         hipSuccess;
-            if (ok) {
-                const hipError_t le = enqueue_loop(E2.dbuf, ctx->cap_stream);
-                const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &E2.graph);
-                ok = le == hipSuccess && ce == hipSuccess && E2.graph;
-            }
-            if (ok) ok = hipGraphInstantiate(&E2.exec, E2.graph, nullptr, nullptr, 0) == hipSuccess;
-            if (ok) ok = hipEventCreateWithFlags(&E2.last, hipEventDisableTiming) == hipSuccess;
-            if (ok) {
-                ge = &(ctx->graphs[key] = E2);
-            } else {   // fall back to eager launches
-                (void)hipGetLastError();
-                if (E2.exec) (void)hipGraphExecDestroy(E2.exec);
-                if (E2.graph) (void)hipGraphDestroy(E2.graph);
-                if (E2.dbuf) ctx->arena.free_now(E2.dbuf);
-            }
+        tomo_status rs = run_loop(ctx, key, m2, enqueue_loop, s, allocs);
+        if (rs != TOMO_OK) {
+            cleanup();
+            return rs;
         }
-    }
-    if (ge) {
-        ge->stamp = ++ctx->graph_clock;
-        CK(hipStreamWaitEvent(s, ge->last, 0));
-        CK(ctx->staging.upload(ge->dbuf, m2.buf.data(), m2.buf.size(), s));
-        CK(hipGraphLaunch(ge->exec, s));
-        CK(hipEventRecord(ge->last, s));
     } else {
         char* dm2 = ctx->arena.alloc(m2.buf.size());
         if (!dm2) {
@@ -824,17 +859,7 @@ long long count_nnz(const Geom& g, const Rect& reg) {
 // C ABI
 // ===========================================================================
 
-#define GUARD_BEGIN try {
-#define GUARD_END(ctx)                                                                  \
-    }                                                                                   \
-    catch (const std::bad_alloc&) {                                                     \
-        return fail((ctx), TOMO_ENOMEM, "host allocation failed");                      \
-    }                                                                                   \
-    catch (...) {                                                                       \
-        return fail((ctx), TOMO_EINVAL, "unexpected host exception");                   \
-    }
-
-static tomo_status need_gpu(tomo_ctx* ctx) {
+tomo_status tomo::need_gpu(tomo_ctx* ctx) {
     if (!ctx) return TOMO_EINVAL;
     if (ctx->host_only) return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
     hipError_t e = hipSetDevice(ctx->device);
@@ -842,7 +867,7 @@ static tomo_status need_gpu(tomo_ctx* ctx) {
     return TOMO_OK;
 }
 
-static tomo_status get_geom(tomo_ctx* ctx, int32_t gid, const Geom** g) {
+tomo_status tomo::get_geom(tomo_ctx* ctx, int32_t gid, const Geom** g) {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (gid < 0 || gid >= (int)ctx->geoms.size()) return fail(ctx, TOMO_ENOENT, "unknown geometry %d", gid);
     *g = &ctx->geoms[gid];

@@ -58,15 +58,18 @@ enum FpMode : int32_t {
     FP_CP_DUAL = 4,          // y <- (y + sigma (fp - b)) * dual_div
     FP_SIRT = 5,             // y <- alpha (b - fp)
     FP_BAND_STORE = 6,       // y = fp
-    FP_RESID = 7             // gout[k][i] = gbase[k][i] + scale * fp
+    FP_RESID = 7,            // gout[k][i] = gbase[k][i] + scale * fp
+    FP_FILTER = 8,           // y = -alpha fp;  gout[k][i] = gbase[k][i] + alpha fp
+    FP_LOCAL = 9             // y = (d - alpha fp, d), d = plane (step + dk0) of gbase
 };
 
 enum BpMode : int32_t {
     BP_STORE = 0,   // x = scale * bp   (optional padded copies)
     BP_ACCUM = 1,   // x += scale * bp
     BP_CP = 2,      // TV dual + primal prox + extrapolation
-    BP_SIRT = 3,    // x = max(0, x + bp)
-    BP_POWER = 4    // x = bp - div grad v, per-tile sums of x^2
+    BP_SIRT = 3,    // x = clamp(x + bp, lo, hi)
+    BP_POWER = 4,   // x = bp - div grad v, per-tile sums of x^2
+    BP_LOCAL = 5    // two-channel band (g, d): x = clamp(v + bp_g, lo, hi), v <- x - bp_d
 };
 
 enum JobFlags : int32_t { JF_HALF = 1, JF_ANISO = 2 };
@@ -82,15 +85,18 @@ struct Job {
     int32_t parity0;         // xbar/z buffer read at launch step s: (s + parity0) & 1
     int32_t ldx;             // pitch of x
     int32_t ntc;             // tiles per row of the BP work decomposition
-    int32_t pad0;
+    int32_t dk0;             // FP_LOCAL: plane of gbase read at launch step s is s + dk0
     float sigma, tau, lam, dual_div, alpha, scale;
+    float lo, hi;            // box of the SIRT-type updates
+    int64_t gstride;         // FP_LOCAL: floats between planes of gbase
     const AngFP* afp;
     const AngBP* abp;
     float* x;                // primal / output image [nr][ldx]
     float* xb[2];            // padded xbar, ping-pong
     float* xt;               // padded transposed xbar
     float* z[2];             // TV dual [2][nr][nc], ping-pong
-    float* y;                // band array [n_angles][bpitch] (dual / FP output / BP input)
+    float* y;                // band array [n_angles][bpitch] (dual / FP output / BP input);
+                             // two-channel modes: [n_angles][bpitch][2]
     const float* b;          // band data [n_angles][bpitch]
     float* gout;             // full-detector sinogram output [n_angles][n_det]
     const float* gbase;      // full-detector sinogram base
@@ -118,9 +124,10 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
 // 0: direct band reads (any group count; latency shape).  Same results.
 // compensated = 1: compensated sums over angles, staged, groups 1, ppt 2 only
 // (the items must be built for that tiling).
+// two_channel = 1: the band holds (g, d) pairs (BP_LOCAL jobs only); direct reads.
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
                      int ppt, hipStream_t s, int contiguous = 1, int staged = 0,
-                     int compensated = 0);
+                     int compensated = 0, int two_channel = 0);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int tp, float v,
                               hipStream_t s);
@@ -135,6 +142,15 @@ hipError_t launch_band_scatter(const float* band, int bpitch, const AngFP* afp, 
                                float* sino, int n_det, int accumulate, hipStream_t s);
 hipError_t launch_ramp(const float* sino, int n_angles, int n_det, const float* taps,
                        const AngFP* afp, float* band, int bpitch, hipStream_t s);
+// Detector convolutions by FFT (length L = 2^log2_len >= 2 n_det - 1, twiddles
+// tw[m] = exp(-2 pi i m / L) in FP32).  spectra: spec[a][L] = FFT of sino row a
+// (zero-padded).  filter_conv: for each angle a and filter pair (2h, 2h + 1) of
+// `filters` [n_filt][n_angles][n_det], out[k][a][i] = sum_j filt[k][a][i - j + ctr[a]] sino[a][j].
+hipError_t launch_spectra(const float* sino, int n_angles, int n_det, int log2_len,
+                          const float2* tw, float2* spec, hipStream_t s);
+hipError_t launch_filter_conv(const float* filters, int n_filt, int n_angles, int n_det,
+                              const int* ctr, int log2_len, const float2* tw, const float2* spec,
+                              float* out, hipStream_t s);
 hipError_t launch_power_normalize(const float* w, int ldx, int nr, int nc, const float* part,
                                   int n_part, float* xb, int xp, float* xt, int tp, float* est,
                                   hipStream_t s);

@@ -146,7 +146,11 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
             switch (mode) {
                 case FP_ACCUM: pre0[r] = J->gout[gidx]; break;
                 case FP_BAND_FROM_GLOBAL:
-                case FP_RESID: pre0[r] = J->gbase[gidx]; break;
+                case FP_RESID:
+                case FP_FILTER: pre0[r] = J->gbase[gidx]; break;
+                case FP_LOCAL:
+                    pre0[r] = J->gbase[(size_t)(step + J->dk0) * (size_t)J->gstride + gidx];
+                    break;
                 case FP_BAND_ADD: pre0[r] = J->y[bidx]; break;
                 case FP_CP_DUAL: pre0[r] = J->y[bidx]; pre1[r] = J->b[bidx]; break;
                 case FP_SIRT: pre1[r] = J->b[bidx]; break;
@@ -391,6 +395,19 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
             case FP_RESID:
                 if (ondet) gout[gidx] = pre0[r] + J->scale * fpv;
                 break;
+            case FP_FILTER:
+                // one step of the filter recursion: the band carries -alpha W c for
+                // the update of c, the filter accumulates alpha W c
+                y[bidx] = ondet ? -(J->alpha * A.bscale) * fpv : 0.f;
+                if (ondet) gout[gidx] = pre0[r] + J->alpha * fpv;
+                break;
+            case FP_LOCAL: {
+                // two-channel band: (d - alpha W_L v, d), d the filtered data
+                const float d = ondet ? pre0[r] : 0.f;
+                const v2f o = ondet ? v2f{A.bscale * (d - J->alpha * fpv), A.bscale * d}
+                                    : v2f{0.f, 0.f};
+                *(v2f*)(y + 2 * bidx) = o;
+            } break;
             default:
                 break;
         }
@@ -407,7 +424,7 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
 // see half-updated values), takes its divergence, then applies the primal
 // prox and the extrapolation to its own pixels.
 // ---------------------------------------------------------------------------
-template <int AG, int PPT, bool STAGED, bool COMP>
+template <int AG, int PPT, bool STAGED, bool COMP, bool TWO>
 __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
                                                  int step, int contiguous) {
@@ -418,6 +435,8 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     __shared__ float zs0[TH + 1][TW + 1];
     __shared__ float zs1[TH + 1][TW + 1];
     __shared__ float red[PPT][AG > 1 ? 256 : 1];   // group partial sums (and the power sums)
+    __shared__ float red2[PPT][(AG > 1 && TWO) ? 256 : 1];   // second channel's partial sums
+    static_assert(!TWO || (!STAGED && !COMP), "two-channel bands use direct reads");
     // Per-angle anchors of the tile, ANC per pass (AG groups x PA angles).
     constexpr int ANC = STAGED ? 256 : 512, PA = ANC / AG;   // (sized for LDS occupancy)
     // Staged band windows: WS entries per angle starting SHIFT below the
@@ -487,6 +506,8 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         xo[q] = 0.f;
         if (inside[q] && (mode == BP_CP || mode == BP_SIRT || mode == BP_ACCUM))
             xo[q] = J->x[(size_t)(R0 + tr + q) * J->ldx + c];
+        if (inside[q] && mode == BP_LOCAL)   // the correction image v (padded copy)
+            xo[q] = J->xb[rpar][(size_t)(R0 + tr + q) * J->xp + c + kLpad];
     }
     constexpr int NZ = ((TH + 1) * (TW + 1) + 255) / 256;
     float zq0[NZ], zq1[NZ];
@@ -571,9 +592,9 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
 
     if (!tv) __syncthreads();   // anchors of the first pass
 
-    float acc[PPT], cacc[PPT];
+    float acc[PPT], cacc[PPT], acc2[PPT];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) acc[q] = cacc[q] = 0.f;
+    for (int q = 0; q < PPT; ++q) acc[q] = cacc[q] = acc2[q] = 0.f;
     // one pixel-angle term w0 y0 + w1 y1; COMP keeps the sum compensated (the
     // filtered-backprojection sums cancel to values far below their terms)
     auto accum = [&](int q, float w0, float y0, float w1, float y1) {
@@ -601,6 +622,61 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         const int ka = kg0 + pass * PA, kb = min(kg1, ka + PA);
         const Anchor* an = anc + g * PA - ka;
         if (!inside[0]) continue;
+        if constexpr (TWO) {
+            // (g, d) pairs: one 16-byte read gives both channels of both taps
+            const unsigned rowb2 = 2u * rowb;
+            constexpr int UA = 8 / PPT;
+            int k = ka;
+            for (; k + UA <= kb; k += UA) {
+                float f[UA][PPT];
+                v4f yv[UA][PPT];
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    const Anchor A = an[k + u];
+                    const __amdgpu_buffer_rsrc_t rs =
+                        make_rsrc(yband + (size_t)(k + u) * 2 * bpitch, rowb2);
+                    float loc = fmaf(dcf, tab[k + u].cu, fmaf(drf, tab[k + u].su, A.f));
+#pragma unroll
+                    for (int q = 0; q < PPT; ++q) {
+                        if (q) loc += tab[k + u].su;
+                        f[u][q] = __builtin_amdgcn_fractf(loc);
+                        yv[u][q] = load4(rs, ((unsigned)loc << 3) + 2u * (unsigned)A.i4, 0);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    const float r = tab[k + u].r, rm1 = tab[k + u].rm1;
+#pragma unroll
+                    for (int q = 0; q < PPT; ++q) {
+                        const float w0 = __builtin_amdgcn_fmed3f(r - f[u][q], 0.f, 1.f);
+                        const float w1 = __builtin_amdgcn_fmed3f(f[u][q] + rm1, 0.f, 1.f);
+                        acc[q] = fmaf(w0, yv[u][q].x, acc[q]);
+                        acc[q] = fmaf(w1, yv[u][q].z, acc[q]);
+                        acc2[q] = fmaf(w0, yv[u][q].y, acc2[q]);
+                        acc2[q] = fmaf(w1, yv[u][q].w, acc2[q]);
+                    }
+                }
+            }
+            for (; k < kb; ++k) {
+                const Anchor A = an[k];
+                const __amdgpu_buffer_rsrc_t rs = make_rsrc(yband + (size_t)k * 2 * bpitch, rowb2);
+                const float r = tab[k].r, rm1 = tab[k].rm1;
+                float loc = fmaf(dcf, tab[k].cu, fmaf(drf, tab[k].su, A.f));
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    if (q) loc += tab[k].su;
+                    const float f = __builtin_amdgcn_fractf(loc);
+                    const v4f yv = load4(rs, ((unsigned)loc << 3) + 2u * (unsigned)A.i4, 0);
+                    const float w0 = __builtin_amdgcn_fmed3f(r - f, 0.f, 1.f);
+                    const float w1 = __builtin_amdgcn_fmed3f(f + rm1, 0.f, 1.f);
+                    acc[q] = fmaf(w0, yv.x, acc[q]);
+                    acc[q] = fmaf(w1, yv.z, acc[q]);
+                    acc2[q] = fmaf(w0, yv.y, acc2[q]);
+                    acc2[q] = fmaf(w1, yv.w, acc2[q]);
+                }
+            }
+            continue;
+        }
         // Each band row is read through its own buffer resource whose range is
         // that row, so a stray coordinate reads 0 instead of a neighbouring row.
         constexpr int UA = 16 / PPT;   // angles per step: 16 paired band loads in flight
@@ -793,14 +869,21 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     }
     if (AG > 1) {
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) red[q][t] = acc[q];
+        for (int q = 0; q < PPT; ++q) {
+            red[q][t] = acc[q];
+            if constexpr (TWO) red2[q][t] = acc2[q];
+        }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             acc[q] = 0.f;
+            acc2[q] = 0.f;
             if (g == 0) {
 #pragma unroll
-                for (int h = 0; h < AG; ++h) acc[q] += red[q][h * P + p];
+                for (int h = 0; h < AG; ++h) {
+                    acc[q] += red[q][h * P + p];
+                    if constexpr (TWO) acc2[q] += red2[q][h * P + p];
+                }
             }
         }
     }
@@ -839,12 +922,20 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                     zw[(size_t)nr * nc + zi] = zn1[q];
                 } break;
                 case BP_SIRT: {
-                    const float xn = fmaxf(0.f, xo[q] + acc[q]);
+                    const float xn = fminf(fmaxf(xo[q] + acc[q], J->lo), J->hi);
                     x[xi] = xn;
                     float* xbw = J->xb[wpar];
                     float* xt = J->xt;
                     xbw[(size_t)r * J->xp + c + kLpad] = xn;
                     xt[(size_t)c * J->tp + r + kLpad] = xn;
+                } break;
+                case BP_LOCAL: {
+                    // x = P_[lo,hi](v + W_L^T g); the new correction v = x - W_L^T d
+                    const float xn = fminf(fmaxf(xo[q] + acc[q], J->lo), J->hi);
+                    x[xi] = xn;
+                    const float vn = xn - acc2[q];
+                    J->xb[wpar][(size_t)r * J->xp + c + kLpad] = vn;
+                    J->xt[(size_t)c * J->tp + r + kLpad] = vn;
                 } break;
                 case BP_POWER: {
                     const float w = acc[q] - divv[q];
@@ -1015,6 +1106,152 @@ __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sin
 
 // Power iteration: v = w / ||w||, ||w|| from the per-tile partial sums (summed
 // in the same fixed order by every block), written into the padded buffers.
+// ---------------------------------------------------------------------------
+// Detector convolutions by FFT: C_u p for a whole bank of angle-dependent
+// filters u_k (Section 3.1, eq. sirtapp; Section 3.3: the convolved data are
+// computed once and shared by every local part).  A linear convolution of two
+// n_det-long rows equals the circular one of length L >= 2 n_det - 1, so one
+// complex transform of length L = 2^LOG per filter PAIR does two rows at once:
+// the pair is packed as u_{2h} + i u_{2h+1}, multiplied by the spectrum of the
+// real data row, and transformed back; the real and imaginary parts are the
+// two convolutions.  The transform lives in LDS: each radix-4 (one radix-2
+// when LOG is odd) self-sorting Stockham stage reads all its butterfly inputs
+// into registers, synchronises, and writes the outputs back in place.
+// ---------------------------------------------------------------------------
+constexpr int kFftThreads = 512;
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// Forward DFT (exp(-2 pi i f n / L)) of z[0..L) in place.  tw[m] = exp(-2 pi i m / L).
+template <int LOG>
+__device__ void fft_lds(float2* z, const float2* __restrict__ tw) {
+    constexpr int L = 1 << LOG, T = kFftThreads;
+    const int t = threadIdx.x;
+    int ns = 1;   // length of the sub-transforms already done
+    if constexpr (LOG & 1) {
+        constexpr int NB = (L / 2 + T - 1) / T;
+        float2 a[NB], b[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * T;
+            if (j < L / 2) {
+                a[i] = z[j];
+                b[i] = z[j + L / 2];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * T;
+            if (j < L / 2) {
+                z[2 * j] = make_float2(a[i].x + b[i].x, a[i].y + b[i].y);
+                z[2 * j + 1] = make_float2(a[i].x - b[i].x, a[i].y - b[i].y);
+            }
+        }
+        __syncthreads();
+        ns = 2;
+    }
+    constexpr int NB = (L / 4 + T - 1) / T;
+    for (; ns < L; ns <<= 2) {
+        float2 v[NB][4];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * T;
+            if (j < L / 4) {
+                const int k = j & (ns - 1);
+                const int m = (L / (4 * ns)) * k;   // twiddle of input r: r m < L
+                v[i][0] = z[j];
+                v[i][1] = cmul(z[j + L / 4], tw[m]);
+                v[i][2] = cmul(z[j + L / 2], tw[2 * m]);
+                v[i][3] = cmul(z[j + 3 * (L / 4)], tw[3 * m]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * T;
+            if (j < L / 4) {
+                const int k = j & (ns - 1);
+                const float2 a0 = make_float2(v[i][0].x + v[i][2].x, v[i][0].y + v[i][2].y);
+                const float2 a1 = make_float2(v[i][0].x - v[i][2].x, v[i][0].y - v[i][2].y);
+                const float2 a2 = make_float2(v[i][1].x + v[i][3].x, v[i][1].y + v[i][3].y);
+                // -i (v1 - v3)
+                const float2 a3 = make_float2(v[i][1].y - v[i][3].y, v[i][3].x - v[i][1].x);
+                const int base = ((j - k) << 2) + k;
+                z[base] = make_float2(a0.x + a2.x, a0.y + a2.y);
+                z[base + ns] = make_float2(a1.x + a3.x, a1.y + a3.y);
+                z[base + 2 * ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
+                z[base + 3 * ns] = make_float2(a1.x - a3.x, a1.y - a3.y);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// spec[a][0..L) = FFT of sinogram row a, zero-padded to L.
+template <int LOG>
+__global__ __launch_bounds__(kFftThreads) void spectra_kernel(const float* __restrict__ sino,
+                                                              int n_det,
+                                                              const float2* __restrict__ tw,
+                                                              float2* __restrict__ spec) {
+    constexpr int L = 1 << LOG;
+    __shared__ float2 z[L];
+    const int a = blockIdx.x;
+    const float* row = sino + (size_t)a * n_det;
+    for (int i = threadIdx.x; i < L; i += kFftThreads)
+        z[i] = make_float2(i < n_det ? row[i] : 0.f, 0.f);
+    __syncthreads();
+    fft_lds<LOG>(z, tw);
+    float2* o = spec + (size_t)a * L;
+    for (int i = threadIdx.x; i < L; i += kFftThreads) o[i] = z[i];
+}
+
+// Block (a, h): rows a of filters 2h and 2h + 1 convolved with data row a.
+// out[k][a][i] = sum_j filt[k][a][i - j + ctr[a]] p[a][j] = (u * p)[i + ctr[a]],
+// zero where i + ctr[a] falls outside the 2 n_det - 1 samples of the linear
+// convolution.
+template <int LOG>
+__global__ __launch_bounds__(kFftThreads) void filter_conv_kernel(
+    const float* __restrict__ filt, int n_filt, int n_angles, int n_det,
+    const int* __restrict__ ctr, const float2* __restrict__ tw, const float2* __restrict__ spec,
+    float* __restrict__ out) {
+    constexpr int L = 1 << LOG;
+    __shared__ float2 z[L];
+    const int npairs = (n_filt + 1) / 2;
+    const int a = blockIdx.x / npairs, h = blockIdx.x % npairs;
+    const int k0 = 2 * h;
+    const bool second = k0 + 1 < n_filt;
+    const size_t plane = (size_t)n_angles * n_det;
+    const float* f0 = filt + (size_t)k0 * plane + (size_t)a * n_det;
+    for (int i = threadIdx.x; i < L; i += kFftThreads) {
+        float2 v = make_float2(0.f, 0.f);
+        if (i < n_det) v = make_float2(f0[i], second ? f0[plane + i] : 0.f);
+        z[i] = v;
+    }
+    __syncthreads();
+    fft_lds<LOG>(z, tw);
+    // times the data spectrum; the inverse transform is conj(FFT(conj(.))) / L
+    const float2* sp = spec + (size_t)a * L;
+    for (int i = threadIdx.x; i < L; i += kFftThreads) {
+        const float2 w = cmul(z[i], sp[i]);
+        z[i] = make_float2(w.x, -w.y);
+    }
+    __syncthreads();
+    fft_lds<LOG>(z, tw);
+    const float inv = 1.f / (float)L;
+    const int c = ctr[a];
+    float* o0 = out + (size_t)k0 * plane + (size_t)a * n_det;
+    for (int i = threadIdx.x; i < n_det; i += kFftThreads) {
+        const int m = i + c;
+        const bool ok = m >= 0 && m <= 2 * n_det - 2;
+        const float2 v = ok ? z[m] : make_float2(0.f, 0.f);
+        o0[i] = v.x * inv;
+        if (second) o0[plane + i] = -v.y * inv;
+    }
+}
+
 __global__ __launch_bounds__(256) void power_normalize_kernel(
     const float* __restrict__ w, int ldx, int nr, int nc, const float* __restrict__ part,
     int n_part, float* __restrict__ xb, int xp, float* __restrict__ xt, int tp,
@@ -1071,13 +1308,29 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
 }
 
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
-                     int ppt, hipStream_t s, int contiguous, int staged, int compensated) {
+                     int ppt, hipStream_t s, int contiguous, int staged, int compensated,
+                     int two_channel) {
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items)), block(256);
-#define TOMO_BP(AGV, PPTV, ST, CO)                                                              \
-    hipLaunchKernelGGL((bp_kernel<AGV, PPTV, ST, CO>), grid, block, 0, s, jobs, items, n_items, \
-                       step, contiguous)
-    if (compensated) {   // one shape only: staged, one group, two pixels per thread
+#define TOMO_BP_T(AGV, PPTV, ST, CO, TW)                                                    \
+    hipLaunchKernelGGL((bp_kernel<AGV, PPTV, ST, CO, TW>), grid, block, 0, s, jobs, items, \
+                       n_items, step, contiguous)
+#define TOMO_BP(AGV, PPTV, ST, CO) TOMO_BP_T(AGV, PPTV, ST, CO, false)
+    if (two_channel) {   // direct reads of (g, d) pairs
+        if (ppt == 2) {
+            switch (groups) {
+                case 1: TOMO_BP_T(1, 2, false, false, true); break;
+                case 2: TOMO_BP_T(2, 2, false, false, true); break;
+                default: TOMO_BP_T(4, 2, false, false, true); break;
+            }
+        } else {
+            switch (groups) {
+                case 1: TOMO_BP_T(1, 1, false, false, true); break;
+                case 2: TOMO_BP_T(2, 1, false, false, true); break;
+                default: TOMO_BP_T(4, 1, false, false, true); break;
+            }
+        }
+    } else if (compensated) {   // one shape only: staged, one group, two pixels per thread
         TOMO_BP(1, 2, true, true);
     } else if (staged) {   // one angle group: a stage's windows serve the whole tile
         if (ppt == 2) TOMO_BP(1, 2, true, false);
@@ -1096,6 +1349,7 @@ hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, 
         }
     }
 #undef TOMO_BP
+#undef TOMO_BP_T
     return hipGetLastError();
 }
 
@@ -1157,5 +1411,42 @@ hipError_t launch_power_normalize(const float* w, int ldx, int nr, int nc, const
                        dim3(256), 0, s, w, ldx, nr, nc, part, n_part, xb, xp, xt, tp, est);
     return hipGetLastError();
 }
+
+#define TOMO_FFT_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+
+hipError_t launch_spectra(const float* sino, int n_angles, int n_det, int log2_len,
+                          const float2* tw, float2* spec, hipStream_t s) {
+    if (n_angles <= 0) return hipSuccess;
+    switch (log2_len) {
+#define X(LG)                                                                                  \
+    case LG:                                                                                   \
+        hipLaunchKernelGGL(spectra_kernel<LG>, dim3(n_angles), dim3(kFftThreads), 0, s, sino,  \
+                           n_det, tw, spec);                                                   \
+        break;
+        TOMO_FFT_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_conv(const float* filters, int n_filt, int n_angles, int n_det,
+                              const int* ctr, int log2_len, const float2* tw, const float2* spec,
+                              float* out, hipStream_t s) {
+    if (n_filt <= 0 || n_angles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(n_angles * ((n_filt + 1) / 2)));
+    switch (log2_len) {
+#define X(LG)                                                                                  \
+    case LG:                                                                                   \
+        hipLaunchKernelGGL(filter_conv_kernel<LG>, grid, dim3(kFftThreads), 0, s, filters,     \
+                           n_filt, n_angles, n_det, ctr, tw, spec, out);                       \
+        break;
+        TOMO_FFT_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+#undef TOMO_FFT_CASES
 
 }  // namespace tomo

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -153,6 +154,20 @@ tomo_status fail(tomo_ctx* ctx, tomo_status st, const char* fmt, ...);
             return ::tomo::fail((ctx), TOMO_EHIP, "%s failed: %s", #expr, hipGetErrorString(e__)); \
     } while (0)
 
+// Host exceptions never cross the C ABI.
+#define GUARD_BEGIN try {
+#define GUARD_END(ctx)                                                                  \
+    }                                                                                   \
+    catch (const std::bad_alloc&) {                                                     \
+        return fail((ctx), TOMO_ENOMEM, "host allocation failed");                      \
+    }                                                                                   \
+    catch (...) {                                                                       \
+        return fail((ctx), TOMO_EINVAL, "unexpected host exception");                   \
+    }
+
+tomo_status need_gpu(tomo_ctx* ctx);   // GPU context with its device made current
+tomo_status get_geom(tomo_ctx* ctx, int32_t gid, const Geom** g);
+
 // ---- solve pipeline shared by roi_solve, roi_solve_batch and serving ----
 
 struct RoiState {
@@ -205,6 +220,11 @@ tomo_status fbp_into(tomo_ctx* ctx, int gid, const float* sino, float* plain, fl
                      const Plan& P, hipStream_t s, std::vector<char*>& allocs, Staging& stg);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+struct Meta;
+// Launches an iteration loop through the context's graph cache (see tomo_capi.cpp).
+tomo_status run_loop(tomo_ctx* ctx, const std::vector<long long>& key, const Meta& m2,
+                     const std::function<hipError_t(char*, hipStream_t)>& enqueue, hipStream_t s,
+                     std::vector<char*>& allocs);
 
 // Packs small host arrays for one upload into one device block.
 struct Meta {

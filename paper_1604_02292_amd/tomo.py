@@ -8,7 +8,8 @@ stream, and nothing here computes on the data.
 import ctypes as C
 
 from . import _lib
-from ._lib import tomo_rect, roi_params, tomo_launch, ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT
+from ._lib import (tomo_rect, roi_params, tomo_launch, ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT,
+                   ROI_LOCAL_SIRT, ROI_FLAG_BOX)
 
 
 class TomoError(RuntimeError):
@@ -46,10 +47,18 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
-def make_params(roi, margin, method="cp", lam=0.0, iters=100, sigma=0.0, tau=0.0, flags=0):
-    m = {"cp": ROI_TV_NONNEG_CP, "sirt": ROI_NONNEG_SIRT}.get(method, method)
+def make_params(roi, margin, method="cp", lam=0.0, iters=100, sigma=0.0, tau=0.0, flags=0,
+                box=None):
+    """roi_params; method "cp", "sirt" or "local" (or the enum value); box=(lo, hi)
+    sets ROI_FLAG_BOX with those bounds."""
+    m = {"cp": ROI_TV_NONNEG_CP, "sirt": ROI_NONNEG_SIRT, "local": ROI_LOCAL_SIRT}.get(method,
+                                                                                    method)
+    lo, hi = 0.0, float("inf")
+    if box is not None:
+        lo, hi = float(box[0]), float(box[1])
+        flags = int(flags) | ROI_FLAG_BOX
     return roi_params(_rect(roi), int(margin), int(m), float(lam), int(iters), float(sigma),
-                      float(tau), int(flags))
+                      float(tau), int(flags), lo, hi)
 
 
 class Context:
@@ -161,6 +170,30 @@ class Context:
         self._check(self.lib.roi_solve_batch(self.h, geom, _ptr(sino, (na, nd), "sino"),
                                              _ptr(x_ext, (n, n), "x_ext"), cnt, parr, oarr,
                                              _stream(stream)))
+
+    # -- the paper's local method (Alg. 1 filters, filtered data, Alg. 2) ----
+    def tomo_sirt_filters(self, geom, iters, filters, stream=None):
+        n, na, nd = self.geoms[geom]
+        self._check(self.lib.tomo_sirt_filters(
+            self.h, geom, int(iters), _ptr(filters, (iters, na, nd), "filters"), _stream(stream)))
+
+    def tomo_sirt_filter_sino(self, geom, filters, sino, out, stream=None):
+        n, na, nd = self.geoms[geom]
+        cnt = int(filters.shape[0]) if filters is not None and filters.dim() == 3 else 0
+        self._check(self.lib.tomo_sirt_filter_sino(
+            self.h, geom, _ptr(filters, (cnt, na, nd), "filters"), cnt,
+            _ptr(sino, (na, nd), "sino"), _ptr(out, (cnt, na, nd), "out"), _stream(stream)))
+
+    def roi_solve_local(self, geom, filtered, params, outs, stream=None):
+        n, na, nd = self.geoms[geom]
+        planes = int(filtered.shape[0]) if filtered is not None and filtered.dim() == 3 else 0
+        cnt = len(params)
+        parr = (roi_params * cnt)(*params)
+        oarr = (C.c_void_p * cnt)(*[_ptr(o, (p.roi.rows, p.roi.cols), "out").value
+                                    for o, p in zip(outs, params)])
+        self._check(self.lib.roi_solve_local(self.h, geom, _ptr(filtered, (planes, na, nd),
+                                                                "filtered"),
+                                             planes, cnt, parr, oarr, _stream(stream)))
 
     def roi_step_size(self, geom, ext):
         v = C.c_float()
