@@ -165,6 +165,91 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
         ctx.close()
 
 
+def local_leg(torch, d, reps=3, iters=None, compare=True):
+    """The paper's own local method on the batch workload: SIRT-approximating filters
+    (Alg. 1, once per geometry), the filtered data C_{u_k} p (once per sinogram), and
+    Alg. 2 with a nonnegativity box for the 64 uneven ROIs in one roi_solve_local
+    call; beside it the same ROIs by nonnegative SIRT after FBP exterior subtraction."""
+    import synth
+    from paper_1604_02292_amd import Context, make_params
+    cfg = d["cfg"]
+    ctx = Context(0, workspace_bytes=8 << 30)
+    try:
+        na, nd = cfg["n_angles"], cfg["n_det"]
+        g = ctx.tomo_set_geometry(cfg["n"], na, nd)
+        sino = torch.from_numpy(d["sino"].astype(np.float32)).cuda()
+        its = iters or cfg["iters"]
+        rois = synth.roi_list("c3")
+        F = torch.empty((its, na, nd), dtype=torch.float32, device="cuda")
+        D = torch.empty_like(F)
+        ctx.tomo_sirt_filters(g, 2, F[:2])            # load the kernels
+        ctx.tomo_sirt_filter_sino(g, F[:2], sino, D[:2])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.tomo_sirt_filters(g, its, F)
+        torch.cuda.synchronize()
+        t_filt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.tomo_sirt_filter_sino(g, F, sino, D)
+        torch.cuda.synchronize()
+        t_conv = (time.perf_counter() - t0) / reps
+        L = 1 << int(np.ceil(np.log2(2 * nd - 1)))
+        # algorithmic traffic of the convolution: read the filters and the data
+        # spectra once, write the filtered data
+        conv_bytes = its * na * nd * 4 * 2 + na * L * 8 * 2 + na * nd * 4
+        log(f"local: filters {its} x {na} x {nd} in {1e3 * t_filt:.1f} ms; filtered data "
+            f"{1e3 * t_conv:.2f} ms ({conv_bytes / t_conv / 1e9:.0f} GB/s algorithmic)")
+        params = [make_params(r[:4], r[4], "local", iters=its, box=(0.0, float("inf")))
+                  for r in rois]
+        outs = [torch.empty((r[2], r[3]), dtype=torch.float32, device="cuda") for r in rois]
+        nnz = sum(ctx.tomo_roi_nnz(g, ctx.tomo_roi_ext(g, r[:4], r[4])) for r in rois)
+        for _ in range(2):   # the second call captures the iteration graph
+            ctx.roi_solve_local(g, D, params, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.roi_solve_local(g, D, params, outs)
+        torch.cuda.synchronize()
+        t_loc = (time.perf_counter() - t0) / reps
+        ctx.tomo_kernel_timing(1)
+        ctx.tomo_kernel_time(0, reset=True)
+        ctx.roi_solve_local(g, D, params, outs)
+        torch.cuda.synchronize()
+        ctx.tomo_kernel_timing(0)
+        n_fp, ms_fp = ctx.tomo_kernel_time(0)
+        n_bp, ms_bp = ctx.tomo_kernel_time(1)
+        fp_us, bp_us = 1e3 * ms_fp / max(1, n_fp), 1e3 * ms_bp / max(1, n_bp)
+        log(f"local: 64 ROIs x {its} its {1e3 * t_loc:.1f} ms per batch; fp {fp_us:.1f} us, "
+            f"two-channel bp {bp_us:.1f} us per launch")
+        res = {"workload": "batch64-n2048-a256: 64 ROIs, sides {32,64,128,256}, margin side/4, "
+                           f"256 angles, 3072 bins; Alg. 2 with box [0, inf), {its} its",
+               "roi_solves_per_s": len(rois) / t_loc, "ms_per_batch": 1e3 * t_loc,
+               "fp_us": fp_us, "bp_us": bp_us,
+               "fp_updates_per_s": nnz / (fp_us * 1e-6), "bp_updates_per_s": nnz / (bp_us * 1e-6),
+               "filters_ms": 1e3 * t_filt, "filtered_data_ms": 1e3 * t_conv,
+               "filtered_data_gb_per_s": conv_bytes / t_conv / 1e9,
+               "filtered_data_bytes": conv_bytes}
+        if compare:
+            xe = torch.empty((cfg["n"], cfg["n"]), dtype=torch.float32, device="cuda")
+            ctx.tomo_fbp_ramlak(g, sino, xe)
+            sp = [make_params(r[:4], r[4], "sirt", iters=its) for r in rois]
+            so = [torch.empty_like(o) for o in outs]
+            for _ in range(2):
+                ctx.roi_solve_batch(g, sino, sp, so, x_ext=xe)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.roi_solve_batch(g, sino, sp, so, x_ext=xe)
+            torch.cuda.synchronize()
+            t_sirt = (time.perf_counter() - t0) / reps
+            log(f"local: exterior-subtraction SIRT batch {1e3 * t_sirt:.1f} ms")
+            res["exterior_sirt_ms_per_batch"] = 1e3 * t_sirt
+        return res
+    finally:
+        ctx.close()
+
+
 def serving_leg(torch, slices, n_req=200, n_warm=64, fractions=(0.25, 0.5, 0.75, 0.9)):
     """64 resident 2048^2 slices (512 angles x 3072 bins); requests with side
     U{32..512}, margin ceil(side/4), 80% CP-TV / 20% nonnegative SIRT, 100-300
@@ -276,7 +361,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
-    ap.add_argument("--only", choices=["batch", "serve"], default=None,
+    ap.add_argument("--skip-local", action="store_true")
+    ap.add_argument("--only", choices=["batch", "serve", "local"], default=None,
                     help="run only one secondary leg (for profiling) and print its JSON")
     ap.add_argument("--iters", type=int, default=None,
                     help="override the iteration count of --only legs (profiling runs)")
@@ -313,7 +399,7 @@ def main():
     gw = args.gen_workers or None
     # all inputs are generated before the GPU is initialised (the generator forks)
     d3 = slices = None
-    if args.only != "serve" and not (args.only is None and args.skip_batch):
+    if args.only != "serve" and not (args.only is None and args.skip_batch and args.skip_local):
         d3 = synth.make_inputs("c3", with_image=False, workers=gw)
     if args.only != "batch" and not (args.only is None and args.skip_serve):
         slices = synth.make_slices("c5", workers=gw)
@@ -327,6 +413,10 @@ def main():
         return
     if args.only == "serve":
         print(json.dumps(serving_leg(torch, slices)), flush=True)
+        return
+    if args.only == "local":
+        print(json.dumps(local_leg(torch, d3, reps=args.steps, iters=args.iters, compare=False)),
+              flush=True)
         return
 
     d = synth.make_inputs("c2", with_image=False, workers=1)
@@ -416,6 +506,11 @@ def main():
             res["batched"] = batched_leg(torch, d3)
         except Exception as e:   # the headline line must still print
             res["batched"] = {"error": repr(e)}
+    if not args.skip_local:
+        try:
+            res["local_method"] = local_leg(torch, d3)
+        except Exception as e:
+            res["local_method"] = {"error": repr(e)}
     if not args.skip_serve:
         try:
             res["serving"] = serving_leg(torch, slices)
