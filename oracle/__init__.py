@@ -24,6 +24,7 @@ Contents and the passages they follow:
   filters    SIRT-approximating FBP filters (Alg. 1, eq. filtcalc, eq. sirtapp), the
              per-angle detector convolution C_u, and the paper's local method
              (eq. localmethod, Alg. 2) with the box prior of eq. sirtbox
+  fista      FGP total-variation denoiser and the paper's local FISTA-TV (Alg. 3)
 
 Every function is pinned by tests in tests/test_oracle_*.py against facts the paper
 or mathematics fixes (adjoint identity between two independent projector codes,
@@ -41,6 +42,7 @@ from .solvers import (cp_tv_nonneg, sirt_nonneg, power_norm_sq, cp_objective, cp
 from .local import exterior_subtract, local_solve, crop, stitch
 from .filters import (sirt_filters, filter_centres, filter_apply, fbp_filter, sirt_iterates,
                       local_method_box)
+from .fista import fgp, local_fista_tv, prox_weight
 
 __all__ = [
     "Geometry", "make_geometry", "roi_extend", "band_exact", "hat_weight", "fp_ray",
@@ -48,5 +50,5 @@ __all__ = [
     "ramp_filter", "fbp_ramlak", "grad", "div", "tv_iso", "tv_aniso", "cp_tv_nonneg",
     "sirt_nonneg", "power_norm_sq", "cp_objective", "cp_steps", "exterior_subtract",
     "local_solve", "crop", "stitch", "sirt_filters", "filter_centres", "filter_apply",
-    "fbp_filter", "sirt_iterates", "local_method_box",
+    "fbp_filter", "sirt_iterates", "local_method_box", "fgp", "local_fista_tv", "prox_weight",
 ]
