@@ -130,9 +130,12 @@ typedef enum {
     ROI_NONNEG_SIRT = 1,    /* x <- P(x + alpha W_L^T (b - W_L x)), alpha = 1/(N_theta N_d),
                                P the box of eq. sirtbox: [0, inf), or [box_lo, box_hi] with
                                ROI_FLAG_BOX (eq. sirtit) */
-    ROI_LOCAL_SIRT = 2      /* the paper's local method (Section 3.2, eq. localmethod, Alg. 2)
-                               for SIRT with the box prior of eq. sirtbox; only through
-                               roi_solve_local */
+    ROI_LOCAL_SIRT = 2,     /* the paper's local method (Section 3.2, eq. localmethod, Alg. 2)
+                               for SIRT with the box prior of eq. sirtbox ([0, inf) unless
+                               ROI_FLAG_BOX); only through roi_solve_local */
+    ROI_LOCAL_FISTA_TV = 3  /* the paper's local FISTA for lambda TV (Alg. 3) with an FGP
+                               inner solver of inner_iters iterations (box: none unless
+                               ROI_FLAG_BOX); only through roi_solve_local */
 } roi_method;
 
 enum {
@@ -147,7 +150,9 @@ enum {
  * 0 for sigma = tau = 1/sqrt(1.01 * lambda_max(W_L^T W_L - Laplacian))
  * from a cached power iteration (per geometry and extended shape); box_lo,
  * box_hi: the box of SIRT-type methods when flags has ROI_FLAG_BOX (box_lo may
- * be -inf, box_hi +inf; box_lo <= box_hi; not accepted for CP). */
+ * be -inf, box_hi +inf; box_lo <= box_hi; not accepted for CP); inner_iters: FGP
+ * iterations per outer iteration of ROI_LOCAL_FISTA_TV (0 = 100, the paper's
+ * count; ignored by the other methods). */
 typedef struct {
     tomo_rect roi;
     int32_t margin;
@@ -157,6 +162,7 @@ typedef struct {
     float sigma, tau;
     uint32_t flags;     /* ROI_FLAG_* */
     float box_lo, box_hi;
+    int32_t inner_iters;
 } roi_params;
 
 /* Solve one ROI: extend, subtract the exterior (x_ext = float[n][n], or NULL to
@@ -200,16 +206,22 @@ tomo_status tomo_sirt_filter_sino(tomo_ctx* ctx, int32_t geom, const float* filt
                                   int32_t count, const float* sino, float* out,
                                   void* hip_stream);
 
-/* The paper's local method (Section 3.2: eq. localmethod, Alg. 2) with SIRT and the
- * box prior of eq. sirtbox, for `count` independent ROIs together.  On the extended
- * part L of each ROI, from v = 0, for k = 1..iters:
- *   x = P(v + W_L^T (d_k - alpha W_L v)),   v <- x - W_L^T d_k,
- * with d_k = filtered[k - 1] (tomo_sirt_filter_sino: W_L^T d_k is the local SIRT
- * approximation FBP_L(p, u_k)), alpha = 1/(n_angles n_det) and P the box of the
- * request; the crop of x is written to outs[i] (float[roi.rows][roi.cols], device).
- * filtered: device float[planes][n_angles][n_det]; params and outs are host
- * arrays of count entries; every params[i].method is ROI_LOCAL_SIRT with
- * iters <= planes (lambda, sigma, tau are ignored).  Stream-ordered.
+/* The paper's local method (Section 3.2: eq. localmethod, Alg. 2, Alg. 3) for `count`
+ * independent ROIs together.  On the extended part L of each ROI, from v = 0, for
+ * k = 1..iters, with d_k = filtered[k - 1] (tomo_sirt_filter_sino: W_L^T d_k is the
+ * local SIRT approximation FBP_L(p, u_k)) and alpha = 1/(n_angles n_det):
+ *   ROI_LOCAL_SIRT (Alg. 2, box prior of eq. sirtbox, P the request's box):
+ *     x = P(v + W_L^T (d_k - alpha W_L v)),   v <- x - W_L^T d_k;
+ *   ROI_LOCAL_FISTA_TV (Alg. 3, FISTA on eq. priorsys with g = TV):
+ *     x^k = FGP(v + W_L^T (d_k - alpha W_L v)),   t^k = (1 + sqrt(1 + 4 (t^{k-1})^2)) / 2,
+ *     v <- x^k + ((t^{k-1} - 1) / t^k)(x^k - x^{k-1}) - W_L^T d_k,   t^0 = 1, x^0 = 0,
+ *     FGP being inner_iters iterations of min_P ||x - w||^2 + 2 gamma TV(x) from a zero
+ *     dual, gamma = alpha lambda / 2 (alpha lambda with ROI_FLAG_HALF_DATA),
+ *     isotropic TV unless ROI_FLAG_ANISO_TV.
+ * The crop of x is written to outs[i] (float[roi.rows][roi.cols], device).
+ * filtered: device float[planes][n_angles][n_det]; params and outs are host arrays of
+ * count entries; every params[i].method is ROI_LOCAL_SIRT or ROI_LOCAL_FISTA_TV with
+ * iters <= planes (sigma, tau are ignored).  Stream-ordered.
  * Errors: EINVAL, ENOENT, ENOMEM, EHIP. */
 tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, int32_t planes,
                             int32_t count, const roi_params* params, float* const* outs,
@@ -316,9 +328,10 @@ tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const 
  * Errors: EINVAL, ENOENT. */
 tomo_status tomo_roi_nnz(tomo_ctx* ctx, int32_t geom, tomo_rect region, int64_t* nnz);
 
-/* Measurement hook for the iteration kernels, forward projection (kernel 0)
- * and backprojection (kernel 1).  mode 1: the solve calls record a HIP event
- * pair on their stream around every iteration launch.  mode 2: each solve
+/* Measurement hook for the iteration kernels, forward projection (kernel 0),
+ * backprojection (kernel 1) and the FGP steps of local FISTA-TV (kernel 2, all
+ * FGP launches of one outer iteration together).  mode 1: the solve calls record a
+ * HIP event pair on their stream around every iteration launch.  mode 2: each solve
  * first runs 50 back-to-back launches of each kernel on its own data, captured
  * in a hipGraph (no dispatch gaps between them) and bracketed by two HIP events
  * on the solve's stream, then clears its state and solves as usual (results

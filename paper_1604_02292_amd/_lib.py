@@ -15,7 +15,7 @@ TOMO_OK, TOMO_EINVAL, TOMO_ENOMEM, TOMO_EHIP, TOMO_EBUSY, TOMO_ENOENT, TOMO_EAGA
 STATUS_NAMES = {0: "TOMO_OK", -1: "TOMO_EINVAL", -2: "TOMO_ENOMEM", -3: "TOMO_EHIP",
                 -4: "TOMO_EBUSY", -5: "TOMO_ENOENT", -6: "TOMO_EAGAIN", -7: "TOMO_ESTATE"}
 
-ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT, ROI_LOCAL_SIRT = 0, 1, 2
+ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT, ROI_LOCAL_SIRT, ROI_LOCAL_FISTA_TV = 0, 1, 2, 3
 ROI_FLAG_HALF_DATA, ROI_FLAG_ANISO_TV, ROI_FLAG_BOX = 1, 2, 4
 
 
@@ -28,7 +28,7 @@ class roi_params(C.Structure):
     _fields_ = [("roi", tomo_rect), ("margin", C.c_int32), ("method", C.c_int32),
                 ("lambda_", C.c_float), ("iters", C.c_int32), ("sigma", C.c_float),
                 ("tau", C.c_float), ("flags", C.c_uint32), ("box_lo", C.c_float),
-                ("box_hi", C.c_float)]
+                ("box_hi", C.c_float), ("inner_iters", C.c_int32)]
 
 
 class tomo_launch(C.Structure):

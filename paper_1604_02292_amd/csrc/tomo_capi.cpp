@@ -101,8 +101,9 @@ tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p) {
     if (p.margin < 0) return fail(ctx, TOMO_EINVAL, "margin < 0");
     if (p.iters <= 0) return fail(ctx, TOMO_EINVAL, "iters must be > 0");
     if (!(p.lambda >= 0.f) || !std::isfinite(p.lambda)) return fail(ctx, TOMO_EINVAL, "lambda must be >= 0");
-    if (p.method != ROI_TV_NONNEG_CP && p.method != ROI_NONNEG_SIRT && p.method != ROI_LOCAL_SIRT)
+    if (p.method < ROI_TV_NONNEG_CP || p.method > ROI_LOCAL_FISTA_TV)
         return fail(ctx, TOMO_EINVAL, "unknown method %d", p.method);
+    if (p.inner_iters < 0) return fail(ctx, TOMO_EINVAL, "inner_iters must be >= 0");
     if (!(p.sigma >= 0.f) || !(p.tau >= 0.f)) return fail(ctx, TOMO_EINVAL, "negative step size");
     if (p.flags & ~7u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
     if (p.flags & ROI_FLAG_BOX) {
@@ -136,8 +137,14 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
     J.alpha = (float)(1.0 / ((double)g.na * (double)g.nd));
     J.scale = 1.f;
     const bool box = (st.prm.flags & ROI_FLAG_BOX) != 0;
-    J.lo = box ? st.prm.box_lo : 0.f;
+    const bool fista = st.prm.method == ROI_LOCAL_FISTA_TV;
+    J.lo = box ? st.prm.box_lo : (fista ? -INFINITY : 0.f);
     J.hi = box ? st.prm.box_hi : INFINITY;
+    // prox weight of TV in the FISTA step: the SIRT step is a gradient step of alpha/2
+    // on ||W x - p||^2 (alpha on 1/2 ||W x - p||^2)
+    J.gamma = (float)((half ? 1.0 : 0.5) * (double)st.prm.lambda /
+                      ((double)g.na * (double)g.nd));
+    J.n_fgp = st.prm.inner_iters > 0 ? st.prm.inner_iters : 100;
     J.afp = st.d_afp;
     J.abp = st.d_abp;
     J.x = st.x;
@@ -491,8 +498,8 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     for (int i = 0; i < count; ++i) {
         tomo_status st = validate_params(ctx, g, params[i]);
         if (st != TOMO_OK) return st;
-        if (params[i].method == ROI_LOCAL_SIRT)
-            return fail(ctx, TOMO_EINVAL, "ROI_LOCAL_SIRT requests go through roi_solve_local");
+        if (params[i].method >= ROI_LOCAL_SIRT)
+            return fail(ctx, TOMO_EINVAL, "local-method requests go through roi_solve_local");
         if (!outs[i]) return fail(ctx, TOMO_EINVAL, "null output pointer for ROI %d", i);
         RoiState& r = R[i];
         r.prm = params[i];
@@ -1521,8 +1528,8 @@ tomo_status tomo_kernel_time(tomo_ctx* ctx, int32_t kernel, int64_t* launches, d
                              int reset) {
     tomo_status st = need_gpu(ctx);
     if (st != TOMO_OK) return st;
-    if (kernel < 0 || kernel > 1 || !launches || !total_ms)
-        return fail(ctx, TOMO_EINVAL, "kernel must be 0 (fp) or 1 (bp)");
+    if (kernel < 0 || kernel > 2 || !launches || !total_ms)
+        return fail(ctx, TOMO_EINVAL, "kernel must be 0 (fp), 1 (bp) or 2 (fgp)");
     for (auto& p : ctx->ev_pending) {
         float ms = 0.f;
         TOMO_HIP(ctx, hipEventSynchronize(std::get<1>(p)));
@@ -1543,8 +1550,8 @@ tomo_status tomo_kernel_time(tomo_ctx* ctx, int32_t kernel, int64_t* launches, d
     *launches = ctx->t_launches[kernel];
     *total_ms = ctx->t_ms[kernel];
     if (reset) {
-        ctx->t_launches[0] = ctx->t_launches[1] = 0;
-        ctx->t_ms[0] = ctx->t_ms[1] = 0.0;
+        ctx->t_launches[0] = ctx->t_launches[1] = ctx->t_launches[2] = 0;
+        ctx->t_ms[0] = ctx->t_ms[1] = ctx->t_ms[2] = 0.0;
     }
     return TOMO_OK;
 }

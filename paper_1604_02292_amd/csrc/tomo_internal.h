@@ -69,7 +69,8 @@ enum BpMode : int32_t {
     BP_CP = 2,      // TV dual + primal prox + extrapolation
     BP_SIRT = 3,    // x = clamp(x + bp, lo, hi)
     BP_POWER = 4,   // x = bp - div grad v, per-tile sums of x^2
-    BP_LOCAL = 5    // two-channel band (g, d): x = clamp(v + bp_g, lo, hi), v <- x - bp_d
+    BP_LOCAL = 5,   // two-channel band (g, d): x = clamp(v + bp_g, lo, hi), v <- x - bp_d
+    BP_FISTA = 6    // two-channel band (g, d): w = v + bp_g, xs = bp_d (FGP input and x_s)
 };
 
 enum JobFlags : int32_t { JF_HALF = 1, JF_ANISO = 2 };
@@ -101,6 +102,15 @@ struct Job {
     float* gout;             // full-detector sinogram output [n_angles][n_det]
     const float* gbase;      // full-detector sinogram base
     float* part;             // per-tile partial sums (BP_POWER)
+    // local FISTA-TV (BP_FISTA + fgp_kernel)
+    float* w;                // FGP input x_s + q [nr][nc]
+    float* xs;               // x_s = W_L^T d [nr][nc]
+    float* fp;               // FGP dual p [2][nr][nc]
+    float* fr;               // FGP dual momentum point r [2][nr][nc]
+    const float* beta_in;    // FGP momentum per inner iteration
+    const float* beta_out;   // FISTA momentum per outer iteration
+    float gamma;             // prox weight of TV
+    int32_t n_fgp;           // FGP iterations per outer iteration
 };
 
 // One block's work.  `tab` points at the block's table (FP: the AngFP entry of
@@ -128,6 +138,13 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
                      int ppt, hipStream_t s, int contiguous = 1, int staged = 0,
                      int compensated = 0, int two_channel = 0);
+// FGP iterations [i0, i0 + kFgpSteps) of every FISTA job, on tiles of
+// kFgpTile x kFgpTile pixels (items: job, tile row, tile column); the launch that
+// reaches a job's last inner iteration also forms x, the FISTA momentum point and
+// the new correction v (written to the padded copies read at step + 1).
+constexpr int kFgpTile = 32, kFgpSteps = 8;
+hipError_t launch_fgp(const Job* jobs, const Item* items, int n_items, int step, int i0,
+                      hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int tp, float v,
                               hipStream_t s);

@@ -506,7 +506,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         xo[q] = 0.f;
         if (inside[q] && (mode == BP_CP || mode == BP_SIRT || mode == BP_ACCUM))
             xo[q] = J->x[(size_t)(R0 + tr + q) * J->ldx + c];
-        if (inside[q] && mode == BP_LOCAL)   // the correction image v (padded copy)
+        if (inside[q] && (mode == BP_LOCAL || mode == BP_FISTA))   // correction v (padded)
             xo[q] = J->xb[rpar][(size_t)(R0 + tr + q) * J->xp + c + kLpad];
     }
     constexpr int NZ = ((TH + 1) * (TW + 1) + 255) / 256;
@@ -937,6 +937,12 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                     J->xb[wpar][(size_t)r * J->xp + c + kLpad] = vn;
                     J->xt[(size_t)c * J->tp + r + kLpad] = vn;
                 } break;
+                case BP_FISTA: {
+                    // FGP input x_s + q = v + W_L^T (d - alpha W_L v), and x_s = W_L^T d
+                    const size_t pi = (size_t)r * nc + c;
+                    J->w[pi] = xo[q] + acc[q];
+                    J->xs[pi] = acc2[q];
+                } break;
                 case BP_POWER: {
                     const float w = acc[q] - divv[q];
                     x[xi] = w;
@@ -1106,6 +1112,127 @@ __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sin
 
 // Power iteration: v = w / ||w||, ||w|| from the per-tile partial sums (summed
 // in the same fixed order by every block), written into the padded buffers.
+// ---------------------------------------------------------------------------
+// FGP (fast gradient projection on the dual of TV denoising, the inner solver of
+// the paper's local FISTA-TV, Alg. 3): min_{lo <= x <= hi} ||x - b||^2 + 2 gamma TV(x),
+//   x = P(b - gamma div r),  p' = P_1(r - grad x / (8 gamma)),  r = p' + beta_i (p' - p).
+// Temporal blocking: a block loads its 32 x 32 tile with a halo of kFgpSteps + 1
+// pixels into LDS and runs kFgpSteps dual iterations there (each iteration's valid
+// area shrinks by one pixel per side), then writes p and r of its tile; no
+// neighbour exchange is needed within a launch.  Outside the region p = r = b = 0;
+// the gradient is zero on the region's last row / column (Neumann), so the duals
+// stay zero there, as in the CP kernel's TV.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fgp_kernel(const Job* __restrict__ jobs,
+                                                  const Item* __restrict__ items, int n_items,
+                                                  int step, int i0) {
+    constexpr int H = kFgpSteps + 1, RW = kFgpTile + 2 * H, RN = RW * RW;
+    __shared__ float sb[RN], sx[RN], sr0[RN], sr1[RN], sp0[RN], sp1[RN];
+    const int bid = blockIdx.x;
+    if (bid >= n_items) return;
+    const Item it = cview(items)[bid];
+    const CONST_AS Job* J = cview(jobs) + it.job;
+    const int nf = J->n_fgp;
+    // this launch's iterations of the job; the launch covering the last one finishes
+    if (!(i0 < nf || (nf == 0 && i0 == 0))) return;
+    const int i1 = min(nf, i0 + kFgpSteps);
+    const bool last = i1 >= nf;
+    const int nr = J->nr, nc = J->nc;
+    const int R0 = it.a * kFgpTile - H, C0 = it.b * kFgpTile - H;
+    const size_t plane = (size_t)nr * nc;
+    const float gamma = J->gamma;
+    const bool iters = gamma > 0.f && i1 > i0;
+    const int t = threadIdx.x;
+    for (int q = t; q < RN; q += 256) {
+        const int rr = R0 + q / RW, cc = C0 + q % RW;
+        float b = 0.f, p0 = 0.f, p1 = 0.f, r0 = 0.f, r1 = 0.f;
+        if (rr >= 0 && rr < nr && cc >= 0 && cc < nc) {
+            const size_t pi = (size_t)rr * nc + cc;
+            b = J->w[pi];
+            if (i0 > 0 && gamma > 0.f) {
+                p0 = J->fp[pi];
+                p1 = J->fp[plane + pi];
+                r0 = J->fr[pi];
+                r1 = J->fr[plane + pi];
+            }
+        }
+        sb[q] = b;
+        sp0[q] = p0;
+        sp1[q] = p1;
+        sr0[q] = r0;
+        sr1[q] = r1;
+    }
+    __syncthreads();
+    const float lo = J->lo, hi = J->hi;
+    if (iters) {
+        const float inv8g = 1.f / (8.f * gamma);
+        const bool aniso = (J->flags & JF_ANISO) != 0;
+        for (int i = i0; i < i1; ++i) {
+            // x = P(b - gamma div r); div r = r0 - r0(up) + r1 - r1(left), zero outside
+            for (int q = t; q < RN; q += 256) {
+                const int lr = q / RW, lc = q % RW;
+                const float up = lr > 0 ? sr0[q - RW] : 0.f;
+                const float left = lc > 0 ? sr1[q - 1] : 0.f;
+                const float d = (sr0[q] - up) + (sr1[q] - left);
+                sx[q] = fminf(fmaxf(sb[q] - gamma * d, lo), hi);
+            }
+            __syncthreads();
+            const float beta = J->beta_in[i];
+            for (int q = t; q < RN; q += 256) {
+                const int lr = q / RW, lc = q % RW;
+                const int rr = R0 + lr, cc = C0 + lc;
+                float n0 = 0.f, n1 = 0.f;
+                if (rr >= 0 && rr < nr && cc >= 0 && cc < nc) {
+                    const float xc = sx[q];
+                    const float g0 = (rr < nr - 1 && lr + 1 < RW) ? sx[q + RW] - xc : 0.f;
+                    const float g1 = (cc < nc - 1 && lc + 1 < RW) ? sx[q + 1] - xc : 0.f;
+                    n0 = sr0[q] - g0 * inv8g;
+                    n1 = sr1[q] - g1 * inv8g;
+                    if (aniso) {
+                        n0 = fminf(fmaxf(n0, -1.f), 1.f);
+                        n1 = fminf(fmaxf(n1, -1.f), 1.f);
+                    } else {
+                        const float sc = fmaxf(1.f, sqrtf(n0 * n0 + n1 * n1));
+                        n0 = n0 / sc;
+                        n1 = n1 / sc;
+                    }
+                }
+                sr0[q] = n0 + beta * (n0 - sp0[q]);
+                sr1[q] = n1 + beta * (n1 - sp1[q]);
+                sp0[q] = n0;
+                sp1[q] = n1;
+            }
+            __syncthreads();
+        }
+    }
+    // the tile's own pixels
+    for (int q = t; q < kFgpTile * kFgpTile; q += 256) {
+        const int lr = H + q / kFgpTile, lc = H + q % kFgpTile;
+        const int rr = R0 + lr, cc = C0 + lc;
+        if (rr >= nr || cc >= nc) continue;
+        const int k = lr * RW + lc;
+        const size_t pi = (size_t)rr * nc + cc;
+        if (!last) {
+            J->fp[pi] = sp0[k];
+            J->fp[plane + pi] = sp1[k];
+            J->fr[pi] = sr0[k];
+            J->fr[plane + pi] = sr1[k];
+            continue;
+        }
+        // x = P(b - gamma div p), then the FISTA momentum point z and v = z - x_s
+        const float d = (sp0[k] - sp0[k - RW]) + (sp1[k] - sp1[k - 1]);
+        const float x = fminf(fmaxf(sb[k] - gamma * d, lo), hi);
+        const size_t xi = (size_t)rr * J->ldx + cc;
+        const float xo = J->x[xi];
+        const float z = x + J->beta_out[step] * (x - xo);
+        const float v = z - J->xs[pi];
+        J->x[xi] = x;
+        const int wpar = ((step + J->parity0) & 1) ^ 1;
+        J->xb[wpar][(size_t)rr * J->xp + cc + kLpad] = v;
+        J->xt[(size_t)cc * J->tp + rr + kLpad] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Detector convolutions by FFT: C_u p for a whole bank of angle-dependent
 // filters u_k (Section 3.1, eq. sirtapp; Section 3.3: the convolved data are
@@ -1409,6 +1536,13 @@ hipError_t launch_power_normalize(const float* w, int ldx, int nr, int nc, const
                                   hipStream_t s) {
     hipLaunchKernelGGL(power_normalize_kernel, dim3(grid_for((size_t)nr * nc, 256, 256)),
                        dim3(256), 0, s, w, ldx, nr, nc, part, n_part, xb, xp, xt, tp, est);
+    return hipGetLastError();
+}
+
+hipError_t launch_fgp(const Job* jobs, const Item* items, int n_items, int step, int i0,
+                      hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fgp_kernel, dim3(n_items), dim3(256), 0, s, jobs, items, n_items, step, i0);
     return hipGetLastError();
 }
 

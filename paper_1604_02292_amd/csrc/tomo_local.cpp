@@ -32,18 +32,23 @@ std::vector<int> filter_centres(const Geom& g) {
 }
 
 // Device state of one local-method job: x, v (padded, ping-pong, and the
-// transposed copy) and the two-channel band.
+// transposed copy), the band (two-channel for the local methods) and, for
+// FISTA-TV, the FGP input, x_s and the FGP duals p and r.
 struct LocalBuf {
     float *x, *xb0, *xb1, *xt, *y;
+    float *w = nullptr, *xs = nullptr, *fp = nullptr, *fr = nullptr;
 };
 
-size_t local_state_floats(const Geom& g, const Plan& p, bool two_channel) {
+size_t local_state_floats(const Geom& g, const Plan& p, bool two_channel, bool fista = false) {
     const size_t nr = p.reg.rows, nc = p.reg.cols;
-    return align_up(nr * nc, 64) + 2 * align_up(nr * p.xp, 64) + align_up(nc * p.tp, 64) +
-           align_up((two_channel ? 2 : 1) * (size_t)g.na * p.bpitch, 64);
+    size_t f = align_up(nr * nc, 64) + 2 * align_up(nr * p.xp, 64) + align_up(nc * p.tp, 64) +
+               align_up((two_channel ? 2 : 1) * (size_t)g.na * p.bpitch, 64);
+    if (fista) f += 2 * align_up(nr * nc, 64) + 2 * align_up(2 * nr * nc, 64);
+    return f;
 }
 
-LocalBuf carve_local(const Geom& g, const Plan& p, bool two_channel, float* f) {
+LocalBuf carve_local(const Geom& g, const Plan& p, bool two_channel, float* f,
+                     bool fista = false) {
     const size_t nr = p.reg.rows, nc = p.reg.cols;
     LocalBuf b;
     auto take = [&](size_t n) {
@@ -56,6 +61,25 @@ LocalBuf carve_local(const Geom& g, const Plan& p, bool two_channel, float* f) {
     b.xb1 = take(nr * p.xp);
     b.xt = take(nc * p.tp);
     b.y = take((two_channel ? 2 : 1) * (size_t)g.na * p.bpitch);
+    if (fista) {
+        b.w = take(nr * nc);
+        b.xs = take(nr * nc);
+        b.fp = take(2 * nr * nc);
+        b.fr = take(2 * nr * nc);
+    }
+    return b;
+}
+
+// Momentum factors (t_{i} - 1) / t_{i+1} of the FISTA recursion
+// t_{i+1} = (1 + sqrt(1 + 4 t_i^2)) / 2 from t_0 = 1, in FP64.
+std::vector<float> fista_betas(int n) {
+    std::vector<float> b(std::max(n, 1));
+    double t = 1.0;
+    for (int i = 0; i < n; ++i) {
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        b[i] = (float)((t - 1.0) / tn);
+        t = tn;
+    }
     return b;
 }
 
@@ -211,10 +235,12 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
     std::vector<size_t> sfl(count);
     long long rays = 0, pix = 0;
     size_t state_total = 0;
+    int max_nf = 0, max_iters = 0;
     for (int i = 0; i < count; ++i) {
         if ((st = validate_params(ctx, g, params[i])) != TOMO_OK) return st;
-        if (params[i].method != ROI_LOCAL_SIRT)
-            return fail(ctx, TOMO_EINVAL, "roi_solve_local takes ROI_LOCAL_SIRT requests only");
+        if (params[i].method != ROI_LOCAL_SIRT && params[i].method != ROI_LOCAL_FISTA_TV)
+            return fail(ctx, TOMO_EINVAL,
+                        "roi_solve_local takes ROI_LOCAL_SIRT and ROI_LOCAL_FISTA_TV requests");
         if (params[i].iters > planes)
             return fail(ctx, TOMO_EINVAL, "ROI %d needs %d filtered planes, %d given", i,
                         params[i].iters, planes);
@@ -226,8 +252,12 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
         r.plan = make_plan(g, r.ext, r.ext);
         rays += (long long)g.na * r.plan.wmax;
         pix += (long long)r.ext.rows * r.ext.cols;
-        sfl[i] = local_state_floats(g, r.plan, true);
+        const bool fista = params[i].method == ROI_LOCAL_FISTA_TV;
+        sfl[i] = local_state_floats(g, r.plan, true, fista);
         state_total += sfl[i] * sizeof(float);
+        if (fista)
+            max_nf = std::max(max_nf, params[i].inner_iters > 0 ? params[i].inner_iters : 100);
+        max_iters = std::max(max_iters, params[i].iters);
     }
     // the backprojector reads the two-channel band directly (no LDS staging)
     LaunchCfg L = choose_launch_for(ctx, geom, count, rays, pix);
@@ -243,6 +273,9 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
         o_afp[i] = m.add(R[i].plan.afp.data(), R[i].plan.afp.size() * sizeof(AngFP));
         o_abp[i] = m.add(R[i].plan.abp.data(), R[i].plan.abp.size() * sizeof(AngBP));
     }
+    const std::vector<float> b_in = fista_betas(max_nf), b_out = fista_betas(max_iters);
+    const size_t o_bin = m.add(b_in.data(), b_in.size() * sizeof(float));
+    const size_t o_bout = m.add(b_out.data(), b_out.size() * sizeof(float));
     char* dm = ctx->arena.alloc(align_up(m.buf.size(), 256) + state_total + 256);
     if (!dm)
         return fail(ctx, TOMO_ENOMEM, "workspace too small for %d local-method states", count);
@@ -252,7 +285,7 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
     {
         float* f = state;
         for (int i = 0; i < count; ++i) {
-            B[i] = carve_local(g, R[i].plan, true, f);
+            B[i] = carve_local(g, R[i].plan, true, f, R[i].prm.method == ROI_LOCAL_FISTA_TV);
             f += sfl[i];
             RoiState& r = R[i];
             r.d_afp = (AngFP*)(dm + o_afp[i]);
@@ -273,37 +306,57 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
         return (long long)R[a].ext.rows * R[a].ext.cols > (long long)R[b].ext.rows * R[b].ext.cols;
     });
     std::vector<Job> jobs(count);
-    std::vector<Item> fi, bi;
-    std::vector<int> fi_end(count), bi_end(count);
+    std::vector<Item> fi, bi, gi;
+    std::vector<int> fi_end(count), bi_end(count), gi_end(count), nf_of(count, 0);
     for (int q = 0; q < count; ++q) {
         RoiState& r = R[order[q]];
-        Job J = make_job(g, r, FP_LOCAL, BP_LOCAL, (r.ext.cols + tw - 1) / tw);
+        const LocalBuf& lb = B[order[q]];
+        const bool fista = r.prm.method == ROI_LOCAL_FISTA_TV;
+        Job J = make_job(g, r, FP_LOCAL, fista ? BP_FISTA : BP_LOCAL, (r.ext.cols + tw - 1) / tw);
         J.gbase = filtered;
         J.gstride = (int64_t)g.na * g.nd;
         J.dk0 = 0;
         J.z[0] = J.z[1] = nullptr;
         J.b = nullptr;
         J.part = nullptr;
+        J.w = lb.w;
+        J.xs = lb.xs;
+        J.fp = lb.fp;
+        J.fr = lb.fr;
+        J.beta_in = (const float*)(dm + o_bin);
+        J.beta_out = (const float*)(dm + o_bout);
         jobs[q] = J;
         fp_items(fi, q, r.plan.afp, L.seg, L.rp, r.d_afp);
         bp_items(bi, q, r.ext.rows, r.ext.cols, L.ag, L.ppt, r.d_abp);
+        if (fista) {
+            nf_of[q] = J.n_fgp;
+            for (int a = 0; a < (r.ext.rows + kFgpTile - 1) / kFgpTile; ++a)
+                for (int b = 0; b < (r.ext.cols + kFgpTile - 1) / kFgpTile; ++b)
+                    gi.push_back(Item{q, a, b, 0, nullptr, 0});
+        }
         fi_end[q] = (int)fi.size();
         bi_end[q] = (int)bi.size();
+        gi_end[q] = (int)gi.size();
     }
     Meta m2;
     const size_t o_jobs = m2.add(jobs.data(), jobs.size() * sizeof(Job));
     const size_t o_fi = m2.add(fi.data(), fi.size() * sizeof(Item));
     const size_t o_bi = m2.add(bi.data(), bi.size() * sizeof(Item));
+    const size_t o_gi = m2.add(gi.data(), gi.size() * sizeof(Item));
     const int max_it = R[order[0]].prm.iters;
     const bool timed = ctx->timing_mode == 1;
     auto enqueue_loop = [&](char* base, hipStream_t sq) -> hipError_t {
         const Job* d_jobs = (const Job*)(base + o_jobs);
         const Item* d_fi = (const Item*)(base + o_fi);
         const Item* d_bi = (const Item*)(base + o_bi);
+        const Item* d_gi = (const Item*)(base + o_gi);
         int active = count;
         for (int it = 0; it < max_it; ++it) {
             while (active > 0 && R[order[active - 1]].prm.iters <= it) --active;
-            hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+            int nf = -1;   // FGP iterations of the running FISTA jobs (-1: none)
+            for (int q = 0; q < active; ++q)
+                if (R[order[q]].prm.method == ROI_LOCAL_FISTA_TV) nf = std::max(nf, nf_of[q]);
+            hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
             hipError_t e;
             if (timed) {
                 e0 = timing_event(ctx);
@@ -322,6 +375,18 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
                 if ((e = hipEventRecord(e2, sq)) != hipSuccess) return e;
                 ctx->ev_pending.emplace_back(e0, e1, 0);
                 ctx->ev_pending.emplace_back(e1, e2, 1);
+            }
+            if (nf >= 0) {   // FGP steps, kFgpSteps per launch; the last one finishes x^k
+                const int nl = std::max(1, (nf + kFgpSteps - 1) / kFgpSteps);
+                for (int l = 0; l < nl; ++l)
+                    if ((e = launch_fgp(d_jobs, d_gi, gi_end[active - 1], it, l * kFgpSteps, sq)) !=
+                        hipSuccess)
+                        return e;
+                if (timed) {
+                    e3 = timing_event(ctx);
+                    if ((e = hipEventRecord(e3, sq)) != hipSuccess) return e;
+                    ctx->ev_pending.emplace_back(e2, e3, 2);
+                }
             }
         }
         return hipSuccess;
@@ -343,6 +408,9 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
             key.push_back(R[order[q]].prm.iters);
             key.push_back(fi_end[q]);
             key.push_back(bi_end[q]);
+            key.push_back(gi_end[q]);
+            key.push_back(nf_of[q]);
+            key.push_back(R[order[q]].prm.method);
         }
         tomo_status rs = run_loop(ctx, key, m2, enqueue_loop, s, allocs);
         if (rs != TOMO_OK) {

@@ -139,8 +139,8 @@ struct tomo_ctx {
     int timing_mode = 0;   // 0 off, 1 events around every launch, 2 graph-bracketed pass
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::tuple<hipEvent_t, hipEvent_t, int>> ev_pending;
-    long long t_launches[2] = {0, 0};
-    double t_ms[2] = {0.0, 0.0};
+    long long t_launches[3] = {0, 0, 0};   // fp, bp, fgp
+    double t_ms[3] = {0.0, 0.0, 0.0};
 };
 
 namespace tomo {

@@ -486,8 +486,8 @@ tomo_status roi_submit(tomo_ctx* ctx, int32_t sino_id, const roi_params* params,
         const Geom& g = ctx->geoms[sp->gid];
         tomo_status st = validate_params(ctx, g, *params);
         if (st != TOMO_OK) return st;
-        if (params->method == ROI_LOCAL_SIRT)
-            return fail(ctx, TOMO_EINVAL, "ROI_LOCAL_SIRT requests go through roi_solve_local");
+        if (params->method >= ROI_LOCAL_SIRT)
+            return fail(ctx, TOMO_EINVAL, "local-method requests go through roi_solve_local");
         const Rect roi{params->roi.row0, params->roi.col0, params->roi.rows, params->roi.cols};
         const Rect ext = extend_rect(roi, params->margin, g.n);
         RoiState probe;

@@ -9,7 +9,7 @@ import ctypes as C
 
 from . import _lib
 from ._lib import (tomo_rect, roi_params, tomo_launch, ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT,
-                   ROI_LOCAL_SIRT, ROI_FLAG_BOX)
+                   ROI_LOCAL_SIRT, ROI_LOCAL_FISTA_TV, ROI_FLAG_BOX)
 
 
 class TomoError(RuntimeError):
@@ -48,17 +48,18 @@ def _stream(stream):
 
 
 def make_params(roi, margin, method="cp", lam=0.0, iters=100, sigma=0.0, tau=0.0, flags=0,
-                box=None):
-    """roi_params; method "cp", "sirt" or "local" (or the enum value); box=(lo, hi)
-    sets ROI_FLAG_BOX with those bounds."""
-    m = {"cp": ROI_TV_NONNEG_CP, "sirt": ROI_NONNEG_SIRT, "local": ROI_LOCAL_SIRT}.get(method,
-                                                                                    method)
+                box=None, inner_iters=0):
+    """roi_params; method "cp", "sirt", "local" or "fista" (or the enum value);
+    box=(lo, hi) sets ROI_FLAG_BOX with those bounds; inner_iters: FGP iterations of
+    "fista" (0: the library's default)."""
+    m = {"cp": ROI_TV_NONNEG_CP, "sirt": ROI_NONNEG_SIRT, "local": ROI_LOCAL_SIRT,
+         "fista": ROI_LOCAL_FISTA_TV}.get(method, method)
     lo, hi = 0.0, float("inf")
     if box is not None:
         lo, hi = float(box[0]), float(box[1])
         flags = int(flags) | ROI_FLAG_BOX
     return roi_params(_rect(roi), int(margin), int(m), float(lam), int(iters), float(sigma),
-                      float(tau), int(flags), lo, hi)
+                      float(tau), int(flags), lo, hi, int(inner_iters))
 
 
 class Context:

@@ -17,6 +17,7 @@ import pytest
 import synth
 import oracle
 from oracle.filters import sirt_filters, filter_apply, local_method_box
+from oracle.fista import local_fista_tv
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -160,6 +161,82 @@ def test_local_method_every_backprojector_shape(ctx, c1, groups, ppt):
         ctx.tomo_set_launch()
     for a, b in zip(got, ref):
         assert rel(a, b) <= 1e-3
+
+
+# (r0, c0, rows, cols, margin, iters, lam, n_fgp, box, flags); flags 1 = 1/2 data term,
+# 2 = anisotropic TV.  Extended parts of 1x1 to 2x2 FGP tiles; FGP counts that end
+# inside a launch (9, 20), on a launch boundary (16) and the default (0 = 100).
+FISTA_C1 = [
+    (48, 48, 32, 32, 16, 30, 500.0, 0, None, 0),
+    (0, 90, 20, 38, 8, 25, 2000.0, 20, (0.0, 1.0), 2),
+    (70, 5, 9, 1, 4, 30, 300.0, 16, None, 0),
+    (100, 100, 28, 3, 6, 12, 100.0, 9, (0.0, float("inf")), 1),
+]
+
+
+def test_local_fista_tv_matches_oracle(ctx, c1):
+    from paper_1604_02292_amd import make_params
+    cfg = c1["cfg"]
+    p32 = c1["sino"].astype(np.float32).astype(np.float64)
+    geo = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    K = max(r[5] for r in FISTA_C1)
+    U = sirt_filters(geo, K, workers=4)
+    ref = []
+    for (r0, c0, rr, cc, m, it, lam, nf, box, fl) in FISTA_C1:
+        lo, hi = box if box else (-np.inf, np.inf)
+        ref.append(local_fista_tv(geo, p32, (r0, c0, rr, cc), m, U[:it], lam, nf or 100, lo, hi,
+                                  aniso=bool(fl & 2), half=bool(fl & 1)))
+    # one local-SIRT request in the same batch
+    sirt_roi = ROIS_C1[0][:5] + (20,) + ROIS_C1[0][6:]
+    ref_sirt = _local_oracle(geo, p32, [sirt_roi], U)[0]
+    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    F = torch.empty((K, cfg["n_angles"], cfg["n_det"]), dtype=torch.float32, device="cuda")
+    ctx.tomo_sirt_filters(g, K, F)
+    D = torch.empty_like(F)
+    ctx.tomo_sirt_filter_sino(g, F, _gpu(p32), D)
+    params, outs = [], []
+    for (r0, c0, rr, cc, m, it, lam, nf, box, fl) in FISTA_C1:
+        params.append(make_params((r0, c0, rr, cc), m, "fista", lam=lam, iters=it, flags=fl,
+                                  box=box, inner_iters=nf))
+        outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
+    r0, c0, rr, cc, m, it, box = sirt_roi
+    params.append(make_params((r0, c0, rr, cc), m, "local", iters=it, box=box))
+    outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
+    print(f"[fista] batch of {len(params)} requests", flush=True)
+    ctx.roi_solve_local(g, D, params, outs)
+    torch.cuda.synchronize()
+    for roi, o, b in zip(FISTA_C1 + [None], outs, ref + [ref_sirt]):
+        a = o.double().cpu().numpy()
+        assert np.linalg.norm(b) > 0
+        e = rel(a, b)
+        print(f"    {roi if roi else 'local sirt'} rel {e:.2e}", flush=True)
+        assert e <= 1e-3
+    # the TV prior acts: the first request differs from unregularised Alg. 2
+    plain = _local_oracle(geo, p32, [(48, 48, 32, 32, 16, 30, (-np.inf, np.inf))], U)[0]
+    assert rel(ref[0], plain) > 1e-2
+
+
+def test_local_fista_timing_kind(ctx, c1):
+    from paper_1604_02292_amd import make_params
+    cfg = c1["cfg"]
+    p32 = c1["sino"].astype(np.float32)
+    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    K = 5
+    F = torch.empty((K, cfg["n_angles"], cfg["n_det"]), dtype=torch.float32, device="cuda")
+    ctx.tomo_sirt_filters(g, K, F)
+    D = torch.empty_like(F)
+    ctx.tomo_sirt_filter_sino(g, F, _gpu(p32), D)
+    out = torch.empty((32, 32), dtype=torch.float32, device="cuda")
+    ctx.tomo_kernel_timing(1)
+    ctx.tomo_kernel_time(0, reset=True)
+    ctx.roi_solve_local(g, D, [make_params((48, 48, 32, 32), 16, "fista", lam=500.0, iters=K)],
+                        [out])
+    torch.cuda.synchronize()
+    ctx.tomo_kernel_timing(0)
+    assert ctx.tomo_kernel_time(0)[0] == K
+    assert ctx.tomo_kernel_time(1)[0] == K
+    n, ms = ctx.tomo_kernel_time(2)
+    assert n == K and ms > 0
 
 
 def test_box_sirt_matches_oracle(ctx, c1):
