@@ -230,6 +230,32 @@ def local_leg(torch, d, reps=3, iters=None, compare=True):
                "filters_ms": 1e3 * t_filt, "filtered_data_ms": 1e3 * t_conv,
                "filtered_data_gb_per_s": conv_bytes / t_conv / 1e9,
                "filtered_data_bytes": conv_bytes}
+        # local FISTA-TV (Alg. 3) on the same ROIs and filtered data: 100 FGP iterations
+        # per outer iteration, TV prox weight gamma = alpha lambda / 2 = 0.02
+        alpha = 1.0 / (na * nd)
+        lam_f = 2 * 0.02 / alpha
+        fparams = [make_params(r[:4], r[4], "fista", lam=lam_f, iters=its, inner_iters=100)
+                   for r in rois]
+        for _ in range(2):
+            ctx.roi_solve_local(g, D, fparams, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.roi_solve_local(g, D, fparams, outs)
+        torch.cuda.synchronize()
+        t_fista = (time.perf_counter() - t0) / reps
+        ctx.tomo_kernel_timing(1)
+        ctx.tomo_kernel_time(0, reset=True)
+        ctx.roi_solve_local(g, D, fparams, outs)
+        torch.cuda.synchronize()
+        ctx.tomo_kernel_timing(0)
+        n_g, ms_g = ctx.tomo_kernel_time(2)
+        fgp_us = 1e3 * ms_g / max(1, n_g)
+        log(f"local FISTA-TV: 64 ROIs x {its} its x 100 FGP {1e3 * t_fista:.1f} ms per batch; "
+            f"FGP {fgp_us:.1f} us per outer iteration (13 launches)")
+        res["fista_tv"] = {"roi_solves_per_s": len(rois) / t_fista, "ms_per_batch": 1e3 * t_fista,
+                           "fgp_us_per_outer_iteration": fgp_us, "fgp_iterations": 100,
+                           "gamma": 0.02, "lambda": lam_f}
         if compare:
             xe = torch.empty((cfg["n"], cfg["n"]), dtype=torch.float32, device="cuda")
             ctx.tomo_fbp_ramlak(g, sino, xe)

@@ -281,7 +281,6 @@ tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
  *                         item list per XCD (L2 locality), 2 = round-robin
  *   bp_variant            backprojector: 1 = direct band reads from memory,
  *                         2 = band windows staged in LDS per block of angles
- *                         (roi_solve_local always reads directly)
  *   bp_groups             backprojector angle groups per pixel, 1, 2 or 4
  *                         (variant 2 always uses 1)
  *   bp_pixels_per_thread  1 or 2

@@ -134,7 +134,8 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
 // 0: direct band reads (any group count; latency shape).  Same results.
 // compensated = 1: compensated sums over angles, staged, groups 1, ppt 2 only
 // (the items must be built for that tiling).
-// two_channel = 1: the band holds (g, d) pairs (BP_LOCAL jobs only); direct reads.
+// two_channel = 1: the band holds (g, d) pairs (BP_LOCAL / BP_FISTA jobs only); staged
+// or direct reads.
 hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, int groups,
                      int ppt, hipStream_t s, int contiguous = 1, int staged = 0,
                      int compensated = 0, int two_channel = 0);

@@ -12,6 +12,8 @@
 // Nothing here is a dense contraction, so there is no MFMA: the projectors are
 // gathers bound by the vector ALU and the load path, the epilogues by HBM.
 
+#include <type_traits>
+
 #include "tomo_internal.h"
 
 namespace tomo {
@@ -436,7 +438,8 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     __shared__ float zs1[TH + 1][TW + 1];
     __shared__ float red[PPT][AG > 1 ? 256 : 1];   // group partial sums (and the power sums)
     __shared__ float red2[PPT][(AG > 1 && TWO) ? 256 : 1];   // second channel's partial sums
-    static_assert(!TWO || (!STAGED && !COMP), "two-channel bands use direct reads");
+    static_assert(!TWO || !COMP, "two-channel bands are not compensated");
+    constexpr int CH = TWO ? 2 : 1;   // floats per band entry
     // Per-angle anchors of the tile, ANC per pass (AG groups x PA angles).
     constexpr int ANC = STAGED ? 256 : 512, PA = ANC / AG;   // (sized for LDS occupancy)
     // Staged band windows: WS entries per angle starting SHIFT below the
@@ -447,13 +450,14 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     constexpr int SHIFT = 32, WS = 64;
     constexpr int PSH = isqrt_above((TW / 2) * (TW / 2) + (TH / 2) * (TH / 2)) + 1;
     static_assert(PSH <= SHIFT, "pixel offsets exceed the window");
-    constexpr int KA = 32 / AG, NW = AG * KA, WPW = NW / 4;   // per stage: angles per group,
-                                                              // windows, windows per wave
+    // per stage: angles per group, windows, windows per wave (two-channel windows hold
+    // twice the data, so half as many per stage keep the LDS footprint)
+    constexpr int KA = (TWO ? 16 : 32) / AG, NW = AG * KA, WPW = NW / 4;
     static_assert(TW * TW + TH * TH <= 36 * 36, "tile too large for the band window");
     __shared__ Anchor anc[ANC];
     // [guard][buffer 0: NW windows][buffer 1][guard]: stray lanes of ragged tiles
     // stay inside the guards
-    __shared__ float win[STAGED ? (2 * NW + 2) * WS : 1];
+    __shared__ float win[STAGED ? (2 * NW + 2) * WS * CH : 1];
     __shared__ WinMeta wmeta[2][STAGED ? NW : 1];
 
     const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
@@ -731,10 +735,11 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     const int wv = uniform_int(t >> 6), lane = t & 63;
     const int bpitch = J->bpitch;
     const int wsmax = bpitch - WS;           // bpitch >= WS by construction
-    const unsigned rowb = (unsigned)bpitch * 4u;
+    const unsigned rowb = (unsigned)bpitch * 4u * CH;
     gcfloat* yband = gview(J->y);
-    const __amdgpu_buffer_rsrc_t rs_band = make_rsrc(yband, (size_t)na * bpitch * sizeof(float));
-    LDS_AS float* const wl = (LDS_AS float*)win + WS;
+    const __amdgpu_buffer_rsrc_t rs_band =
+        make_rsrc(yband, (size_t)na * bpitch * CH * sizeof(float));
+    LDS_AS float* const wl = (LDS_AS float*)win + WS * CH;
     const unsigned wl_bytes = (unsigned)(size_t)wl;
     for (int pass = 0; pass < npass; ++pass) {
         if (pass > 0) {
@@ -764,6 +769,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
             }
         };
         float sv[WPW];
+        v2f sv2[TWO ? WPW : 1];
         auto stage_load = [&](int st) {
             Anchor A[WPW];
             win_anchors(st, A);
@@ -771,12 +777,16 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
             for (int i = 0; i < WPW; ++i) {
                 bool ok;
                 const int kk = win_kk(st, wv * WPW + i, &ok);
-                sv[i] = 0.f;
+                if constexpr (TWO) sv2[i] = v2f{0.f, 0.f};
+                else sv[i] = 0.f;
                 if (ok) {   // the window lies inside its band row: ws in [0, bpitch - WS]
                     const int ws = min(max((uniform_int(A[i].i4) >> 2) + PSH - SHIFT, 0), wsmax);
-                    sv[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                         rs_band, (unsigned)lane * 4u,
-                                                         (unsigned)kk * rowb + (unsigned)ws * 4u, 0));
+                    const unsigned soff = (unsigned)kk * rowb + (unsigned)ws * 4u * CH;
+                    if constexpr (TWO)
+                        sv2[i] = load2(rs_band, (unsigned)lane * 8u, soff);
+                    else
+                        sv[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                             rs_band, (unsigned)lane * 4u, soff, 0));
                 }
             }
         };
@@ -792,10 +802,11 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                 const int I = (uniform_int(A[i].i4) >> 2) + PSH;
                 const int ws = min(max(I - SHIFT, 0), wsmax);
                 const int slot = (buf * NW + w) * WS;
-                wl[slot + lane] = sv[i];
+                if constexpr (TWO) ((LDS_AS v2f*)wl)[slot + lane] = sv2[i];
+                else wl[slot + lane] = sv[i];
                 if (lane == 0) {
                     wmeta[buf][w].f = A[i].f;
-                    wmeta[buf][w].base = wl_bytes + (unsigned)(slot + I - PSH - ws) * 4u;
+                    wmeta[buf][w].base = wl_bytes + (unsigned)(slot + I - PSH - ws) * 4u * CH;
                 }
             }
         };
@@ -812,10 +823,34 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
             if (inside[0]) {
                 const WinMeta* wm = wmeta[buf] + g * KA;
                 constexpr int UA = 8 / PPT;   // LDS latency is short: 8 pair reads in flight
+                // the band pair of a pixel-angle: (y0, y1), or (g0, d0, g1, d1) for two channels
+                using Pair = typename std::conditional<TWO, v4f, v2f>::type;
+                auto fetch = [&](float loc, unsigned base) -> Pair {
+                    if constexpr (TWO) {
+                        const LDS_AS v2f* pp =
+                            (const LDS_AS v2f*)(size_t)(((unsigned)loc << 3) + base);
+                        const v2f e0 = pp[0], e1 = pp[1];
+                        return v4f{e0.x, e0.y, e1.x, e1.y};
+                    } else {
+                        const LDS_AS float* pp =
+                            (const LDS_AS float*)(size_t)(((unsigned)loc << 2) + base);
+                        return v2f{pp[0], pp[1]};
+                    }
+                };
+                auto apply = [&](int q, float w0, float w1, const Pair& v) {
+                    if constexpr (TWO) {
+                        acc[q] = fmaf(w0, v.x, acc[q]);
+                        acc[q] = fmaf(w1, v.z, acc[q]);
+                        acc2[q] = fmaf(w0, v.y, acc2[q]);
+                        acc2[q] = fmaf(w1, v.w, acc2[q]);
+                    } else {
+                        accum(q, w0, v.x, w1, v.y);
+                    }
+                };
                 int j = 0;
                 for (; j + UA <= nj; j += UA) {
                     float f[UA][PPT];
-                    v2f yv[UA][PPT];
+                    Pair yv[UA][PPT];
 #pragma unroll
                     for (int u = 0; u < UA; ++u) {
                         const WinMeta M = wm[j + u];
@@ -825,9 +860,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                         for (int q = 0; q < PPT; ++q) {
                             if (q) loc += a.su;
                             f[u][q] = __builtin_amdgcn_fractf(loc);
-                            const LDS_AS float* pp =
-                                (const LDS_AS float*)(size_t)(((unsigned)loc << 2) + M.base);
-                            yv[u][q] = v2f{pp[0], pp[1]};
+                            yv[u][q] = fetch(loc, M.base);
                         }
                     }
 #pragma unroll
@@ -838,7 +871,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                             // clamp to [0, 1] == max(0, .) here: r <= 1 and f >= 0
                             const float w0 = __builtin_amdgcn_fmed3f(r - f[u][q], 0.f, 1.f);
                             const float w1 = __builtin_amdgcn_fmed3f(f[u][q] + rm1, 0.f, 1.f);
-                            accum(q, w0, yv[u][q].x, w1, yv[u][q].y);
+                            apply(q, w0, w1, yv[u][q]);
                         }
                     }
                 }
@@ -850,11 +883,10 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                     for (int q = 0; q < PPT; ++q) {
                         if (q) loc += a.su;
                         const float f = __builtin_amdgcn_fractf(loc);
-                        const LDS_AS float* pp =
-                            (const LDS_AS float*)(size_t)(((unsigned)loc << 2) + M.base);
+                        const Pair v = fetch(loc, M.base);
                         const float w0 = __builtin_amdgcn_fmed3f(a.r - f, 0.f, 1.f);
                         const float w1 = __builtin_amdgcn_fmed3f(f + a.rm1, 0.f, 1.f);
-                        accum(q, w0, pp[0], w1, pp[1]);
+                        apply(q, w0, w1, v);
                     }
                 }
             }
@@ -1123,11 +1155,16 @@ __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sin
 // the gradient is zero on the region's last row / column (Neumann), so the duals
 // stay zero there, as in the CP kernel's TV.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void fgp_kernel(const Job* __restrict__ jobs,
+constexpr int kFgpThreads = 512;
+
+__global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict__ jobs,
                                                   const Item* __restrict__ items, int n_items,
                                                   int step, int i0) {
     constexpr int H = kFgpSteps + 1, RW = kFgpTile + 2 * H, RN = RW * RW;
-    __shared__ float sb[RN], sx[RN], sr0[RN], sr1[RN], sp0[RN], sp1[RN];
+    constexpr int NQ = (RN + kFgpThreads - 1) / kFgpThreads;   // region pixels per thread
+    // Each thread keeps its own pixels' b, p and r in registers; only x and r,
+    // which neighbours read, go through LDS.
+    __shared__ float sx[RN], sr0[RN], sr1[RN];
     const int bid = blockIdx.x;
     if (bid >= n_items) return;
     const Item it = cview(items)[bid];
@@ -1141,53 +1178,71 @@ __global__ __launch_bounds__(256) void fgp_kernel(const Job* __restrict__ jobs,
     const int R0 = it.a * kFgpTile - H, C0 = it.b * kFgpTile - H;
     const size_t plane = (size_t)nr * nc;
     const float gamma = J->gamma;
-    const bool iters = gamma > 0.f && i1 > i0;
     const int t = threadIdx.x;
-    for (int q = t; q < RN; q += 256) {
-        const int rr = R0 + q / RW, cc = C0 + q % RW;
-        float b = 0.f, p0 = 0.f, p1 = 0.f, r0 = 0.f, r1 = 0.f;
-        if (rr >= 0 && rr < nr && cc >= 0 && cc < nc) {
-            const size_t pi = (size_t)rr * nc + cc;
-            b = J->w[pi];
-            if (i0 > 0 && gamma > 0.f) {
-                p0 = J->fp[pi];
-                p1 = J->fp[plane + pi];
-                r0 = J->fr[pi];
-                r1 = J->fr[plane + pi];
+    // per own pixel: flags (inside, has up / left / down / right neighbour in the
+    // region, gradient rows / columns nonzero), b, p, r
+    enum { IN = 1, UP = 2, LEFT = 4, DOWN = 8, RIGHT = 16, G0 = 32, G1 = 64 };
+    int fl[NQ];
+    float b[NQ], p0[NQ], p1[NQ], r0[NQ], r1[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = t + kFgpThreads * u;
+        const int lr = q / RW, lc = q % RW;
+        const int rr = R0 + lr, cc = C0 + lc;
+        int f = 0;
+        b[u] = p0[u] = p1[u] = r0[u] = r1[u] = 0.f;
+        if (q < RN) {
+            f |= (lr > 0 ? UP : 0) | (lc > 0 ? LEFT : 0) | (lr + 1 < RW ? DOWN : 0) |
+                 (lc + 1 < RW ? RIGHT : 0);
+            if (rr >= 0 && rr < nr && cc >= 0 && cc < nc) {
+                f |= IN | (rr < nr - 1 ? G0 : 0) | (cc < nc - 1 ? G1 : 0);
+                const size_t pi = (size_t)rr * nc + cc;
+                b[u] = J->w[pi];
+                if (i0 > 0 && gamma > 0.f) {
+                    p0[u] = J->fp[pi];
+                    p1[u] = J->fp[plane + pi];
+                    r0[u] = J->fr[pi];
+                    r1[u] = J->fr[plane + pi];
+                }
             }
+            sr0[q] = r0[u];
+            sr1[q] = r1[u];
         }
-        sb[q] = b;
-        sp0[q] = p0;
-        sp1[q] = p1;
-        sr0[q] = r0;
-        sr1[q] = r1;
+        fl[u] = f;
     }
     __syncthreads();
     const float lo = J->lo, hi = J->hi;
-    if (iters) {
+    if (gamma > 0.f && i1 > i0) {
         const float inv8g = 1.f / (8.f * gamma);
         const bool aniso = (J->flags & JF_ANISO) != 0;
+#pragma unroll 1
         for (int i = i0; i < i1; ++i) {
             // x = P(b - gamma div r); div r = r0 - r0(up) + r1 - r1(left), zero outside
-            for (int q = t; q < RN; q += 256) {
-                const int lr = q / RW, lc = q % RW;
-                const float up = lr > 0 ? sr0[q - RW] : 0.f;
-                const float left = lc > 0 ? sr1[q - 1] : 0.f;
-                const float d = (sr0[q] - up) + (sr1[q] - left);
-                sx[q] = fminf(fmaxf(sb[q] - gamma * d, lo), hi);
+            float xr[NQ];
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = t + kFgpThreads * u;
+                xr[u] = 0.f;
+                if (q < RN) {
+                    const float up = (fl[u] & UP) ? sr0[q - RW] : 0.f;
+                    const float left = (fl[u] & LEFT) ? sr1[q - 1] : 0.f;
+                    const float d = (r0[u] - up) + (r1[u] - left);
+                    xr[u] = fminf(fmaxf(b[u] - gamma * d, lo), hi);
+                    sx[q] = xr[u];
+                }
             }
             __syncthreads();
             const float beta = J->beta_in[i];
-            for (int q = t; q < RN; q += 256) {
-                const int lr = q / RW, lc = q % RW;
-                const int rr = R0 + lr, cc = C0 + lc;
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int q = t + kFgpThreads * u;
+                if (q >= RN) continue;
                 float n0 = 0.f, n1 = 0.f;
-                if (rr >= 0 && rr < nr && cc >= 0 && cc < nc) {
-                    const float xc = sx[q];
-                    const float g0 = (rr < nr - 1 && lr + 1 < RW) ? sx[q + RW] - xc : 0.f;
-                    const float g1 = (cc < nc - 1 && lc + 1 < RW) ? sx[q + 1] - xc : 0.f;
-                    n0 = sr0[q] - g0 * inv8g;
-                    n1 = sr1[q] - g1 * inv8g;
+                if (fl[u] & IN) {
+                    const float g0 = (fl[u] & G0) && (fl[u] & DOWN) ? sx[q + RW] - xr[u] : 0.f;
+                    const float g1 = (fl[u] & G1) && (fl[u] & RIGHT) ? sx[q + 1] - xr[u] : 0.f;
+                    n0 = r0[u] - g0 * inv8g;
+                    n1 = r1[u] - g1 * inv8g;
                     if (aniso) {
                         n0 = fminf(fmaxf(n0, -1.f), 1.f);
                         n1 = fminf(fmaxf(n1, -1.f), 1.f);
@@ -1197,31 +1252,47 @@ __global__ __launch_bounds__(256) void fgp_kernel(const Job* __restrict__ jobs,
                         n1 = n1 / sc;
                     }
                 }
-                sr0[q] = n0 + beta * (n0 - sp0[q]);
-                sr1[q] = n1 + beta * (n1 - sp1[q]);
-                sp0[q] = n0;
-                sp1[q] = n1;
+                r0[u] = n0 + beta * (n0 - p0[u]);
+                r1[u] = n1 + beta * (n1 - p1[u]);
+                p0[u] = n0;
+                p1[u] = n1;
+                sr0[q] = r0[u];
+                sr1[q] = r1[u];
             }
             __syncthreads();
         }
     }
+    if (last) {   // p (not r) forms the result: share it through the r arrays
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int q = t + kFgpThreads * u;
+            if (q < RN) {
+                sr0[q] = p0[u];
+                sr1[q] = p1[u];
+            }
+        }
+        __syncthreads();
+    }
     // the tile's own pixels
-    for (int q = t; q < kFgpTile * kFgpTile; q += 256) {
-        const int lr = H + q / kFgpTile, lc = H + q % kFgpTile;
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = t + kFgpThreads * u;
+        if (q >= RN) continue;
+        const int lr = q / RW, lc = q % RW;
+        if (lr < H || lr >= H + kFgpTile || lc < H || lc >= H + kFgpTile) continue;
         const int rr = R0 + lr, cc = C0 + lc;
         if (rr >= nr || cc >= nc) continue;
-        const int k = lr * RW + lc;
         const size_t pi = (size_t)rr * nc + cc;
         if (!last) {
-            J->fp[pi] = sp0[k];
-            J->fp[plane + pi] = sp1[k];
-            J->fr[pi] = sr0[k];
-            J->fr[plane + pi] = sr1[k];
+            J->fp[pi] = p0[u];
+            J->fp[plane + pi] = p1[u];
+            J->fr[pi] = r0[u];
+            J->fr[plane + pi] = r1[u];
             continue;
         }
         // x = P(b - gamma div p), then the FISTA momentum point z and v = z - x_s
-        const float d = (sp0[k] - sp0[k - RW]) + (sp1[k] - sp1[k - 1]);
-        const float x = fminf(fmaxf(sb[k] - gamma * d, lo), hi);
+        const float d = (p0[u] - sr0[q - RW]) + (p1[u] - sr1[q - 1]);
+        const float x = fminf(fmaxf(b[u] - gamma * d, lo), hi);
         const size_t xi = (size_t)rr * J->ldx + cc;
         const float xo = J->x[xi];
         const float z = x + J->beta_out[step] * (x - xo);
@@ -1443,7 +1514,10 @@ hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, 
     hipLaunchKernelGGL((bp_kernel<AGV, PPTV, ST, CO, TW>), grid, block, 0, s, jobs, items, \
                        n_items, step, contiguous)
 #define TOMO_BP(AGV, PPTV, ST, CO) TOMO_BP_T(AGV, PPTV, ST, CO, false)
-    if (two_channel) {   // direct reads of (g, d) pairs
+    if (two_channel && staged) {   // (g, d) pairs staged in LDS
+        if (ppt == 2) TOMO_BP_T(1, 2, true, false, true);
+        else TOMO_BP_T(1, 1, true, false, true);
+    } else if (two_channel) {   // direct reads of (g, d) pairs
         if (ppt == 2) {
             switch (groups) {
                 case 1: TOMO_BP_T(1, 2, false, false, true); break;
@@ -1542,7 +1616,8 @@ hipError_t launch_power_normalize(const float* w, int ldx, int nr, int nc, const
 hipError_t launch_fgp(const Job* jobs, const Item* items, int n_items, int step, int i0,
                       hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fgp_kernel, dim3(n_items), dim3(256), 0, s, jobs, items, n_items, step, i0);
+    hipLaunchKernelGGL(fgp_kernel, dim3(n_items), dim3(kFgpThreads), 0, s, jobs, items, n_items,
+                       step, i0);
     return hipGetLastError();
 }
 

@@ -259,9 +259,7 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
             max_nf = std::max(max_nf, params[i].inner_iters > 0 ? params[i].inner_iters : 100);
         max_iters = std::max(max_iters, params[i].iters);
     }
-    // the backprojector reads the two-channel band directly (no LDS staging)
     LaunchCfg L = choose_launch_for(ctx, geom, count, rays, pix);
-    L.staged = 0;
     int th, tw;
     bp_tile(L.ag, L.ppt, &th, &tw);
 
@@ -368,8 +366,8 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
                 hipSuccess)
                 return e;
             if (timed && (e = hipEventRecord(e1, sq)) != hipSuccess) return e;
-            if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, sq, L.cbp, 0, 0,
-                               1)) != hipSuccess)
+            if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, sq, L.cbp,
+                               L.staged, 0, 1)) != hipSuccess)
                 return e;
             if (timed) {
                 if ((e = hipEventRecord(e2, sq)) != hipSuccess) return e;

@@ -144,8 +144,9 @@ def test_local_method_matches_oracle(ctx, c1):
     assert rel(got1[0], ref[0]) <= 1e-3
 
 
-@pytest.mark.parametrize("groups,ppt", [(1, 1), (2, 1), (4, 1), (1, 2), (2, 2), (4, 2)])
-def test_local_method_every_backprojector_shape(ctx, c1, groups, ppt):
+@pytest.mark.parametrize("variant,groups,ppt", [(1, 1, 1), (1, 2, 1), (1, 4, 1), (1, 1, 2),
+                                                (1, 2, 2), (1, 4, 2), (2, 1, 1), (2, 1, 2)])
+def test_local_method_every_backprojector_shape(ctx, c1, variant, groups, ppt):
     cfg = c1["cfg"]
     p32 = c1["sino"].astype(np.float32).astype(np.float64)
     geo = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
@@ -153,8 +154,8 @@ def test_local_method_every_backprojector_shape(ctx, c1, groups, ppt):
     K = 50
     U = sirt_filters(geo, K, workers=4)
     ref = _local_oracle(geo, p32, rois, U)
-    print(f"[local shape] groups={groups} ppt={ppt}", flush=True)
-    ctx.tomo_set_launch(bp_variant=1, bp_groups=groups, bp_pixels_per_thread=ppt)
+    print(f"[local shape] variant={variant} groups={groups} ppt={ppt}", flush=True)
+    ctx.tomo_set_launch(bp_variant=variant, bp_groups=groups, bp_pixels_per_thread=ppt)
     try:
         got, _, _ = _local_gpu(ctx, cfg, p32, rois, K)
     finally:
@@ -174,7 +175,8 @@ FISTA_C1 = [
 ]
 
 
-def test_local_fista_tv_matches_oracle(ctx, c1):
+@pytest.mark.parametrize("variant", [1, 2])
+def test_local_fista_tv_matches_oracle(ctx, c1, variant):
     from paper_1604_02292_amd import make_params
     cfg = c1["cfg"]
     p32 = c1["sino"].astype(np.float32).astype(np.float64)
@@ -202,9 +204,13 @@ def test_local_fista_tv_matches_oracle(ctx, c1):
     r0, c0, rr, cc, m, it, box = sirt_roi
     params.append(make_params((r0, c0, rr, cc), m, "local", iters=it, box=box))
     outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
-    print(f"[fista] batch of {len(params)} requests", flush=True)
-    ctx.roi_solve_local(g, D, params, outs)
-    torch.cuda.synchronize()
+    print(f"[fista] batch of {len(params)} requests, backprojector variant {variant}", flush=True)
+    ctx.tomo_set_launch(bp_variant=variant)
+    try:
+        ctx.roi_solve_local(g, D, params, outs)
+        torch.cuda.synchronize()
+    finally:
+        ctx.tomo_set_launch()
     for roi, o, b in zip(FISTA_C1 + [None], outs, ref + [ref_sirt]):
         a = o.double().cpu().numpy()
         assert np.linalg.norm(b) > 0
