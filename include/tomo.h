@@ -227,6 +227,30 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
                             int32_t count, const roi_params* params, float* const* outs,
                             void* hip_stream);
 
+/* Disc subtraction (Section 3.3): out = sino - c W disc, where disc is the image that
+ * is 1 on the pixels whose centres lie within n/2 of the grid centre (decided exactly)
+ * and c = sum_a S_a T_a / sum_a T_a^2 minimises the l2 norm of the projections'
+ * zero-frequency components (S_a, T_a: FP64 row sums of sino and of W disc).  c is
+ * written to *value (device float, caller-owned); out may be sino.  Undo it on a
+ * result with tomo_disc_add.  Stream-ordered; the disc's projection lives in the
+ * workspace during the call.  Errors: EINVAL (null), ENOENT, ENOMEM, EHIP. */
+tomo_status tomo_disc_subtract(tomo_ctx* ctx, int32_t geom, const float* sino, float* out,
+                               float* value, void* hip_stream);
+
+/* Adds *value (device float) to the pixels of img (float[region.rows][region.cols],
+ * the given region of the grid, device) that belong to the disc of
+ * tomo_disc_subtract.  Stream-ordered.  Errors: EINVAL, ENOENT, EHIP. */
+tomo_status tomo_disc_add(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* value,
+                          float* img, void* hip_stream);
+
+/* Constant padding of truncated data (Section 4): trunc holds n_bins measured bins per
+ * angle (float[n_angles][n_bins], device), detector bins first_bin .. first_bin +
+ * n_bins - 1 of the geometry; out (float[n_angles][n_det], device) receives them with
+ * every row extended by its first and last measured values.  Stream-ordered.
+ * Errors: EINVAL (null, bins outside the detector), ENOENT, EHIP. */
+tomo_status tomo_pad_truncated(tomo_ctx* ctx, int32_t geom, const float* trunc, int32_t first_bin,
+                               int32_t n_bins, float* out, void* hip_stream);
+
 /* The CP step size the library would use for extended region `ext` (host float
  * out).  Runs the power iteration if the shape is not cached (blocking).
  * Errors: EINVAL, ENOENT, ENOMEM, EHIP. */

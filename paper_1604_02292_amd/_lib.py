@@ -59,6 +59,9 @@ SIGNATURES = {
     "tomo_sirt_filters": (C.c_int, [_P, _I, _I, _P, _P]),
     "tomo_sirt_filter_sino": (C.c_int, [_P, _I, _P, _I, _P, _P, _P]),
     "roi_solve_local": (C.c_int, [_P, _I, _P, _I, _I, C.POINTER(roi_params), C.POINTER(_P), _P]),
+    "tomo_disc_subtract": (C.c_int, [_P, _I, _P, _P, _P, _P]),
+    "tomo_disc_add": (C.c_int, [_P, _I, tomo_rect, _P, _P, _P]),
+    "tomo_pad_truncated": (C.c_int, [_P, _I, _P, _I, _I, _P, _P]),
     "tomo_register_sinogram": (C.c_int, [_P, _I, _P, C.POINTER(_I)]),
     "tomo_unregister_sinogram": (C.c_int, [_P, _I]),
     "roi_submit": (C.c_int, [_P, _I, C.POINTER(roi_params), _P, C.POINTER(C.c_uint64)]),

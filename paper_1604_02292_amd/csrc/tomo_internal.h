@@ -146,6 +146,21 @@ hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, 
 constexpr int kFgpTile = 32, kFgpSteps = 8;
 hipError_t launch_fgp(const Job* jobs, const Item* items, int n_items, int step, int i0,
                       hipStream_t s);
+// Disc of diameter n about the grid centre (exact integer test): add = 0 writes its
+// indicator into the region (r0, c0, rows, cols) of img (pitch ld); add = 1 adds *value
+// on its pixels.
+hipError_t launch_disc(float* img, int ld, int n, int r0, int c0, int rows, int cols,
+                       const float* value, int add, hipStream_t s);
+// *value = sum_a S_a T_a / sum_a T_a^2 with S, T the FP64 row sums of p and D (st: 2 na doubles).
+hipError_t launch_disc_value(const float* p, const float* D, int na, int nd, double* st,
+                             float* value, hipStream_t s);
+// out = p - *value * D (out may be p).
+hipError_t launch_disc_apply(const float* p, const float* D, size_t n, const float* value,
+                             float* out, hipStream_t s);
+// Rows of nb measured bins starting at detector bin `first`, extended to nd bins with
+// their edge values.
+hipError_t launch_pad_truncated(const float* trunc, int na, int nb, int first, int nd,
+                                float* out, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int tp, float v,
                               hipStream_t s);

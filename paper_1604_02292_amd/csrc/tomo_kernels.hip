@@ -12,6 +12,7 @@
 // Nothing here is a dense contraction, so there is no MFMA: the projectors are
 // gathers bound by the vector ALU and the load path, the epilogues by HBM.
 
+#include <algorithm>
 #include <type_traits>
 
 #include "tomo_internal.h"
@@ -1145,6 +1146,100 @@ __global__ __launch_bounds__(256) void ramp_kernel(const float* __restrict__ sin
 // Power iteration: v = w / ||w||, ||w|| from the per-tile partial sums (summed
 // in the same fixed order by every block), written into the padded buffers.
 // ---------------------------------------------------------------------------
+// Preprocessing of the local method (Section 3.3 disc subtraction; Section 4
+// constant padding of truncated data).  A pixel belongs to the disc of
+// diameter n about the grid centre when (2c - n + 1)^2 + (2r - n + 1)^2 <= n^2,
+// decided exactly in integers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool in_disc(int n, int r, int c) {
+    const long long dx = 2LL * c - (n - 1), dy = 2LL * r - (n - 1);
+    return dx * dx + dy * dy <= (long long)n * n;
+}
+
+// img[r][c] (region (r0, c0) of the grid, pitch ld): add = 0 writes the disc
+// indicator; add = 1 adds *value on the disc's pixels.
+__global__ void disc_kernel(float* __restrict__ img, int ld, int n, int r0, int c0, int rows,
+                            int cols, const float* __restrict__ value, int add) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= cols || r >= rows) return;
+    const bool in = in_disc(n, r0 + r, c0 + c);
+    float* q = img + (size_t)r * ld + c;
+    if (add) {
+        if (in) *q += *value;
+    } else {
+        *q = in ? 1.f : 0.f;
+    }
+}
+
+// Row sums of the data and of the disc's projection, in FP64: st[2a] = sum_i p[a][i],
+// st[2a + 1] = sum_i D[a][i].  One block per angle.
+__global__ __launch_bounds__(256) void disc_sums_kernel(const float* __restrict__ p,
+                                                        const float* __restrict__ D, int nd,
+                                                        double* __restrict__ st) {
+    __shared__ double s0[256], s1[256];
+    const int a = blockIdx.x, t = threadIdx.x;
+    double u = 0.0, v = 0.0;
+    for (int i = t; i < nd; i += 256) {
+        u += (double)p[(size_t)a * nd + i];
+        v += (double)D[(size_t)a * nd + i];
+    }
+    s0[t] = u;
+    s1[t] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            s0[t] += s0[t + h];
+            s1[t] += s1[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        st[2 * a] = s0[0];
+        st[2 * a + 1] = s1[0];
+    }
+}
+
+// value = sum_a S_a T_a / sum_a T_a^2 (one block).
+__global__ __launch_bounds__(256) void disc_value_kernel(const double* __restrict__ st, int na,
+                                                         float* __restrict__ value) {
+    __shared__ double s0[256], s1[256];
+    const int t = threadIdx.x;
+    double u = 0.0, v = 0.0;
+    for (int a = t; a < na; a += 256) {
+        u += st[2 * a] * st[2 * a + 1];
+        v += st[2 * a + 1] * st[2 * a + 1];
+    }
+    s0[t] = u;
+    s1[t] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            s0[t] += s0[t + h];
+            s1[t] += s1[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) *value = s1[0] > 0.0 ? (float)(s0[0] / s1[0]) : 0.f;
+}
+
+__global__ void disc_apply_kernel(const float* __restrict__ p, const float* __restrict__ D,
+                                  size_t n, const float* __restrict__ value, float* out) {
+    const float v = *value;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        out[i] = fmaf(-v, D[i], p[i]);
+}
+
+// out[a][i] = trunc[a][clamp(i - first, 0, nb - 1)]
+__global__ void pad_truncated_kernel(const float* __restrict__ trunc, int nb, int first, int nd,
+                                     float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, a = blockIdx.y;
+    if (i >= nd) return;
+    const int j = min(max(i - first, 0), nb - 1);
+    out[(size_t)a * nd + i] = trunc[(size_t)a * nb + j];
+}
+
+// ---------------------------------------------------------------------------
 // FGP (fast gradient projection on the dual of TV denoising, the inner solver of
 // the paper's local FISTA-TV, Alg. 3): min_{lo <= x <= hi} ||x - b||^2 + 2 gamma TV(x),
 //   x = P(b - gamma div r),  p' = P_1(r - grad x / (8 gamma)),  r = p' + beta_i (p' - p).
@@ -1618,6 +1713,38 @@ hipError_t launch_fgp(const Job* jobs, const Item* items, int n_items, int step,
     if (n_items <= 0) return hipSuccess;
     hipLaunchKernelGGL(fgp_kernel, dim3(n_items), dim3(kFgpThreads), 0, s, jobs, items, n_items,
                        step, i0);
+    return hipGetLastError();
+}
+
+hipError_t launch_disc(float* img, int ld, int n, int r0, int c0, int rows, int cols,
+                       const float* value, int add, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(disc_kernel, dim3((cols + 255) / 256, rows), dim3(256), 0, s, img, ld, n,
+                       r0, c0, rows, cols, value, add);
+    return hipGetLastError();
+}
+
+hipError_t launch_disc_value(const float* p, const float* D, int na, int nd, double* st,
+                             float* value, hipStream_t s) {
+    if (na <= 0) return hipSuccess;
+    hipLaunchKernelGGL(disc_sums_kernel, dim3(na), dim3(256), 0, s, p, D, nd, st);
+    hipLaunchKernelGGL(disc_value_kernel, dim3(1), dim3(256), 0, s, st, na, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_disc_apply(const float* p, const float* D, size_t n, const float* value,
+                             float* out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(disc_apply_kernel, dim3(blocks), dim3(256), 0, s, p, D, n, value, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_truncated(const float* trunc, int na, int nb, int first, int nd,
+                                float* out, hipStream_t s) {
+    if (na <= 0 || nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pad_truncated_kernel, dim3((nd + 255) / 256, na), dim3(256), 0, s, trunc,
+                       nb, first, nd, out);
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
-// The paper's own local method (Sections 3.1-3.2): the SIRT-approximating
-// filters of Alg. 1, the filtered data C_{u_k} p shared by all local parts, and
-// the iteration of Alg. 2 with the box prior of eq. sirtbox, batched over many
-// ROIs the same way as the exterior-subtraction solvers.
+// The paper's own local method (Sections 3.1-3.3): the SIRT-approximating
+// filters of Alg. 1, the filtered data C_{u_k} p shared by all local parts, the
+// iterations of Alg. 2 (box prior) and Alg. 3 (FISTA-TV) batched over many ROIs
+// the same way as the exterior-subtraction solvers, and the data preprocessing
+// (disc subtraction, constant padding of truncated data).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -432,6 +433,77 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
     }
 #undef CK
     cleanup();
+    return TOMO_OK;
+    GUARD_END(ctx)
+}
+
+tomo_status tomo_disc_subtract(tomo_ctx* ctx, int32_t geom, const float* sino, float* out,
+                               float* value, void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!sino || !out || !value) return fail(ctx, TOMO_EINVAL, "null pointer");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const Geom& g = *gp;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t npix = (size_t)g.n * g.n, nsino = (size_t)g.na * g.nd;
+    char* blk = ctx->arena.alloc(align_up(npix * sizeof(float), 256) +
+                                 align_up(nsino * sizeof(float), 256) + 2 * g.na * sizeof(double));
+    if (!blk) return fail(ctx, TOMO_ENOMEM, "workspace too small for the disc projection");
+    std::vector<char*> allocs{blk};
+    float* disc = (float*)blk;
+    float* D = (float*)(blk + align_up(npix * sizeof(float), 256));
+    double* sums = (double*)((char*)D + align_up(nsino * sizeof(float), 256));
+    hipError_t e = launch_disc(disc, g.n, g.n, 0, 0, g.n, g.n, nullptr, 0, s);
+    if (e != hipSuccess) {
+        ctx->arena.free_after(allocs, s);
+        return fail(ctx, TOMO_EHIP, "disc image: %s", hipGetErrorString(e));
+    }
+    // D = W disc through the library's own projection call
+    st = tomo_fp(ctx, geom, tomo_rect{0, 0, g.n, g.n}, disc, D, 0, hip_stream);
+    if (st == TOMO_OK) {
+        e = launch_disc_value(sino, D, g.na, g.nd, sums, value, s);
+        if (e == hipSuccess) e = launch_disc_apply(sino, D, nsino, value, out, s);
+        if (e != hipSuccess) st = fail(ctx, TOMO_EHIP, "disc subtraction: %s", hipGetErrorString(e));
+    }
+    ctx->arena.free_after(allocs, s);
+    return st;
+    GUARD_END(ctx)
+}
+
+tomo_status tomo_disc_add(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* value,
+                          float* img, void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!value || !img) return fail(ctx, TOMO_EINVAL, "null pointer");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const Geom& g = *gp;
+    if (region.rows < 1 || region.cols < 1 || region.row0 < 0 || region.col0 < 0 ||
+        region.row0 + region.rows > g.n || region.col0 + region.cols > g.n)
+        return fail(ctx, TOMO_EINVAL, "region is empty or outside the grid");
+    TOMO_HIP(ctx, launch_disc(img, region.cols, g.n, region.row0, region.col0, region.rows,
+                              region.cols, value, 1, (hipStream_t)hip_stream));
+    return TOMO_OK;
+    GUARD_END(ctx)
+}
+
+tomo_status tomo_pad_truncated(tomo_ctx* ctx, int32_t geom, const float* trunc, int32_t first_bin,
+                               int32_t n_bins, float* out, void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!trunc || !out) return fail(ctx, TOMO_EINVAL, "null pointer");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    const Geom& g = *gp;
+    if (n_bins < 1 || first_bin < 0 || first_bin + n_bins > g.nd)
+        return fail(ctx, TOMO_EINVAL, "measured bins [%d, %d) outside the %d-bin detector",
+                    first_bin, first_bin + n_bins, g.nd);
+    TOMO_HIP(ctx, launch_pad_truncated(trunc, g.na, n_bins, first_bin, g.nd, out,
+                                       (hipStream_t)hip_stream));
     return TOMO_OK;
     GUARD_END(ctx)
 }

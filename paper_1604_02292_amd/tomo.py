@@ -196,6 +196,25 @@ class Context:
                                                                 "filtered"),
                                              planes, cnt, parr, oarr, _stream(stream)))
 
+    # -- preprocessing of the local method ------------------------------------
+    def tomo_disc_subtract(self, geom, sino, out, value, stream=None):
+        n, na, nd = self.geoms[geom]
+        self._check(self.lib.tomo_disc_subtract(
+            self.h, geom, _ptr(sino, (na, nd), "sino"), _ptr(out, (na, nd), "out"),
+            _ptr(value, (1,), "value"), _stream(stream)))
+
+    def tomo_disc_add(self, geom, region, value, img, stream=None):
+        r = _rect(region)
+        self._check(self.lib.tomo_disc_add(self.h, geom, r, _ptr(value, (1,), "value"),
+                                           _ptr(img, (r.rows, r.cols), "img"), _stream(stream)))
+
+    def tomo_pad_truncated(self, geom, trunc, first_bin, out, stream=None):
+        n, na, nd = self.geoms[geom]
+        nb = int(trunc.shape[1]) if trunc is not None and trunc.dim() == 2 else 0
+        self._check(self.lib.tomo_pad_truncated(
+            self.h, geom, _ptr(trunc, (na, nb), "trunc"), int(first_bin), nb,
+            _ptr(out, (na, nd), "out"), _stream(stream)))
+
     def roi_step_size(self, geom, ext):
         v = C.c_float()
         self._check(self.lib.roi_step_size(self.h, geom, _rect(ext), C.byref(v)))
