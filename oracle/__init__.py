@@ -26,6 +26,7 @@ Contents and the passages they follow:
              (eq. localmethod, Alg. 2) with the box prior of eq. sirtbox
   fista      FGP total-variation denoiser and the paper's local FISTA-TV (Alg. 3)
   preprocess disc subtraction (Section 3.3) and constant padding of truncated data (Section 4)
+  haar       Haar wavelet l1 prior (eq. sirtista) and its local FISTA
 
 Every function is pinned by tests in tests/test_oracle_*.py against facts the paper
 or mathematics fixes (adjoint identity between two independent projector codes,
@@ -45,6 +46,7 @@ from .filters import (sirt_filters, filter_centres, filter_apply, fbp_filter, si
                       local_method_box)
 from .fista import fgp, local_fista_tv, prox_weight
 from .preprocess import disc_image, disc_value, disc_subtract, disc_add, pad_truncated
+from .haar import haar_forward, haar_inverse, haar_prox, local_fista_haar
 
 __all__ = [
     "Geometry", "make_geometry", "roi_extend", "band_exact", "hat_weight", "fp_ray",
@@ -53,5 +55,6 @@ __all__ = [
     "sirt_nonneg", "power_norm_sq", "cp_objective", "cp_steps", "exterior_subtract",
     "local_solve", "crop", "stitch", "sirt_filters", "filter_centres", "filter_apply",
     "fbp_filter", "sirt_iterates", "local_method_box", "fgp", "local_fista_tv", "prox_weight",
-    "disc_image", "disc_value", "disc_subtract", "disc_add", "pad_truncated",
+    "disc_image", "disc_value", "disc_subtract", "disc_add", "pad_truncated", "haar_forward",
+    "haar_inverse", "haar_prox", "local_fista_haar",
 ]

@@ -92,8 +92,16 @@ def local_fista_tv(geom, sino, rect, margin, filters, lam, n_fgp, lo=-np.inf, hi
                    aniso=False, half=False, alpha=None, xs_iterates=None, full=False):
     """Alg. 3 on the extended local part.  filters: U from sirt_filters (U[k-1] = u_k);
     xs_iterates (optional, [K, N, N]) replaces FBP_L(p, u_k) by those images."""
-    alpha = default_alpha(geom) if alpha is None else alpha
     gamma = prox_weight(geom, lam, alpha, half)
+    return local_fista(geom, sino, rect, margin, filters,
+                       lambda w: fgp(w, gamma, n_fgp, lo, hi, aniso), alpha, xs_iterates, full,
+                       gamma)
+
+
+def local_fista(geom, sino, rect, margin, filters, prox, alpha=None, xs_iterates=None,
+                full=False, gamma=None):
+    """Alg. 3 with any proximal step `prox` (image -> image) in place of FGP."""
+    alpha = default_alpha(geom) if alpha is None else alpha
     ext = roi_extend(rect, margin, geom.n)
     r0, c0, rr, cc = ext
     WL = sparse_local(geom, ext)
@@ -108,7 +116,7 @@ def local_fista_tv(geom, sino, rect, margin, filters, lam, n_fgp, lo=-np.inf, hi
         else:
             xs = np.asarray(xs_iterates[k])[r0:r0 + rr, c0:c0 + cc].ravel()
         q = zl - alpha * (WL.T @ (WL @ zl))
-        x = fgp((xs + q).reshape(rr, cc), gamma, n_fgp, lo, hi, aniso).ravel()
+        x = np.asarray(prox((xs + q).reshape(rr, cc)), dtype=np.float64).ravel()
         t_new = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0
         z = x + ((t - 1.0) / t_new) * (x - x_prev)
         zl = z - xs
