@@ -256,6 +256,29 @@ def local_leg(torch, d, reps=3, iters=None, compare=True):
         res["fista_tv"] = {"roi_solves_per_s": len(rois) / t_fista, "ms_per_batch": 1e3 * t_fista,
                            "fgp_us_per_outer_iteration": fgp_us, "fgp_iterations": 100,
                            "gamma": 0.02, "lambda": lam_f}
+        # the Haar l1 prior (4 levels, threshold gamma = 0.02) with the same local FISTA
+        hparams = [make_params(r[:4], r[4], "haar", lam=lam_f, iters=its, inner_iters=4)
+                   for r in rois]
+        for _ in range(2):
+            ctx.roi_solve_local(g, D, hparams, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.roi_solve_local(g, D, hparams, outs)
+        torch.cuda.synchronize()
+        t_haar = (time.perf_counter() - t0) / reps
+        ctx.tomo_kernel_timing(1)
+        ctx.tomo_kernel_time(0, reset=True)
+        ctx.roi_solve_local(g, D, hparams, outs)
+        torch.cuda.synchronize()
+        ctx.tomo_kernel_timing(0)
+        n_h, ms_h = ctx.tomo_kernel_time(2)
+        haar_us = 1e3 * ms_h / max(1, n_h)
+        log(f"local FISTA-Haar: 64 ROIs x {its} its {1e3 * t_haar:.1f} ms per batch; "
+            f"Haar prox {haar_us:.1f} us per outer iteration")
+        res["fista_haar"] = {"roi_solves_per_s": len(rois) / t_haar, "ms_per_batch": 1e3 * t_haar,
+                             "prox_us_per_outer_iteration": haar_us, "levels": 4,
+                             "gamma": 0.02, "lambda": lam_f}
         if compare:
             xe = torch.empty((cfg["n"], cfg["n"]), dtype=torch.float32, device="cuda")
             ctx.tomo_fbp_ramlak(g, sino, xe)

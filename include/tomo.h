@@ -133,9 +133,12 @@ typedef enum {
     ROI_LOCAL_SIRT = 2,     /* the paper's local method (Section 3.2, eq. localmethod, Alg. 2)
                                for SIRT with the box prior of eq. sirtbox ([0, inf) unless
                                ROI_FLAG_BOX); only through roi_solve_local */
-    ROI_LOCAL_FISTA_TV = 3  /* the paper's local FISTA for lambda TV (Alg. 3) with an FGP
+    ROI_LOCAL_FISTA_TV = 3, /* the paper's local FISTA for lambda TV (Alg. 3) with an FGP
                                inner solver of inner_iters iterations (box: none unless
                                ROI_FLAG_BOX); only through roi_solve_local */
+    ROI_LOCAL_FISTA_HAAR = 4 /* the same local FISTA for lambda ||B x||_1, B the orthonormal
+                               Haar transform with inner_iters levels (eq. sirtista);
+                               no box; only through roi_solve_local */
 } roi_method;
 
 enum {
@@ -150,9 +153,10 @@ enum {
  * 0 for sigma = tau = 1/sqrt(1.01 * lambda_max(W_L^T W_L - Laplacian))
  * from a cached power iteration (per geometry and extended shape); box_lo,
  * box_hi: the box of SIRT-type methods when flags has ROI_FLAG_BOX (box_lo may
- * be -inf, box_hi +inf; box_lo <= box_hi; not accepted for CP); inner_iters: FGP
- * iterations per outer iteration of ROI_LOCAL_FISTA_TV (0 = 100, the paper's
- * count; ignored by the other methods). */
+ * be -inf, box_hi +inf; box_lo <= box_hi; not accepted for CP and the Haar prior);
+ * inner_iters: FGP iterations per outer iteration of ROI_LOCAL_FISTA_TV (0 = 100, the
+ * paper's count), Haar levels of ROI_LOCAL_FISTA_HAAR (0 = 4, at most 6); ignored by
+ * the other methods. */
 typedef struct {
     tomo_rect roi;
     int32_t margin;
@@ -217,11 +221,15 @@ tomo_status tomo_sirt_filter_sino(tomo_ctx* ctx, int32_t geom, const float* filt
  *     v <- x^k + ((t^{k-1} - 1) / t^k)(x^k - x^{k-1}) - W_L^T d_k,   t^0 = 1, x^0 = 0,
  *     FGP being inner_iters iterations of min_P ||x - w||^2 + 2 gamma TV(x) from a zero
  *     dual, gamma = alpha lambda / 2 (alpha lambda with ROI_FLAG_HALF_DATA),
- *     isotropic TV unless ROI_FLAG_ANISO_TV.
+ *     isotropic TV unless ROI_FLAG_ANISO_TV;
+ *   ROI_LOCAL_FISTA_HAAR: the same iteration with x^k = B^T soft(B w, gamma), B the
+ *     orthonormal Haar transform with inner_iters levels on the extended part (pairs
+ *     (a, b) -> ((a + b)/sqrt 2, (a - b)/sqrt 2) along rows then columns of the block
+ *     of sums, an unpaired last entry carried as a sum), every coefficient thresholded.
  * The crop of x is written to outs[i] (float[roi.rows][roi.cols], device).
  * filtered: device float[planes][n_angles][n_det]; params and outs are host arrays of
- * count entries; every params[i].method is ROI_LOCAL_SIRT or ROI_LOCAL_FISTA_TV with
- * iters <= planes (sigma, tau are ignored).  Stream-ordered.
+ * count entries; every params[i].method is ROI_LOCAL_SIRT, ROI_LOCAL_FISTA_TV or
+ * ROI_LOCAL_FISTA_HAAR with iters <= planes (sigma, tau are ignored).  Stream-ordered.
  * Errors: EINVAL, ENOENT, ENOMEM, EHIP. */
 tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, int32_t planes,
                             int32_t count, const roi_params* params, float* const* outs,

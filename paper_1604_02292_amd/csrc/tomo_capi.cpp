@@ -101,14 +101,17 @@ tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p) {
     if (p.margin < 0) return fail(ctx, TOMO_EINVAL, "margin < 0");
     if (p.iters <= 0) return fail(ctx, TOMO_EINVAL, "iters must be > 0");
     if (!(p.lambda >= 0.f) || !std::isfinite(p.lambda)) return fail(ctx, TOMO_EINVAL, "lambda must be >= 0");
-    if (p.method < ROI_TV_NONNEG_CP || p.method > ROI_LOCAL_FISTA_TV)
+    if (p.method < ROI_TV_NONNEG_CP || p.method > ROI_LOCAL_FISTA_HAAR)
         return fail(ctx, TOMO_EINVAL, "unknown method %d", p.method);
     if (p.inner_iters < 0) return fail(ctx, TOMO_EINVAL, "inner_iters must be >= 0");
+    if (p.method == ROI_LOCAL_FISTA_HAAR && p.inner_iters > kHaarMaxLevels)
+        return fail(ctx, TOMO_EINVAL, "at most %d Haar levels", kHaarMaxLevels);
     if (!(p.sigma >= 0.f) || !(p.tau >= 0.f)) return fail(ctx, TOMO_EINVAL, "negative step size");
     if (p.flags & ~7u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
     if (p.flags & ROI_FLAG_BOX) {
-        if (p.method == ROI_TV_NONNEG_CP)
-            return fail(ctx, TOMO_EINVAL, "ROI_FLAG_BOX applies to the SIRT-type methods only");
+        if (p.method == ROI_TV_NONNEG_CP || p.method == ROI_LOCAL_FISTA_HAAR)
+            return fail(ctx, TOMO_EINVAL,
+                        "ROI_FLAG_BOX applies to the SIRT-type methods and FISTA-TV only");
         if (!(p.box_lo <= p.box_hi)) return fail(ctx, TOMO_EINVAL, "box needs box_lo <= box_hi");
     }
     return TOMO_OK;
@@ -137,7 +140,7 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
     J.alpha = (float)(1.0 / ((double)g.na * (double)g.nd));
     J.scale = 1.f;
     const bool box = (st.prm.flags & ROI_FLAG_BOX) != 0;
-    const bool fista = st.prm.method == ROI_LOCAL_FISTA_TV;
+    const bool fista = st.prm.method == ROI_LOCAL_FISTA_TV || st.prm.method == ROI_LOCAL_FISTA_HAAR;
     J.lo = box ? st.prm.box_lo : (fista ? -INFINITY : 0.f);
     J.hi = box ? st.prm.box_hi : INFINITY;
     // prox weight of TV in the FISTA step: the SIRT step is a gradient step of alpha/2
@@ -145,6 +148,7 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
     J.gamma = (float)((half ? 1.0 : 0.5) * (double)st.prm.lambda /
                       ((double)g.na * (double)g.nd));
     J.n_fgp = st.prm.inner_iters > 0 ? st.prm.inner_iters : 100;
+    J.levels = st.prm.inner_iters > 0 ? st.prm.inner_iters : 4;
     J.afp = st.d_afp;
     J.abp = st.d_abp;
     J.x = st.x;

@@ -109,8 +109,9 @@ struct Job {
     float* fr;               // FGP dual momentum point r [2][nr][nc]
     const float* beta_in;    // FGP momentum per inner iteration
     const float* beta_out;   // FISTA momentum per outer iteration
-    float gamma;             // prox weight of TV
+    float gamma;             // prox weight of TV / threshold of the Haar coefficients
     int32_t n_fgp;           // FGP iterations per outer iteration
+    int32_t levels;          // Haar levels (local FISTA with the Haar l1 prior)
 };
 
 // One block's work.  `tab` points at the block's table (FP: the AngFP entry of
@@ -146,6 +147,12 @@ hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, 
 constexpr int kFgpTile = 32, kFgpSteps = 8;
 hipError_t launch_fgp(const Job* jobs, const Item* items, int n_items, int step, int i0,
                       hipStream_t s);
+// Haar l1 prox of local FISTA: per aligned 2^levels tile of the job (items: job, tile
+// row, tile column), forward transform, soft threshold gamma, inverse, then the FISTA
+// momentum point and the new correction v (as the last FGP launch).  levels 1..6.
+constexpr int kHaarMaxLevels = 6;
+hipError_t launch_haar(const Job* jobs, const Item* items, int n_items, int step, int levels,
+                       hipStream_t s);
 // Disc of diameter n about the grid centre (exact integer test): add = 0 writes its
 // indicator into the region (r0, c0, rows, cols) of img (pitch ld); add = 1 adds *value
 // on its pixels.

@@ -1400,6 +1400,120 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Haar l1 prior (eq. sirtista with FISTA): the prox of gamma ||B x||_1 is
+// B^T soft(B w, gamma) for the orthonormal Haar transform B.  With L levels, B acts
+// independently on the region's aligned 2^L x 2^L tiles (a level-j pair always lies in
+// one aligned 2^j block), so one block transforms one tile in LDS: per level, rows
+// then columns of the current block of sums, (a, b) -> ((a + b)/sqrt 2, (a - b)/sqrt 2)
+// with the sums first, an unpaired last entry passed on as the last sum; threshold;
+// inverse; then the FISTA momentum point and the new correction v.
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(256) void haar_kernel(const Job* __restrict__ jobs,
+                                                   const Item* __restrict__ items, int n_items,
+                                                   int step) {
+    constexpr int T = 1 << L, P = T + 1;
+    __shared__ float A[T * P], Bf[T * P];
+    const int bid = blockIdx.x;
+    if (bid >= n_items) return;
+    const Item it = cview(items)[bid];
+    const CONST_AS Job* J = cview(jobs) + it.job;
+    const int nr = J->nr, nc = J->nc;
+    const int R0 = it.a * T, C0 = it.b * T;
+    const int th = min(T, nr - R0), tw = min(T, nc - C0);
+    const int t = threadIdx.x;
+    const float s2 = 0.70710678118654752f;
+    for (int q = t; q < T * T; q += 256) {
+        const int lr = q / T, lc = q % T;
+        A[lr * P + lc] = (lr < th && lc < tw) ? J->w[(size_t)(R0 + lr) * nc + C0 + lc] : 0.f;
+    }
+    __syncthreads();
+    int hs[L], ws[L];
+    {
+        int h = th, w = tw;
+        for (int l = 0; l < L; ++l) {
+            hs[l] = h;
+            ws[l] = w;
+            h = (h + 1) / 2;
+            w = (w + 1) / 2;
+        }
+    }
+    // forward
+    for (int l = 0; l < L; ++l) {
+        const int h = hs[l], w = ws[l];
+        const int mw = w / 2, aw = w - mw, mh = h / 2, ah = h - mh;
+        for (int q = t; q < h * w; q += 256) {   // rows: A -> Bf
+            const int r = q / w, j = q % w;
+            float v;
+            if (j < mw) v = (A[r * P + 2 * j] + A[r * P + 2 * j + 1]) * s2;
+            else if (j < aw) v = A[r * P + w - 1];
+            else v = (A[r * P + 2 * (j - aw)] - A[r * P + 2 * (j - aw) + 1]) * s2;
+            Bf[r * P + j] = v;
+        }
+        __syncthreads();
+        for (int q = t; q < h * w; q += 256) {   // columns: Bf -> A
+            const int i = q / w, c = q % w;
+            float v;
+            if (i < mh) v = (Bf[2 * i * P + c] + Bf[(2 * i + 1) * P + c]) * s2;
+            else if (i < ah) v = Bf[(h - 1) * P + c];
+            else v = (Bf[2 * (i - ah) * P + c] - Bf[(2 * (i - ah) + 1) * P + c]) * s2;
+            A[i * P + c] = v;
+        }
+        __syncthreads();
+    }
+    const float gam = J->gamma;
+    for (int q = t; q < th * tw; q += 256) {
+        const int r = q / tw, c = q % tw;
+        const float v = A[r * P + c];
+        A[r * P + c] = copysignf(fmaxf(fabsf(v) - gam, 0.f), v);
+    }
+    __syncthreads();
+    // inverse
+    for (int l = L - 1; l >= 0; --l) {
+        const int h = hs[l], w = ws[l];
+        const int mw = w / 2, aw = w - mw, mh = h / 2, ah = h - mh;
+        for (int q = t; q < h * w; q += 256) {   // columns: A -> Bf
+            const int r = q / w, c = q % w;
+            float v;
+            if (r < 2 * mh) {
+                const float a = A[(r >> 1) * P + c], d = A[(ah + (r >> 1)) * P + c];
+                v = (r & 1) ? (a - d) * s2 : (a + d) * s2;
+            } else {
+                v = A[mh * P + c];
+            }
+            Bf[r * P + c] = v;
+        }
+        __syncthreads();
+        for (int q = t; q < h * w; q += 256) {   // rows: Bf -> A
+            const int r = q / w, c = q % w;
+            float v;
+            if (c < 2 * mw) {
+                const float a = Bf[r * P + (c >> 1)], d = Bf[r * P + aw + (c >> 1)];
+                v = (c & 1) ? (a - d) * s2 : (a + d) * s2;
+            } else {
+                v = Bf[r * P + mw];
+            }
+            A[r * P + c] = v;
+        }
+        __syncthreads();
+    }
+    const int wpar = ((step + J->parity0) & 1) ^ 1;
+    for (int q = t; q < th * tw; q += 256) {
+        const int lr = q / tw, lc = q % tw;
+        const int rr = R0 + lr, cc = C0 + lc;
+        const float x = A[lr * P + lc];
+        const size_t pi = (size_t)rr * nc + cc;
+        const size_t xi = (size_t)rr * J->ldx + cc;
+        const float xo = J->x[xi];
+        const float z = x + J->beta_out[step] * (x - xo);
+        const float v = z - J->xs[pi];
+        J->x[xi] = x;
+        J->xb[wpar][(size_t)rr * J->xp + cc + kLpad] = v;
+        J->xt[(size_t)cc * J->tp + rr + kLpad] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Detector convolutions by FFT: C_u p for a whole bank of angle-dependent
 // filters u_k (Section 3.1, eq. sirtapp; Section 3.3: the convolved data are
 // computed once and shared by every local part).  A linear convolution of two
@@ -1745,6 +1859,22 @@ hipError_t launch_pad_truncated(const float* trunc, int na, int nb, int first, i
     if (na <= 0 || nd <= 0) return hipSuccess;
     hipLaunchKernelGGL(pad_truncated_kernel, dim3((nd + 255) / 256, na), dim3(256), 0, s, trunc,
                        nb, first, nd, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_haar(const Job* jobs, const Item* items, int n_items, int step, int levels,
+                       hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    switch (levels) {
+#define X(LV)                                                                                  \
+    case LV:                                                                                   \
+        hipLaunchKernelGGL(haar_kernel<LV>, dim3(n_items), dim3(256), 0, s, jobs, items,       \
+                           n_items, step);                                                     \
+        break;
+        X(1) X(2) X(3) X(4) X(5) X(6)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -239,9 +239,8 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
     int max_nf = 0, max_iters = 0;
     for (int i = 0; i < count; ++i) {
         if ((st = validate_params(ctx, g, params[i])) != TOMO_OK) return st;
-        if (params[i].method != ROI_LOCAL_SIRT && params[i].method != ROI_LOCAL_FISTA_TV)
-            return fail(ctx, TOMO_EINVAL,
-                        "roi_solve_local takes ROI_LOCAL_SIRT and ROI_LOCAL_FISTA_TV requests");
+        if (params[i].method < ROI_LOCAL_SIRT)
+            return fail(ctx, TOMO_EINVAL, "roi_solve_local takes the local methods only");
         if (params[i].iters > planes)
             return fail(ctx, TOMO_EINVAL, "ROI %d needs %d filtered planes, %d given", i,
                         params[i].iters, planes);
@@ -254,7 +253,8 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
         rays += (long long)g.na * r.plan.wmax;
         pix += (long long)r.ext.rows * r.ext.cols;
         const bool fista = params[i].method == ROI_LOCAL_FISTA_TV;
-        sfl[i] = local_state_floats(g, r.plan, true, fista);
+        const bool haar = params[i].method == ROI_LOCAL_FISTA_HAAR;
+        sfl[i] = local_state_floats(g, r.plan, true, fista || haar);
         state_total += sfl[i] * sizeof(float);
         if (fista)
             max_nf = std::max(max_nf, params[i].inner_iters > 0 ? params[i].inner_iters : 100);
@@ -284,7 +284,7 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
     {
         float* f = state;
         for (int i = 0; i < count; ++i) {
-            B[i] = carve_local(g, R[i].plan, true, f, R[i].prm.method == ROI_LOCAL_FISTA_TV);
+            B[i] = carve_local(g, R[i].plan, true, f, R[i].prm.method >= ROI_LOCAL_FISTA_TV);
             f += sfl[i];
             RoiState& r = R[i];
             r.d_afp = (AngFP*)(dm + o_afp[i]);
@@ -307,11 +307,18 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
     std::vector<Job> jobs(count);
     std::vector<Item> fi, bi, gi;
     std::vector<int> fi_end(count), bi_end(count), gi_end(count), nf_of(count, 0);
+    // Haar prox items, one list per level count
+    std::vector<Item> hi[kHaarMaxLevels + 1];
+    std::vector<int> hi_end[kHaarMaxLevels + 1];
+    for (auto& v : hi_end) v.assign(count, 0);
+    std::vector<int> lv_of(count, 0);
     for (int q = 0; q < count; ++q) {
         RoiState& r = R[order[q]];
         const LocalBuf& lb = B[order[q]];
         const bool fista = r.prm.method == ROI_LOCAL_FISTA_TV;
-        Job J = make_job(g, r, FP_LOCAL, fista ? BP_FISTA : BP_LOCAL, (r.ext.cols + tw - 1) / tw);
+        const bool haar = r.prm.method == ROI_LOCAL_FISTA_HAAR;
+        Job J = make_job(g, r, FP_LOCAL, (fista || haar) ? BP_FISTA : BP_LOCAL,
+                         (r.ext.cols + tw - 1) / tw);
         J.gbase = filtered;
         J.gstride = (int64_t)g.na * g.nd;
         J.dk0 = 0;
@@ -333,15 +340,25 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
                 for (int b = 0; b < (r.ext.cols + kFgpTile - 1) / kFgpTile; ++b)
                     gi.push_back(Item{q, a, b, 0, nullptr, 0});
         }
+        if (haar) {
+            const int L = J.levels, T = 1 << L;
+            lv_of[q] = L;
+            for (int a = 0; a < (r.ext.rows + T - 1) / T; ++a)
+                for (int b = 0; b < (r.ext.cols + T - 1) / T; ++b)
+                    hi[L].push_back(Item{q, a, b, 0, nullptr, 0});
+        }
         fi_end[q] = (int)fi.size();
         bi_end[q] = (int)bi.size();
         gi_end[q] = (int)gi.size();
+        for (int L = 1; L <= kHaarMaxLevels; ++L) hi_end[L][q] = (int)hi[L].size();
     }
     Meta m2;
     const size_t o_jobs = m2.add(jobs.data(), jobs.size() * sizeof(Job));
     const size_t o_fi = m2.add(fi.data(), fi.size() * sizeof(Item));
     const size_t o_bi = m2.add(bi.data(), bi.size() * sizeof(Item));
     const size_t o_gi = m2.add(gi.data(), gi.size() * sizeof(Item));
+    size_t o_hi[kHaarMaxLevels + 1];
+    for (int L = 1; L <= kHaarMaxLevels; ++L) o_hi[L] = m2.add(hi[L].data(), hi[L].size() * sizeof(Item));
     const int max_it = R[order[0]].prm.iters;
     const bool timed = ctx->timing_mode == 1;
     auto enqueue_loop = [&](char* base, hipStream_t sq) -> hipError_t {
@@ -353,8 +370,11 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
         for (int it = 0; it < max_it; ++it) {
             while (active > 0 && R[order[active - 1]].prm.iters <= it) --active;
             int nf = -1;   // FGP iterations of the running FISTA jobs (-1: none)
-            for (int q = 0; q < active; ++q)
+            bool any_haar = false;
+            for (int q = 0; q < active; ++q) {
                 if (R[order[q]].prm.method == ROI_LOCAL_FISTA_TV) nf = std::max(nf, nf_of[q]);
+                if (R[order[q]].prm.method == ROI_LOCAL_FISTA_HAAR) any_haar = true;
+            }
             hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
             hipError_t e;
             if (timed) {
@@ -381,6 +401,15 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
                     if ((e = launch_fgp(d_jobs, d_gi, gi_end[active - 1], it, l * kFgpSteps, sq)) !=
                         hipSuccess)
                         return e;
+            }
+            if (any_haar) {   // one tiled Haar prox launch per level count in use
+                for (int L = 1; L <= kHaarMaxLevels; ++L)
+                    if (hi_end[L][active - 1] > 0 &&
+                        (e = launch_haar(d_jobs, (const Item*)(base + o_hi[L]),
+                                         hi_end[L][active - 1], it, L, sq)) != hipSuccess)
+                        return e;
+            }
+            if (nf >= 0 || any_haar) {
                 if (timed) {
                     e3 = timing_event(ctx);
                     if ((e = hipEventRecord(e3, sq)) != hipSuccess) return e;
@@ -409,6 +438,7 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
             key.push_back(bi_end[q]);
             key.push_back(gi_end[q]);
             key.push_back(nf_of[q]);
+            key.push_back(lv_of[q]);
             key.push_back(R[order[q]].prm.method);
         }
         tomo_status rs = run_loop(ctx, key, m2, enqueue_loop, s, allocs);

@@ -9,7 +9,7 @@ import ctypes as C
 
 from . import _lib
 from ._lib import (tomo_rect, roi_params, tomo_launch, ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT,
-                   ROI_LOCAL_SIRT, ROI_LOCAL_FISTA_TV, ROI_FLAG_BOX)
+                   ROI_LOCAL_SIRT, ROI_LOCAL_FISTA_TV, ROI_LOCAL_FISTA_HAAR, ROI_FLAG_BOX)
 
 
 class TomoError(RuntimeError):
@@ -49,11 +49,11 @@ def _stream(stream):
 
 def make_params(roi, margin, method="cp", lam=0.0, iters=100, sigma=0.0, tau=0.0, flags=0,
                 box=None, inner_iters=0):
-    """roi_params; method "cp", "sirt", "local" or "fista" (or the enum value);
+    """roi_params; method "cp", "sirt", "local", "fista" or "haar" (or the enum value);
     box=(lo, hi) sets ROI_FLAG_BOX with those bounds; inner_iters: FGP iterations of
-    "fista" (0: the library's default)."""
+    "fista", Haar levels of "haar" (0: the library's default)."""
     m = {"cp": ROI_TV_NONNEG_CP, "sirt": ROI_NONNEG_SIRT, "local": ROI_LOCAL_SIRT,
-         "fista": ROI_LOCAL_FISTA_TV}.get(method, method)
+         "fista": ROI_LOCAL_FISTA_TV, "haar": ROI_LOCAL_FISTA_HAAR}.get(method, method)
     lo, hi = 0.0, float("inf")
     if box is not None:
         lo, hi = float(box[0]), float(box[1])

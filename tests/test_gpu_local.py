@@ -18,6 +18,7 @@ import synth
 import oracle
 from oracle.filters import sirt_filters, filter_apply, local_method_box
 from oracle.fista import local_fista_tv
+from oracle.haar import local_fista_haar
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -220,6 +221,68 @@ def test_local_fista_tv_matches_oracle(ctx, c1, variant):
     # the TV prior acts: the first request differs from unregularised Alg. 2
     plain = _local_oracle(geo, p32, [(48, 48, 32, 32, 16, 30, (-np.inf, np.inf))], U)[0]
     assert rel(ref[0], plain) > 1e-2
+
+
+# (r0, c0, rows, cols, margin, iters, lam, levels, flags): extended parts of one full
+# 64^2 tile (6 levels), ragged 36 x 54, 17 x 9 and 40 x 15 parts, the default level
+# count (0 = 4); regions inside the object, where the thresholds leave a nonzero result
+HAAR_C1 = [
+    (48, 48, 32, 32, 16, 30, 300.0, 6, 0),
+    (40, 70, 20, 38, 8, 25, 150.0, 3, 1),
+    (70, 45, 9, 1, 4, 30, 60.0, 0, 0),
+    (60, 60, 28, 3, 6, 12, 100.0, 1, 0),
+]
+
+
+def test_local_fista_haar_matches_oracle(ctx, c1):
+    from paper_1604_02292_amd import make_params
+    cfg = c1["cfg"]
+    p32 = c1["sino"].astype(np.float32).astype(np.float64)
+    geo = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    K = max(r[5] for r in HAAR_C1)
+    U = sirt_filters(geo, K, workers=4)
+    ref = [local_fista_haar(geo, p32, (r0, c0, rr, cc), m, U[:it], lam, lv or 4, half=bool(fl & 1))
+           for (r0, c0, rr, cc, m, it, lam, lv, fl) in HAAR_C1]
+    # a TV request in the same batch
+    tv = FISTA_C1[0]
+    ref_tv = local_fista_tv(geo, p32, tv[:4], tv[4], U[:tv[5]], tv[6], 100)
+    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    F = torch.empty((K, cfg["n_angles"], cfg["n_det"]), dtype=torch.float32, device="cuda")
+    ctx.tomo_sirt_filters(g, K, F)
+    D = torch.empty_like(F)
+    ctx.tomo_sirt_filter_sino(g, F, _gpu(p32), D)
+    params, outs = [], []
+    for (r0, c0, rr, cc, m, it, lam, lv, fl) in HAAR_C1:
+        params.append(make_params((r0, c0, rr, cc), m, "haar", lam=lam, iters=it, flags=fl,
+                                  inner_iters=lv))
+        outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
+    params.append(make_params(tv[:4], tv[4], "fista", lam=tv[6], iters=tv[5]))
+    outs.append(torch.empty((tv[2], tv[3]), dtype=torch.float32, device="cuda"))
+    print(f"[haar] batch of {len(params)} requests", flush=True)
+    ctx.roi_solve_local(g, D, params, outs)
+    torch.cuda.synchronize()
+    for roi, o, b in zip(HAAR_C1 + [None], outs, ref + [ref_tv]):
+        a = o.double().cpu().numpy()
+        assert np.linalg.norm(b) > 0
+        e = rel(a, b)
+        print(f"    {roi if roi else 'fista-tv'} rel {e:.2e}", flush=True)
+        assert e <= 1e-3
+    # the threshold acts: the first request differs from unregularised Alg. 2
+    plain = _local_oracle(geo, p32, [(48, 48, 32, 32, 16, 30, (-np.inf, np.inf))], U)[0]
+    assert rel(ref[0], plain) > 1e-2
+
+
+def test_local_haar_errors(ctx):
+    from paper_1604_02292_amd import make_params, TomoError
+    g = ctx.tomo_set_geometry(64, 8, 96)
+    D = torch.zeros((5, 8, 96), dtype=torch.float32, device="cuda")
+    out = torch.empty((8, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(TomoError, match="EINVAL"):   # too many levels
+        ctx.roi_solve_local(g, D, [make_params((0, 0, 8, 8), 2, "haar", iters=5, inner_iters=7)],
+                            [out])
+    with pytest.raises(TomoError, match="EINVAL"):   # no box with the Haar prior
+        ctx.roi_solve_local(g, D, [make_params((0, 0, 8, 8), 2, "haar", iters=5,
+                                               box=(0.0, 1.0))], [out])
 
 
 def test_local_fista_timing_kind(ctx, c1):
