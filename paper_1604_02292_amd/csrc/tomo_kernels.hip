@@ -1312,13 +1312,17 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
         const bool aniso = (J->flags & JF_ANISO) != 0;
 #pragma unroll 1
         for (int i = i0; i < i1; ++i) {
+            // Values stay exact on rows / columns [s, RW - 1 - s] after the s-th step of
+            // this launch; rows outside [s - 1, RW - s] are not needed by any later step.
+            const int s = i - i0 + 1, wlo = s - 1, whi = RW - s;
             // x = P(b - gamma div r); div r = r0 - r0(up) + r1 - r1(left), zero outside
             float xr[NQ];
 #pragma unroll
             for (int u = 0; u < NQ; ++u) {
                 const int q = t + kFgpThreads * u;
                 xr[u] = 0.f;
-                if (q < RN) {
+                const int lr = q / RW;
+                if (q < RN && lr >= wlo && lr <= whi) {
                     const float up = (fl[u] & UP) ? sr0[q - RW] : 0.f;
                     const float left = (fl[u] & LEFT) ? sr1[q - 1] : 0.f;
                     const float d = (r0[u] - up) + (r1[u] - left);
@@ -1331,7 +1335,8 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
 #pragma unroll
             for (int u = 0; u < NQ; ++u) {
                 const int q = t + kFgpThreads * u;
-                if (q >= RN) continue;
+                const int lr = q / RW;
+                if (q >= RN || lr < wlo || lr > whi) continue;
                 float n0 = 0.f, n1 = 0.f;
                 if (fl[u] & IN) {
                     const float g0 = (fl[u] & G0) && (fl[u] & DOWN) ? sx[q + RW] - xr[u] : 0.f;
@@ -1531,9 +1536,31 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 
-// Forward DFT (exp(-2 pi i f n / L)) of z[0..L) in place.  tw[m] = exp(-2 pi i m / L).
+// Twiddles from two small LDS tables: exp(-2 pi i m / L) = t1[m / kTw2] t2[m % kTw2]
+// (kTw2 = min(64, L) entries of fine angles, L / kTw2 of coarse ones), loaded from the
+// full FP32 table tw[m] = exp(-2 pi i m / L) at the block's start.
 template <int LOG>
-__device__ void fft_lds(float2* z, const float2* __restrict__ tw) {
+struct FftTw {
+    static constexpr int L = 1 << LOG;
+    static constexpr int N2 = L < 64 ? L : 64, N1 = L / N2;
+    float2 t1[N1], t2[N2];
+    __device__ void load(const float2* __restrict__ tw) {
+        for (int i = threadIdx.x; i < N1; i += blockDim.x) t1[i] = tw[i * N2];
+        for (int i = threadIdx.x; i < N2; i += blockDim.x) t2[i] = tw[i];
+    }
+    __device__ float2 operator()(int m) const;
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b);
+
+template <int LOG>
+__device__ float2 FftTw<LOG>::operator()(int m) const {
+    return cmul(t1[m / N2], t2[m % N2]);
+}
+
+// Forward DFT (exp(-2 pi i f n / L)) of z[0..L) in place, twiddles from `tw`.
+template <int LOG>
+__device__ void fft_lds(float2* z, const FftTw<LOG>& tw) {
     constexpr int L = 1 << LOG, T = kFftThreads;
     const int t = threadIdx.x;
     int ns = 1;   // length of the sub-transforms already done
@@ -1561,6 +1588,7 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw) {
         ns = 2;
     }
     constexpr int NB = (L / 4 + T - 1) / T;
+#pragma unroll 1
     for (; ns < L; ns <<= 2) {
         float2 v[NB][4];
 #pragma unroll
@@ -1570,9 +1598,9 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw) {
                 const int k = j & (ns - 1);
                 const int m = (L / (4 * ns)) * k;   // twiddle of input r: r m < L
                 v[i][0] = z[j];
-                v[i][1] = cmul(z[j + L / 4], tw[m]);
-                v[i][2] = cmul(z[j + L / 2], tw[2 * m]);
-                v[i][3] = cmul(z[j + 3 * (L / 4)], tw[3 * m]);
+                v[i][1] = cmul(z[j + L / 4], tw(m));
+                v[i][2] = cmul(z[j + L / 2], tw(2 * m));
+                v[i][3] = cmul(z[j + 3 * (L / 4)], tw(3 * m));
             }
         }
         __syncthreads();
@@ -1599,18 +1627,20 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw) {
 
 // spec[a][0..L) = FFT of sinogram row a, zero-padded to L.
 template <int LOG>
-__global__ __launch_bounds__(kFftThreads) void spectra_kernel(const float* __restrict__ sino,
+__global__ __launch_bounds__(kFftThreads, 4) void spectra_kernel(const float* __restrict__ sino,
                                                               int n_det,
                                                               const float2* __restrict__ tw,
                                                               float2* __restrict__ spec) {
     constexpr int L = 1 << LOG;
     __shared__ float2 z[L];
+    __shared__ FftTw<LOG> twl;
+    twl.load(tw);
     const int a = blockIdx.x;
     const float* row = sino + (size_t)a * n_det;
     for (int i = threadIdx.x; i < L; i += kFftThreads)
         z[i] = make_float2(i < n_det ? row[i] : 0.f, 0.f);
     __syncthreads();
-    fft_lds<LOG>(z, tw);
+    fft_lds<LOG>(z, twl);
     float2* o = spec + (size_t)a * L;
     for (int i = threadIdx.x; i < L; i += kFftThreads) o[i] = z[i];
 }
@@ -1620,12 +1650,14 @@ __global__ __launch_bounds__(kFftThreads) void spectra_kernel(const float* __res
 // zero where i + ctr[a] falls outside the 2 n_det - 1 samples of the linear
 // convolution.
 template <int LOG>
-__global__ __launch_bounds__(kFftThreads) void filter_conv_kernel(
+__global__ __launch_bounds__(kFftThreads, 4) void filter_conv_kernel(
     const float* __restrict__ filt, int n_filt, int n_angles, int n_det,
     const int* __restrict__ ctr, const float2* __restrict__ tw, const float2* __restrict__ spec,
     float* __restrict__ out) {
     constexpr int L = 1 << LOG;
     __shared__ float2 z[L];
+    __shared__ FftTw<LOG> twl;
+    twl.load(tw);
     const int npairs = (n_filt + 1) / 2;
     const int a = blockIdx.x / npairs, h = blockIdx.x % npairs;
     const int k0 = 2 * h;
@@ -1638,7 +1670,7 @@ __global__ __launch_bounds__(kFftThreads) void filter_conv_kernel(
         z[i] = v;
     }
     __syncthreads();
-    fft_lds<LOG>(z, tw);
+    fft_lds<LOG>(z, twl);
     // times the data spectrum; the inverse transform is conj(FFT(conj(.))) / L
     const float2* sp = spec + (size_t)a * L;
     for (int i = threadIdx.x; i < L; i += kFftThreads) {
@@ -1646,7 +1678,7 @@ __global__ __launch_bounds__(kFftThreads) void filter_conv_kernel(
         z[i] = make_float2(w.x, -w.y);
     }
     __syncthreads();
-    fft_lds<LOG>(z, tw);
+    fft_lds<LOG>(z, twl);
     const float inv = 1.f / (float)L;
     const int c = ctr[a];
     float* o0 = out + (size_t)k0 * plane + (size_t)a * n_det;
