@@ -870,6 +870,10 @@ long long count_nnz(const Geom& g, const Rect& reg) {
 // C ABI
 // ===========================================================================
 
+tomo::ArenaRelease::~ArenaRelease() {
+    if (!ptrs.empty()) ctx->arena.free_after(ptrs, s);
+}
+
 tomo_status tomo::need_gpu(tomo_ctx* ctx) {
     if (!ctx) return TOMO_EINVAL;
     if (ctx->host_only) return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
@@ -1084,7 +1088,7 @@ tomo_status tomo_fp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
     J.xt = xt;
     J.gout = sino;
     std::memcpy(m.buf.data() + o_job, &J, sizeof J);
-    std::vector<char*> allocs{dm};
+    ArenaRelease rel{ctx, s, {dm}};   // also on an early error return
     TOMO_HIP(ctx, ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s));
     TOMO_HIP(ctx, launch_fill(xb, nb + nt, 0.f, s));
     TOMO_HIP(ctx, launch_pad_copy(img, r.cols, 0, 0, r.rows, r.cols, xb, P.xp, xt, P.tp, nullptr,
@@ -1092,7 +1096,6 @@ tomo_status tomo_fp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
     if (!accumulate) TOMO_HIP(ctx, launch_fill(sino, (size_t)g.na * g.nd, 0.f, s));
     TOMO_HIP(ctx, launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
                             0, L.seg, s, L.cfp, L.rp));
-    ctx->arena.free_after(allocs, s);
     return TOMO_OK;
     GUARD_END(ctx)
 }
@@ -1140,12 +1143,11 @@ tomo_status tomo_bp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
     J.x = img;
     J.y = band;
     std::memcpy(m.buf.data() + o_job, &J, sizeof J);
-    std::vector<char*> allocs{dm};
+    ArenaRelease rel{ctx, s, {dm}};   // also on an early error return
     TOMO_HIP(ctx, ctx->staging.upload(dm, m.buf.data(), m.buf.size(), s));
     TOMO_HIP(ctx, launch_band_gather(sino, g.nd, J.afp, g.na, band, P.bpitch, s));
     TOMO_HIP(ctx, launch_bp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
                             0, L.ag, L.ppt, s, L.cbp, L.staged));
-    ctx->arena.free_after(allocs, s);
     return TOMO_OK;
     GUARD_END(ctx)
 }

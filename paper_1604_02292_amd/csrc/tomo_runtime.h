@@ -166,6 +166,15 @@ tomo_status fail(tomo_ctx* ctx, tomo_status st, const char* fmt, ...);
     }
 
 tomo_status need_gpu(tomo_ctx* ctx);   // GPU context with its device made current
+
+// Returns the listed workspace blocks to the arena after the work already queued
+// on `s` when the scope ends (also on an early error return).
+struct ArenaRelease {
+    tomo_ctx* ctx;
+    hipStream_t s;
+    std::vector<char*> ptrs;
+    ~ArenaRelease();
+};
 tomo_status get_geom(tomo_ctx* ctx, int32_t gid, const Geom** g);
 
 // ---- solve pipeline shared by roi_solve, roi_solve_batch and serving ----
