@@ -369,16 +369,23 @@ def _sino_in_subprocess(name, tmpdir):
     return np.load(path)
 
 
-def test_local_method_full_size_first_iterate(ctx, tmp_path_factory):
-    """The 64-ROI batch on the 2048^2 grid (256 angles, 3072 bins) in the launch shape
-    of the benchmark, one iteration: x^1 = P(W_L^T C_{u_1} p) with u_1 = alpha W e.
-    The oracle computes u_1 from the impulse's own column of W and x^1 on each
-    sampled ROI; the filter recursion's depth is covered at the smaller sizes."""
+@pytest.mark.parametrize("name,sampled", [("c3", (0, 17, 40, 63)), ("c4", (0, 7, 86, 169))])
+def test_local_methods_full_size_first_iterate(ctx, tmp_path_factory, name, sampled):
+    """The batched workloads at full size in the launch shape of the benchmark (64 uneven
+    ROIs on 2048^2, 256 angles, 3072 bins; 256 tiles on 4096^2, 512 angles, 6144 bins, the
+    16384-point FFT), one iteration of each local method: with u_1 = alpha W e and
+    d_1 = C_{u_1} p, x^1 = P(W_L^T d_1) (Alg. 2, a box that clips part of the values),
+    FGP(W_L^T d_1) (Alg. 3, TV) and
+    B^T soft(B W_L^T d_1) (Haar).  The oracle computes u_1 from the impulse's own column
+    of W and each method's first iterate on the sampled ROIs; the depth of the filter
+    recursion and of the iterations is covered at the smaller sizes."""
     from paper_1604_02292_amd import make_params
-    cfg = synth.workload("c3")
+    from oracle.fista import fgp, prox_weight
+    from oracle.haar import haar_prox
+    cfg = synth.workload(name)
     n, na, nd = cfg["n"], cfg["n_angles"], cfg["n_det"]
-    print("[local c3] generating inputs", flush=True)
-    p32 = _sino_in_subprocess("c3", tmp_path_factory.mktemp("c3l")).astype(np.float32)
+    print(f"[local {name}] generating inputs", flush=True)
+    p32 = _sino_in_subprocess(name, tmp_path_factory.mktemp(name + "l")).astype(np.float32)
     geo = oracle.make_geometry(n, na, nd)
     ci = n // 2
     u1 = (1.0 / (na * nd)) * oracle.fp_ray(geo, np.ones((1, 1)), (ci, ci, 1, 1))
@@ -396,17 +403,40 @@ def test_local_method_full_size_first_iterate(ctx, tmp_path_factory):
     e = rel(D[0].double().cpu().numpy(), d1)
     print(f"    C_u1 p rel {e:.2e}", flush=True)
     assert e <= 1e-5
-    rois = synth.roi_list("c3")
-    params, outs = [], []
-    for (r0, c0, rr, cc, m) in rois:
-        params.append(make_params((r0, c0, rr, cc), m, "local", iters=1, box=(0.0, 0.7)))
-        outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
-    ctx.roi_solve_local(g, _gpu(d1[None]), params, outs)
-    torch.cuda.synchronize()
-    for i in (0, 17, 40, 63):
+    del F, D
+    rois = synth.roi_list(name)
+    d1g = _gpu(d1[None])
+    lam = 2 * 0.02 * na * nd          # prox weight gamma = alpha lam / 2 = 0.02
+    gamma = prox_weight(geo, lam)
+    xs_of = {}
+    for i in sampled:
         r0, c0, rr, cc, m = rois[i]
-        xs = oracle.bp_pixel(geo, d1, (r0, c0, rr, cc))
-        ref = np.clip(xs, 0.0, 0.7)
-        e = rel(outs[i].double().cpu().numpy(), ref)
-        print(f"    roi {i} {rois[i]} rel {e:.2e}", flush=True)
-        assert e <= 1e-5
+        ext = oracle.roi_extend((r0, c0, rr, cc), m, n)
+        xs_of[i] = (ext, oracle.bp_pixel(geo, d1, ext))
+    # an upper bound that clips about half of the first sampled ROI's first iterate
+    top = float(np.median(xs_of[sampled[0]][1]))
+    for method in ("local", "fista", "haar"):
+        params, outs = [], []
+        for (r0, c0, rr, cc, m) in rois:
+            if method == "local":
+                params.append(make_params((r0, c0, rr, cc), m, "local", iters=1, box=(0.0, top)))
+            else:
+                params.append(make_params((r0, c0, rr, cc), m, method, lam=lam, iters=1,
+                                          inner_iters=100 if method == "fista" else 4))
+            outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
+        ctx.roi_solve_local(g, d1g, params, outs)
+        torch.cuda.synchronize()
+        for i in sampled:
+            r0, c0, rr, cc, m = rois[i]
+            ext, xs = xs_of[i]
+            if method == "local":
+                ref_ext, bar = np.clip(xs, 0.0, np.float32(top)), 1e-5
+            elif method == "fista":
+                ref_ext, bar = fgp(xs, gamma, 100), 1e-4
+            else:
+                ref_ext, bar = haar_prox(xs, gamma, 4), 1e-5
+            ref = oracle.crop(ref_ext, ext, (r0, c0, rr, cc))
+            e = rel(outs[i].double().cpu().numpy(), ref)
+            print(f"    {method} roi {i} {rois[i]} rel {e:.2e}", flush=True)
+            assert e <= bar
+        del outs
