@@ -325,6 +325,8 @@ def serving_leg(torch, slices, n_req=200, n_warm=64, fractions=(0.25, 0.5, 0.75,
                 t = ctx.roi_submit(sids[reqs[i]["slice"] % len(sids)], prm(reqs[i]), outs[i])
                 pend[t] = i
                 i += 1
+                if i % 500 == 0:
+                    log(f"serving: {i} of {len(reqs)} requests submitted")
             for t in list(pend):
                 done, ms = ctx.roi_poll(t)
                 if done:
@@ -411,6 +413,9 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-local", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests per serving load point (the survey's full run uses 2000)")
+    ap.add_argument("--serve-warmup", type=int, default=64)
     ap.add_argument("--only", choices=["batch", "serve", "local"], default=None,
                     help="run only one secondary leg (for profiling) and print its JSON")
     ap.add_argument("--iters", type=int, default=None,
@@ -461,7 +466,8 @@ def main():
                                      fixed_step=args.fixed_step)), flush=True)
         return
     if args.only == "serve":
-        print(json.dumps(serving_leg(torch, slices)), flush=True)
+        print(json.dumps(serving_leg(torch, slices, args.serve_requests, args.serve_warmup)),
+              flush=True)
         return
     if args.only == "local":
         print(json.dumps(local_leg(torch, d3, reps=args.steps, iters=args.iters, compare=False)),
@@ -562,7 +568,7 @@ def main():
             res["local_method"] = {"error": repr(e)}
     if not args.skip_serve:
         try:
-            res["serving"] = serving_leg(torch, slices)
+            res["serving"] = serving_leg(torch, slices, args.serve_requests, args.serve_warmup)
         except Exception as e:
             res["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
