@@ -1558,7 +1558,16 @@ __device__ float2 FftTw<LOG>::operator()(int m) const {
     return cmul(t1[m / N2], t2[m % N2]);
 }
 
-// Forward DFT (exp(-2 pi i f n / L)) of z[0..L) in place, twiddles from `tw`.
+// LDS index of transform entry i: one padding entry per 32 breaks the bank
+// conflicts of the strided writes of the first stages.
+__device__ __forceinline__ int fpad(int i) { return i + (i >> 5); }
+template <int L>
+struct FftLds {
+    static constexpr int N = L + L / 32;
+};
+
+// Forward DFT (exp(-2 pi i f n / L)) of z[0..L) in place (stored at fpad(i)), twiddles
+// from `tw`.
 template <int LOG>
 __device__ void fft_lds(float2* z, const FftTw<LOG>& tw) {
     constexpr int L = 1 << LOG, T = kFftThreads;
@@ -1571,8 +1580,8 @@ __device__ void fft_lds(float2* z, const FftTw<LOG>& tw) {
         for (int i = 0; i < NB; ++i) {
             const int j = t + i * T;
             if (j < L / 2) {
-                a[i] = z[j];
-                b[i] = z[j + L / 2];
+                a[i] = z[fpad(j)];
+                b[i] = z[fpad(j + L / 2)];
             }
         }
         __syncthreads();
@@ -1580,8 +1589,8 @@ __device__ void fft_lds(float2* z, const FftTw<LOG>& tw) {
         for (int i = 0; i < NB; ++i) {
             const int j = t + i * T;
             if (j < L / 2) {
-                z[2 * j] = make_float2(a[i].x + b[i].x, a[i].y + b[i].y);
-                z[2 * j + 1] = make_float2(a[i].x - b[i].x, a[i].y - b[i].y);
+                z[fpad(2 * j)] = make_float2(a[i].x + b[i].x, a[i].y + b[i].y);
+                z[fpad(2 * j + 1)] = make_float2(a[i].x - b[i].x, a[i].y - b[i].y);
             }
         }
         __syncthreads();
@@ -1597,10 +1606,10 @@ __device__ void fft_lds(float2* z, const FftTw<LOG>& tw) {
             if (j < L / 4) {
                 const int k = j & (ns - 1);
                 const int m = (L / (4 * ns)) * k;   // twiddle of input r: r m < L
-                v[i][0] = z[j];
-                v[i][1] = cmul(z[j + L / 4], tw(m));
-                v[i][2] = cmul(z[j + L / 2], tw(2 * m));
-                v[i][3] = cmul(z[j + 3 * (L / 4)], tw(3 * m));
+                v[i][0] = z[fpad(j)];
+                v[i][1] = cmul(z[fpad(j + L / 4)], tw(m));
+                v[i][2] = cmul(z[fpad(j + L / 2)], tw(2 * m));
+                v[i][3] = cmul(z[fpad(j + 3 * (L / 4))], tw(3 * m));
             }
         }
         __syncthreads();
@@ -1615,10 +1624,10 @@ __device__ void fft_lds(float2* z, const FftTw<LOG>& tw) {
                 // -i (v1 - v3)
                 const float2 a3 = make_float2(v[i][1].y - v[i][3].y, v[i][3].x - v[i][1].x);
                 const int base = ((j - k) << 2) + k;
-                z[base] = make_float2(a0.x + a2.x, a0.y + a2.y);
-                z[base + ns] = make_float2(a1.x + a3.x, a1.y + a3.y);
-                z[base + 2 * ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
-                z[base + 3 * ns] = make_float2(a1.x - a3.x, a1.y - a3.y);
+                z[fpad(base)] = make_float2(a0.x + a2.x, a0.y + a2.y);
+                z[fpad(base + ns)] = make_float2(a1.x + a3.x, a1.y + a3.y);
+                z[fpad(base + 2 * ns)] = make_float2(a0.x - a2.x, a0.y - a2.y);
+                z[fpad(base + 3 * ns)] = make_float2(a1.x - a3.x, a1.y - a3.y);
             }
         }
         __syncthreads();
@@ -1632,17 +1641,17 @@ __global__ __launch_bounds__(kFftThreads, 4) void spectra_kernel(const float* __
                                                               const float2* __restrict__ tw,
                                                               float2* __restrict__ spec) {
     constexpr int L = 1 << LOG;
-    __shared__ float2 z[L];
+    __shared__ float2 z[FftLds<L>::N];
     __shared__ FftTw<LOG> twl;
     twl.load(tw);
     const int a = blockIdx.x;
     const float* row = sino + (size_t)a * n_det;
     for (int i = threadIdx.x; i < L; i += kFftThreads)
-        z[i] = make_float2(i < n_det ? row[i] : 0.f, 0.f);
+        z[fpad(i)] = make_float2(i < n_det ? row[i] : 0.f, 0.f);
     __syncthreads();
     fft_lds<LOG>(z, twl);
     float2* o = spec + (size_t)a * L;
-    for (int i = threadIdx.x; i < L; i += kFftThreads) o[i] = z[i];
+    for (int i = threadIdx.x; i < L; i += kFftThreads) o[i] = z[fpad(i)];
 }
 
 // Block (a, h): rows a of filters 2h and 2h + 1 convolved with data row a.
@@ -1655,7 +1664,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void filter_conv_kernel(
     const int* __restrict__ ctr, const float2* __restrict__ tw, const float2* __restrict__ spec,
     float* __restrict__ out) {
     constexpr int L = 1 << LOG;
-    __shared__ float2 z[L];
+    __shared__ float2 z[FftLds<L>::N];
     __shared__ FftTw<LOG> twl;
     twl.load(tw);
     const int npairs = (n_filt + 1) / 2;
@@ -1667,15 +1676,15 @@ __global__ __launch_bounds__(kFftThreads, 4) void filter_conv_kernel(
     for (int i = threadIdx.x; i < L; i += kFftThreads) {
         float2 v = make_float2(0.f, 0.f);
         if (i < n_det) v = make_float2(f0[i], second ? f0[plane + i] : 0.f);
-        z[i] = v;
+        z[fpad(i)] = v;
     }
     __syncthreads();
     fft_lds<LOG>(z, twl);
     // times the data spectrum; the inverse transform is conj(FFT(conj(.))) / L
     const float2* sp = spec + (size_t)a * L;
     for (int i = threadIdx.x; i < L; i += kFftThreads) {
-        const float2 w = cmul(z[i], sp[i]);
-        z[i] = make_float2(w.x, -w.y);
+        const float2 w = cmul(z[fpad(i)], sp[i]);
+        z[fpad(i)] = make_float2(w.x, -w.y);
     }
     __syncthreads();
     fft_lds<LOG>(z, twl);
@@ -1685,7 +1694,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void filter_conv_kernel(
     for (int i = threadIdx.x; i < n_det; i += kFftThreads) {
         const int m = i + c;
         const bool ok = m >= 0 && m <= 2 * n_det - 2;
-        const float2 v = ok ? z[m] : make_float2(0.f, 0.f);
+        const float2 v = ok ? z[fpad(m)] : make_float2(0.f, 0.f);
         o0[i] = v.x * inv;
         if (second) o0[plane + i] = -v.y * inv;
     }
