@@ -106,6 +106,51 @@ def cpu_baseline(d, cfg, roi, margin):
                       f"(measured {t_fbp + t_ext + t_step + t_10:.1f}s)"}
 
 
+def local_cpu_baseline(d, iters):
+    """The FP64 oracle's Alg. 2 (oracle/filters.py, as it stands: every iteration
+    convolves the whole sinogram with that iteration's filters and applies the sparse
+    W_L) on a bounded sample of the 64-ROI batch: four iterations on one ROI of side 32
+    and one of side 128 with filters of the workload's shape, the sparse W_L build timed
+    apart; per-ROI cost a + b * area (b >= 0) fitted to the two and summed over the 64 ROIs
+    times the iteration count.  The one-time filter recursion is not included."""
+    import oracle
+    import synth
+    from oracle.filters import local_method_box
+    cfg = d["cfg"]
+    geo = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    sino = d["sino"].astype(np.float32).astype(np.float64)
+    n_it = 4
+    U = np.random.default_rng(0).normal(size=(n_it, cfg["n_angles"], cfg["n_det"])) * 1e-6
+    rois = synth.roi_list("c3")
+    pts = []
+    for side in (32, 128):
+        r0, c0, rr, cc, m = next(r for r in rois if r[2] == side)
+        ext = oracle.roi_extend((r0, c0, rr, cc), m, cfg["n"])
+        t0 = time.perf_counter()
+        oracle.sparse_local(geo, ext)
+        t_wl = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        local_method_box(geo, sino, (r0, c0, rr, cc), m, U, 0.0, np.inf)
+        t_2 = time.perf_counter() - t0
+        pts.append((ext[2] * ext[3], t_wl, (t_2 - t_wl) / n_it))
+    (a1, w1, i1), (a2, w2, i2) = pts
+    def fit(v1, v2, area):   # nondecreasing in the area
+        return v1 + max(v2 - v1, 0.0) * (area - a1) / (a2 - a1)
+    total = 0.0
+    for (r0, c0, rr, cc, m) in rois:
+        e = oracle.roi_extend((r0, c0, rr, cc), m, cfg["n"])
+        area = e[2] * e[3]
+        total += max(fit(w1, w2, area), 0.0) + iters * max(fit(i1, i2, area), 0.0)
+    log(f"cpu oracle (local method): iteration {i1:.2f}s (ext {a1} px) / {i2:.2f}s (ext {a2} px) "
+        f"-> {total:.0f}s per batch")
+    return {"value": len(rois) / total, "unit": "ROI solves/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 NumPy oracle Alg. 2 (whole-sinogram filter convolution and sparse "
+                      "W_L products per iteration, single thread): 4 iterations on one 32^2 "
+                      "and one 128^2 ROI plus their W_L builds, cost linear in the extended "
+                      f"area fitted to those and summed over the 64 ROIs x {iters} iterations "
+                      "(filter recursion excluded)"}
+
+
 def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
     """64 uneven ROIs (sides 32..256, margin side/4) on a 2048^2 grid, 256 angles,
     3072 bins, 200 CP-TV iterations: one roi_solve_batch call vs the same ROIs
@@ -165,7 +210,7 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
         ctx.close()
 
 
-def local_leg(torch, d, reps=3, iters=None, compare=True):
+def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
     """The paper's own local method on the batch workload: SIRT-approximating filters
     (Alg. 1, once per geometry), the filtered data C_{u_k} p (once per sinogram), and
     Alg. 2 with a nonnegativity box for the 64 uneven ROIs in one roi_solve_local
@@ -294,6 +339,8 @@ def local_leg(torch, d, reps=3, iters=None, compare=True):
             t_sirt = (time.perf_counter() - t0) / reps
             log(f"local: exterior-subtraction SIRT batch {1e3 * t_sirt:.1f} ms")
             res["exterior_sirt_ms_per_batch"] = 1e3 * t_sirt
+        if cpu:
+            res["cpu_baseline"] = local_cpu_baseline(d, its)
         return res
     finally:
         ctx.close()
@@ -470,8 +517,8 @@ def main():
               flush=True)
         return
     if args.only == "local":
-        print(json.dumps(local_leg(torch, d3, reps=args.steps, iters=args.iters, compare=False)),
-              flush=True)
+        print(json.dumps(local_leg(torch, d3, reps=args.steps, iters=args.iters, compare=False,
+                                   cpu=False)), flush=True)
         return
 
     d = synth.make_inputs("c2", with_image=False, workers=1)
@@ -563,7 +610,7 @@ def main():
             res["batched"] = {"error": repr(e)}
     if not args.skip_local:
         try:
-            res["local_method"] = local_leg(torch, d3)
+            res["local_method"] = local_leg(torch, d3, cpu=not args.no_cpu_baseline)
         except Exception as e:
             res["local_method"] = {"error": repr(e)}
     if not args.skip_serve:
