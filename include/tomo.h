@@ -366,7 +366,8 @@ tomo_status tomo_roi_nnz(tomo_ctx* ctx, int32_t geom, tomo_rect region, int64_t*
  * first runs 50 back-to-back launches of each kernel on its own data, captured
  * in a hipGraph (no dispatch gaps between them) and bracketed by two HIP events
  * on the solve's stream, then clears its state and solves as usual (results
- * are unchanged).  mode 0: off.  tomo_kernel_time waits for the recorded
+ * are unchanged; roi_solve and roi_solve_batch only).  mode 0: off.  tomo_kernel_time
+ * waits for the recorded
  * events and returns, per kernel, the number of timed launches and their total
  * GPU time in milliseconds (host outputs); reset = 1 clears the totals. */
 tomo_status tomo_kernel_timing(tomo_ctx* ctx, int mode);

@@ -77,7 +77,7 @@ enum JobFlags : int32_t { JF_HALF = 1, JF_ANISO = 2 };
 
 struct Job {
     int32_t nr, nc;          // region rows, cols
-    int32_t xp, tp;          // pitch of padded xbar [nr][xp] (col c at c+1) and of xbarT [nc][tp]
+    int32_t xp, tp;          // pitch of padded xbar [nr][xp] (col c at c + kLpad) and of xbarT [nc][tp]
     int32_t n_angles;        // band rows
     int32_t bpitch;          // band pitch (band position j stored at j + 1)
     int32_t n_det;           // detector bins (off-detector band entries are kept at 0)
