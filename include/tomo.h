@@ -144,7 +144,9 @@ typedef enum {
 enum {
     ROI_FLAG_HALF_DATA = 1, /* use 1/2 ||W_L x - b||^2 as the data term */
     ROI_FLAG_ANISO_TV = 2,  /* anisotropic TV (sum of |d/dr| + |d/dc|) */
-    ROI_FLAG_BOX = 4        /* SIRT-type methods: box [box_lo, box_hi] instead of [0, inf) */
+    ROI_FLAG_BOX = 4,       /* SIRT-type methods: box [box_lo, box_hi] instead of [0, inf) */
+    ROI_FLAG_NO_MOMENTUM = 8 /* local FISTA methods without momentum: the ISTA form
+                               (eq. sirtista), z = x^k */
 };
 
 /* One local reconstruction request.  roi: the part the caller wants; margin:

@@ -89,18 +89,20 @@ def prox_weight(geom, lam, alpha=None, half=False):
 
 
 def local_fista_tv(geom, sino, rect, margin, filters, lam, n_fgp, lo=-np.inf, hi=np.inf,
-                   aniso=False, half=False, alpha=None, xs_iterates=None, full=False):
+                   aniso=False, half=False, alpha=None, xs_iterates=None, full=False,
+                   momentum=True):
     """Alg. 3 on the extended local part.  filters: U from sirt_filters (U[k-1] = u_k);
     xs_iterates (optional, [K, N, N]) replaces FBP_L(p, u_k) by those images."""
     gamma = prox_weight(geom, lam, alpha, half)
     return local_fista(geom, sino, rect, margin, filters,
                        lambda w: fgp(w, gamma, n_fgp, lo, hi, aniso), alpha, xs_iterates, full,
-                       gamma)
+                       gamma, momentum)
 
 
 def local_fista(geom, sino, rect, margin, filters, prox, alpha=None, xs_iterates=None,
-                full=False, gamma=None):
-    """Alg. 3 with any proximal step `prox` (image -> image) in place of FGP."""
+                full=False, gamma=None, momentum=True):
+    """Alg. 3 with any proximal step `prox` (image -> image) in place of FGP; without
+    momentum (z = x^k) it is the ISTA form, eq. sirtista, of the same local method."""
     alpha = default_alpha(geom) if alpha is None else alpha
     ext = roi_extend(rect, margin, geom.n)
     r0, c0, rr, cc = ext
@@ -118,7 +120,7 @@ def local_fista(geom, sino, rect, margin, filters, prox, alpha=None, xs_iterates
         q = zl - alpha * (WL.T @ (WL @ zl))
         x = np.asarray(prox((xs + q).reshape(rr, cc)), dtype=np.float64).ravel()
         t_new = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0
-        z = x + ((t - 1.0) / t_new) * (x - x_prev)
+        z = x + ((t - 1.0) / t_new) * (x - x_prev) if momentum else x
         zl = z - xs
         x_prev, t = x, t_new
     x = x_prev.reshape(rr, cc)

@@ -86,8 +86,10 @@ def haar_prox(w, gamma, levels):
 
 
 def local_fista_haar(geom, sino, rect, margin, filters, lam, levels=4, half=False, alpha=None,
-                     xs_iterates=None, full=False):
-    """The local method (Alg. 3 form) with the Haar l1 prox."""
+                     xs_iterates=None, full=False, momentum=True):
+    """The local method (Alg. 3 form) with the Haar l1 prox; momentum=False gives the
+    ISTA iteration of eq. sirtista."""
     gamma = prox_weight(geom, lam, alpha, half)
     return local_fista(geom, sino, rect, margin, filters,
-                       lambda w: haar_prox(w, gamma, levels), alpha, xs_iterates, full, gamma)
+                       lambda w: haar_prox(w, gamma, levels), alpha, xs_iterates, full, gamma,
+                       momentum)

@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "TOMO_OK", -1: "TOMO_EINVAL", -2: "TOMO_ENOMEM", -3: "TOMO_EH
                 -4: "TOMO_EBUSY", -5: "TOMO_ENOENT", -6: "TOMO_EAGAIN", -7: "TOMO_ESTATE"}
 
 ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT, ROI_LOCAL_SIRT, ROI_LOCAL_FISTA_TV, ROI_LOCAL_FISTA_HAAR = 0, 1, 2, 3, 4
-ROI_FLAG_HALF_DATA, ROI_FLAG_ANISO_TV, ROI_FLAG_BOX = 1, 2, 4
+ROI_FLAG_HALF_DATA, ROI_FLAG_ANISO_TV, ROI_FLAG_BOX, ROI_FLAG_NO_MOMENTUM = 1, 2, 4, 8
 
 
 class tomo_rect(C.Structure):

@@ -107,7 +107,9 @@ tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p) {
     if (p.method == ROI_LOCAL_FISTA_HAAR && p.inner_iters > kHaarMaxLevels)
         return fail(ctx, TOMO_EINVAL, "at most %d Haar levels", kHaarMaxLevels);
     if (!(p.sigma >= 0.f) || !(p.tau >= 0.f)) return fail(ctx, TOMO_EINVAL, "negative step size");
-    if (p.flags & ~7u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & ~15u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
+    if ((p.flags & ROI_FLAG_NO_MOMENTUM) && p.method < ROI_LOCAL_FISTA_TV)
+        return fail(ctx, TOMO_EINVAL, "ROI_FLAG_NO_MOMENTUM applies to the local FISTA methods");
     if (p.flags & ROI_FLAG_BOX) {
         if (p.method == ROI_TV_NONNEG_CP || p.method == ROI_LOCAL_FISTA_HAAR)
             return fail(ctx, TOMO_EINVAL,

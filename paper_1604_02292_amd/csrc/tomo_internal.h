@@ -73,7 +73,7 @@ enum BpMode : int32_t {
     BP_FISTA = 6    // two-channel band (g, d): w = v + bp_g, xs = bp_d (FGP input and x_s)
 };
 
-enum JobFlags : int32_t { JF_HALF = 1, JF_ANISO = 2 };
+enum JobFlags : int32_t { JF_HALF = 1, JF_ANISO = 2, JF_NO_MOMENTUM = 8 };
 
 struct Job {
     int32_t nr, nc;          // region rows, cols

@@ -1395,7 +1395,8 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
         const float x = fminf(fmaxf(b[u] - gamma * d, lo), hi);
         const size_t xi = (size_t)rr * J->ldx + cc;
         const float xo = J->x[xi];
-        const float z = x + J->beta_out[step] * (x - xo);
+        const float beta = (J->flags & JF_NO_MOMENTUM) ? 0.f : J->beta_out[step];
+        const float z = x + beta * (x - xo);
         const float v = z - J->xs[pi];
         J->x[xi] = x;
         const int wpar = ((step + J->parity0) & 1) ^ 1;
@@ -1510,7 +1511,8 @@ __global__ __launch_bounds__(256) void haar_kernel(const Job* __restrict__ jobs,
         const size_t pi = (size_t)rr * nc + cc;
         const size_t xi = (size_t)rr * J->ldx + cc;
         const float xo = J->x[xi];
-        const float z = x + J->beta_out[step] * (x - xo);
+        const float beta = (J->flags & JF_NO_MOMENTUM) ? 0.f : J->beta_out[step];
+        const float z = x + beta * (x - xo);
         const float v = z - J->xs[pi];
         J->x[xi] = x;
         J->xb[wpar][(size_t)rr * J->xp + cc + kLpad] = v;

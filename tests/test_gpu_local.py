@@ -272,6 +272,36 @@ def test_local_fista_haar_matches_oracle(ctx, c1):
     assert rel(ref[0], plain) > 1e-2
 
 
+def test_local_ista_form_matches_oracle(ctx, c1):
+    """ROI_FLAG_NO_MOMENTUM: the ISTA form (eq. sirtista) of both l1 priors."""
+    from paper_1604_02292_amd import make_params
+    cfg = c1["cfg"]
+    p32 = c1["sino"].astype(np.float32).astype(np.float64)
+    geo = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    K = 20
+    U = sirt_filters(geo, K, workers=4)
+    rect, m = (48, 48, 32, 32), 16
+    ref_h = local_fista_haar(geo, p32, rect, m, U, 300.0, 3, momentum=False)
+    ref_t = local_fista_tv(geo, p32, rect, m, U, 500.0, 40, momentum=False)
+    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    F = torch.empty((K, cfg["n_angles"], cfg["n_det"]), dtype=torch.float32, device="cuda")
+    ctx.tomo_sirt_filters(g, K, F)
+    D = torch.empty_like(F)
+    ctx.tomo_sirt_filter_sino(g, F, _gpu(p32), D)
+    outs = [torch.empty((32, 32), dtype=torch.float32, device="cuda") for _ in range(2)]
+    ctx.roi_solve_local(g, D, [make_params(rect, m, "haar", lam=300.0, iters=K, inner_iters=3,
+                                           flags=8),
+                               make_params(rect, m, "fista", lam=500.0, iters=K, inner_iters=40,
+                                           flags=8)], outs)
+    torch.cuda.synchronize()
+    for o, b, name in zip(outs, (ref_h, ref_t), ("ista-haar", "ista-tv")):
+        e = rel(o.double().cpu().numpy(), b)
+        print(f"[{name}] rel {e:.2e}", flush=True)
+        assert e <= 1e-3
+    # the flag changes the result (momentum acts from the second iteration on)
+    assert rel(local_fista_haar(geo, p32, rect, m, U, 300.0, 3), ref_h) > 1e-3
+
+
 def test_local_haar_errors(ctx):
     from paper_1604_02292_amd import make_params, TomoError
     g = ctx.tomo_set_geometry(64, 8, 96)
@@ -283,6 +313,9 @@ def test_local_haar_errors(ctx):
     with pytest.raises(TomoError, match="EINVAL"):   # no box with the Haar prior
         ctx.roi_solve_local(g, D, [make_params((0, 0, 8, 8), 2, "haar", iters=5,
                                                box=(0.0, 1.0))], [out])
+    with pytest.raises(TomoError, match="EINVAL"):   # no momentum to drop in Alg. 2
+        ctx.roi_solve_local(g, D, [make_params((0, 0, 8, 8), 2, "local", iters=5, flags=8)],
+                            [out])
 
 
 def test_local_fista_timing_kind(ctx, c1):

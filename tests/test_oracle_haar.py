@@ -104,3 +104,24 @@ def test_local_fista_haar_bridge_to_global():
         z = x + ((t - 1) / t_new) * (x - x_prev)
         x_prev, t = x, t_new
     assert np.abs(got - x_prev.reshape(n, n)).max() <= 1e-12 * np.abs(x_prev).max()
+
+
+def test_ista_form_is_eq_sirtista_on_the_whole_grid():
+    """Without momentum, with the exact SIRT iterates on the whole grid, the local method
+    is eq. sirtista: x^{k+1} = B^-1 P(B S(x^k)) from x = 0."""
+    n = 16
+    g = make_geometry(n, 12, 23)
+    yy, xx = np.mgrid[0:n, 0:n] - (n - 1) / 2.0
+    p = fp_ray(g, 1.0 * (xx ** 2 + yy ** 2 < 30))
+    K, lam, L = 5, 300.0, 3
+    X = sirt_iterates(g, p, K)
+    got = local_fista_haar(g, p, (0, 0, n, n), 0, None, lam, L, xs_iterates=X, momentum=False)
+    W = sparse_local(g)
+    alpha = default_alpha(g)
+    gamma = prox_weight(g, lam, alpha)
+    x = np.zeros(n * n)
+    for _ in range(K):
+        s = x + alpha * (W.T @ (p.ravel() - W @ x))
+        x = haar_inverse(np.sign(haar_forward(s.reshape(n, n), L)) *
+                         np.maximum(np.abs(haar_forward(s.reshape(n, n), L)) - gamma, 0), L).ravel()
+    assert np.abs(got - x.reshape(n, n)).max() <= 1e-12 * np.abs(x).max()
