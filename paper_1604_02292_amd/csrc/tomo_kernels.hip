@@ -1277,7 +1277,7 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
     // per own pixel: flags (inside, has up / left / down / right neighbour in the
     // region, gradient rows / columns nonzero), b, p, r
     enum { IN = 1, UP = 2, LEFT = 4, DOWN = 8, RIGHT = 16, G0 = 32, G1 = 64 };
-    int fl[NQ];
+    int fl[NQ], lrow[NQ];
     float b[NQ], p0[NQ], p1[NQ], r0[NQ], r1[NQ];
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
@@ -1285,6 +1285,7 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
         const int lr = q / RW, lc = q % RW;
         const int rr = R0 + lr, cc = C0 + lc;
         int f = 0;
+        lrow[u] = q < RN ? lr : RW;   // past the last row: outside every window
         b[u] = p0[u] = p1[u] = r0[u] = r1[u] = 0.f;
         if (q < RN) {
             f |= (lr > 0 ? UP : 0) | (lc > 0 ? LEFT : 0) | (lr + 1 < RW ? DOWN : 0) |
@@ -1321,8 +1322,7 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
             for (int u = 0; u < NQ; ++u) {
                 const int q = t + kFgpThreads * u;
                 xr[u] = 0.f;
-                const int lr = q / RW;
-                if (q < RN && lr >= wlo && lr <= whi) {
+                if (lrow[u] >= wlo && lrow[u] <= whi) {
                     const float up = (fl[u] & UP) ? sr0[q - RW] : 0.f;
                     const float left = (fl[u] & LEFT) ? sr1[q - 1] : 0.f;
                     const float d = (r0[u] - up) + (r1[u] - left);
@@ -1335,8 +1335,7 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
 #pragma unroll
             for (int u = 0; u < NQ; ++u) {
                 const int q = t + kFgpThreads * u;
-                const int lr = q / RW;
-                if (q >= RN || lr < wlo || lr > whi) continue;
+                if (lrow[u] < wlo || lrow[u] > whi) continue;
                 float n0 = 0.f, n1 = 0.f;
                 if (fl[u] & IN) {
                     const float g0 = (fl[u] & G0) && (fl[u] & DOWN) ? sx[q + RW] - xr[u] : 0.f;
@@ -1347,9 +1346,11 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
                         n0 = fminf(fmaxf(n0, -1.f), 1.f);
                         n1 = fminf(fmaxf(n1, -1.f), 1.f);
                     } else {
-                        const float sc = fmaxf(1.f, sqrtf(n0 * n0 + n1 * n1));
-                        n0 = n0 / sc;
-                        n1 = n1 / sc;
+                        // onto the unit ball: scale by 1/|n| only where |n| > 1
+                        const float q2 = fmaf(n0, n0, n1 * n1);
+                        const float sc = q2 > 1.f ? __builtin_amdgcn_rsqf(q2) : 1.f;
+                        n0 *= sc;
+                        n1 *= sc;
                     }
                 }
                 r0[u] = n0 + beta * (n0 - p0[u]);
