@@ -297,7 +297,7 @@ def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
         n_g, ms_g = ctx.tomo_kernel_time(2)
         fgp_us = 1e3 * ms_g / max(1, n_g)
         log(f"local FISTA-TV: 64 ROIs x {its} its x 100 FGP {1e3 * t_fista:.1f} ms per batch; "
-            f"FGP {fgp_us:.1f} us per outer iteration (13 launches)")
+            f"FGP {fgp_us:.1f} us per outer iteration")
         res["fista_tv"] = {"roi_solves_per_s": len(rois) / t_fista, "ms_per_batch": 1e3 * t_fista,
                            "fgp_us_per_outer_iteration": fgp_us, "fgp_iterations": 100,
                            "gamma": 0.02, "lambda": lam_f}
