@@ -274,7 +274,20 @@ def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
                "fp_updates_per_s": nnz / (fp_us * 1e-6), "bp_updates_per_s": nnz / (bp_us * 1e-6),
                "filters_ms": 1e3 * t_filt, "filtered_data_ms": 1e3 * t_conv,
                "filtered_data_gb_per_s": conv_bytes / t_conv / 1e9,
-               "filtered_data_bytes": conv_bytes}
+               "filtered_data_bytes": conv_bytes,
+               # the iteration's dominant kernel against the ALU roof of the projectors
+               # (both channels share one weight per update), and the filtered data
+               # against HBM (algorithmic bytes: filters and data spectra read,
+               # filtered data written)
+               "roofline": {"bound": "alu", "kernel": "bp_kernel (two-channel)",
+                            "achieved": nnz / (bp_us * 1e-6) / 1e9,
+                            "peak": PEAK_UPDATES / 1e9, "unit": "Gupdate/s",
+                            "frac": nnz / (bp_us * 1e-6) / PEAK_UPDATES,
+                            "avg_launch_us": bp_us, "updates_per_launch": nnz},
+               "filtered_data_roofline": {"bound": "hbm", "kernel": "filter_conv_kernel",
+                                          "achieved": conv_bytes / t_conv / 1e9,
+                                          "peak": 8000.0, "unit": "GB/s",
+                                          "frac": conv_bytes / t_conv / 8e12}}
         # local FISTA-TV (Alg. 3) on the same ROIs and filtered data: 100 FGP iterations
         # per outer iteration, TV prox weight gamma = alpha lambda / 2 = 0.02
         alpha = 1.0 / (na * nd)
