@@ -534,7 +534,7 @@ def main():
                                    cpu=False)), flush=True)
         return
 
-    d = synth.make_inputs("c2", with_image=False, workers=1)
+    d = synth.make_inputs("c2", with_image=True, workers=1)
     cfg = d["cfg"]
     r0, c0, rr, cc, margin = synth.roi_list("c2")[0]
     roi = (r0, c0, rr, cc)
@@ -615,6 +615,32 @@ def main():
         "fp_updates_per_s": fp_rate, "bp_updates_per_s": bp_rate,
         "roofline": roofline,
     }
+    # quality, not timed: the ROI of the global TV solve on the whole 1024^2 grid (same
+    # lambda and iterations, no exterior), and the local, global and FBP results against
+    # the phantom inside the ROI
+    n = cfg["n"]
+    gout = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    gprm = make_params((0, 0, n, n), 0, "cp", cfg["lam"], cfg["iters"])
+    ctx.roi_solve(g, sino, gprm, gout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.roi_solve(g, sino, gprm, gout)
+    torch.cuda.synchronize()
+    t_glob = time.perf_counter() - t0
+    fbp = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ctx.tomo_fbp_ramlak(g, sino, fbp)
+    torch.cuda.synchronize()
+    loc = out.double().cpu().numpy()
+    glob = gout.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
+    fbp_r = fbp.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
+    truth = d["image"][r0:r0 + rr, c0:c0 + cc]
+    relq = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    res["quality"] = {"local_vs_global_rel": relq(loc, glob), "local_vs_phantom_rel": relq(loc, truth),
+                      "global_vs_phantom_rel": relq(glob, truth),
+                      "fbp_vs_phantom_rel": relq(fbp_r, truth), "global_solve_ms": 1e3 * t_glob}
+    log(f"quality: local vs global {res['quality']['local_vs_global_rel']:.3e}; vs phantom: local "
+        f"{res['quality']['local_vs_phantom_rel']:.3e}, global {res['quality']['global_vs_phantom_rel']:.3e}"
+        f", FBP {res['quality']['fbp_vs_phantom_rel']:.3e}; global solve {1e3 * t_glob:.1f} ms")
     ctx.close()
     if not args.skip_batch:
         try:
