@@ -1258,8 +1258,14 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
     constexpr int H = kFgpSteps + 1, RW = kFgpTile + 2 * H, RN = RW * RW;
     constexpr int NQ = (RN + kFgpThreads - 1) / kFgpThreads;   // region pixels per thread
     // Each thread keeps its own pixels' b, p and r in registers; only x and r,
-    // which neighbours read, go through LDS.
-    __shared__ float sx[RN], sr0[RN], sr1[RN];
+    // which neighbours read, go through LDS.  The arrays are padded so that every
+    // neighbour read stays in bounds without a test: r0 of pixel q sits at
+    // sr0[RW + q] (the up neighbour of the first row reads the zero row in front),
+    // r1 at sr1[1 + q], and x has a zero row behind the window.  A neighbour read
+    // that crosses the window's edge returns another finite pixel's value instead of
+    // zero; it only feeds pixels on the window's rim, which are outside the exact
+    // area from the first step on.
+    __shared__ float sx[RN + RW], sr0[RW + RN], sr1[1 + RN];
     const int bid = blockIdx.x;
     if (bid >= n_items) return;
     const Item it = cview(items)[bid];
@@ -1274,24 +1280,29 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
     const size_t plane = (size_t)nr * nc;
     const float gamma = J->gamma;
     const int t = threadIdx.x;
-    // per own pixel: flags (inside, has up / left / down / right neighbour in the
-    // region, gradient rows / columns nonzero), b, p, r
-    enum { IN = 1, UP = 2, LEFT = 4, DOWN = 8, RIGHT = 16, G0 = 32, G1 = 64 };
-    int fl[NQ], lrow[NQ];
+    if (t < RW) {
+        sr0[t] = 0.f;
+        sx[RN + t] = 0.f;
+    }
+    if (t == 0) sr1[0] = 0.f;
+    // per own pixel: gradient rows / columns taken (1 inside the region but not on its
+    // last row / column, else 0; every value in sx is finite, so a product with 0 is 0),
+    // b, p and r
+    float g0m[NQ], g1m[NQ];
+    int lrow[NQ];
     float b[NQ], p0[NQ], p1[NQ], r0[NQ], r1[NQ];
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
         const int q = t + kFgpThreads * u;
         const int lr = q / RW, lc = q % RW;
         const int rr = R0 + lr, cc = C0 + lc;
-        int f = 0;
         lrow[u] = q < RN ? lr : RW;   // past the last row: outside every window
+        g0m[u] = g1m[u] = 0.f;
         b[u] = p0[u] = p1[u] = r0[u] = r1[u] = 0.f;
         if (q < RN) {
-            f |= (lr > 0 ? UP : 0) | (lc > 0 ? LEFT : 0) | (lr + 1 < RW ? DOWN : 0) |
-                 (lc + 1 < RW ? RIGHT : 0);
             if (rr >= 0 && rr < nr && cc >= 0 && cc < nc) {
-                f |= IN | (rr < nr - 1 ? G0 : 0) | (cc < nc - 1 ? G1 : 0);
+                g0m[u] = rr < nr - 1 && lr + 1 < RW ? 1.f : 0.f;
+                g1m[u] = cc < nc - 1 && lc + 1 < RW ? 1.f : 0.f;
                 const size_t pi = (size_t)rr * nc + cc;
                 b[u] = J->w[pi];
                 if (i0 > 0 && gamma > 0.f) {
@@ -1301,10 +1312,9 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
                     r1[u] = J->fr[plane + pi];
                 }
             }
-            sr0[q] = r0[u];
-            sr1[q] = r1[u];
+            sr0[RW + q] = r0[u];
+            sr1[1 + q] = r1[u];
         }
-        fl[u] = f;
     }
     __syncthreads();
     const float lo = J->lo, hi = J->hi;
@@ -1323,8 +1333,7 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
                 const int q = t + kFgpThreads * u;
                 xr[u] = 0.f;
                 if (lrow[u] >= wlo && lrow[u] <= whi) {
-                    const float up = (fl[u] & UP) ? sr0[q - RW] : 0.f;
-                    const float left = (fl[u] & LEFT) ? sr1[q - 1] : 0.f;
+                    const float up = sr0[q], left = sr1[q];
                     const float d = (r0[u] - up) + (r1[u] - left);
                     xr[u] = fminf(fmaxf(b[u] - gamma * d, lo), hi);
                     sx[q] = xr[u];
@@ -1336,29 +1345,28 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
             for (int u = 0; u < NQ; ++u) {
                 const int q = t + kFgpThreads * u;
                 if (lrow[u] < wlo || lrow[u] > whi) continue;
-                float n0 = 0.f, n1 = 0.f;
-                if (fl[u] & IN) {
-                    const float g0 = (fl[u] & G0) && (fl[u] & DOWN) ? sx[q + RW] - xr[u] : 0.f;
-                    const float g1 = (fl[u] & G1) && (fl[u] & RIGHT) ? sx[q + 1] - xr[u] : 0.f;
-                    n0 = r0[u] - g0 * inv8g;
-                    n1 = r1[u] - g1 * inv8g;
-                    if (aniso) {
-                        n0 = fminf(fmaxf(n0, -1.f), 1.f);
-                        n1 = fminf(fmaxf(n1, -1.f), 1.f);
-                    } else {
-                        // onto the unit ball: scale by 1/|n| only where |n| > 1
-                        const float q2 = fmaf(n0, n0, n1 * n1);
-                        const float sc = q2 > 1.f ? __builtin_amdgcn_rsqf(q2) : 1.f;
-                        n0 *= sc;
-                        n1 *= sc;
-                    }
+                const float dn = sx[q + RW], rt = sx[q + 1];
+                const float g0 = g0m[u] * (dn - xr[u]);
+                const float g1 = g1m[u] * (rt - xr[u]);
+                // outside the region r stays zero: no gradient is taken there
+                float n0 = r0[u] - g0 * inv8g;
+                float n1 = r1[u] - g1 * inv8g;
+                if (aniso) {
+                    n0 = fminf(fmaxf(n0, -1.f), 1.f);
+                    n1 = fminf(fmaxf(n1, -1.f), 1.f);
+                } else {
+                    // onto the unit ball: scale by 1/|n| only where |n| > 1
+                    const float q2 = fmaf(n0, n0, n1 * n1);
+                    const float sc = q2 > 1.f ? __builtin_amdgcn_rsqf(q2) : 1.f;
+                    n0 *= sc;
+                    n1 *= sc;
                 }
                 r0[u] = n0 + beta * (n0 - p0[u]);
                 r1[u] = n1 + beta * (n1 - p1[u]);
                 p0[u] = n0;
                 p1[u] = n1;
-                sr0[q] = r0[u];
-                sr1[q] = r1[u];
+                sr0[RW + q] = r0[u];
+                sr1[1 + q] = r1[u];
             }
             __syncthreads();
         }
@@ -1368,8 +1376,8 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
         for (int u = 0; u < NQ; ++u) {
             const int q = t + kFgpThreads * u;
             if (q < RN) {
-                sr0[q] = p0[u];
-                sr1[q] = p1[u];
+                sr0[RW + q] = p0[u];
+                sr1[1 + q] = p1[u];
             }
         }
         __syncthreads();
@@ -1392,7 +1400,7 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
             continue;
         }
         // x = P(b - gamma div p), then the FISTA momentum point z and v = z - x_s
-        const float d = (p0[u] - sr0[q - RW]) + (p1[u] - sr1[q - 1]);
+        const float d = (p0[u] - sr0[q]) + (p1[u] - sr1[q]);
         const float x = fminf(fmaxf(b[u] - gamma * d, lo), hi);
         const size_t xi = (size_t)rr * J->ldx + cc;
         const float xo = J->x[xi];
