@@ -1285,24 +1285,23 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
         sx[RN + t] = 0.f;
     }
     if (t == 0) sr1[0] = 0.f;
-    // per own pixel: gradient rows / columns taken (1 inside the region but not on its
-    // last row / column, else 0; every value in sx is finite, so a product with 0 is 0),
-    // b, p and r
-    float g0m[NQ], g1m[NQ];
-    int lrow[NQ];
+    // per own pixel: its window row (bits 0-7; RW past the last pixel) and whether the
+    // gradient row / column is taken (bits 8, 9: inside the region and not on its last
+    // row / column), b, p and r
+    static_assert(RW < 256, "window row must fit in 8 bits");
+    int meta[NQ];
     float b[NQ], p0[NQ], p1[NQ], r0[NQ], r1[NQ];
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
         const int q = t + kFgpThreads * u;
         const int lr = q / RW, lc = q % RW;
         const int rr = R0 + lr, cc = C0 + lc;
-        lrow[u] = q < RN ? lr : RW;   // past the last row: outside every window
-        g0m[u] = g1m[u] = 0.f;
+        meta[u] = q < RN ? lr : RW;   // past the last row: outside every window
         b[u] = p0[u] = p1[u] = r0[u] = r1[u] = 0.f;
         if (q < RN) {
             if (rr >= 0 && rr < nr && cc >= 0 && cc < nc) {
-                g0m[u] = rr < nr - 1 && lr + 1 < RW ? 1.f : 0.f;
-                g1m[u] = cc < nc - 1 && lc + 1 < RW ? 1.f : 0.f;
+                meta[u] |= (rr < nr - 1 && lr + 1 < RW ? 256 : 0) |
+                           (cc < nc - 1 && lc + 1 < RW ? 512 : 0);
                 const size_t pi = (size_t)rr * nc + cc;
                 b[u] = J->w[pi];
                 if (i0 > 0 && gamma > 0.f) {
@@ -1327,16 +1326,14 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
             // this launch; rows outside [s - 1, RW - s] are not needed by any later step.
             const int s = i - i0 + 1, wlo = s - 1, whi = RW - s;
             // x = P(b - gamma div r); div r = r0 - r0(up) + r1 - r1(left), zero outside
-            float xr[NQ];
 #pragma unroll
             for (int u = 0; u < NQ; ++u) {
                 const int q = t + kFgpThreads * u;
-                xr[u] = 0.f;
-                if (lrow[u] >= wlo && lrow[u] <= whi) {
+                const int lr = meta[u] & 255;
+                if (lr >= wlo && lr <= whi) {
                     const float up = sr0[q], left = sr1[q];
                     const float d = (r0[u] - up) + (r1[u] - left);
-                    xr[u] = fminf(fmaxf(b[u] - gamma * d, lo), hi);
-                    sx[q] = xr[u];
+                    sx[q] = fminf(fmaxf(b[u] - gamma * d, lo), hi);
                 }
             }
             __syncthreads();
@@ -1344,10 +1341,12 @@ __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict_
 #pragma unroll
             for (int u = 0; u < NQ; ++u) {
                 const int q = t + kFgpThreads * u;
-                if (lrow[u] < wlo || lrow[u] > whi) continue;
-                const float dn = sx[q + RW], rt = sx[q + 1];
-                const float g0 = g0m[u] * (dn - xr[u]);
-                const float g1 = g1m[u] * (rt - xr[u]);
+                const int lr = meta[u] & 255;
+                if (lr < wlo || lr > whi) continue;
+                const float xq = sx[q];
+                const float dn = sx[q + RW] - xq, rt = sx[q + 1] - xq;
+                const float g0 = (meta[u] & 256) ? dn : 0.f;
+                const float g1 = (meta[u] & 512) ? rt : 0.f;
                 // outside the region r stays zero: no gradient is taken there
                 float n0 = r0[u] - g0 * inv8g;
                 float n1 = r1[u] - g1 * inv8g;
