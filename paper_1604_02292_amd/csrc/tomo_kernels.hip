@@ -1710,6 +1710,263 @@ __global__ __launch_bounds__(kFftThreads, 4) void filter_conv_kernel(
     }
 }
 
+// The same convolution for L >= 512 with radix-16 stages (one radix-2, 4 or 8 stage
+// covers the remaining bits): four LDS passes per transform instead of seven.  The
+// forward transform's first stage reads the filter rows straight from global memory;
+// its last stage, the product with the data spectrum and the inverse transform's first
+// stage run on the same registers (the last stage of a self-sorting transform leaves
+// entry j + r L/16 with the thread that the next transform's first stage gives it);
+// the inverse's last stage writes the outputs straight to global memory.
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+    return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+    return make_float2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ float2 cmi(float2 a) { return make_float2(a.y, -a.x); }   // -i a
+__device__ __forceinline__ float2 cmulc(float2 a, float wr, float wi) {
+    return make_float2(fmaf(a.x, wr, -a.y * wi), fmaf(a.x, wi, a.y * wr));
+}
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+    const float2 a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3), a3 = cmi(csub(x1, x3));
+    x0 = cadd(a0, a2);
+    x1 = cadd(a1, a3);
+    x2 = csub(a0, a2);
+    x3 = csub(a1, a3);
+}
+// Forward DFT of v[0..R) in registers (exp(-2 pi i n k / R)), natural order.
+template <int R>
+__device__ __forceinline__ void dft_reg(float2* v);
+template <>
+__device__ __forceinline__ void dft_reg<2>(float2* v) {
+    const float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+template <>
+__device__ __forceinline__ void dft_reg<4>(float2* v) {
+    dft4(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ __forceinline__ void dft_reg<8>(float2* v) {
+    // n = 2 n1 + n2, k = k1 + 4 k2: 4-point DFTs over n1, twiddles W8^(n2 k1), pairs
+    constexpr float H = 0.70710678118654752f;
+    dft4(v[0], v[2], v[4], v[6]);
+    dft4(v[1], v[3], v[5], v[7]);
+    v[3] = cmulc(v[3], H, -H);
+    v[5] = cmi(v[5]);
+    v[7] = cmulc(v[7], -H, -H);
+    float2 o[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        o[k1] = cadd(v[2 * k1], v[2 * k1 + 1]);
+        o[k1 + 4] = csub(v[2 * k1], v[2 * k1 + 1]);
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = o[r];
+}
+template <>
+__device__ __forceinline__ void dft_reg<16>(float2* v) {
+    // n = 4 n1 + n2, k = k1 + 4 k2: 4-point DFTs over n1, twiddles W16^(n2 k1), 4-point
+    // DFTs over n2
+    constexpr float C = 0.92387953251128676f, S = 0.38268343236508977f,
+                    H = 0.70710678118654752f;
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+    // Y[n2][k1] sits at v[n2 + 4 k1]
+    v[5] = cmulc(v[5], C, -S);      // W^1
+    v[9] = cmulc(v[9], H, -H);      // W^2
+    v[13] = cmulc(v[13], S, -C);    // W^3
+    v[6] = cmulc(v[6], H, -H);      // W^2
+    v[10] = cmi(v[10]);             // W^4
+    v[14] = cmulc(v[14], -H, -H);   // W^6
+    v[7] = cmulc(v[7], S, -C);      // W^3
+    v[11] = cmulc(v[11], -H, -H);   // W^6
+    v[15] = cmulc(v[15], -C, S);    // W^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+        dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // X[k1 + 4 k2] sits at v[4 k1 + k2]
+    float2 o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = o[r];
+}
+// v[r] *= exp(-2 pi i r m / L) for r = 1 .. R-1 (r m < L): four table twiddles at most,
+// the others as products of two of them.
+template <int LOG, int R>
+__device__ __forceinline__ void twiddle_reg(float2* v, int m, const FftTw<LOG>& tw) {
+    float2 w[R];
+    w[1] = tw(m);
+    if constexpr (R >= 4) {
+        w[2] = tw(2 * m);
+        w[3] = cmul(w[1], w[2]);
+    }
+    if constexpr (R >= 8) {
+        w[4] = tw(4 * m);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+    }
+    if constexpr (R >= 16) {
+        w[8] = tw(8 * m);
+#pragma unroll
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+}
+// One self-sorting radix-R stage through LDS: R sub-transforms of length ns become one
+// of length R ns.
+template <int LOG, int R>
+__device__ void fft_stage_lds(float2* z, int ns, const FftTw<LOG>& tw) {
+    constexpr int L = 1 << LOG, NBF = L / R, NB = (NBF + kFftThreads - 1) / kFftThreads;
+    const int t = threadIdx.x;
+    float2 v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = t + i * kFftThreads;
+        if (j < NBF) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = z[fpad(j + r * NBF)];
+            twiddle_reg<LOG, R>(v[i], (L / (R * ns)) * (j & (ns - 1)), tw);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = t + i * kFftThreads;
+        if (j < NBF) {
+            const int k = j & (ns - 1);
+            dft_reg<R>(v[i]);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) z[fpad(base + r * ns)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int LOG>
+__global__ __launch_bounds__(kFftThreads, 4) void filter_conv16_kernel(
+    const float* __restrict__ filt, int n_filt, int n_angles, int n_det,
+    const int* __restrict__ ctr, const float2* __restrict__ tw, const float2* __restrict__ spec,
+    float* __restrict__ out) {
+    static_assert(LOG >= 9, "the radix-16 path takes L >= 512");
+    constexpr int L = 1 << LOG, Q = LOG / 4, RB = LOG % 4;
+    constexpr int RE = RB ? (1 << RB) : 16;   // radix of the first forward / last inverse stage
+    constexpr int NMID = RB ? Q - 1 : Q - 2;   // radix-16 stages through LDS per transform
+    __shared__ float2 z[FftLds<L>::N];
+    __shared__ FftTw<LOG> twl;
+    twl.load(tw);
+    const int npairs = (n_filt + 1) / 2;
+    const int a = blockIdx.x / npairs, h = blockIdx.x % npairs;
+    const int k0 = 2 * h;
+    const bool second = k0 + 1 < n_filt;
+    const size_t plane = (size_t)n_angles * n_det;
+    const float* f0 = filt + (size_t)k0 * plane + (size_t)a * n_det;
+    const int t = threadIdx.x;
+    // forward, first stage (ns = 1, no twiddles) from the filter pair u_{2h} + i u_{2h+1}
+    {
+        constexpr int NBF = L / RE, NB = (NBF + kFftThreads - 1) / kFftThreads;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * kFftThreads;
+            if (j < NBF) {
+                float2 v[RE];
+#pragma unroll
+                for (int r = 0; r < RE; ++r) {
+                    const int e = j + r * NBF;
+                    v[r] = e < n_det ? make_float2(f0[e], second ? f0[plane + e] : 0.f)
+                                     : make_float2(0.f, 0.f);
+                }
+                dft_reg<RE>(v);
+#pragma unroll
+                for (int r = 0; r < RE; ++r) z[fpad(j * RE + r)] = v[r];
+            }
+        }
+        __syncthreads();
+    }
+    int ns = RE;
+#pragma unroll 1
+    for (int q = 0; q < NMID; ++q, ns *= 16) fft_stage_lds<LOG, 16>(z, ns, twl);
+    // forward last stage (ns = L / 16: twiddle index j, outputs at j + r L / 16), times
+    // the data spectrum, conjugated (the inverse is conj(FFT(conj(.))) / L), and the
+    // inverse's first stage (ns = 1, inputs at j + r L / 16)
+    {
+        constexpr int NBF = L / 16, NB = (NBF + kFftThreads - 1) / kFftThreads;
+        float2 v[NB][16];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * kFftThreads;
+            if (j < NBF) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[i][r] = z[fpad(j + r * NBF)];
+                twiddle_reg<LOG, 16>(v[i], j, twl);
+            }
+        }
+        __syncthreads();
+        const float2* sp = spec + (size_t)a * L;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * kFftThreads;
+            if (j < NBF) {
+                dft_reg<16>(v[i]);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float2 w = cmul(v[i][r], sp[j + r * NBF]);
+                    v[i][r] = make_float2(w.x, -w.y);
+                }
+                dft_reg<16>(v[i]);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) z[fpad(j * 16 + r)] = v[i][r];
+            }
+        }
+        __syncthreads();
+    }
+    ns = 16;
+#pragma unroll 1
+    for (int q = 0; q < NMID; ++q, ns *= 16) fft_stage_lds<LOG, 16>(z, ns, twl);
+    // inverse last stage (ns = L / RE: twiddle index j, outputs at j + r L / RE) straight
+    // to the filtered data: out[k][a][i] = full[i + ctr[a]], zero off the 2 n_det - 1
+    // samples of the linear convolution
+    const float inv = 1.f / (float)L;
+    const int c = ctr[a];
+    float* o0 = out + (size_t)k0 * plane + (size_t)a * n_det;
+    {
+        constexpr int NBF = L / RE, NB = (NBF + kFftThreads - 1) / kFftThreads;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * kFftThreads;
+            if (j < NBF) {
+                float2 v[RE];
+#pragma unroll
+                for (int r = 0; r < RE; ++r) v[r] = z[fpad(j + r * NBF)];
+                twiddle_reg<LOG, RE>(v, j, twl);
+                dft_reg<RE>(v);
+#pragma unroll
+                for (int r = 0; r < RE; ++r) {
+                    const int m = j + r * NBF, o = m - c;
+                    if (m <= 2 * n_det - 2 && o >= 0 && o < n_det) {
+                        o0[o] = v[r].x * inv;
+                        if (second) o0[plane + o] = -v[r].y * inv;
+                    }
+                }
+            }
+        }
+    }
+    for (int i = t; i < n_det; i += kFftThreads) {
+        const int m = i + c;
+        if (m < 0 || m > 2 * n_det - 2) {
+            o0[i] = 0.f;
+            if (second) o0[plane + i] = 0.f;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void power_normalize_kernel(
     const float* __restrict__ w, int ldx, int nr, int nc, const float* __restrict__ part,
     int n_part, float* __restrict__ xb, int xp, float* __restrict__ xt, int tp,
@@ -1930,6 +2187,8 @@ hipError_t launch_haar(const Job* jobs, const Item* items, int n_items, int step
 }
 
 #define TOMO_FFT_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+#define TOMO_FFT_SMALL(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+#define TOMO_FFT_LARGE(X) X(9) X(10) X(11) X(12) X(13) X(14)
 
 hipError_t launch_spectra(const float* sino, int n_angles, int n_det, int log2_len,
                           const float2* tw, float2* spec, hipStream_t s) {
@@ -1958,12 +2217,21 @@ hipError_t launch_filter_conv(const float* filters, int n_filt, int n_angles, in
         hipLaunchKernelGGL(filter_conv_kernel<LG>, grid, dim3(kFftThreads), 0, s, filters,     \
                            n_filt, n_angles, n_det, ctr, tw, spec, out);                       \
         break;
-        TOMO_FFT_CASES(X)
+        TOMO_FFT_SMALL(X)
+#undef X
+#define X(LG)                                                                                  \
+    case LG:                                                                                   \
+        hipLaunchKernelGGL(filter_conv16_kernel<LG>, grid, dim3(kFftThreads), 0, s, filters,   \
+                           n_filt, n_angles, n_det, ctr, tw, spec, out);                       \
+        break;
+        TOMO_FFT_LARGE(X)
 #undef X
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 #undef TOMO_FFT_CASES
+#undef TOMO_FFT_SMALL
+#undef TOMO_FFT_LARGE
 
 }  // namespace tomo
