@@ -1,0 +1,47 @@
+"""Host-side checks of the benchmark script: the one-GPU contract and the lookup of the
+committed HBM-traffic records (valid only while the kernel source is unchanged)."""
+
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_roofline_peak_is_the_alu_roof():
+    # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, 4.5 lane-instructions per update
+    assert abs(bench.PEAK_UPDATES - 256 * 4 * 16 * 2.4e9 / 4.5) <= 1e-6 * bench.PEAK_UPDATES
+
+
+def _record(h, nbytes):
+    return "traffic-json: " + json.dumps({
+        "workload": "single-roi-1024", "kernel": "bp_kernel", "kernel_source_sha256": h,
+        "bytes_per_launch": nbytes})
+
+
+def test_traffic_record_needs_the_current_kernel_source(tmp_path, monkeypatch):
+    src = tmp_path / "kernels.hip"
+    src.write_text("// kernel source\n")
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+    monkeypatch.setattr(bench, "PROFILES", str(prof))
+    h = bench.kernel_source_hash()
+    (prof / "bp.md").write_text("# summary\n\n" + _record("0" * 16, 111) + "\n" +
+                                _record(h, 2315898) + "\n")
+    assert bench.profiled_traffic("single-roi-1024", "bp_kernel") == 2315898
+    assert bench.profiled_traffic("single-roi-1024", "fp_kernel") is None
+    # any edit of the kernel source voids the record
+    src.write_text("// kernel source, changed\n")
+    assert bench.profiled_traffic("single-roi-1024", "bp_kernel") is None
