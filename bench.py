@@ -476,6 +476,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests per serving load point (the survey's full run uses 2000)")
     ap.add_argument("--serve-warmup", type=int, default=64)
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the untimed quality comparison of the single-ROI leg "
+                         "(global solve, Alg. 2 and FBP against the phantom)")
     ap.add_argument("--only", choices=["batch", "serve", "local"], default=None,
                     help="run only one secondary leg (for profiling) and print its JSON")
     ap.add_argument("--iters", type=int, default=None,
@@ -618,44 +621,45 @@ def main():
     # quality, not timed: the ROI of the global TV solve on the whole 1024^2 grid (same
     # lambda and iterations, no exterior), and the local, global and FBP results against
     # the phantom inside the ROI
-    n = cfg["n"]
-    gout = torch.empty((n, n), dtype=torch.float32, device="cuda")
-    gprm = make_params((0, 0, n, n), 0, "cp", cfg["lam"], cfg["iters"])
-    ctx.roi_solve(g, sino, gprm, gout)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.roi_solve(g, sino, gprm, gout)
-    torch.cuda.synchronize()
-    t_glob = time.perf_counter() - t0
-    fbp = torch.empty((n, n), dtype=torch.float32, device="cuda")
-    ctx.tomo_fbp_ramlak(g, sino, fbp)
-    torch.cuda.synchronize()
-    loc = out.double().cpu().numpy()
-    glob = gout.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
-    fbp_r = fbp.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
-    truth = d["image"][r0:r0 + rr, c0:c0 + cc]
-    # the paper's own local method on the same ROI (Alg. 1 filters, Alg. 2, box [0, inf),
-    # as many iterations as the CP solve)
-    its = cfg["iters"]
-    F = torch.empty((its, cfg["n_angles"], cfg["n_det"]), dtype=torch.float32, device="cuda")
-    D = torch.empty_like(F)
-    ctx.tomo_sirt_filters(g, its, F)
-    ctx.tomo_sirt_filter_sino(g, F, sino, D)
-    alg2 = torch.empty((rr, cc), dtype=torch.float32, device="cuda")
-    ctx.roi_solve_local(g, D, [make_params(roi, margin, "local", iters=its,
-                                           box=(0.0, float("inf")))], [alg2])
-    torch.cuda.synchronize()
-    alg2 = alg2.double().cpu().numpy()
-    del F, D
-    relq = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
-    res["quality"] = {"local_vs_global_rel": relq(loc, glob), "local_vs_phantom_rel": relq(loc, truth),
-                      "global_vs_phantom_rel": relq(glob, truth),
-                      "fbp_vs_phantom_rel": relq(fbp_r, truth),
-                      "alg2_vs_phantom_rel": relq(alg2, truth), "global_solve_ms": 1e3 * t_glob}
-    log(f"quality: local vs global {res['quality']['local_vs_global_rel']:.3e}; vs phantom: local "
-        f"{res['quality']['local_vs_phantom_rel']:.3e}, global {res['quality']['global_vs_phantom_rel']:.3e}"
-        f", FBP {res['quality']['fbp_vs_phantom_rel']:.3e}, Alg. 2 "
-        f"{res['quality']['alg2_vs_phantom_rel']:.3e}; global solve {1e3 * t_glob:.1f} ms")
+    if not args.no_quality:
+        n = cfg["n"]
+        gout = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        gprm = make_params((0, 0, n, n), 0, "cp", cfg["lam"], cfg["iters"])
+        ctx.roi_solve(g, sino, gprm, gout)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.roi_solve(g, sino, gprm, gout)
+        torch.cuda.synchronize()
+        t_glob = time.perf_counter() - t0
+        fbp = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        ctx.tomo_fbp_ramlak(g, sino, fbp)
+        torch.cuda.synchronize()
+        loc = out.double().cpu().numpy()
+        glob = gout.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
+        fbp_r = fbp.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
+        truth = d["image"][r0:r0 + rr, c0:c0 + cc]
+        # the paper's own local method on the same ROI (Alg. 1 filters, Alg. 2, box [0, inf),
+        # as many iterations as the CP solve)
+        its = cfg["iters"]
+        F = torch.empty((its, cfg["n_angles"], cfg["n_det"]), dtype=torch.float32, device="cuda")
+        D = torch.empty_like(F)
+        ctx.tomo_sirt_filters(g, its, F)
+        ctx.tomo_sirt_filter_sino(g, F, sino, D)
+        alg2 = torch.empty((rr, cc), dtype=torch.float32, device="cuda")
+        ctx.roi_solve_local(g, D, [make_params(roi, margin, "local", iters=its,
+                                               box=(0.0, float("inf")))], [alg2])
+        torch.cuda.synchronize()
+        alg2 = alg2.double().cpu().numpy()
+        del F, D
+        relq = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        res["quality"] = {"local_vs_global_rel": relq(loc, glob), "local_vs_phantom_rel": relq(loc, truth),
+                          "global_vs_phantom_rel": relq(glob, truth),
+                          "fbp_vs_phantom_rel": relq(fbp_r, truth),
+                          "alg2_vs_phantom_rel": relq(alg2, truth), "global_solve_ms": 1e3 * t_glob}
+        log(f"quality: local vs global {res['quality']['local_vs_global_rel']:.3e}; vs phantom: local "
+            f"{res['quality']['local_vs_phantom_rel']:.3e}, global {res['quality']['global_vs_phantom_rel']:.3e}"
+            f", FBP {res['quality']['fbp_vs_phantom_rel']:.3e}, Alg. 2 "
+            f"{res['quality']['alg2_vs_phantom_rel']:.3e}; global solve {1e3 * t_glob:.1f} ms")
     ctx.close()
     if not args.skip_batch:
         try:
