@@ -65,7 +65,13 @@ def test_sirt_filters_match_oracle(ctx, n, na, nd, K):
 
 
 @pytest.mark.parametrize("n,na,nd,count,offset", [
-    (128, 32, 192, 7, 0.0),      # L = 512 (odd log2: one radix-2 stage), odd filter count
+    # L >= 512: radix-16 stages plus one radix-2 / 4 / 8 stage (none when log2 L is a
+    # multiple of 4); below, radix-4 stages plus one radix-2 stage
+    (128, 32, 192, 7, 0.0),      # L = 512 (radix 2 + 16 + 16), odd filter count
+    (64, 5, 300, 3, 0.0),        # L = 1024 (radix 4 + 16 + 16)
+    (64, 5, 700, 3, 25.0),       # L = 2048 (radix 8 + 16 + 16), detector offset
+    (64, 4, 1536, 2, 0.0),       # L = 4096 (radix 16 x 3)
+    (40, 4, 1100, 1, 900.0),     # L = 4096, impulse projects off the detector
     (65, 24, 97, 4, 0.0),        # L = 256
     (65, 24, 97, 3, 60.0),       # impulse projects off the detector: lag beyond the rows
     (64, 6, 3072, 2, 0.0),       # L = 8192
