@@ -8,6 +8,7 @@ the GPU after the same number of iterations.
 """
 
 import os
+import time
 import subprocess
 import sys
 
@@ -73,6 +74,11 @@ def test_batched_workload_sampled_parity(ctx, name, tmp_path_factory):
     print(f"[batch {name}] solving {len(rois)} ROIs in one batch", flush=True)
     ctx.roi_solve_batch(g, sino, params, outs)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()   # again, with the step sizes cached (reported, not checked)
+    ctx.roi_solve_batch(g, sino, params, outs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"    one batch of {len(rois)} ROI solves: {1e3 * t_batch:.1f} ms", flush=True)
     for i in sorted(sampled):
         assert tuple(gold[f"rect_{i}"][:4]) == tuple(rois[i][:4])
         e = rel(outs[i].double().cpu().numpy(), gold[f"x_{i}"])
@@ -93,8 +99,14 @@ def test_batched_workload_sampled_parity(ctx, name, tmp_path_factory):
         # against which the stitched tiles are compared
         n = cfg["n"]
         glob = torch.empty((n, n), dtype=torch.float32, device="cuda")
-        ctx.roi_solve(g, sino, make_params((0, 0, n, n), 0, "cp", cfg["lam"], cfg["iters"]), glob)
+        gprm = make_params((0, 0, n, n), 0, "cp", cfg["lam"], cfg["iters"])
+        ctx.roi_solve(g, sino, gprm, glob)
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.roi_solve(g, sino, gprm, glob)
+        torch.cuda.synchronize()
+        print(f"    global solve of the whole slice: {1e3 * (time.perf_counter() - t0):.1f} ms",
+              flush=True)
         e = float(torch.linalg.norm(full - glob) / torch.linalg.norm(glob))
         # data fit of both after the same iteration count: ||W x - p|| / ||p||
         fit = []
