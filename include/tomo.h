@@ -306,7 +306,8 @@ tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
 /* Kernel launch shape of the two projector kernels.  Every field 0 = choose
  * automatically (from an autotuned entry for the problem's shape class when
  * tomo_autotune has measured one, else from the problem size).
- *   fp_segments           forward projector: waves per ray, 1, 2 or 4
+ *   fp_segments           forward projector: waves per ray, 1, 2, 4 or 8 (8: blocks
+ *                         of 8 waves, one group of 64 rays each)
  *   fp_rays_per_lane      1, or 2 (with one segment): each lane projects two
  *                         adjacent rays from 4-pixel reads (detector spacing
  *                         below sqrt 2 pixels; otherwise 1 is used)

@@ -42,7 +42,7 @@ LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long tot
     // Split rays / pixels across more waves while the whole problem is too small
     // to fill 256 CUs with at least ~8 waves each.
     const long long want = 256LL * 8 * 64;
-    L.seg = total_rays >= 4 * want ? 1 : (total_rays >= 2 * want ? 2 : 4);
+    L.seg = total_rays >= 4 * want ? 1 : total_rays >= 2 * want ? 2 : total_rays >= want / 2 ? 4 : 8;
     L.ag = total_pixels >= 4 * want ? 1 : (total_pixels >= 2 * want ? 2 : 4);
     // two pixels per thread share the per-angle position work once the problem
     // is large enough that halving the thread count still fills the chip
@@ -166,9 +166,12 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
 }
 
 // Items of the forward projector for job `jj` with tables `afp`.
+// rays per forward-projector block: 4 waves (SEG waves when SEG > 4), SEG per ray group
+static int fp_rays_per_block(int seg, int rp) { return (seg > 4 ? 64 * seg : 256) * rp / seg; }
+
 void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg, int rp,
               const AngFP* d_afp) {
-    const int rpb = 256 * rp / seg;
+    const int rpb = fp_rays_per_block(seg, rp);
     for (int k = 0; k < (int)afp.size(); ++k) {
         const int nch = (afp[k].w + rpb - 1) / rpb;
         for (int ch = 0; ch < nch; ++ch) out.push_back(Item{jj, k, ch, 0, d_afp + k, 0});
@@ -176,7 +179,7 @@ void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int
 }
 
 size_t count_fp_items(const std::vector<AngFP>& afp, int seg, int rp) {
-    const int rpb = 256 * rp / seg;
+    const int rpb = fp_rays_per_block(seg, rp);
     size_t n = 0;
     for (const AngFP& a : afp) n += (size_t)((a.w + rpb - 1) / rpb);
     return n;
@@ -1347,7 +1350,7 @@ tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const 
     // (timing mode 2: 50 back-to-back launches in a graph between two events).
     std::vector<tomo_launch> fpc, bpc;
     for (int xo = 1; xo <= 2; ++xo)
-        for (int sg : {1, 2, 4})
+        for (int sg : {1, 2, 4, 8})
             for (int rp = 1; rp <= (sg == 1 ? 2 : 1); ++rp) {
                 tomo_launch k{};
                 k.fp_segments = sg;
@@ -1491,11 +1494,11 @@ tomo_status tomo_set_launch(tomo_ctx* ctx, const tomo_launch* cfg) {
     if (cfg) k = *cfg;
     auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
     auto in012 = [](int v) { return v >= 0 && v <= 2; };
-    if (!ok(k.fp_segments) || !ok(k.bp_groups) || !in012(k.bp_pixels_per_thread) ||
-        !in012(k.fp_rays_per_lane) ||
+    if (!(ok(k.fp_segments) || k.fp_segments == 8) || !ok(k.bp_groups) ||
+        !in012(k.bp_pixels_per_thread) || !in012(k.fp_rays_per_lane) ||
         !in012(k.bp_variant) || !in012(k.fp_xcd_order) || !in012(k.bp_xcd_order))
-        return fail(ctx, TOMO_EINVAL, "launch knobs: segments/groups in {0,1,2,4}, pixels in "
-                    "{0,1,2}, variant and xcd order in {0,1,2}");
+        return fail(ctx, TOMO_EINVAL, "launch knobs: segments in {0,1,2,4,8}, groups in "
+                    "{0,1,2,4}, pixels in {0,1,2}, variant and xcd order in {0,1,2}");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     ctx->knobs = k;
     return TOMO_OK;

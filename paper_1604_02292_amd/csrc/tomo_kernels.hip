@@ -103,19 +103,22 @@ __device__ __forceinline__ v4f load4(__amdgpu_buffer_rsrc_t rs, unsigned voff, u
 }
 
 // ---------------------------------------------------------------------------
-// Forward projection.  One block = one angle of one job and 256/SEG rays;
-// each ray is split into SEG consecutive segments of outer lines (rows, or
-// columns for |sin| > |cos|) handled by different waves and summed in a fixed
-// order.  A wave's 64 lanes are 64 adjacent rays, so at every outer line they
+// Forward projection.  One block = one angle of one job and 64 * max(4, SEG) / SEG
+// rays (4 waves, or SEG waves when SEG > 4); each ray is split into SEG consecutive
+// segments of outer lines (rows, or columns for |sin| > |cos|) handled by different
+// waves and summed in a fixed order.  A wave's 64 lanes are 64 adjacent rays, so at every outer line they
 // read nearly contiguous pixels of one image row (the transposed copy of the
 // image serves the column-stepping angles, keeping those reads contiguous).
 // ---------------------------------------------------------------------------
+template <int SEG>
+constexpr int fp_threads() { return SEG > 4 ? 64 * SEG : 256; }
+
 template <int SEG, int RP>
-__global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
+__global__ __launch_bounds__(fp_threads<SEG>()) void fp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
                                                  int step, int contiguous) {
-    constexpr int SUBS = 4 / SEG;
-    __shared__ float red[SEG > 1 ? RP * 256 : 1];
+    constexpr int NT = fp_threads<SEG>(), SUBS = NT / 64 / SEG;
+    __shared__ float red[SEG > 1 ? RP * NT : 1];
     const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
     if (bid >= n_items) return;
     const Item it = cview(items)[bid];
@@ -350,14 +353,14 @@ __global__ __launch_bounds__(256) void fp_kernel(const Job* __restrict__ jobs,
     }
     if (SEG > 1) {
 #pragma unroll
-        for (int r = 0; r < RP; ++r) red[r * 256 + threadIdx.x] = acc[r];
+        for (int r = 0; r < RP; ++r) red[r * NT + threadIdx.x] = acc[r];
         __syncthreads();
         if (seg != 0) return;
 #pragma unroll
         for (int r = 0; r < RP; ++r) {
             acc[r] = 0.f;
 #pragma unroll
-            for (int q = 0; q < SEG; ++q) acc[r] += red[r * 256 + (sub * SEG + q) * 64 + lane];
+            for (int q = 0; q < SEG; ++q) acc[r] += red[r * NT + (sub * SEG + q) * 64 + lane];
         }
     }
 
@@ -2008,15 +2011,17 @@ inline unsigned pad8(int n) { return (unsigned)((n + 7) & ~7); }
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
                      hipStream_t s, int contiguous, int rays_per_lane) {
     if (n_items <= 0) return hipSuccess;
-    const dim3 grid(pad8(n_items)), block(256);
-#define TOMO_FP(SG, R) \
-    hipLaunchKernelGGL((fp_kernel<SG, R>), grid, block, 0, s, jobs, items, n_items, step, contiguous)
+    const dim3 grid(pad8(n_items));
+#define TOMO_FP(SG, R)                                                                 \
+    hipLaunchKernelGGL((fp_kernel<SG, R>), grid, dim3(fp_threads<SG>()), 0, s, jobs, items, \
+                       n_items, step, contiguous)
     if (rays_per_lane == 2) {   // one segment per ray
         TOMO_FP(1, 2);
     } else {
         switch (segments) {
             case 1: TOMO_FP(1, 1); break;
             case 2: TOMO_FP(2, 1); break;
+            case 8: TOMO_FP(8, 1); break;
             default: TOMO_FP(4, 1); break;
         }
     }

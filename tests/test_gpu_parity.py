@@ -108,7 +108,7 @@ def test_every_launch_shape_matches_oracle(ctx, gname, rect):
     ref_fp = oracle.fp_ray(geo, img.astype(np.float64), rect)
     ref_bp = oracle.bp_pixel(geo, y.astype(np.float64), rect)
     try:
-        for seg in (1, 2, 4):
+        for seg in (1, 2, 4, 8):
             for xo in (1, 2):
                 ctx.tomo_set_launch(fp_segments=seg, fp_xcd_order=xo)
                 sino = torch.empty((na, nd), dtype=torch.float32, device="cuda")
@@ -148,7 +148,7 @@ def test_autotune_picks_a_valid_shape(ctx):
     scratch = [torch.empty_like(o) for o in before]
     best, fp_ms, bp_ms = ctx.tomo_autotune(g, sino, params, scratch)
     say(f"    tuned {best} fp {fp_ms * 1e3:.1f} us bp {bp_ms * 1e3:.1f} us")
-    assert best["fp_segments"] in (1, 2, 4) and best["fp_xcd_order"] in (1, 2)
+    assert best["fp_segments"] in (1, 2, 4, 8) and best["fp_xcd_order"] in (1, 2)
     assert best["bp_variant"] in (1, 2) and best["bp_pixels_per_thread"] in (1, 2)
     assert best["bp_groups"] in (1, 2, 4) and best["bp_xcd_order"] in (1, 2)
     assert 0 < fp_ms < 10 and 0 < bp_ms < 10
