@@ -316,8 +316,9 @@ tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
  *                         item list per XCD (L2 locality), 2 = round-robin
  *   bp_variant            backprojector: 1 = direct band reads from memory,
  *                         2 = band windows staged in LDS per block of angles
- *   bp_groups             backprojector angle groups per pixel, 1, 2 or 4
- *                         (variant 2 always uses 1)
+ *   bp_groups             backprojector angle groups per pixel, 1, 2, 4 or 8
+ *                         (8: blocks of 8 waves; variant 2 always uses 1, and the
+ *                         two-channel bands of the local method use 4 for 8)
  *   bp_pixels_per_thread  1 or 2
  *   bp_xcd_order          as fp_xcd_order, for the backprojector
  * Results agree to FP32 rounding across shapes; the two variants give

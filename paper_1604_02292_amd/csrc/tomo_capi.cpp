@@ -19,8 +19,8 @@ namespace tomo {
 static constexpr int kPowerIters = 50;
 
 void bp_tile(int ag, int ppt, int* th, int* tw) {
-    const int P = 256 / ag;
-    *tw = (ag == 4) ? 8 : 16;
+    const int P = (ag > 4 ? 64 * ag : 256) / ag;   // threads per angle group
+    *tw = (ag >= 4) ? 8 : 16;
     *th = (P / *tw) * ppt;
 }
 
@@ -43,7 +43,7 @@ LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long tot
     // to fill 256 CUs with at least ~8 waves each.
     const long long want = 256LL * 8 * 64;
     L.seg = total_rays >= 4 * want ? 1 : total_rays >= 2 * want ? 2 : total_rays >= want / 2 ? 4 : 8;
-    L.ag = total_pixels >= 4 * want ? 1 : (total_pixels >= 2 * want ? 2 : 4);
+    L.ag = total_pixels >= 4 * want ? 1 : total_pixels >= 2 * want ? 2 : total_pixels >= want / 2 ? 4 : 8;
     // two pixels per thread share the per-angle position work once the problem
     // is large enough that halving the thread count still fills the chip
     L.ppt = total_pixels >= 8 * want ? 2 : 1;
@@ -1366,7 +1366,7 @@ tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const 
             k.bp_pixels_per_thread = pp;
             k.bp_xcd_order = xo;
             bpc.push_back(k);
-            for (int ag : {1, 2, 4}) {
+            for (int ag : {1, 2, 4, 8}) {
                 k.bp_variant = 1;
                 k.bp_groups = ag;
                 bpc.push_back(k);
@@ -1494,11 +1494,11 @@ tomo_status tomo_set_launch(tomo_ctx* ctx, const tomo_launch* cfg) {
     if (cfg) k = *cfg;
     auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
     auto in012 = [](int v) { return v >= 0 && v <= 2; };
-    if (!(ok(k.fp_segments) || k.fp_segments == 8) || !ok(k.bp_groups) ||
+    if (!(ok(k.fp_segments) || k.fp_segments == 8) || !(ok(k.bp_groups) || k.bp_groups == 8) ||
         !in012(k.bp_pixels_per_thread) || !in012(k.fp_rays_per_lane) ||
         !in012(k.bp_variant) || !in012(k.fp_xcd_order) || !in012(k.bp_xcd_order))
-        return fail(ctx, TOMO_EINVAL, "launch knobs: segments in {0,1,2,4,8}, groups in "
-                    "{0,1,2,4}, pixels in {0,1,2}, variant and xcd order in {0,1,2}");
+        return fail(ctx, TOMO_EINVAL, "launch knobs: segments and groups in {0,1,2,4,8}, "
+                    "pixels in {0,1,2}, variant and xcd order in {0,1,2}");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     ctx->knobs = k;
     return TOMO_OK;

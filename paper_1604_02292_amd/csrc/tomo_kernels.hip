@@ -430,18 +430,22 @@ __global__ __launch_bounds__(fp_threads<SEG>()) void fp_kernel(const Job* __rest
 // see half-updated values), takes its divergence, then applies the primal
 // prox and the extrapolation to its own pixels.
 // ---------------------------------------------------------------------------
+template <int AG>
+constexpr int bp_threads() { return AG > 4 ? 64 * AG : 256; }
+
 template <int AG, int PPT, bool STAGED, bool COMP, bool TWO>
-__global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
+__global__ __launch_bounds__(bp_threads<AG>()) void bp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
                                                  int step, int contiguous) {
-    constexpr int P = 256 / AG;              // threads per angle group (a multiple of 64)
-    constexpr int TW = (AG == 4) ? 8 : 16;
+    constexpr int NT = bp_threads<AG>();     // 4 waves, or one wave per group beyond 4
+    constexpr int P = NT / AG;               // threads per angle group (a multiple of 64)
+    constexpr int TW = (AG >= 4) ? 8 : 16;
     constexpr int TH = (P / TW) * PPT;       // pixel rows of the tile
     __shared__ float xs[TH + 2][TW + 2];
     __shared__ float zs0[TH + 1][TW + 1];
     __shared__ float zs1[TH + 1][TW + 1];
-    __shared__ float red[PPT][AG > 1 ? 256 : 1];   // group partial sums (and the power sums)
-    __shared__ float red2[PPT][(AG > 1 && TWO) ? 256 : 1];   // second channel's partial sums
+    __shared__ float red[PPT][AG > 1 ? NT : 1];   // group partial sums (and the power sums)
+    __shared__ float red2[PPT][(AG > 1 && TWO) ? NT : 1];   // second channel's partial sums
     static_assert(!TWO || !COMP, "two-channel bands are not compensated");
     constexpr int CH = TWO ? 2 : 1;   // floats per band entry
     // Per-angle anchors of the tile, ANC per pass (AG groups x PA angles).
@@ -491,7 +495,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     const CONST_AS AngBP* tab = cview((const AngBP*)it.tab);
     const int npass = ((na + AG - 1) / AG + PA - 1) / PA;
     auto fill_anchors = [&](int pass) {
-        for (int e = t; e < ANC; e += 256) {
+        for (int e = t; e < ANC; e += NT) {
             const int gg = e / PA;
             const int kk = (na * gg) / AG + pass * PA + e % PA;
             if (kk < (na * (gg + 1)) / AG) {
@@ -517,7 +521,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         if (inside[q] && (mode == BP_LOCAL || mode == BP_FISTA))   // correction v (padded)
             xo[q] = J->xb[rpar][(size_t)(R0 + tr + q) * J->xp + c + kLpad];
     }
-    constexpr int NZ = ((TH + 1) * (TW + 1) + 255) / 256;
+    constexpr int NZ = ((TH + 1) * (TW + 1) + NT - 1) / NT;
     float zq0[NZ], zq1[NZ];
     float divv[PPT], zn0[PPT], zn1[PPT];
 #pragma unroll
@@ -529,7 +533,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         gcfloat* zo = gview(J->z[rpar]);
 #pragma unroll
         for (int u = 0; u < NZ; ++u) {
-            const int q = t + 256 * u;
+            const int q = t + NT * u;
             const int lr = q / (TW + 1), lc = q % (TW + 1);
             const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
             zq0[u] = 0.f;
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
                 zq1[u] = zo[plane + zi];
             }
         }
-        for (int q = t; q < (TH + 2) * (TW + 2); q += 256) {
+        for (int q = t; q < (TH + 2) * (TW + 2); q += NT) {
             const int lr = q / (TW + 2), lc = q % (TW + 2);
             const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
             float v = 0.f;
@@ -553,7 +557,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
         const int aniso = J->flags & JF_ANISO;
 #pragma unroll
         for (int u = 0; u < NZ; ++u) {
-            const int q = t + 256 * u;
+            const int q = t + NT * u;
             if (q >= (TH + 1) * (TW + 1)) break;
             const int lr = q / (TW + 1), lc = q % (TW + 1);
             const int rr = R0 - 1 + lr, cc = C0 - 1 + lc;
@@ -991,12 +995,12 @@ __global__ __launch_bounds__(256) void bp_kernel(const Job* __restrict__ jobs,
     }
     if (mode == BP_POWER) {
         // block sum of the squares, in the anchor table's LDS (no longer needed)
-        static_assert(sizeof(anc) >= 256 * sizeof(float), "anchor table too small to reuse");
+        static_assert(sizeof(anc) >= NT * sizeof(float), "anchor table too small to reuse");
         float* psum = (float*)anc;
         __syncthreads();
         psum[t] = sq;
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
+        for (int h = NT / 2; h > 0; h >>= 1) {
             if (t < h) psum[t] += psum[t + h];
             __syncthreads();
         }
@@ -2033,10 +2037,10 @@ hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, 
                      int ppt, hipStream_t s, int contiguous, int staged, int compensated,
                      int two_channel) {
     if (n_items <= 0) return hipSuccess;
-    const dim3 grid(pad8(n_items)), block(256);
-#define TOMO_BP_T(AGV, PPTV, ST, CO, TW)                                                    \
-    hipLaunchKernelGGL((bp_kernel<AGV, PPTV, ST, CO, TW>), grid, block, 0, s, jobs, items, \
-                       n_items, step, contiguous)
+    const dim3 grid(pad8(n_items));
+#define TOMO_BP_T(AGV, PPTV, ST, CO, TW)                                                   \
+    hipLaunchKernelGGL((bp_kernel<AGV, PPTV, ST, CO, TW>), grid, dim3(bp_threads<AGV>()), 0, \
+                       s, jobs, items, n_items, step, contiguous)
 #define TOMO_BP(AGV, PPTV, ST, CO) TOMO_BP_T(AGV, PPTV, ST, CO, false)
     if (two_channel && staged) {   // (g, d) pairs staged in LDS
         if (ppt == 2) TOMO_BP_T(1, 2, true, false, true);
@@ -2064,12 +2068,14 @@ hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, 
         switch (groups) {
             case 1: TOMO_BP(1, 2, false, false); break;
             case 2: TOMO_BP(2, 2, false, false); break;
+            case 8: TOMO_BP(8, 2, false, false); break;
             default: TOMO_BP(4, 2, false, false); break;
         }
     } else {
         switch (groups) {
             case 1: TOMO_BP(1, 1, false, false); break;
             case 2: TOMO_BP(2, 1, false, false); break;
+            case 8: TOMO_BP(8, 1, false, false); break;
             default: TOMO_BP(4, 1, false, false); break;
         }
     }

@@ -88,7 +88,7 @@ def test_fp_bp_parity(ctx, gname, rect):
     assert abs(lhs - rhs) <= PROJ_TOL * abs(lhs)
 
 
-SHAPES_BP = [dict(bp_variant=1, bp_groups=a, bp_pixels_per_thread=q) for a in (1, 2, 4)
+SHAPES_BP = [dict(bp_variant=1, bp_groups=a, bp_pixels_per_thread=q) for a in (1, 2, 4, 8)
              for q in (1, 2)] + [dict(bp_variant=2, bp_pixels_per_thread=q) for q in (1, 2)]
 
 
@@ -150,7 +150,7 @@ def test_autotune_picks_a_valid_shape(ctx):
     say(f"    tuned {best} fp {fp_ms * 1e3:.1f} us bp {bp_ms * 1e3:.1f} us")
     assert best["fp_segments"] in (1, 2, 4, 8) and best["fp_xcd_order"] in (1, 2)
     assert best["bp_variant"] in (1, 2) and best["bp_pixels_per_thread"] in (1, 2)
-    assert best["bp_groups"] in (1, 2, 4) and best["bp_xcd_order"] in (1, 2)
+    assert best["bp_groups"] in (1, 2, 4, 8) and best["bp_xcd_order"] in (1, 2)
     assert 0 < fp_ms < 10 and 0 < bp_ms < 10
     assert ctx.tomo_resolve_launch(g, params) == best
     after = [torch.empty_like(o) for o in before]
