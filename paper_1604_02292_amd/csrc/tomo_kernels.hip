@@ -422,9 +422,9 @@ __global__ __launch_bounds__(fp_threads<SEG>()) void fp_kernel(const Job* __rest
 
 // ---------------------------------------------------------------------------
 // Backprojection (pixel-driven gather: no atomics, bit-reproducible).  One
-// block = one tile of 256/AG threads of one job, each thread owning PPT
-// vertically adjacent pixels; each pixel's angles are split into AG contiguous
-// groups summed in a fixed order.  For the CP mode the block first computes
+// block = one tile of 256/AG threads of one job (64 when AG = 8: 8-wave
+// blocks), each thread owning PPT vertically adjacent pixels; each pixel's
+// angles are split into AG contiguous groups summed in a fixed order.  For the CP mode the block first computes
 // the TV dual update on its tile plus a one-pixel top/left halo (from the
 // previous xbar and z, which are double-buffered so neighbouring tiles never
 // see half-updated values), takes its divergence, then applies the primal
@@ -1720,7 +1720,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void filter_conv_kernel(
 }
 
 // The same convolution for L >= 512 with radix-16 stages (one radix-2, 4 or 8 stage
-// covers the remaining bits): four LDS passes per transform instead of seven.  The
+// covers the remaining bits): at L = 8192 four passes per transform instead of seven.  The
 // forward transform's first stage reads the filter rows straight from global memory;
 // its last stage, the product with the data spectrum and the inverse transform's first
 // stage run on the same registers (the last stage of a self-sorting transform leaves

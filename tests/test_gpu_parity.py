@@ -93,7 +93,8 @@ SHAPES_BP = [dict(bp_variant=1, bp_groups=a, bp_pixels_per_thread=q) for a in (1
 
 
 @pytest.mark.parametrize("gname,rect", [("c1", (0, 100, 40, 28)), ("c2", (416, 416, 192, 192)),
-                                        ("c4", (1000, 37, 300, 261)), ("odd", (3, 5, 31, 77))])
+                                        ("c4", (1000, 37, 300, 261)), ("odd", (3, 5, 31, 77)),
+                                        ("odd", (96, 0, 1, 1)), ("c1", (0, 127, 128, 1))])
 def test_every_launch_shape_matches_oracle(ctx, gname, rect):
     """Every forward-projector and backprojector launch shape (segments, XCD
     order, direct or LDS-staged band reads, groups, pixels per thread) agrees
