@@ -9,7 +9,7 @@ iterations (TV lambda = 0.02 + nonnegativity), crop.  The sinogram is resident
 in HBM before timing starts.  The CP step size is a per-(geometry, shape)
 plan computed once by a power iteration and cached, like an FFT plan.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the benchmark runs on one GPU.
 """
 
 import argparse
@@ -507,7 +507,7 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "ROI solves are independent and would be sharded across GPUs without "
               "per-iteration communication, but no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
