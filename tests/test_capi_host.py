@@ -102,3 +102,33 @@ def test_nnz_count_matches_oracle(n, na, nd, rect):
     g = ctx.tomo_set_geometry(n, na, nd)
     WL = oracle.sparse_local(oracle.make_geometry(n, na, nd), rect)
     assert ctx.tomo_roi_nnz(g, rect) == WL.nnz
+
+
+def test_launch_shapes_by_problem_size():
+    """The size heuristics: a single small region (the 1024^2 workload's 192^2 extended ROI,
+    128 angles: 35 k rays, 37 k pixels) gets the most waves per ray and per pixel (8
+    forward-projector segments, 8 backprojector angle groups, direct band reads); the
+    64-ROI batch on 2048^2 gets one segment with two rays per lane and the LDS-staged
+    backprojector with two pixels per thread.  Forced knobs are validated and kept."""
+    import synth
+    from paper_1604_02292_amd.tomo import make_params
+    ctx = Context(device=-1)
+    g = ctx.tomo_set_geometry(1024, 128, 1536)
+    small = ctx.tomo_resolve_launch(g, [make_params((448, 448, 128, 128), 32, "cp", 0.02, 300)])
+    assert (small["fp_segments"], small["fp_rays_per_lane"]) == (8, 1)
+    assert (small["bp_variant"], small["bp_groups"], small["bp_pixels_per_thread"]) == (1, 8, 1)
+    g3 = ctx.tomo_set_geometry(2048, 256, 3072)
+    batch = [make_params(r[:4], r[4], "cp", 0.02, 200) for r in synth.roi_list("c3")]
+    big = ctx.tomo_resolve_launch(g3, batch)
+    assert (big["fp_segments"], big["fp_rays_per_lane"]) == (1, 2)
+    assert (big["bp_variant"], big["bp_groups"], big["bp_pixels_per_thread"]) == (2, 1, 2)
+    ctx.tomo_set_launch(fp_segments=4, bp_groups=2)
+    forced = ctx.tomo_resolve_launch(g, [make_params((448, 448, 128, 128), 32, "cp", 0.02, 300)])
+    assert (forced["fp_segments"], forced["bp_groups"]) == (4, 2)
+    for bad in [dict(fp_segments=3), dict(fp_segments=16), dict(bp_groups=16),
+                dict(bp_pixels_per_thread=3), dict(bp_variant=5)]:
+        with pytest.raises(TomoError) as e:
+            ctx.tomo_set_launch(**bad)
+        assert e.value.status == _lib.TOMO_EINVAL
+    assert ctx.tomo_get_launch()["fp_segments"] == 4   # a rejected call changes nothing
+    ctx.tomo_set_launch()
