@@ -146,21 +146,38 @@ tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s) {
 
 namespace {
 
-// Prepare one admitted slot on the scheduler stream: tables, b = r + W_L x_ext|L,
-// step size, zeroed state.
-tomo_status prepare_slot(tomo_ctx* ctx, ServeState& S, Slot& sl) {
+// A slot's device tables (angle tables, and the job and items of its exterior
+// subtraction), laid out for one upload.
+struct SlotTables {
+    Meta m;
+    size_t o_afp = 0, o_abp = 0, o_job = 0, o_it = 0;
+};
+
+void slot_tables(const RoiState& r, SlotTables& T) {
+    T.o_afp = T.m.add(r.plan.afp.data(), r.plan.afp.size() * sizeof(AngFP));
+    T.o_abp = T.m.add(r.plan.abp.data(), r.plan.abp.size() * sizeof(AngBP));
+    T.o_job = T.m.reserve(sizeof(Job));
+    T.o_it = T.m.reserve(count_fp_items(r.plan.afp, kServeSeg, 1) * sizeof(Item));
+}
+
+// A slot's share of the batch lists (its job, forward and backprojector items,
+// and the alignment of the three arrays).
+size_t slot_list_bytes(const RoiState& r) {
+    return sizeof(Job) + 3 * 64 +
+           (count_fp_items(r.plan.afp, kServeSeg, 1) +
+            count_bp_items(r.ext.rows, r.ext.cols, kServeAG, kServePPT)) *
+               sizeof(Item);
+}
+
+// Prepare one admitted slot on the scheduler stream: tables (uploaded into `dm`,
+// allocated at admission), b = r + W_L x_ext|L, step size, zeroed state.
+tomo_status prepare_slot(tomo_ctx* ctx, ServeState& S, Slot& sl, SlotTables& T, char* dm) {
     const Geom& g = ctx->geoms[sl.sino->gid];
     RoiState& r = sl.st;
     hipStream_t s = S.stream;
-    Meta m;
-    const size_t o_afp = m.add(r.plan.afp.data(), r.plan.afp.size() * sizeof(AngFP));
-    const size_t o_abp = m.add(r.plan.abp.data(), r.plan.abp.size() * sizeof(AngBP));
-    const size_t o_job = m.reserve(sizeof(Job));
+    Meta& m = T.m;
+    const size_t o_afp = T.o_afp, o_abp = T.o_abp, o_job = T.o_job, o_it = T.o_it;
     std::vector<Item> items;
-    const size_t o_it = m.reserve(count_fp_items(r.plan.afp, kServeSeg, 1) * sizeof(Item));
-    char* dm = ctx->arena.alloc(m.buf.size(), false);
-    if (!dm) return fail(ctx, TOMO_ENOMEM, "workspace full");
-    sl.allocs.push_back(dm);
     r.d_afp = (AngFP*)(dm + o_afp);
     r.d_abp = (AngBP*)(dm + o_abp);
     fp_items(items, 0, r.plan.afp, kServeSeg, 1, r.d_afp);
@@ -198,6 +215,7 @@ void scheduler(tomo_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     std::vector<std::unique_ptr<Slot>> slots;
     char* d_lists = nullptr;
+    size_t list_bytes = 0;   // the admitted slots' shares of the batch lists
     const Job* d_jobs = nullptr;
     const Item* d_fi = nullptr;
     const Item* d_bi = nullptr;
@@ -253,14 +271,35 @@ void scheduler(tomo_ctx* ctx) {
             const size_t scratch = step_size_scratch_bytes(ctx, sl->sino->gid, r);
             char* blk = ctx->arena.alloc(state_bytes(g, r.plan), false);
             if (!blk && slots.empty()) blk = ctx->arena.alloc(state_bytes(g, r.plan), true);
+            SlotTables T;
+            slot_tables(r, T);
+            char* tab = nullptr;
+            if (blk) {
+                tab = ctx->arena.alloc(T.m.buf.size(), false);
+                if (!tab && slots.empty()) tab = ctx->arena.alloc(T.m.buf.size(), true);
+                if (!tab) {
+                    ctx->arena.free_now(blk);
+                    blk = nullptr;
+                }
+            }
             char* probe = nullptr;
             if (blk && scratch) {
                 probe = ctx->arena.alloc(scratch, false);
                 if (!probe && slots.empty()) probe = ctx->arena.alloc(scratch, true);
                 if (!probe) {
+                    ctx->arena.free_now(tab);
                     ctx->arena.free_now(blk);
                     blk = nullptr;
                 }
+            }
+            // the batch lists are rebuilt, with this slot in, after admission: while
+            // other slots run, admit it only if they will fit next to everything held
+            if (blk && !slots.empty() &&
+                ctx->arena.largest_free() < list_bytes + slot_list_bytes(r) + 1024) {
+                if (probe) ctx->arena.free_now(probe);
+                ctx->arena.free_now(tab);
+                ctx->arena.free_now(blk);
+                blk = nullptr;
             }
             if (!blk) {
                 if (slots.empty()) {   // cannot ever fit: fail it rather than stall
@@ -281,10 +320,11 @@ void scheduler(tomo_ctx* ctx) {
                 S.queue.pop_front();
             }
             sl->allocs.push_back(blk);
+            sl->allocs.push_back(tab);
             carve_state(g, r, blk);
             if (probe) ctx->arena.free_now(probe);
             t_err.clear();
-            tomo_status st = prepare_slot(ctx, S, *sl);
+            tomo_status st = prepare_slot(ctx, S, *sl, T, tab);
             if (st != TOMO_OK) {
                 finish_ticket(S, req.ticket, 2, 0.f, t_err);
                 (void)hipStreamSynchronize(S.stream);
@@ -293,6 +333,7 @@ void scheduler(tomo_ctx* ctx) {
                 continue;
             }
             sl->parity0 = (int)((2 - (S.step & 1)) & 1);   // (step + parity0) even at it = 0
+            list_bytes += slot_list_bytes(sl->st);
             slots.push_back(std::move(sl));
             changed = true;
         }
@@ -329,6 +370,7 @@ void scheduler(tomo_ctx* ctx) {
                     sl->sino->users--;
                 }
                 slots.clear();
+                list_bytes = 0;
                 continue;
             }
             d_jobs = (const Job*)(d_lists + o_j);
@@ -369,9 +411,11 @@ void scheduler(tomo_ctx* ctx) {
         if (e != hipSuccess) {
             for (auto& sl : slots) {
                 finish_ticket(S, sl->req.ticket, 2, 0.f, hipGetErrorString(e));
+                ctx->arena.free_after(sl->allocs, S.stream);
                 sl->sino->users--;
             }
             slots.clear();
+            list_bytes = 0;
             changed = true;
             continue;
         }
@@ -380,6 +424,7 @@ void scheduler(tomo_ctx* ctx) {
             finish_ticket(S, sl.req.ticket, 1, (float)(tnow - sl.req.t_submit), "");
             ctx->arena.free_after(sl.allocs, S.stream);
             sl.sino->users--;
+            list_bytes -= slot_list_bytes(sl.st);
             slots.erase(slots.begin() + (long)*qi);
             changed = true;
         }
