@@ -293,7 +293,7 @@ tomo_status roi_submit(tomo_ctx* ctx, int32_t sino_id, const roi_params* params,
  * Errors: ENOENT (unknown or already reported ticket), EHIP (the request failed). */
 tomo_status roi_poll(tomo_ctx* ctx, uint64_t ticket, int* done, float* latency_ms);
 
-/* Serving knobs: maximum concurrent slots (default 64) and iterations per
+/* Serving knobs: maximum concurrent slots (default 32) and iterations per
  * scheduler tick (default 4); 0 leaves a value unchanged. */
 tomo_status tomo_serving_config(tomo_ctx* ctx, int32_t max_slots, int32_t iters_per_tick);
 

@@ -74,7 +74,7 @@ struct ServeState {
     uint64_t next_ticket = 1;
     bool stop = false;
     bool busy = false;
-    int max_slots = 64;
+    int max_slots = 32;
     int iters_per_tick = 4;
     hipStream_t stream = nullptr;
     Staging staging;
