@@ -32,7 +32,8 @@ double now_ms() {
 // Fixed launch shape for served slots (see the note at the top of the file).
 // The backprojector variant (direct or LDS-staged) may change with the mix:
 // for one group and pixel count per thread both give the same bits.
-constexpr int kServeSeg = 2;
+constexpr int kServeSeg = 1;   // forward projector: one segment per ray,
+constexpr int kServeRP = 2;    // two rays per lane (the shape of large batches)
 constexpr int kServeAG = 1;
 constexpr int kServePPT = 2;
 constexpr long long kServeStagedPixels = 1LL << 19;   // staged once the mix is this large
@@ -157,14 +158,14 @@ void slot_tables(const RoiState& r, SlotTables& T) {
     T.o_afp = T.m.add(r.plan.afp.data(), r.plan.afp.size() * sizeof(AngFP));
     T.o_abp = T.m.add(r.plan.abp.data(), r.plan.abp.size() * sizeof(AngBP));
     T.o_job = T.m.reserve(sizeof(Job));
-    T.o_it = T.m.reserve(count_fp_items(r.plan.afp, kServeSeg, 1) * sizeof(Item));
+    T.o_it = T.m.reserve(count_fp_items(r.plan.afp, kServeSeg, kServeRP) * sizeof(Item));
 }
 
 // A slot's share of the batch lists (its job, forward and backprojector items,
 // and the alignment of the three arrays).
 size_t slot_list_bytes(const RoiState& r) {
     return sizeof(Job) + 3 * 64 +
-           (count_fp_items(r.plan.afp, kServeSeg, 1) +
+           (count_fp_items(r.plan.afp, kServeSeg, kServeRP) +
             count_bp_items(r.ext.rows, r.ext.cols, kServeAG, kServePPT)) *
                sizeof(Item);
 }
@@ -180,7 +181,7 @@ tomo_status prepare_slot(tomo_ctx* ctx, ServeState& S, Slot& sl, SlotTables& T, 
     std::vector<Item> items;
     r.d_afp = (AngFP*)(dm + o_afp);
     r.d_abp = (AngBP*)(dm + o_abp);
-    fp_items(items, 0, r.plan.afp, kServeSeg, 1, r.d_afp);
+    fp_items(items, 0, r.plan.afp, kServeSeg, kServeRP, r.d_afp);
     m.put(o_it, items.data(), items.size() * sizeof(Item));
     Job J = make_job(g, r, FP_BAND_FROM_GLOBAL, BP_STORE, 0);
     J.xb[1] = J.xb[0];
@@ -193,7 +194,7 @@ tomo_status prepare_slot(tomo_ctx* ctx, ServeState& S, Slot& sl, SlotTables& T, 
     TOMO_HIP(ctx, launch_pad_copy(sl.sino->x_plain, g.n, r.ext.r0, r.ext.c0, r.ext.rows,
                                   r.ext.cols, r.xb0, r.plan.xp, r.xt, r.plan.tp, nullptr, 0, s));
     TOMO_HIP(ctx, launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
-                            0, kServeSeg, s));
+                            0, kServeSeg, s, 1, kServeRP));
     tomo_status st = step_size_for(ctx, sl.sino->gid, r, s, S.staging);
     if (st != TOMO_OK) return st;
     TOMO_HIP(ctx, launch_fill((float*)r.block, r.state_floats, 0.f, s));
@@ -352,7 +353,7 @@ void scheduler(tomo_ctx* ctx) {
                                  (sl.st.ext.cols + tw - 1) / tw);
                 J.parity0 = sl.parity0;
                 jobs.push_back(J);
-                fp_items(fi, (int)q, sl.st.plan.afp, kServeSeg, 1, sl.st.d_afp);
+                fp_items(fi, (int)q, sl.st.plan.afp, kServeSeg, kServeRP, sl.st.d_afp);
                 bp_items(bi, (int)q, sl.st.ext.rows, sl.st.ext.cols, kServeAG, kServePPT,
                          sl.st.d_abp);
             }
@@ -390,7 +391,7 @@ void scheduler(tomo_ctx* ctx) {
         for (int t = 0; t < tick && e == hipSuccess; ++t) {
             const int stp = (int)(S.step & 0x3fffffff);
             // slots of uneven size: items dealt round-robin over the XCDs
-            e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream, 0);
+            e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream, 0, kServeRP);
             if (e == hipSuccess)
                 e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, kServePPT, S.stream, 0, staged);
             S.step++;
