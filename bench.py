@@ -184,6 +184,14 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
         t_batch = (time.perf_counter() - t0) / reps
         kern = {"launch": best, "fp_us": 1e3 * t_fp, "bp_us": 1e3 * t_bp,
                 "fp_updates_per_s": nnz / (t_fp * 1e-3), "bp_updates_per_s": nnz / (t_bp * 1e-3)}
+        # the batch's dominant iteration kernel against the ALU roof of the projectors
+        dom_fp = t_fp >= t_bp
+        rate = nnz / ((t_fp if dom_fp else t_bp) * 1e-3)
+        kern["roofline"] = {"bound": "alu", "kernel": "fp_kernel" if dom_fp else "bp_kernel",
+                            "achieved": rate / 1e9, "peak": PEAK_UPDATES / 1e9,
+                            "unit": "Gupdate/s", "frac": rate / PEAK_UPDATES,
+                            "avg_launch_us": 1e3 * (t_fp if dom_fp else t_bp),
+                            "updates_per_launch": nnz}
         if not compare:
             return {"roi_solves_per_s": len(rois) / t_batch, "ms_per_batch": 1e3 * t_batch,
                     "updates_per_s": updates / t_batch, **kern}
