@@ -52,7 +52,8 @@ def stitch(n, rects, crops, fill=0.0):
 
 
 def local_solve(geom, sino, rect, margin, method="cp", lam=0.0, iters=100, sigma=None,
-                tau=None, x_ext=None, half=False, aniso=False, workers=1, full=False):
+                tau=None, x_ext=None, half=False, aniso=False, workers=1, full=False,
+                dual_callback=None):
     """Reconstruct ROI rect: extend, subtract the exterior, iterate on L, crop.
 
     Returns the ROI crop (rows, cols), or with full=True a dict that also holds
@@ -70,7 +71,8 @@ def local_solve(geom, sino, rect, margin, method="cp", lam=0.0, iters=100, sigma
     if method == "cp":
         if sigma is None or tau is None:
             sigma, tau = cp_steps(WL, shape)
-        x = cp_tv_nonneg(WL, b, shape, lam, sigma, tau, iters, half=half, aniso=aniso)
+        x = cp_tv_nonneg(WL, b, shape, lam, sigma, tau, iters, half=half, aniso=aniso,
+                         dual_callback=dual_callback)
     elif method == "sirt":
         alpha = 1.0 / (geom.n_angles * geom.n_det)
         x = sirt_nonneg(WL, b, shape, alpha, iters)

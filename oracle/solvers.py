@@ -49,8 +49,14 @@ def cp_steps(WL, shape, iters=100, safety=1.01):
 
 
 def cp_tv_nonneg(WL, b, shape, lam, sigma, tau, iters, theta=1.0, half=False, aniso=False,
-                 nonneg=True, x0=None, callback=None):
-    """K Chambolle-Pock iterations; returns the final primal iterate (rows, cols)."""
+                 nonneg=True, x0=None, callback=None, dual_callback=None):
+    """K Chambolle-Pock iterations; returns the final primal iterate (rows, cols).
+
+    half: data term 1/2 ||W_L x - b||^2 (prox of sigma F1* divides by 1 + sigma).
+    aniso: anisotropic TV, whose dual prox clamps each component to [-lambda, lambda].
+    callback(it, x) sees each new primal iterate; dual_callback(it, zt) sees the TV dual
+    z + sigma grad xbar before its projection (so a caller can tell where it clips).
+    """
     b = np.asarray(b, dtype=np.float64).ravel()
     x = np.zeros(shape) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     xbar = x.copy()
@@ -60,6 +66,8 @@ def cp_tv_nonneg(WL, b, shape, lam, sigma, tau, iters, theta=1.0, half=False, an
     for it in range(iters):
         y = (y + sigma * (WL @ xbar.ravel() - b)) / dual_scale
         z = z + sigma * grad(xbar)
+        if dual_callback is not None:
+            dual_callback(it, z)
         if aniso:
             z = np.clip(z, -lam, lam)
         else:

@@ -27,25 +27,32 @@ def _grad_matrix(rows, cols):
     return D
 
 
-def _admm_tv_nonneg(W, b, rows, cols, lam, rho=None, iters=100000):
-    """Independent minimiser of ||Wx - b||^2 + lam sum_j ||(Dx)_j||_2 s.t. x >= 0 (ADMM
-    with splittings u = Dx, v = x; dense Cholesky solves)."""
+def _admm_tv_nonneg(W, b, rows, cols, lam, rho=None, iters=100000, half=False, aniso=False):
+    """Independent minimiser of c ||Wx - b||^2 + lam TV(x) s.t. x >= 0 (c = 1, or 1/2 with
+    half), TV isotropic (sum_j ||(Dx)_j||_2) or anisotropic (||Dx||_1), by ADMM with the
+    splittings u = Dx, v = x and dense Cholesky solves.  The u-step is the prox of the
+    penalty: block shrinkage of each pixel's 2-vector (isotropic) or soft thresholding of
+    each component (anisotropic)."""
     P = rows * cols
     D = _grad_matrix(rows, cols)
+    cdat = 0.5 if half else 1.0
     if rho is None:
         rho = float(np.linalg.norm(W, 2) ** 2)
-    A = 2 * W.T @ W + rho * D.T @ D + rho * np.eye(P)
+    A = 2 * cdat * W.T @ W + rho * D.T @ D + rho * np.eye(P)
     cf = sla.cho_factor(A)
-    Wb2 = 2 * W.T @ b
+    Wb2 = 2 * cdat * W.T @ b
     u = np.zeros(2 * P); a = np.zeros(2 * P)
     v = np.zeros(P); c = np.zeros(P)
     for _ in range(iters):
         x = sla.cho_solve(cf, Wb2 + rho * D.T @ (u - a) + rho * (v - c))
         Dx = D @ x
         q = Dx + a
-        nrm = np.sqrt(q[:P] ** 2 + q[P:] ** 2)
-        scale = np.maximum(0.0, 1.0 - (lam / rho) / np.maximum(nrm, 1e-300))
-        u = np.concatenate([q[:P] * scale, q[P:] * scale])
+        if aniso:
+            u = np.sign(q) * np.maximum(0.0, np.abs(q) - lam / rho)
+        else:
+            nrm = np.sqrt(q[:P] ** 2 + q[P:] ** 2)
+            scale = np.maximum(0.0, 1.0 - (lam / rho) / np.maximum(nrm, 1e-300))
+            u = np.concatenate([q[:P] * scale, q[P:] * scale])
         v = np.maximum(0.0, x + c)
         a += Dx - u
         c += x - v
@@ -113,13 +120,62 @@ def test_cp_unregularised_converges_to_exact_solution():
     assert np.abs(x - truth).max() < 1e-6
 
 
-def test_cp_half_flag_changes_dual_prox():
-    g = oracle.make_geometry(8, 4, 12)
+@pytest.mark.parametrize("half,aniso,lam", [(True, False, 1.5), (False, True, 1.0),
+                                            (True, True, 0.5)])
+def test_cp_variants_converge_to_independent_admm_minimiser(half, aniso, lam):
+    """The 1/2-data reading (prox of sigma F1* divides by 1 + sigma) and the anisotropic
+    reading of ||grad x||_1 (per-component clamp to [-lambda, lambda]) each converge to
+    the minimiser of their own objective, found by ADMM with the matching data weight and
+    shrinkage (eq. priorsys with and without 1/2; Section 2.3, g = ||grad x||_1).  A
+    swapped divisor or a wrong clamp bound lands on another problem's minimiser: the
+    four problems' minima differ by far more than the 3e-5 gap allowed here.  lambda is
+    chosen per reading so that nonnegativity is active at the minimiser."""
+    n, na, nd = 8, 6, 12
+    g = oracle.make_geometry(n, na, nd)
+    rng = np.random.default_rng(n)
+    truth = np.zeros((n, n))
+    truth[2:n - 3, 3:n - 2] = 1.0
+    truth[4:6, 4:7] = 0.0
     WL = oracle.sparse_local(g)
-    b = WL @ np.ones(64)
-    x1 = oracle.cp_tv_nonneg(WL, b, (8, 8), 0.1, 0.1, 0.1, 5)
-    x2 = oracle.cp_tv_nonneg(WL, b, (8, 8), 0.1, 0.1, 0.1, 5, half=True)
-    assert np.abs(x1 - x2).max() > 1e-6
+    b = WL @ truth.ravel() + 0.3 * rng.standard_normal(WL.shape[0])
+    W = WL.toarray()
+    rho = float(np.linalg.norm(W, 2) ** 2)
+    mins = {}
+    for hh in (False, True):
+        for aa in (False, True):
+            xa = _admm_tv_nonneg(W, b, n, n, lam, rho=rho, iters=10000, half=hh, aniso=aa)
+            mins[hh, aa] = (xa, oracle.cp_objective(WL, b, xa, lam, half=hh, aniso=aa))
+    xa, f1 = mins[half, aniso]
+    xa2 = _admm_tv_nonneg(W, b, n, n, lam, rho=rho / 10, iters=10000, half=half, aniso=aniso)
+    assert abs(oracle.cp_objective(WL, b, xa2, lam, half=half, aniso=aniso) - f1) <= 1e-8 * f1
+    # the other readings' minimisers are clearly suboptimal for this objective
+    for key, (xo, _) in mins.items():
+        if key != (half, aniso):
+            assert oracle.cp_objective(WL, b, xo, lam, half=half, aniso=aniso) - f1 > 1e-3 * f1
+    s, t = oracle.cp_steps(WL, (n, n), iters=300)
+    x = oracle.cp_tv_nonneg(WL, b, (n, n), lam, s, t, 40000, half=half, aniso=aniso)
+    gap = oracle.cp_objective(WL, b, x, lam, half=half, aniso=aniso) - f1
+    assert x.min() >= 0.0 and (x == 0).sum() > 0
+    assert -1e-9 * f1 <= gap <= 3e-5 * f1, gap
+    assert np.abs(x - xa).max() < 2e-2
+
+
+def test_cp_dual_callback_sees_the_unprojected_dual():
+    """dual_callback receives z + sigma grad xbar before the projection: on the first
+    iteration (z = 0, xbar = 0) it is zero, on the second sigma grad(xbar_1); the
+    projected dual never leaves the lambda-ball while the unprojected one does."""
+    g = oracle.make_geometry(12, 8, 18)
+    WL = oracle.sparse_local(g)
+    truth = np.zeros((12, 12)); truth[3:9, 2:7] = 5.0
+    b = WL @ truth.ravel()
+    seen, xs = [], []
+    oracle.cp_tv_nonneg(WL, b, (12, 12), 0.05, 0.05, 0.05, 30,
+                        dual_callback=lambda it, z: seen.append(z.copy()),
+                        callback=lambda it, x: xs.append(x.copy()))
+    assert np.all(seen[0] == 0.0)
+    xbar1 = 2 * xs[0]                        # x0 = 0, so xbar1 = 2 x1 - x0
+    np.testing.assert_allclose(seen[1], 0.05 * oracle.grad(xbar1), rtol=0, atol=1e-15)
+    assert max(np.hypot(z[0], z[1]).max() for z in seen) > 0.05
 
 
 def test_cp_is_stable_under_data_perturbation():
