@@ -220,38 +220,51 @@ def _c1_problem():
     return d, cfg, geo, p32
 
 
-@pytest.mark.parametrize("lam_scale,method", [(1.0, "cp"), (100.0, "cp"), (1.0, "sirt")])
-def test_roi_solve_c1_parity(ctx, lam_scale, method):
+# (lambda multiple, method, flags, share of pixels whose TV dual the lambda-ball projection
+# must clip in the last iteration: > 0 where the projection is active, None where it is
+# not expected to be).  At the workload's lambda the projection clips ~80 % of the
+# pixels; at 10x about half; at 100x the duals (growing by sigma grad xbar, sigma ~ 0.022,
+# per iteration) do not reach the ball within 100 iterations, the inactive regime.
+C1_CASES = [(1.0, "cp", 0, True), (10.0, "cp", 0, True), (100.0, "cp", 0, None),
+            (1.0, "sirt", 0, None), (1.0, "cp", 1, True), (1.0, "cp", 2, True),
+            (10.0, "cp", 3, True)]
+
+
+@pytest.mark.parametrize("lam_scale,method,flags,clips", C1_CASES)
+def test_roi_solve_c1_parity(ctx, lam_scale, method, flags, clips):
     """Full local pipeline on the 128-grid workload: GPU Ram-Lak FBP exterior,
     exterior subtraction, 100 iterations, crop; compared with the oracle run on
-    the same FP32 data with the same step sizes."""
+    the same FP32 data with the same step sizes.  flags 1 = 1/2 data term (eq. priorsys
+    with 1/2), 2 = anisotropic TV (per-component clamp), 3 = both.  Where the TV dual
+    projection is meant to be active, the oracle's run shows it clipping on a nonzero
+    share of the pixels in the last iteration (||z + sigma grad xbar|| > lambda, or a
+    component beyond lambda for the anisotropic reading)."""
+    from paper_1604_02292_amd import make_params
     d, cfg, geo, p32 = _c1_problem()
     g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
     r0, c0, rr, cc, m = synth.roi_list("c1")[0]
     lam = cfg["lam"] * lam_scale
-    say(f"[roi_solve c1] method {method} lambda {lam}")
+    half, aniso = bool(flags & 1), bool(flags & 2)
+    say(f"[roi_solve c1] method {method} lambda {lam} flags {flags}")
+    clip = []
+
+    def on_dual(it, zt):
+        if it == cfg["iters"] - 1:
+            over = (np.abs(zt) > lam).any(axis=0) if aniso else np.hypot(zt[0], zt[1]) > lam
+            clip.append(float(np.mean(over)))
     res = oracle.local_solve(geo, p32.astype(np.float64), (r0, c0, rr, cc), m, method=method,
-                             lam=lam, iters=cfg["iters"], full=True)
-    from paper_1604_02292_amd import make_params
+                             lam=lam, iters=cfg["iters"], half=half, aniso=aniso, full=True,
+                             dual_callback=on_dual)
     sig = res["sigma"] if method == "cp" else 0.0
-    prm = make_params((r0, c0, rr, cc), m, method, lam, cfg["iters"], sig or 0.0, sig or 0.0)
+    prm = make_params((r0, c0, rr, cc), m, method, lam, cfg["iters"], sig or 0.0, sig or 0.0,
+                      flags=flags)
     out = torch.empty((rr, cc), dtype=torch.float32, device="cuda")
     ctx.roi_solve(g, dev(p32), prm, out)
     e = rel(host(out), res["x"])
-    say(f"    rel {e:.2e}")
+    say(f"    rel {e:.2e}" + (f", TV dual clipped on {clip[0]:.3f} of the pixels" if clip else ""))
     assert e <= SOLVE_TOL
-    if method == "cp" and lam_scale > 1:
-        # the TV dual projection is active on a nonzero fraction of pixels (oracle side)
-        WL, b, ext = res["WL"], res["b"], res["ext"]
-        shape = (ext[2], ext[3])
-        clipped = []
-
-        def cb(it, x):
-            if it == cfg["iters"] - 1:
-                gz = oracle.grad(x)
-                clipped.append(np.mean(np.hypot(gz[0], gz[1]) > 0))
-        oracle.cp_tv_nonneg(WL, b, shape, lam, res["sigma"], res["tau"], cfg["iters"], callback=cb)
-        assert clipped[0] > 0
+    if clips:
+        assert clip and clip[0] > 0.0
 
 
 def test_step_size_matches_oracle(ctx):
