@@ -116,6 +116,22 @@ tomo_status tomo_bp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
 tomo_status tomo_fbp_ramlak(tomo_ctx* ctx, int32_t geom, const float* sino, float* img,
                             void* hip_stream);
 
+/* tomo_fbp_ramlak for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments and the same result bits; the call allocates nothing (no hipMalloc,
+ * no workspace block, no pinned staging): its scratch - work list, job
+ * descriptor, per-angle tables and the filtered band, about
+ * 4 * n_angles * (sqrt(2) * n + 8) + n^2 / 16 bytes - lives in one static
+ * 32 MiB device array per GPU, set up when the first context on that GPU is
+ * created and held until the process ends.  Every call on a GPU shares that
+ * array, so calls that overlap on one GPU (on different streams or from
+ * different threads) race; calls in one stream order do not.  Errors: EINVAL
+ * when the geometry needs more scratch than the array holds (the 4096-pixel,
+ * 512-angle geometry needs 12.4 MiB, an 8192-pixel, 1024-angle one 49 MiB);
+ * otherwise as tomo_fbp_ramlak. */
+tomo_status tomo_fbp_ramlak_noalloc(tomo_ctx* ctx, int32_t geom, const float* sino, float* img,
+                                    void* hip_stream);
+
 /* Exterior subtraction through W = W_L + W_F (eq. locouter): for the extended
  * local part ext_roi, sino_local = sino - W M_F x_ext on every bin of the
  * region's band that lies on the detector, and 0 on all other bins.

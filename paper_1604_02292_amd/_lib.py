@@ -52,6 +52,7 @@ SIGNATURES = {
     "tomo_fp": (C.c_int, [_P, _I, tomo_rect, _P, _P, C.c_int, _P]),
     "tomo_bp": (C.c_int, [_P, _I, tomo_rect, _P, _P, C.c_int, _P]),
     "tomo_fbp_ramlak": (C.c_int, [_P, _I, _P, _P, _P]),
+    "tomo_fbp_ramlak_noalloc": (C.c_int, [_P, _I, _P, _P, _P]),
     "tomo_exterior_subtract": (C.c_int, [_P, _I, tomo_rect, _P, _P, _P, _P]),
     "roi_solve": (C.c_int, [_P, _I, _P, _P, C.POINTER(roi_params), _P, _P]),
     "roi_solve_batch": (C.c_int, [_P, _I, _P, _P, _I, C.POINTER(roi_params), C.POINTER(_P), _P]),

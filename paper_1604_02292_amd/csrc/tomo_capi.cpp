@@ -927,6 +927,10 @@ tomo_status tomo_create(int device, void* workspace, size_t workspace_bytes, tom
             delete ctx;
             return TOMO_EHIP;
         }
+        if (noalloc_setup(device) != hipSuccess) {
+            delete ctx;
+            return TOMO_EHIP;
+        }
         ctx->ws = (char*)workspace;
         ctx->ws_bytes = workspace_bytes;
         ctx->arena.init(ctx->ws, workspace_bytes);
@@ -996,6 +1000,7 @@ tomo_status tomo_set_geometry(tomo_ctx* ctx, int32_t n, int32_t n_angles, int32_
         g.ystep.push_back(ys);
         g.m.push_back(ys ? std::fabs(c) : std::fabs(s));
     }
+    g.full = make_plan(g, Rect{0, 0, n, n}, Rect{0, 0, n, n});
     if (!ctx->host_only) {
         tomo_status st = need_gpu(ctx);
         if (st != TOMO_OK) return st;

@@ -29,6 +29,17 @@ struct Rect {
     int r0, c0, rows, cols;
 };
 
+// Host tables of one job: an image region and the detector band of a (possibly
+// different) band source region.
+struct Plan {
+    Rect reg{};
+    std::vector<AngFP> afp;
+    std::vector<AngBP> abp;
+    int wmax = 0;
+    int bpitch = 0;
+    int xp = 0, tp = 0;
+};
+
 // Parallel-beam geometry (Section 2.1); the row/column-stepping branch of
 // Joseph's method is decided here, once, in FP64.
 struct Geom {
@@ -39,17 +50,7 @@ struct Geom {
     float* d_taps = nullptr;   // Ram-Lak taps h[d] / spacing as FP32 pairs (hi, lo), d < nd
                                // (device, GPU contexts)
     size_t taps_off = 0;
-};
-
-// Host tables of one job: an image region and the detector band of a (possibly
-// different) band source region.
-struct Plan {
-    Rect reg{};
-    std::vector<AngFP> afp;
-    std::vector<AngBP> abp;
-    int wmax = 0;
-    int bpitch = 0;
-    int xp = 0, tp = 0;
+    Plan full;                 // tables of the whole grid (FBP), made once with the geometry
 };
 
 void band_of(const Geom& g, const Rect& b, int k, int* i0, int* w);
@@ -166,6 +167,10 @@ tomo_status fail(tomo_ctx* ctx, tomo_status st, const char* fmt, ...);
     }
 
 tomo_status need_gpu(tomo_ctx* ctx);   // GPU context with its device made current
+
+// Looks up, once per device (the device current), the address of the static scratch array
+// of the allocation-free entry point (tomo_noalloc.hip).
+hipError_t noalloc_setup(int device);
 
 // Returns the listed workspace blocks to the arena after the work already queued
 // on `s` when the scope ends (also on an early error return).

@@ -146,6 +146,12 @@ class Context:
         self._check(self.lib.tomo_fbp_ramlak(self.h, geom, _ptr(sino, (na, nd), "sino"),
                                              _ptr(img, (n, n), "img"), _stream(stream)))
 
+    def tomo_fbp_ramlak_noalloc(self, geom, sino, img, stream=None):
+        n, na, nd = self.geoms[geom]
+        self._check(self.lib.tomo_fbp_ramlak_noalloc(
+            self.h, geom, _ptr(sino, (na, nd), "sino"), _ptr(img, (n, n), "img"),
+            _stream(stream)))
+
     def tomo_exterior_subtract(self, geom, ext_roi, sino, x_ext, sino_local, stream=None):
         n, na, nd = self.geoms[geom]
         self._check(self.lib.tomo_exterior_subtract(
