@@ -126,8 +126,8 @@ def _sino_chunk(args):
     ct, st = np.cos(th), np.sin(th)
     q = (np.arange(subrays) + 0.5) / subrays - 0.5
     centre = (n_det - 1) / 2.0
-    flat = np.zeros(n_angles * n_det, dtype=np.float64)
     kk = np.arange(n_angles)
+    cols, wts = [], []
     for e in idx:
         cx, cy, a, b, phi, v = (ell.cx[e], ell.cy[e], ell.a[e], ell.b[e], ell.phi[e], ell.v[e])
         proj = cx * ct + cy * st                      # centre's detector coordinate
@@ -145,9 +145,18 @@ def _sino_chunk(args):
             val += np.where(d > 0, np.sqrt(np.maximum(d, 0.0)), 0.0)
         val *= (2.0 * a * b * v / subrays) / r2[:, None]
         ok = (ii >= 0) & (ii < n_det) & (val != 0)
-        flat += np.bincount((kk[:, None] * n_det + ii)[ok], weights=val[ok],
-                            minlength=n_angles * n_det)
-    return flat
+        cols.append((kk[:, None] * n_det + ii)[ok])
+        wts.append(val[ok])
+    # one accumulation over the chunk: every bin appears at most once per ellipse and
+    # bincount adds in input order, so each bin's sum runs over the ellipses in order.
+    # Only the nonzero bins of the chunk's partial sum are returned (adding the zeros
+    # would change nothing), which keeps the transfer from worker processes small.
+    if not cols:
+        return np.zeros(0, dtype=np.int64), np.zeros(0)
+    part = np.bincount(np.concatenate(cols), weights=np.concatenate(wts),
+                       minlength=n_angles * n_det)
+    nz = np.flatnonzero(part)
+    return nz, part[nz]
 
 
 def analytic_sinogram(ell, n_angles, n_det, spacing=1.0, offset=0.0, subrays=4,
@@ -171,8 +180,8 @@ def analytic_sinogram(ell, n_angles, n_det, spacing=1.0, offset=0.0, subrays=4,
     else:
         parts = [_sino_chunk(j) for j in jobs]
     flat = np.zeros(len(th) * n_det)
-    for part in parts:
-        flat += part
+    for nz, val in parts:
+        flat[nz] += val
     return flat.reshape(len(th), n_det)
 
 
