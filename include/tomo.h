@@ -142,7 +142,10 @@ tomo_status tomo_exterior_subtract(tomo_ctx* ctx, int32_t geom, tomo_rect ext_ro
                                    void* hip_stream);
 
 typedef enum {
-    ROI_TV_NONNEG_CP = 0,   /* Chambolle-Pock on ||W_L x - b||^2 + lambda TV(x), x >= 0 */
+    ROI_TV_NONNEG_CP = 0,   /* Chambolle-Pock on h^2 ||W_L x - b||^2 + lambda TV(x), x >= 0
+                               (eq. priorsys), h = 1/n: path lengths and line integrals
+                               measured with the image side as the unit of length
+                               (h = 1 with ROI_FLAG_PIXEL_UNITS) */
     ROI_NONNEG_SIRT = 1,    /* x <- P(x + alpha W_L^T (b - W_L x)), alpha = 1/(N_theta N_d),
                                P the box of eq. sirtbox: [0, inf), or [box_lo, box_hi] with
                                ROI_FLAG_BOX (eq. sirtit) */
@@ -161,15 +164,17 @@ enum {
     ROI_FLAG_HALF_DATA = 1, /* use 1/2 ||W_L x - b||^2 as the data term */
     ROI_FLAG_ANISO_TV = 2,  /* anisotropic TV (sum of |d/dr| + |d/dc|) */
     ROI_FLAG_BOX = 4,       /* SIRT-type methods: box [box_lo, box_hi] instead of [0, inf) */
-    ROI_FLAG_NO_MOMENTUM = 8 /* local FISTA methods without momentum: the ISTA form
+    ROI_FLAG_NO_MOMENTUM = 8, /* local FISTA methods without momentum: the ISTA form
                                (eq. sirtista), z = x^k */
+    ROI_FLAG_PIXEL_UNITS = 16 /* CP only: data term in pixel units, ||W_L x - b||^2 (h = 1) */
 };
 
 /* One local reconstruction request.  roi: the part the caller wants; margin:
  * padding on each side (Section 3.3), clipped to the grid; lambda: TV weight;
  * iters: fixed iteration count (no early stop); sigma, tau: CP step sizes, or
- * 0 for sigma = tau = 1/sqrt(1.01 * lambda_max(W_L^T W_L - Laplacian))
- * from a cached power iteration (per geometry and extended shape); box_lo,
+ * 0 for sigma = tau = 1/sqrt(1.01 h^2 mu + 8), mu = lambda_max(W_L^T W_L - Laplacian)
+ * from a cached power iteration (per geometry and extended shape), an upper bound of
+ * ||[h W_L; grad]||^2 since ||grad||^2 <= 8; box_lo,
  * box_hi: the box of SIRT-type methods when flags has ROI_FLAG_BOX (box_lo may
  * be -inf, box_hi +inf; box_lo <= box_hi; not accepted for CP and the Haar prior);
  * inner_iters: FGP iterations per outer iteration of ROI_LOCAL_FISTA_TV (0 = 100, the
@@ -203,6 +208,16 @@ tomo_status roi_solve(tomo_ctx* ctx, int32_t geom, const float* sino, const floa
 tomo_status roi_solve_batch(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
                             int32_t count, const roi_params* params, float* const* outs,
                             void* hip_stream);
+
+/* roi_solve_batch with the crops stitched into one image (Section 5.6: local parts
+ * placed side by side, no blending, as in the tiled reconstruction of a whole slice):
+ * ROI i's crop is written to img[roi.row0 + r][roi.col0 + c] (img is a device
+ * float[n][ld], ld >= n); pixels no ROI covers are left as they are, and where ROIs
+ * overlap the later one in params wins.  Errors as roi_solve_batch, and EINVAL for
+ * ld < n. */
+tomo_status roi_solve_stitched(tomo_ctx* ctx, int32_t geom, const float* sino,
+                               const float* x_ext, int32_t count, const roi_params* params,
+                               float* img, int32_t ld, void* hip_stream);
 
 /* SIRT-approximating FBP filters (Section 3.1: eq. filtcalc, eq. sirtapp, Alg. 1).
  * filters: device float[iters][n_angles][n_det], caller-owned; plane k - 1

@@ -10,7 +10,9 @@ Pieces and the passages they follow:
     is ignored);
   * independent local parts are placed side by side without blending (Section 5.6).
 
-The exterior estimate defaults to the Ram-Lak FBP of the whole sinogram.
+The exterior estimate defaults to the Ram-Lak FBP of the whole sinogram.  The CP
+solve's data term is measured with the image side as the unit of length (h = 1/N,
+see solvers.py) unless h is given.
 """
 
 import numpy as np
@@ -53,7 +55,7 @@ def stitch(n, rects, crops, fill=0.0):
 
 def local_solve(geom, sino, rect, margin, method="cp", lam=0.0, iters=100, sigma=None,
                 tau=None, x_ext=None, half=False, aniso=False, workers=1, full=False,
-                dual_callback=None):
+                dual_callback=None, h=None):
     """Reconstruct ROI rect: extend, subtract the exterior, iterate on L, crop.
 
     Returns the ROI crop (rows, cols), or with full=True a dict that also holds
@@ -68,11 +70,13 @@ def local_solve(geom, sino, rect, margin, method="cp", lam=0.0, iters=100, sigma
     bins = used.reshape(geom.n_angles, geom.n_det)
     b = exterior_subtract(geom, sino, x_ext, ext, bins=bins)
     shape = (ext[2], ext[3])
+    if h is None:
+        h = 1.0 / geom.n
     if method == "cp":
         if sigma is None or tau is None:
-            sigma, tau = cp_steps(WL, shape)
+            sigma, tau = cp_steps(WL, shape, h=h)
         x = cp_tv_nonneg(WL, b, shape, lam, sigma, tau, iters, half=half, aniso=aniso,
-                         dual_callback=dual_callback)
+                         dual_callback=dual_callback, h=h)
     elif method == "sirt":
         alpha = 1.0 / (geom.n_angles * geom.n_det)
         x = sirt_nonneg(WL, b, shape, alpha, iters)
@@ -81,5 +85,5 @@ def local_solve(geom, sino, rect, margin, method="cp", lam=0.0, iters=100, sigma
     out = crop(x, ext, rect)
     if full:
         return dict(x=out, x_ext_full=x, ext=ext, b=b, sigma=sigma, tau=tau, x_ext=x_ext,
-                    WL=WL, bins=bins)
+                    WL=WL, bins=bins, h=h)
     return out

@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "TOMO_OK", -1: "TOMO_EINVAL", -2: "TOMO_ENOMEM", -3: "TOMO_EH
 
 ROI_TV_NONNEG_CP, ROI_NONNEG_SIRT, ROI_LOCAL_SIRT, ROI_LOCAL_FISTA_TV, ROI_LOCAL_FISTA_HAAR = 0, 1, 2, 3, 4
 ROI_FLAG_HALF_DATA, ROI_FLAG_ANISO_TV, ROI_FLAG_BOX, ROI_FLAG_NO_MOMENTUM = 1, 2, 4, 8
+ROI_FLAG_PIXEL_UNITS = 16
 
 
 class tomo_rect(C.Structure):
@@ -56,6 +57,7 @@ SIGNATURES = {
     "tomo_exterior_subtract": (C.c_int, [_P, _I, tomo_rect, _P, _P, _P, _P]),
     "roi_solve": (C.c_int, [_P, _I, _P, _P, C.POINTER(roi_params), _P, _P]),
     "roi_solve_batch": (C.c_int, [_P, _I, _P, _P, _I, C.POINTER(roi_params), C.POINTER(_P), _P]),
+    "roi_solve_stitched": (C.c_int, [_P, _I, _P, _P, _I, C.POINTER(roi_params), _P, _I, _P]),
     "roi_step_size": (C.c_int, [_P, _I, tomo_rect, C.POINTER(C.c_float)]),
     "tomo_sirt_filters": (C.c_int, [_P, _I, _I, _P, _P]),
     "tomo_sirt_filter_sino": (C.c_int, [_P, _I, _P, _I, _P, _P, _P]),

@@ -107,7 +107,9 @@ tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p) {
     if (p.method == ROI_LOCAL_FISTA_HAAR && p.inner_iters > kHaarMaxLevels)
         return fail(ctx, TOMO_EINVAL, "at most %d Haar levels", kHaarMaxLevels);
     if (!(p.sigma >= 0.f) || !(p.tau >= 0.f)) return fail(ctx, TOMO_EINVAL, "negative step size");
-    if (p.flags & ~15u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
+    if (p.flags & ~31u) return fail(ctx, TOMO_EINVAL, "unknown flags 0x%x", p.flags);
+    if ((p.flags & ROI_FLAG_PIXEL_UNITS) && p.method != ROI_TV_NONNEG_CP)
+        return fail(ctx, TOMO_EINVAL, "ROI_FLAG_PIXEL_UNITS applies to ROI_TV_NONNEG_CP only");
     if ((p.flags & ROI_FLAG_NO_MOMENTUM) && p.method < ROI_LOCAL_FISTA_TV)
         return fail(ctx, TOMO_EINVAL, "ROI_FLAG_NO_MOMENTUM applies to the local FISTA methods");
     if (p.flags & ROI_FLAG_BOX) {
@@ -139,6 +141,9 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
     J.lam = st.prm.lambda;
     const bool half = (st.prm.flags & ROI_FLAG_HALF_DATA) != 0;
     J.dual_div = (float)(1.0 / (1.0 + (half ? (double)st.sigma : 0.5 * (double)st.sigma)));
+    // data length unit of CP: the image side (h = 1/n), or the pixel
+    const double h = (st.prm.flags & ROI_FLAG_PIXEL_UNITS) ? 1.0 : 1.0 / (double)g.n;
+    J.sigma_y = (float)((double)st.sigma * h * h);
     J.alpha = (float)(1.0 / ((double)g.na * (double)g.nd));
     J.scale = 1.f;
     const bool box = (st.prm.flags & ROI_FLAG_BOX) != 0;
@@ -330,12 +335,17 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     const Geom& g = ctx->geoms[gid];
     const int nr = std::min(g.n, (st.ext.rows + 15) / 16 * 16);
     const int nc = std::min(g.n, (st.ext.cols + 15) / 16 * 16);
+    // sigma = tau = 1 / L, L^2 = 1.01 h^2 mu + 8 >= ||[h W_L; grad]||^2 with mu =
+    // lambda_max(W_L^T W_L - Laplacian) from the power iteration (mu >= ||W_L||^2, and
+    // ||grad||^2 <= 8); h is the data length unit (1/n, or 1 in pixel units)
+    const double hu = (st.prm.flags & ROI_FLAG_PIXEL_UNITS) ? 1.0 : 1.0 / (double)g.n;
+    auto step_of = [hu](float mu) { return (float)(1.0 / std::sqrt(1.01 * hu * hu * (double)mu + 8.0)); };
     const auto key = std::make_tuple(gid, nr, nc);
     {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         auto it = ctx->step_cache.find(key);
         if (it != ctx->step_cache.end()) {
-            st.sigma = st.tau = it->second;
+            st.sigma = st.tau = step_of(it->second);
             return TOMO_OK;
         }
     }
@@ -400,12 +410,11 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
     if (e != hipSuccess) return done(fail(ctx, TOMO_EHIP, "power iteration: %s", hipGetErrorString(e)));
     if (!(h_est > 0.f) || !std::isfinite(h_est))
         return done(fail(ctx, TOMO_EHIP, "power iteration gave a non-positive norm estimate"));
-    const float stp = (float)(1.0 / std::sqrt(1.01 * (double)h_est));
     {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        ctx->step_cache[key] = stp;
+        ctx->step_cache[key] = h_est;
     }
-    st.sigma = st.tau = stp;
+    st.sigma = st.tau = step_of(h_est);
     return done(TOMO_OK);
 }
 
@@ -498,7 +507,7 @@ tomo_status run_loop(tomo_ctx* ctx, const std::vector<long long>& key, const Met
 // registered sinogram whose x_ext and residual r = p - W x_ext are resident.
 tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* x_ext_user,
                         const SinoState* reg, int count, const roi_params* params,
-                        float* const* outs, hipStream_t s) {
+                        float* const* outs, hipStream_t s, int ldo) {
     const Geom& g = ctx->geoms[gid];
     const Rect full{0, 0, g.n, g.n};
     std::vector<RoiState> R(count);
@@ -827,7 +836,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     for (int i = 0; i < count; ++i) {
         const RoiState& r = R[i];
         CK(launch_crop(r.x, r.ext.cols, r.roi.r0 - r.ext.r0, r.roi.c0 - r.ext.c0, r.roi.rows,
-                       r.roi.cols, outs[i], s));
+                       r.roi.cols, outs[i], ldo > 0 ? ldo : r.roi.cols, s));
     }
 #undef CK
     cleanup();
@@ -1269,6 +1278,27 @@ tomo_status tomo_exterior_subtract(tomo_ctx* ctx, int32_t geom, tomo_rect ext_ro
             hipSuccess)
         return fin(fail(ctx, TOMO_EHIP, "exterior subtraction: %s", hipGetErrorString(e)));
     return fin(TOMO_OK);
+    GUARD_END(ctx)
+}
+
+tomo_status roi_solve_stitched(tomo_ctx* ctx, int32_t geom, const float* sino,
+                               const float* x_ext, int32_t count, const roi_params* params,
+                               float* img, int32_t ld, void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!sino || !params || !img || count < 1)
+        return fail(ctx, TOMO_EINVAL, "null pointer or count < 1");
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    if (ld < gp->n) return fail(ctx, TOMO_EINVAL, "row pitch %d < grid side %d", ld, gp->n);
+    std::vector<float*> outs(count);
+    for (int i = 0; i < count; ++i) {
+        if ((st = validate_params(ctx, *gp, params[i])) != TOMO_OK) return st;
+        outs[i] = img + (size_t)params[i].roi.row0 * ld + params[i].roi.col0;
+    }
+    return solve_batch(ctx, geom, sino, x_ext, nullptr, count, params, outs.data(),
+                       (hipStream_t)hip_stream, ld);
     GUARD_END(ctx)
 }
 

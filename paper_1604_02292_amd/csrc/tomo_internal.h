@@ -73,7 +73,7 @@ enum BpMode : int32_t {
     BP_FISTA = 6    // two-channel band (g, d): w = v + bp_g, xs = bp_d (FGP input and x_s)
 };
 
-enum JobFlags : int32_t { JF_HALF = 1, JF_ANISO = 2, JF_NO_MOMENTUM = 8 };
+enum JobFlags : int32_t { JF_HALF = 1, JF_ANISO = 2, JF_NO_MOMENTUM = 8, JF_PIXEL_UNITS = 16 };
 
 struct Job {
     int32_t nr, nc;          // region rows, cols
@@ -88,6 +88,7 @@ struct Job {
     int32_t ntc;             // tiles per row of the BP work decomposition
     int32_t dk0;             // FP_LOCAL: plane of gbase read at launch step s is s + dk0
     float sigma, tau, lam, dual_div, alpha, scale;
+    float sigma_y;           // CP data-dual step: sigma h^2 (the dual is stored as h y)
     float lo, hi;            // box of the SIRT-type updates
     int64_t gstride;         // FP_LOCAL: floats between planes of gbase
     const AngFP* afp;
@@ -174,8 +175,9 @@ hipError_t launch_fill_padded(float* xb, float* xt, int nr, int nc, int xp, int 
 hipError_t launch_pad_copy(const float* src, int lds, int r0, int c0, int nr, int nc,
                            float* xb, int xp, float* xt, int tp, float* dst, int ldd,
                            hipStream_t s);
+// out[r][c] (row pitch ldo) = x[r + dr][c + dc] (row pitch ldx), r < rows, c < cols.
 hipError_t launch_crop(const float* x, int ldx, int dr, int dc, int rows, int cols, float* out,
-                       hipStream_t s);
+                       int ldo, hipStream_t s);
 hipError_t launch_band_gather(const float* sino, int n_det, const AngFP* afp, int n_angles,
                               float* band, int bpitch, hipStream_t s);
 hipError_t launch_band_scatter(const float* band, int bpitch, const AngFP* afp, int n_angles,

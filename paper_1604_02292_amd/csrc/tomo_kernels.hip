@@ -389,8 +389,9 @@ __global__ __launch_bounds__(fp_threads<SEG>()) void fp_kernel(const Job* __rest
                 y[bidx] = ondet ? pre0[r] + J->scale * fpv : 0.f;
                 break;
             case FP_CP_DUAL:
-                // prox of sigma F1*, F1(v) = ||v - b||^2 (or 1/2 ||v - b||^2), on B * y
-                y[bidx] = ondet ? (pre0[r] + (J->sigma * A.bscale) * (fpv - pre1[r])) * J->dual_div : 0.f;
+                // prox of sigma F1*, F1(v) = ||v - h b||^2 (or 1/2 ||v - h b||^2) on the rows
+                // h W_L of K, kept as B * h y: h y <- (h y + sigma h^2 (W_L xbar - b)) / (1 + sigma/2)
+                y[bidx] = ondet ? (pre0[r] + (J->sigma_y * A.bscale) * (fpv - pre1[r])) * J->dual_div : 0.f;
                 break;
             case FP_SIRT:
                 y[bidx] = ondet ? (J->alpha * A.bscale) * (pre1[r] - fpv) : 0.f;
@@ -1060,12 +1061,12 @@ __global__ void pad_copy_kernel(const float* __restrict__ src, int lds, int r0, 
 }
 
 __global__ void crop_kernel(const float* __restrict__ x, int ldx, int dr, int dc, int rows,
-                            int cols, float* __restrict__ out) {
+                            int cols, float* __restrict__ out, int ldo) {
     const size_t n = (size_t)rows * cols;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const int rr = (int)(i / cols), cc = (int)(i % cols);
-        out[i] = x[(size_t)(rr + dr) * ldx + cc + dc];
+        out[(size_t)rr * ldo + cc] = x[(size_t)(rr + dr) * ldx + cc + dc];
     }
 }
 
@@ -2107,9 +2108,9 @@ hipError_t launch_pad_copy(const float* src, int lds, int r0, int c0, int nr, in
 }
 
 hipError_t launch_crop(const float* x, int ldx, int dr, int dc, int rows, int cols, float* out,
-                       hipStream_t s) {
+                       int ldo, hipStream_t s) {
     hipLaunchKernelGGL(crop_kernel, dim3(grid_for((size_t)rows * cols, 256)), dim3(256), 0, s, x,
-                       ldx, dr, dc, rows, cols, out);
+                       ldx, dr, dc, rows, cols, out, ldo);
     return hipGetLastError();
 }
 

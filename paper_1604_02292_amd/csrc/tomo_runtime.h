@@ -124,6 +124,7 @@ struct tomo_ctx {
     std::string err;
     std::recursive_mutex mu;   // geometry list, caches, registrations
     std::deque<tomo::Geom> geoms;   // deque: references stay valid while serving reads them
+    // lambda_max(W_L^T W_L - Laplacian) by (geometry, rounded rows, rounded cols)
     std::map<std::tuple<int, int, int>, float> step_cache;
     tomo_launch knobs{};   // launch shape forced by the user; 0 fields = automatic
     std::map<std::tuple<int, int, int>, tomo_launch> tuned;   // autotuner results by class

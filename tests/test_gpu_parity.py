@@ -220,14 +220,15 @@ def _c1_problem():
     return d, cfg, geo, p32
 
 
-# (lambda multiple, method, flags, share of pixels whose TV dual the lambda-ball projection
-# must clip in the last iteration: > 0 where the projection is active, None where it is
-# not expected to be).  At the workload's lambda the projection clips ~80 % of the
-# pixels; at 10x about half; at 100x the duals (growing by sigma grad xbar, sigma ~ 0.022,
-# per iteration) do not reach the ball within 100 iterations, the inactive regime.
+# (lambda multiple, method, flags, whether the lambda-ball projection of the TV dual must
+# clip on a nonzero share of the pixels in the last iteration: True where it is active,
+# None where it is not expected to be).  With the data in units of the image side
+# (h = 1/128, sigma ~ 0.35) the projection clips ~65 % of the pixels at the workload's
+# lambda and ~10 % at 10x; at 100x the prior flattens the iterate and the duals stay
+# inside the ball.  Flags 16 (pixel units, sigma ~ 0.022) clip ~80 %.
 C1_CASES = [(1.0, "cp", 0, True), (10.0, "cp", 0, True), (100.0, "cp", 0, None),
             (1.0, "sirt", 0, None), (1.0, "cp", 1, True), (1.0, "cp", 2, True),
-            (10.0, "cp", 3, True)]
+            (1.0, "cp", 3, True), (1.0, "cp", 16, True), (100.0, "cp", 17, None)]
 
 
 @pytest.mark.parametrize("lam_scale,method,flags,clips", C1_CASES)
@@ -235,7 +236,8 @@ def test_roi_solve_c1_parity(ctx, lam_scale, method, flags, clips):
     """Full local pipeline on the 128-grid workload: GPU Ram-Lak FBP exterior,
     exterior subtraction, 100 iterations, crop; compared with the oracle run on
     the same FP32 data with the same step sizes.  flags 1 = 1/2 data term (eq. priorsys
-    with 1/2), 2 = anisotropic TV (per-component clamp), 3 = both.  Where the TV dual
+    with 1/2), 2 = anisotropic TV (per-component clamp), 3 = both, 16 = data term in pixel
+    units instead of the image side (h = 1 instead of 1/128).  Where the TV dual
     projection is meant to be active, the oracle's run shows it clipping on a nonzero
     share of the pixels in the last iteration (||z + sigma grad xbar|| > lambda, or a
     component beyond lambda for the anisotropic reading)."""
@@ -254,7 +256,7 @@ def test_roi_solve_c1_parity(ctx, lam_scale, method, flags, clips):
             clip.append(float(np.mean(over)))
     res = oracle.local_solve(geo, p32.astype(np.float64), (r0, c0, rr, cc), m, method=method,
                              lam=lam, iters=cfg["iters"], half=half, aniso=aniso, full=True,
-                             dual_callback=on_dual)
+                             dual_callback=on_dual, h=1.0 if flags & 16 else None)
     sig = res["sigma"] if method == "cp" else 0.0
     prm = make_params((r0, c0, rr, cc), m, method, lam, cfg["iters"], sig or 0.0, sig or 0.0,
                       flags=flags)
@@ -272,10 +274,12 @@ def test_step_size_matches_oracle(ctx):
     g = ctx.tomo_set_geometry(n, na, nd)
     geo = oracle.make_geometry(n, na, nd)
     # the library caches the step per extended shape rounded up to a multiple of 16
+    # (the default data unit, the image side: h = 1/n)
+    h = 1.0 / n
     for ext, rounded in [((32, 32, 64, 64), (0, 0, 64, 64)), ((0, 0, 40, 56), (0, 0, 48, 64))]:
         s_gpu = ctx.roi_step_size(g, ext)
-        s_ref, _ = oracle.cp_steps(oracle.sparse_local(geo, rounded), (rounded[2], rounded[3]))
-        s_exact, _ = oracle.cp_steps(oracle.sparse_local(geo, ext), (ext[2], ext[3]))
+        s_ref, _ = oracle.cp_steps(oracle.sparse_local(geo, rounded), (rounded[2], rounded[3]), h=h)
+        s_exact, _ = oracle.cp_steps(oracle.sparse_local(geo, ext), (ext[2], ext[3]), h=h)
         say(f"[step] {ext} gpu {s_gpu:.6g} oracle(rounded) {s_ref:.6g} oracle(exact) {s_exact:.6g}")
         assert abs(s_gpu - s_ref) <= 2e-3 * s_ref
         assert s_gpu <= s_exact * (1 + 2e-3)      # a safe (not larger) step for the exact shape

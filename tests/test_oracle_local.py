@@ -25,8 +25,14 @@ def test_whole_image_roi_is_the_global_solve():
     s, t = oracle.cp_steps(WL, (32, 32))
     glob = oracle.cp_tv_nonneg(WL, p, (32, 32), 0.5, s, t, 30)
     loc = oracle.local_solve(g, p, (0, 0, 32, 32), 8, lam=0.5, iters=30, sigma=s, tau=t,
-                             x_ext=rng.random((32, 32)))
+                             x_ext=rng.random((32, 32)), h=1.0)
     assert np.array_equal(glob, loc)
+    # the same with the default unit, the image side (h = 1/32)
+    s2, t2 = oracle.cp_steps(WL, (32, 32), h=1 / 32)
+    glob2 = oracle.cp_tv_nonneg(WL, p, (32, 32), 0.5, s2, t2, 30, h=1 / 32)
+    loc2 = oracle.local_solve(g, p, (0, 0, 32, 32), 8, lam=0.5, iters=30, sigma=s2, tau=t2,
+                              x_ext=rng.random((32, 32)))
+    assert np.array_equal(glob2, loc2)
 
 
 def test_exterior_subtract_equals_residual_plus_local_projection():
@@ -59,27 +65,28 @@ def test_true_exterior_recovers_phantom_inside_L():
 
 
 def test_local_tracks_global_better_than_fbp_and_improves_with_margin():
-    """On the 128-grid workload (lambda raised to 50 so that TV acts at this data
-    scale, iterated to near convergence) the local solve agrees with the global
-    regularised solve inside the ROI better than the FBP exterior estimate does,
-    and the widest margin agrees best (Section 3.3 padding; Section 5.3)."""
+    """On the 128-grid workload at its lambda (0.05, data in units of the image side) the
+    local solve agrees with the global regularised solve inside the ROI better than the
+    FBP exterior estimate does, and the agreement improves monotonically as the margin
+    grows over 0, 8, 16 and 32 pixels (Section 3.3 padding; Section 5.3).  Measured:
+    rel-L2 0.11, 0.036, 0.022, 0.009 against 0.30 for the FBP."""
     d = synth.make_inputs("c1")
     cfg = d["cfg"]
     g = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
     xe = oracle.fbp_ramlak(g, d["sino"])
     rect = (48, 48, 32, 32)
-    lam, iters = 50.0, 2000
+    lam, iters, h = cfg["lam"], 500, 1.0 / cfg["n"]
     WG = oracle.sparse_local(g)
-    s, t = oracle.cp_steps(WG, (128, 128))
-    glob = oracle.cp_tv_nonneg(WG, d["sino"], (128, 128), lam, s, t, iters)
+    s, t = oracle.cp_steps(WG, (128, 128), h=h)
+    glob = oracle.cp_tv_nonneg(WG, d["sino"], (128, 128), lam, s, t, iters, h=h)
     gr = glob[48:80, 48:80]
 
     def rel(a):
         return np.linalg.norm(a - gr) / np.linalg.norm(gr)
     errs = [rel(oracle.local_solve(g, d["sino"], rect, m, lam=lam, iters=iters, x_ext=xe))
-            for m in (0, 16, 32)]
+            for m in (0, 8, 16, 32)]
     assert max(errs) < rel(xe[48:80, 48:80]), errs
-    assert errs[2] < errs[0], errs
+    assert all(a > b for a, b in zip(errs, errs[1:])), errs
 
 
 def test_crop_and_stitch_roundtrip():

@@ -71,6 +71,26 @@ def test_power_iteration_matches_eigvalsh():
     assert s * t * lam_max < 1.0
 
 
+@pytest.mark.parametrize("h", [1.0, 0.2, 1.0 / 64])
+def test_cp_steps_bound_the_operator_norm(h):
+    """sigma tau ||K||^2 < 1 for K = [h W_L; grad] whatever the data unit h, with
+    ||K||^2 from eigvalsh of the explicit h^2 W^T W + D^T D, on a 64-grid part with the
+    workload's 32 angles (the power iteration alone, started from all ones, misses most
+    of the Laplacian's top eigenvalue when h is small); and the step is within 3 % of
+    the largest admissible one when the data part dominates (h = 1)."""
+    g = oracle.make_geometry(128, 32, 192)
+    ext = (32, 32, 24, 24)
+    WL = oracle.sparse_local(g, ext)
+    D = _grad_matrix(24, 24)
+    W = WL.toarray()
+    norm2 = np.linalg.eigvalsh(h * h * W.T @ W + D.T @ D)[-1]
+    s, t = oracle.cp_steps(WL, (24, 24), h=h)
+    assert s * t * norm2 < 1.0
+    assert np.linalg.eigvalsh(D.T @ D)[-1] < 8.0
+    if h == 1.0:
+        assert s * t * norm2 > 0.97
+
+
 @pytest.mark.parametrize("n,na,nd,lam", [(8, 6, 12, 3.0), (12, 5, 17, 1.5)])
 def test_cp_converges_to_independent_admm_minimiser(n, na, nd, lam):
     """CP's objective approaches the minimum found by an independent ADMM minimiser
@@ -120,16 +140,17 @@ def test_cp_unregularised_converges_to_exact_solution():
     assert np.abs(x - truth).max() < 1e-6
 
 
-@pytest.mark.parametrize("half,aniso,lam", [(True, False, 1.5), (False, True, 1.0),
-                                            (True, True, 0.5)])
-def test_cp_variants_converge_to_independent_admm_minimiser(half, aniso, lam):
-    """The 1/2-data reading (prox of sigma F1* divides by 1 + sigma) and the anisotropic
-    reading of ||grad x||_1 (per-component clamp to [-lambda, lambda]) each converge to
-    the minimiser of their own objective, found by ADMM with the matching data weight and
-    shrinkage (eq. priorsys with and without 1/2; Section 2.3, g = ||grad x||_1).  A
-    swapped divisor or a wrong clamp bound lands on another problem's minimiser: the
-    four problems' minima differ by far more than the 3e-5 gap allowed here.  lambda is
-    chosen per reading so that nonnegativity is active at the minimiser."""
+@pytest.mark.parametrize("half,aniso,lam,h", [(True, False, 1.5, 1.0), (False, True, 1.0, 1.0),
+                                              (True, True, 0.5, 1.0), (False, False, 0.1875, 0.25)])
+def test_cp_variants_converge_to_independent_admm_minimiser(half, aniso, lam, h):
+    """The 1/2-data reading (prox of sigma F1* divides by 1 + sigma), the anisotropic
+    reading of ||grad x||_1 (per-component clamp to [-lambda, lambda]) and a data length
+    unit h != 1 (data term ||h W x - h b||^2) each converge to the minimiser of their own
+    objective, found by ADMM with the matching data weight, operator and shrinkage
+    (eq. priorsys with and without 1/2; Section 2.3, g = ||grad x||_1).  A swapped
+    divisor, a wrong clamp bound or a dropped unit lands on another problem's minimiser:
+    those minima differ by far more than the 3e-5 gap allowed here.  lambda is chosen
+    per reading so that nonnegativity is active at the minimiser."""
     n, na, nd = 8, 6, 12
     g = oracle.make_geometry(n, na, nd)
     rng = np.random.default_rng(n)
@@ -139,22 +160,26 @@ def test_cp_variants_converge_to_independent_admm_minimiser(half, aniso, lam):
     WL = oracle.sparse_local(g)
     b = WL @ truth.ravel() + 0.3 * rng.standard_normal(WL.shape[0])
     W = WL.toarray()
-    rho = float(np.linalg.norm(W, 2) ** 2)
+    rho = float(np.linalg.norm(h * W, 2) ** 2)
     mins = {}
     for hh in (False, True):
         for aa in (False, True):
-            xa = _admm_tv_nonneg(W, b, n, n, lam, rho=rho, iters=10000, half=hh, aniso=aa)
-            mins[hh, aa] = (xa, oracle.cp_objective(WL, b, xa, lam, half=hh, aniso=aa))
-    xa, f1 = mins[half, aniso]
-    xa2 = _admm_tv_nonneg(W, b, n, n, lam, rho=rho / 10, iters=10000, half=half, aniso=aniso)
-    assert abs(oracle.cp_objective(WL, b, xa2, lam, half=half, aniso=aniso) - f1) <= 1e-8 * f1
+            for hu in {h, 1.0}:
+                xa = _admm_tv_nonneg(hu * W, hu * b, n, n, lam, rho=rho, iters=10000, half=hh,
+                                     aniso=aa)
+                mins[hh, aa, hu] = xa
+    xa = mins[half, aniso, h]
+    f1 = oracle.cp_objective(WL, b, xa, lam, half=half, aniso=aniso, h=h)
+    xa2 = _admm_tv_nonneg(h * W, h * b, n, n, lam, rho=rho / 10, iters=10000, half=half,
+                          aniso=aniso)
+    assert abs(oracle.cp_objective(WL, b, xa2, lam, half=half, aniso=aniso, h=h) - f1) <= 1e-8 * f1
     # the other readings' minimisers are clearly suboptimal for this objective
-    for key, (xo, _) in mins.items():
-        if key != (half, aniso):
-            assert oracle.cp_objective(WL, b, xo, lam, half=half, aniso=aniso) - f1 > 1e-3 * f1
-    s, t = oracle.cp_steps(WL, (n, n), iters=300)
-    x = oracle.cp_tv_nonneg(WL, b, (n, n), lam, s, t, 40000, half=half, aniso=aniso)
-    gap = oracle.cp_objective(WL, b, x, lam, half=half, aniso=aniso) - f1
+    for key, xo in mins.items():
+        if key != (half, aniso, h):
+            assert oracle.cp_objective(WL, b, xo, lam, half=half, aniso=aniso, h=h) - f1 > 1e-3 * f1
+    s, t = oracle.cp_steps(WL, (n, n), iters=300, h=h)
+    x = oracle.cp_tv_nonneg(WL, b, (n, n), lam, s, t, 40000, half=half, aniso=aniso, h=h)
+    gap = oracle.cp_objective(WL, b, x, lam, half=half, aniso=aniso, h=h) - f1
     assert x.min() >= 0.0 and (x == 0).sum() > 0
     assert -1e-9 * f1 <= gap <= 3e-5 * f1, gap
     assert np.abs(x - xa).max() < 2e-2
