@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the local-ROI hot path on one MI355X.
 
-One step = one complete local reconstruction of the single-ROI workload:
-1024^2 grid, 128 angles, 1536 bins, Poisson noise (I0 = 1e4), 128^2 ROI with
-a 32 px margin (192^2 extended part): Ram-Lak FBP exterior estimate of the
-whole sinogram, exterior subtraction on the ROI's detector band, 300 CP
-iterations (TV lambda = 0.02 + nonnegativity), crop.  The sinogram is resident
-in HBM before timing starts.  The CP step size is a per-(geometry, shape)
-plan computed once by a power iteration and cached, like an FFT plan.
+One step = one complete tiled reconstruction of a 4096^2 slice (512 angles, 6144
+bins, Poisson noise I0 = 5e3): the Ram-Lak FBP exterior estimate of the whole
+sinogram, the exterior residual, the band subtraction of 256 local parts (16 x 16
+tiles of 256^2, each extended by a 32 px margin), 200 CP iterations of TV
+(lambda = 0.01) + nonnegativity on all 256 parts together (one launch per operator
+per iteration, captured in a hipGraph), and the crops stitched into the 4096^2 image
+without blending.  The sinogram is resident in HBM before timing starts; the CP step
+sizes are per-(geometry, shape) plans computed once by a power iteration and cached.
+`value` = tile solves/s.
+
+Secondary legs: the single 128^2 ROI of a 1024^2 slice solved one at a time (with a
+quality comparison against the phantom and the global solve), 64 uneven ROIs of a
+2048^2 slice batched (vs one at a time), the paper's own local method (Alg. 1, 2, 3)
+on those ROIs, and serving of ROI requests over 64 resident 2048^2 slices.
 
 Prints one JSON line.  --gpus N > 1 is refused: the benchmark runs on one GPU.
 """
@@ -17,6 +24,7 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -24,15 +32,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Roofline peaks.  FP/BP are bound by the vector ALU (nothing is a dense
-# contraction and the algorithmic intensity is ~10-60 updates per HBM byte):
-# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.32e12 FP32 lane-instructions/s,
-# and one Joseph update needs at least 4.5 of them (per pair of taps: position,
-# clamp, fraction, index, address, then difference, FMA and sum).
+# Roofline of the projectors.  Nothing here is a dense contraction, and a projector
+# moves 0.03-0.2 B of compulsory HBM traffic per pixel-ray update, so the bound is the
+# vector ALU: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.32e12 FP32 lane-instructions/s,
+# and a minimal Joseph sample needs about 2.5 of them per update (coordinate step,
+# floor, fraction, lerp and accumulate, shared by the two taps of an interpolation):
+# 15.7e12 updates/s.  The kernels here issue about 4.5 lane-instructions per update
+# (the position is re-anchored, the band or image read is addressed, the weights are
+# clamped); the share of the lane-instruction rate that corresponds to is reported
+# beside the roofline fraction as valu_frac_at_4_5.
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-OPS_PER_UPDATE = 4.5
+OPS_PER_UPDATE = 2.5
 PEAK_UPDATES = VALU_LANE_OPS / OPS_PER_UPDATE
+KERNEL_OPS_PER_UPDATE = 4.5
 HBM_PEAK_GBS = 8000.0
+
+
+def alu_roofline(kernel, updates_per_launch, launch_us, traffic=None):
+    """Roofline object of a projector kernel: algorithmic updates (the exact nonzero
+    count of W_L over the launch's regions) per average launch duration."""
+    rate = updates_per_launch / (launch_us * 1e-6)
+    return {"bound": "alu", "kernel": kernel, "achieved": rate / 1e9,
+            "peak": PEAK_UPDATES / 1e9, "unit": "Gupdate/s", "frac": rate / PEAK_UPDATES,
+            "traffic": traffic, "avg_launch_us": launch_us,
+            "updates_per_launch": updates_per_launch,
+            "valu_frac_at_4_5": rate * KERNEL_OPS_PER_UPDATE / VALU_LANE_OPS}
+
+
+def total_nnz(ctx, g, exts, workers=16):
+    """Exact nonzero count of W_L summed over the regions (host count, in threads: the
+    library call releases the interpreter)."""
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        return int(sum(ex.map(lambda e: ctx.tomo_roi_nnz(g, e), exts)))
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1604_02292_amd", "csrc", "tomo_kernels.hip")
@@ -91,10 +122,11 @@ def cpu_baseline(d, cfg, roi, margin):
     t_ext = time.perf_counter() - t0
     shape = (ext[2], ext[3])
     t0 = time.perf_counter()
-    s, t = oracle.cp_steps(WL, shape)
+    h = 1.0 / cfg["n"]
+    s, t = oracle.cp_steps(WL, shape, h=h)
     t_step = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.cp_tv_nonneg(WL, b, shape, cfg["lam"], s, t, 10)
+    oracle.cp_tv_nonneg(WL, b, shape, cfg["lam"], s, t, 10, h=h)
     t_10 = time.perf_counter() - t0
     est = t_fbp + t_ext + t_step + t_10 * cfg["iters"] / 10.0
     log(f"cpu oracle: fbp {t_fbp:.2f}s ext {t_ext:.2f}s step {t_step:.2f}s 10 its {t_10:.2f}s "
@@ -170,7 +202,7 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
                   for r in rois]
         outs = [torch.empty((r[2], r[3]), dtype=torch.float32, device="cuda") for r in rois]
         log(f"batched: inputs ready, {len(rois)} ROIs, {its} iterations")
-        nnz = sum(ctx.tomo_roi_nnz(g, ctx.tomo_roi_ext(g, r[:4], r[4])) for r in rois)
+        nnz = total_nnz(ctx, g, [ctx.tomo_roi_ext(g, r[:4], r[4]) for r in rois])
         updates = 2 * its * nnz
         best, t_fp, t_bp = ctx.tomo_autotune(g, sino, params, outs, x_ext=xe)
         log(f"batched: autotune {best} (fp {1e3 * t_fp:.1f} us, bp {1e3 * t_bp:.1f} us per launch)")
@@ -186,12 +218,9 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
                 "fp_updates_per_s": nnz / (t_fp * 1e-3), "bp_updates_per_s": nnz / (t_bp * 1e-3)}
         # the batch's dominant iteration kernel against the ALU roof of the projectors
         dom_fp = t_fp >= t_bp
-        rate = nnz / ((t_fp if dom_fp else t_bp) * 1e-3)
-        kern["roofline"] = {"bound": "alu", "kernel": "fp_kernel" if dom_fp else "bp_kernel",
-                            "achieved": rate / 1e9, "peak": PEAK_UPDATES / 1e9,
-                            "unit": "Gupdate/s", "frac": rate / PEAK_UPDATES,
-                            "avg_launch_us": 1e3 * (t_fp if dom_fp else t_bp),
-                            "updates_per_launch": nnz}
+        kname = "fp_kernel" if dom_fp else "bp_kernel"
+        kern["roofline"] = alu_roofline(kname, nnz, 1e3 * (t_fp if dom_fp else t_bp),
+                                        profiled_traffic("batch64-n2048-a256", kname))
         if not compare:
             return {"roi_solves_per_s": len(rois) / t_batch, "ms_per_batch": 1e3 * t_batch,
                     "updates_per_s": updates / t_batch, **kern}
@@ -256,7 +285,7 @@ def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
         params = [make_params(r[:4], r[4], "local", iters=its, box=(0.0, float("inf")))
                   for r in rois]
         outs = [torch.empty((r[2], r[3]), dtype=torch.float32, device="cuda") for r in rois]
-        nnz = sum(ctx.tomo_roi_nnz(g, ctx.tomo_roi_ext(g, r[:4], r[4])) for r in rois)
+        nnz = total_nnz(ctx, g, [ctx.tomo_roi_ext(g, r[:4], r[4]) for r in rois])
         for _ in range(2):   # the second call captures the iteration graph
             ctx.roi_solve_local(g, D, params, outs)
         torch.cuda.synchronize()
@@ -287,11 +316,7 @@ def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
                # (both channels share one weight per update), and the filtered data
                # against HBM (algorithmic bytes: filters and data spectra read,
                # filtered data written)
-               "roofline": {"bound": "alu", "kernel": "bp_kernel (two-channel)",
-                            "achieved": nnz / (bp_us * 1e-6) / 1e9,
-                            "peak": PEAK_UPDATES / 1e9, "unit": "Gupdate/s",
-                            "frac": nnz / (bp_us * 1e-6) / PEAK_UPDATES,
-                            "avg_launch_us": bp_us, "updates_per_launch": nnz},
+               "roofline": alu_roofline("bp_kernel (two-channel)", nnz, bp_us),
                "filtered_data_roofline": {"bound": "hbm", "kernel": "filter_conv_kernel",
                                           "achieved": conv_bytes / t_conv / 1e9,
                                           "peak": 8000.0, "unit": "GB/s",
@@ -389,12 +414,12 @@ def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
         ctx.close()
 
 
-def serving_leg(torch, slices, n_req=200, n_warm=64, fractions=(0.25, 0.5, 0.75, 0.9)):
+def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.75, 0.9)):
     """64 resident 2048^2 slices (512 angles x 3072 bins); requests with side
     U{32..512}, margin ceil(side/4), 80% CP-TV / 20% nonnegative SIRT, 100-300
     iterations.  Capacity = completion rate with all requests queued at once;
     latency = submit-to-done at Poisson arrivals of the given fractions of that
-    rate; plain = the same requests solved one at a time with roi_solve; small
+    rate; plain = the first 200 of those requests solved one at a time with roi_solve; small
     budget = the capacity run again with a workspace that holds only a few
     slots next to two resident slices, so admission by HBM budget binds."""
     import synth
@@ -448,22 +473,24 @@ def serving_leg(torch, slices, n_req=200, n_warm=64, fractions=(0.25, 0.5, 0.75,
                           "p99_ms": pct(lat_open, 99)})
             log(f"serving: {fr:.2f} x capacity ({fr * cap:.1f} req/s): p50 {pct(lat_open, 50):.1f} "
                 f"ms p99 {pct(lat_open, 99):.1f} ms")
-        # plain one-at-a-time solves of the capacity requests (same exterior estimates)
+        # plain one-at-a-time solves of the first n_plain capacity requests (same
+        # exterior estimates)
+        n_plain = min(len(reqs), 200)
         xes = {}
-        for r in reqs:
+        for r in reqs[:n_plain]:
             if r["slice"] not in xes:
                 xe = torch.empty((cfg["n"], cfg["n"]), device="cuda")
                 ctx.tomo_fbp_ramlak(g, sinos[r["slice"]], xe)
                 xes[r["slice"]] = xe
         torch.cuda.synchronize()
-        plain_outs = [torch.empty_like(o) for o in outs]
+        plain_outs = [torch.empty_like(o) for o in outs[:n_plain]]
         t0 = time.perf_counter()
-        for r, o in zip(reqs, plain_outs):
+        for r, o in zip(reqs[:n_plain], plain_outs):
             ctx.roi_solve(g, sinos[r["slice"]], prm(r), o, x_ext=xes[r["slice"]])
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         diff = max(float((a - b).abs().max() / (b.abs().max() + 1e-30))
-                   for a, b in zip(outs, plain_outs))
+                   for a, b in zip(outs[:n_plain], plain_outs))
         del xes
     finally:
         ctx.close()
@@ -479,42 +506,307 @@ def serving_leg(torch, slices, n_req=200, n_warm=64, fractions=(0.25, 0.5, 0.75,
     finally:
         ctx.close()
     mid = sweep[min(1, len(sweep) - 1)]
-    log(f"serving: register {t_reg:.2f}s; capacity {cap:.1f} req/s; plain {n_req / t_plain:.1f} "
+    log(f"serving: register {t_reg:.2f}s; capacity {cap:.1f} req/s; plain {n_plain / t_plain:.1f} "
         f"req/s; {small >> 20} MiB budget: {len(reqs_small) / t_small:.1f} req/s")
     return {"workload": "serve-64x2048-a512: 64 resident slices, side U{32..512}, 80% CP-TV / "
                         "20% SIRT, 100-300 its",
             "capacity_solves_per_s": cap, "offered_qps": mid["offered_qps"],
             "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "latency_sweep": sweep,
             "saturated_p50_ms": pct(lat_cap, 50), "saturated_p99_ms": pct(lat_cap, 99),
-            "one_at_a_time_solves_per_s": n_req / t_plain,
-            "requests": n_req, "max_rel_diff_served_vs_plain": diff,
+            "one_at_a_time_solves_per_s": n_plain / t_plain, "one_at_a_time_requests": n_plain,
+            "requests": n_req, "warmup_requests": n_warm, "max_rel_diff_served_vs_plain": diff,
             "small_budget": {"workspace_mib": small >> 20, "resident_slices": 2,
                              "capacity_solves_per_s": len(reqs_small) / t_small,
                              "p50_ms": pct(lat_small, 50), "p99_ms": pct(lat_small, 99),
                              "workspace_usage": peak}}
 
 
+def tiles_cpu_baseline(d, n_ang_sample=16, n_cp=3, n_pow=3):
+    """The FP64 oracle, one thread, on a bounded sample of the tiled 4096^2 workload:
+    the Ram-Lak filter of the whole sinogram; the pixel-driven backprojection of one
+    256^2 tile of the grid (x 256 for the whole FBP); for one interior tile (extended
+    320^2) the sparse W_L build, the exterior subtraction on n_ang_sample of the 512
+    angles (x 512 / n_ang_sample), n_cp CP iterations (x 200 / n_cp) and n_pow
+    power-iteration steps (x 100 / n_pow, once for each of the 4 extended shapes of the
+    tiling).  The batch time is the sum with the tile costs times 256, a labelled
+    extrapolation from the measured pieces."""
+    import oracle
+    import synth
+    cfg = d["cfg"]
+    n, na = cfg["n"], cfg["n_angles"]
+    geo = oracle.make_geometry(n, na, cfg["n_det"])
+    sino = d["sino"].astype(np.float32).astype(np.float64)
+    rois = synth.roi_list("c4")
+    tm = {}
+    t0 = time.perf_counter()
+    q = oracle.fbp.ramp_filter(geo, sino)
+    tm["ramp_filter"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.bp_pixel(geo, q, (1920, 1920, 256, 256), workers=1)
+    tm["bp_256"] = time.perf_counter() - t0
+    r0, c0, rr, cc, m = rois[16 * 5 + 6]
+    ext = oracle.roi_extend((r0, c0, rr, cc), m, n)
+    t0 = time.perf_counter()
+    WL = oracle.sparse_local(geo, ext)
+    tm["wl_build"] = time.perf_counter() - t0
+    used = np.zeros(na * geo.n_det, bool)
+    used[np.unique(WL.tocoo().row)] = True
+    used = used.reshape(na, geo.n_det)
+    sample = np.zeros_like(used)
+    pick = np.arange(0, na, na // n_ang_sample)[:n_ang_sample]
+    sample[pick] = used[pick]
+    xe = np.zeros((n, n))
+    t0 = time.perf_counter()
+    b = oracle.exterior_subtract(geo, sino, xe, ext, bins=sample)
+    tm["exterior_sample"] = time.perf_counter() - t0
+    shape, h = (ext[2], ext[3]), 1.0 / n
+    t0 = time.perf_counter()
+    oracle.power_norm_sq(WL, shape, n_pow, h)
+    tm["power_sample"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.cp_tv_nonneg(WL, b, shape, cfg["lam"], 0.35, 0.35, n_cp, h=h)
+    tm["cp_sample"] = time.perf_counter() - t0
+    measured = sum(tm.values())
+    t_fbp = tm["ramp_filter"] + tm["bp_256"] * (n * n) / (256 * 256)
+    t_tile = (tm["wl_build"] + tm["exterior_sample"] * na / len(pick) +
+              tm["cp_sample"] * cfg["iters"] / n_cp)
+    t_power = 4 * tm["power_sample"] * 100 / n_pow
+    t_batch = t_fbp + len(rois) * t_tile + t_power
+    log(f"cpu oracle (tiles): {', '.join(f'{k} {v:.2f}s' for k, v in tm.items())} -> tile "
+        f"{t_tile:.0f}s, batch {t_batch:.0f}s (one thread, extrapolated)")
+    return {"value": len(rois) / t_batch, "unit": "tile solves/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 NumPy oracle on one thread: Ram-Lak filter of the whole sinogram, "
+                      "backprojection of one 256^2 tile of the grid (x256 for the FBP), and for "
+                      f"one interior tile the sparse W_L build, the exterior subtraction on "
+                      f"{len(pick)} of {na} angles, {n_cp} CP iterations and {n_pow} power "
+                      f"steps; measured {measured:.1f}s, extrapolated to the 256-tile batch "
+                      f"({t_batch:.0f}s per batch, {t_tile:.0f}s per tile)",
+            "pieces_s": tm, "tile_s": t_tile, "batch_s": t_batch}
+
+
+def tiles_leg(torch, d, steps, warmup, quality=True):
+    """Headline: the 4096^2 slice as 16 x 16 tiles of 256^2 + 32 px margin, 512 angles,
+    6144 bins, 200 CP-TV iterations, stitched; each step one roi_solve_stitched call."""
+    import synth
+    from paper_1604_02292_amd import Context, make_params
+    cfg = d["cfg"]
+    n = cfg["n"]
+    rois = synth.roi_list("c4")
+    ctx = Context(0, workspace_bytes=16 << 30)
+    try:
+        g = ctx.tomo_set_geometry(n, cfg["n_angles"], cfg["n_det"])
+        sino = torch.from_numpy(d["sino"].astype(np.float32)).cuda()
+        params = [make_params(r[:4], r[4], "cp", cfg["lam"], cfg["iters"]) for r in rois]
+        img = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+        t0 = time.perf_counter()
+        nnz = total_nnz(ctx, g, [ctx.tomo_roi_ext(g, r[:4], r[4]) for r in rois])
+        log(f"tiles: {len(rois)} tiles, nnz(W_L) summed {nnz} (counted in "
+            f"{time.perf_counter() - t0:.1f}s)")
+        launch = ctx.tomo_resolve_launch(g, params)
+        for _ in range(max(2, warmup)):   # step sizes, then the graph capture
+            ctx.roi_solve_stitched(g, sino, params, img)
+        torch.cuda.synchronize()
+        lat = []
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            ctx.roi_solve_stitched(g, sino, params, img)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        total = time.perf_counter() - t_start
+        # kernel durations: the next solve first replays 50 back-to-back launches of each
+        # iteration kernel on its own data between two HIP events on the solve's stream
+        ctx.tomo_kernel_timing(2)
+        ctx.tomo_kernel_time(0, reset=True)
+        ctx.roi_solve_stitched(g, sino, params, img)
+        torch.cuda.synchronize()
+        ctx.tomo_kernel_timing(0)
+        n_fp, ms_fp = ctx.tomo_kernel_time(0)
+        n_bp, ms_bp = ctx.tomo_kernel_time(1)
+        fp_us, bp_us = 1e3 * ms_fp / max(1, n_fp), 1e3 * ms_bp / max(1, n_bp)
+        # the exterior estimate alone (Ram-Lak FBP of the whole sinogram)
+        fbp = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        ctx.tomo_fbp_ramlak(g, sino, fbp)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(3):
+            ctx.tomo_fbp_ramlak(g, sino, fbp)
+        ev1.record()
+        torch.cuda.synchronize()
+        fbp_ms = ev0.elapsed_time(ev1) / 3
+        dom_fp = fp_us >= bp_us
+        kname = "fp_kernel" if dom_fp else "bp_kernel"
+        traffic = profiled_traffic("tiles256-n4096-a512", kname)
+        roof = alu_roofline(kname, nnz, fp_us if dom_fp else bp_us, traffic)
+        if traffic:
+            roof["hbm_gb_per_s"] = traffic / ((fp_us if dom_fp else bp_us) * 1e-6) / 1e9
+        ms = 1e3 * total / steps
+        log(f"tiles: {steps} steps {ms:.1f} ms/step ({len(rois) * steps / total:.1f} tile solves/s); "
+            f"fp {fp_us:.1f} us, bp {bp_us:.1f} us per launch ({nnz / (fp_us * 1e-6) / 1e12:.2f} / "
+            f"{nnz / (bp_us * 1e-6) / 1e12:.2f} T updates/s); FBP {fbp_ms:.2f} ms")
+        res = {"value": len(rois) * steps / total, "ms_per_step": ms,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "launch": launch, "fp_us": fp_us, "bp_us": bp_us,
+               "fp_updates_per_s": nnz / (fp_us * 1e-6), "bp_updates_per_s": nnz / (bp_us * 1e-6),
+               "updates_per_s": 2 * cfg["iters"] * nnz / (total / steps), "fbp_ms": fbp_ms,
+               "roofline": roof}
+        if quality:
+            # the global CP-TV solve of the whole slice (same lambda and iterations), the
+            # FBP, and the stitched tiles, against each other and the phantom
+            glob = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            gprm = make_params((0, 0, n, n), 0, "cp", cfg["lam"], cfg["iters"])
+            ctx.roi_solve(g, sino, gprm, glob)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.roi_solve(g, sino, gprm, glob)
+            torch.cuda.synchronize()
+            t_glob = time.perf_counter() - t0
+            fit = []
+            for x in (img, glob):
+                proj = torch.empty_like(sino)
+                ctx.tomo_fp(g, (0, 0, n, n), x, proj)
+                torch.cuda.synchronize()
+                fit.append(float(torch.linalg.norm(proj - sino) / torch.linalg.norm(sino)))
+            truth = d["image"]
+            st, gl, fb = (t.double().cpu().numpy() for t in (img, glob, fbp))
+            relq = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            res["quality"] = {"stitched_vs_global_rel": relq(st, gl),
+                              "stitched_vs_phantom_rel": relq(st, truth),
+                              "global_vs_phantom_rel": relq(gl, truth),
+                              "fbp_vs_phantom_rel": relq(fb, truth),
+                              "data_residual_stitched": fit[0], "data_residual_global": fit[1],
+                              "global_solve_ms": 1e3 * t_glob}
+            log("tiles quality: " + ", ".join(f"{k} {v:.4g}" for k, v in res["quality"].items()))
+        return res
+    finally:
+        ctx.close()
+
+
+def single_roi_leg(torch, d, steps, warmup, autotune=False, quality=True, cpu=True):
+    """One 128^2 ROI + 32 px margin of a 1024^2 slice (128 angles, 1536 bins), 300 CP-TV
+    iterations, solved one at a time: FBP exterior, band subtraction, iterations, crop."""
+    from paper_1604_02292_amd import Context, make_params
+    cfg = d["cfg"]
+    import synth
+    r0, c0, rr, cc, margin = synth.roi_list("c2")[0]
+    roi = (r0, c0, rr, cc)
+    ctx = Context(0, workspace_bytes=8 << 30)
+    try:
+        g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+        prm = make_params(roi, margin, "cp", cfg["lam"], cfg["iters"])
+        sino = torch.from_numpy(d["sino"].astype(np.float32)).cuda()
+        out = torch.empty((rr, cc), dtype=torch.float32, device="cuda")
+        ext = ctx.tomo_roi_ext(g, roi, margin)
+        nnz = ctx.tomo_roi_nnz(g, ext)
+        if autotune:
+            best, t_fp, t_bp = ctx.tomo_autotune(g, sino, [prm], [torch.empty_like(out)])
+            log(f"single ROI autotune: {best}")
+        else:
+            # the size heuristics' shapes (for this workload also the autotuner's), so that
+            # a profiled run of this command runs the same kernels
+            best = ctx.tomo_resolve_launch(g, [prm])
+        for _ in range(max(2, warmup)):   # the second solve captures the iteration graph
+            ctx.roi_solve(g, sino, prm, out)
+        torch.cuda.synchronize()
+        lat = []
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            ctx.roi_solve(g, sino, prm, out)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        total = time.perf_counter() - t_start
+        ctx.tomo_kernel_timing(2)
+        ctx.tomo_kernel_time(0, reset=True)
+        for _ in range(3):
+            ctx.roi_solve(g, sino, prm, out)
+        torch.cuda.synchronize()
+        ctx.tomo_kernel_timing(0)
+        n_fp, ms_fp = ctx.tomo_kernel_time(0)
+        n_bp, ms_bp = ctx.tomo_kernel_time(1)
+        fp_us = 1e3 * ms_fp / max(1, n_fp)
+        bp_us = 1e3 * ms_bp / max(1, n_bp)
+        log(f"single ROI: {steps} steps {1e3 * total / steps:.3f} ms/step; fp {fp_us:.2f} us, "
+            f"bp {bp_us:.2f} us per launch; nnz/launch {nnz}")
+        dom_bp = ms_bp >= ms_fp
+        kname = "bp_kernel" if dom_bp else "fp_kernel"
+        res = {"workload": "single-roi-1024: 1024^2 grid, 128 angles, 1536 bins, 128^2 ROI + 32 px "
+                           "margin, CP-TV lambda 0.02 + nonneg, 300 its, one ROI at a time",
+               "roi_solves_per_s": steps / total, "ms_per_solve": 1e3 * total / steps,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "launch": best, "extended_roi": list(ext),
+               "fp_updates_per_s": nnz / (fp_us * 1e-6), "bp_updates_per_s": nnz / (bp_us * 1e-6),
+               "roofline": alu_roofline(kname, nnz, bp_us if dom_bp else fp_us,
+                                        profiled_traffic("single-roi-1024", kname))}
+        if quality:
+            # the ROI of the global TV solve on the whole grid (same lambda and iterations),
+            # the FBP and the paper's own local method (Alg. 1 filters, Alg. 2 with box
+            # [0, inf), as many iterations), against the phantom inside the ROI
+            n = cfg["n"]
+            gout = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            gprm = make_params((0, 0, n, n), 0, "cp", cfg["lam"], cfg["iters"])
+            ctx.roi_solve(g, sino, gprm, gout)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.roi_solve(g, sino, gprm, gout)
+            torch.cuda.synchronize()
+            t_glob = time.perf_counter() - t0
+            fbp = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            ctx.tomo_fbp_ramlak(g, sino, fbp)
+            its = cfg["iters"]
+            F = torch.empty((its, cfg["n_angles"], cfg["n_det"]), dtype=torch.float32,
+                            device="cuda")
+            D = torch.empty_like(F)
+            ctx.tomo_sirt_filters(g, its, F)
+            ctx.tomo_sirt_filter_sino(g, F, sino, D)
+            alg2 = torch.empty((rr, cc), dtype=torch.float32, device="cuda")
+            ctx.roi_solve_local(g, D, [make_params(roi, margin, "local", iters=its,
+                                                   box=(0.0, float("inf")))], [alg2])
+            torch.cuda.synchronize()
+            del F, D
+            loc = out.double().cpu().numpy()
+            glob = gout.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
+            fbp_r = fbp.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
+            truth = d["image"][r0:r0 + rr, c0:c0 + cc]
+            alg2 = alg2.double().cpu().numpy()
+            relq = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            res["quality"] = {"local_vs_global_rel": relq(loc, glob),
+                              "fbp_vs_global_rel": relq(fbp_r, glob),
+                              "local_vs_phantom_rel": relq(loc, truth),
+                              "global_vs_phantom_rel": relq(glob, truth),
+                              "fbp_vs_phantom_rel": relq(fbp_r, truth),
+                              "alg2_vs_phantom_rel": relq(alg2, truth),
+                              "global_solve_ms": 1e3 * t_glob}
+            log("single ROI quality: " + ", ".join(f"{k} {v:.4g}" for k, v in res["quality"].items()))
+    finally:
+        ctx.close()
+    if cpu:
+        res["cpu_baseline"] = cpu_baseline(d, cfg, roi, margin)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-single", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-local", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="requests per serving load point (the survey's full run uses 2000)")
-    ap.add_argument("--serve-warmup", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests per serving load point")
+    ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--no-quality", action="store_true",
-                    help="skip the untimed quality comparison of the single-ROI leg "
-                         "(global solve, Alg. 2 and FBP against the phantom)")
-    ap.add_argument("--only", choices=["batch", "serve", "local"], default=None,
-                    help="run only one secondary leg (for profiling) and print its JSON")
+                    help="skip the untimed quality comparisons (global solves, FBP, Alg. 2 "
+                         "against the phantom)")
+    ap.add_argument("--only", choices=["tiles", "single", "batch", "serve", "local"], default=None,
+                    help="run only one leg (for profiling) and print its JSON")
     ap.add_argument("--iters", type=int, default=None,
-                    help="override the iteration count of --only legs (profiling runs)")
+                    help="override the iteration count of the batch and local legs (profiling)")
     ap.add_argument("--fixed-step", type=float, default=0.0,
-                    help="explicit CP step for --only legs, skipping the power iteration")
+                    help="explicit CP step for the batch leg, skipping the power iteration")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes for input generation (0 = one per core, at most 16)")
     ap.add_argument("--autotune", action="store_true",
@@ -544,15 +836,21 @@ def main():
 
     import synth
     gw = args.gen_workers or None
+    want = (lambda leg: args.only == leg) if args.only else (lambda leg: True)
+    quality = not args.no_quality
     # all inputs are generated before the GPU is initialised (the generator forks)
-    d3 = slices = None
-    if args.only != "serve" and not (args.only is None and args.skip_batch and args.skip_local):
-        d3 = synth.make_inputs("c3", with_image=False, workers=gw)
-    if args.only != "batch" and not (args.only is None and args.skip_serve):
-        slices = synth.make_slices("c5", workers=gw)
-    log("inputs generated")
+    t0 = time.perf_counter()
+    d4 = synth.make_inputs("c4", with_image=quality and args.only is None,
+                           workers=gw) if want("tiles") else None
+    d2 = (synth.make_inputs("c2", with_image=quality, workers=1)
+          if want("single") and not args.skip_single else None)
+    d3 = (synth.make_inputs("c3", with_image=False, workers=gw)
+          if (want("batch") and not args.skip_batch) or (want("local") and not args.skip_local)
+          else None)
+    slices = (synth.make_slices("c5", workers=gw)
+              if want("serve") and not args.skip_serve else None)
+    log(f"inputs generated ({time.perf_counter() - t0:.1f}s)")
     import torch
-    from paper_1604_02292_amd import Context, make_params
 
     if args.only == "batch":
         print(json.dumps(batched_leg(torch, d3, reps=args.steps, compare=False, iters=args.iters,
@@ -566,135 +864,43 @@ def main():
         print(json.dumps(local_leg(torch, d3, reps=args.steps, iters=args.iters, compare=False,
                                    cpu=False)), flush=True)
         return
+    if args.only == "single":
+        print(json.dumps(single_roi_leg(torch, d2, args.steps, args.warmup, args.autotune,
+                                        quality=False, cpu=False)), flush=True)
+        return
 
-    d = synth.make_inputs("c2", with_image=True, workers=1)
-    cfg = d["cfg"]
-    r0, c0, rr, cc, margin = synth.roi_list("c2")[0]
-    roi = (r0, c0, rr, cc)
-    ctx = Context(0, workspace_bytes=8 << 30)
-    g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
-    prm = make_params(roi, margin, "cp", cfg["lam"], cfg["iters"])
-    sino = torch.from_numpy(d["sino"].astype(np.float32)).cuda()
-    out = torch.empty((rr, cc), dtype=torch.float32, device="cuda")
-    ext = ctx.tomo_roi_ext(g, roi, margin)
-    nnz = ctx.tomo_roi_nnz(g, ext)
-
-    if args.autotune:
-        # one-time plan step (like an FFT plan): time every launch shape of the
-        # two projector kernels on this problem and keep the fastest for its class
-        best, t_fp, t_bp = ctx.tomo_autotune(g, sino, [prm], [torch.empty_like(out)])
-        log(f"autotune: {best} (fp {1e3 * t_fp:.2f} us, bp {1e3 * t_bp:.2f} us per launch)")
-    else:
-        # the size heuristics' shapes (for this workload they are also the ones the
-        # autotuner picks), so that a profiled run of this command runs the same kernels
-        best = ctx.tomo_resolve_launch(g, [prm])
-    for _ in range(max(2, args.warmup)):   # the second solve captures the iteration graph
-        ctx.roi_solve(g, sino, prm, out)
-    torch.cuda.synchronize()
-
-    # timed region: per-step latency (launch to completion); the iteration loop
-    # replays the cached hipGraph
-    lat = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        ctx.roi_solve(g, sino, prm, out)
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - t0) * 1e3)
-    t_end = time.perf_counter()
-    total = t_end - t_start
-
-    # kernel durations: each of these solves first replays 50 back-to-back
-    # launches of each iteration kernel on its own data (a captured graph, no
-    # dispatch gaps) between two HIP events on the solve's stream
-    ctx.tomo_kernel_timing(2)
-    ctx.tomo_kernel_time(0, reset=True)
-    t_ev = time.perf_counter()
-    n_ev = 3
-    for _ in range(n_ev):
-        ctx.roi_solve(g, sino, prm, out)
-    torch.cuda.synchronize()
-    t_ev = time.perf_counter() - t_ev
-    ctx.tomo_kernel_timing(0)
-    n_fp, ms_fp = ctx.tomo_kernel_time(0)
-    n_bp, ms_bp = ctx.tomo_kernel_time(1)
-    fp_us = 1e3 * ms_fp / max(1, n_fp)
-    bp_us = 1e3 * ms_bp / max(1, n_bp)
-    fp_rate = nnz / (fp_us * 1e-6)
-    bp_rate = nnz / (bp_us * 1e-6)
-    log(f"steps {args.steps} total {total:.3f}s ({1e3 * total / args.steps:.3f} ms/step); "
-        f"event pass {n_ev} solves {1e3 * t_ev / n_ev:.3f} ms/solve; fp {n_fp} launches avg "
-        f"{fp_us:.2f}us ({fp_rate / 1e9:.1f} Gupd/s), bp {n_bp} avg {bp_us:.2f}us "
-        f"({bp_rate / 1e9:.1f} Gupd/s); nnz/launch {nnz}")
-    dom_bp = ms_bp >= ms_fp
-    rate = bp_rate if dom_bp else fp_rate
-    kname = "bp_kernel" if dom_bp else "fp_kernel"
-    roofline = {"bound": "alu", "kernel": kname,
-                "achieved": rate / 1e9, "peak": PEAK_UPDATES / 1e9, "unit": "Gupdate/s",
-                "frac": rate / PEAK_UPDATES,
-                "traffic": profiled_traffic("single-roi-1024", kname),
-                "avg_launch_us": bp_us if dom_bp else fp_us, "updates_per_launch": nnz}
+    t = tiles_leg(torch, d4, args.steps, args.warmup, quality=quality and args.only is None)
+    cfg4 = d4["cfg"]
     res = {
-        "metric": "ROI solves/s (single 128^2 ROI, 300 CP-TV iterations, FBP exterior)",
-        "value": args.steps / total, "unit": "ROI solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps,
+        "metric": "tile solves/s (4096^2 slice as 256 local parts, 200 CP-TV iterations each, "
+                  "FBP exterior, stitched)",
+        "value": t.pop("value"), "unit": "tile solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t.pop("ms_per_step"),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded random-ellipse phantom, exact line integrals, Poisson noise)",
-        "config": {"workload": "single-roi-1024: 1024^2 grid, 128 angles, 1536 bins, "
-                               "128^2 ROI + 32 px margin, CP-TV lambda 0.02 + nonneg, 300 its",
-                   "extended_roi": list(ext), "launch": best},
-        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-        "fp_updates_per_s": fp_rate, "bp_updates_per_s": bp_rate,
-        "roofline": roofline,
+        "data": "synthetic (seeded random-ellipse phantom + texture, exact line integrals, "
+                "Poisson noise)",
+        "config": {"workload": "tiles256-n4096-a512: 4096^2 grid, 512 angles, 6144 bins, "
+                               "16 x 16 tiles of 256^2 + 32 px margin, CP-TV lambda "
+                               f"{cfg4['lam']} + nonneg, {cfg4['iters']} its, stitched",
+                   "tiles": 256, "launch": t.pop("launch")},
+        "p50_ms": t.pop("p50_ms"), "p99_ms": t.pop("p99_ms"),
+        "roofline": t.pop("roofline"),
     }
-    # quality, not timed: the ROI of the global TV solve on the whole 1024^2 grid (same
-    # lambda and iterations, no exterior), and the local, global and FBP results against
-    # the phantom inside the ROI
-    if not args.no_quality:
-        n = cfg["n"]
-        gout = torch.empty((n, n), dtype=torch.float32, device="cuda")
-        gprm = make_params((0, 0, n, n), 0, "cp", cfg["lam"], cfg["iters"])
-        ctx.roi_solve(g, sino, gprm, gout)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.roi_solve(g, sino, gprm, gout)
-        torch.cuda.synchronize()
-        t_glob = time.perf_counter() - t0
-        fbp = torch.empty((n, n), dtype=torch.float32, device="cuda")
-        ctx.tomo_fbp_ramlak(g, sino, fbp)
-        torch.cuda.synchronize()
-        loc = out.double().cpu().numpy()
-        glob = gout.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
-        fbp_r = fbp.double().cpu().numpy()[r0:r0 + rr, c0:c0 + cc]
-        truth = d["image"][r0:r0 + rr, c0:c0 + cc]
-        # the paper's own local method on the same ROI (Alg. 1 filters, Alg. 2, box [0, inf),
-        # as many iterations as the CP solve)
-        its = cfg["iters"]
-        F = torch.empty((its, cfg["n_angles"], cfg["n_det"]), dtype=torch.float32, device="cuda")
-        D = torch.empty_like(F)
-        ctx.tomo_sirt_filters(g, its, F)
-        ctx.tomo_sirt_filter_sino(g, F, sino, D)
-        alg2 = torch.empty((rr, cc), dtype=torch.float32, device="cuda")
-        ctx.roi_solve_local(g, D, [make_params(roi, margin, "local", iters=its,
-                                               box=(0.0, float("inf")))], [alg2])
-        torch.cuda.synchronize()
-        alg2 = alg2.double().cpu().numpy()
-        del F, D
-        relq = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
-        res["quality"] = {"local_vs_global_rel": relq(loc, glob), "local_vs_phantom_rel": relq(loc, truth),
-                          "global_vs_phantom_rel": relq(glob, truth),
-                          "fbp_vs_phantom_rel": relq(fbp_r, truth),
-                          "alg2_vs_phantom_rel": relq(alg2, truth), "global_solve_ms": 1e3 * t_glob}
-        log(f"quality: local vs global {res['quality']['local_vs_global_rel']:.3e}; vs phantom: local "
-            f"{res['quality']['local_vs_phantom_rel']:.3e}, global {res['quality']['global_vs_phantom_rel']:.3e}"
-            f", FBP {res['quality']['fbp_vs_phantom_rel']:.3e}, Alg. 2 "
-            f"{res['quality']['alg2_vs_phantom_rel']:.3e}; global solve {1e3 * t_glob:.1f} ms")
-    ctx.close()
+    res.update(t)
+    if args.only == "tiles":
+        print(json.dumps(res), flush=True)
+        return
+    if not args.skip_single:
+        try:
+            res["single_roi"] = single_roi_leg(torch, d2, max(5, args.steps), args.warmup,
+                                               args.autotune, quality=quality,
+                                               cpu=not args.no_cpu_baseline)
+        except Exception as e:   # the headline line must still print
+            res["single_roi"] = {"error": repr(e)}
     if not args.skip_batch:
         try:
             res["batched"] = batched_leg(torch, d3)
-        except Exception as e:   # the headline line must still print
+        except Exception as e:
             res["batched"] = {"error": repr(e)}
     if not args.skip_local:
         try:
@@ -707,7 +913,7 @@ def main():
         except Exception as e:
             res["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(d, cfg, roi, margin)
+        res["cpu_baseline"] = tiles_cpu_baseline(d4)
     print(json.dumps(res), flush=True)
 
 

@@ -459,7 +459,7 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
     for (int i = 0; i < count; ++i) {
         const RoiState& r = R[i];
         CK(launch_crop(r.x, r.ext.cols, r.roi.r0 - r.ext.r0, r.roi.c0 - r.ext.c0, r.roi.rows,
-                       r.roi.cols, outs[i], s));
+                       r.roi.cols, outs[i], r.roi.cols, s));
     }
 #undef CK
     cleanup();

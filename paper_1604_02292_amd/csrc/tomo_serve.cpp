@@ -405,7 +405,7 @@ void scheduler(tomo_ctx* ctx) {
             const RoiState& r = slots[q]->st;
             if (e == hipSuccess)
                 e = launch_crop(r.x, r.ext.cols, r.roi.r0 - r.ext.r0, r.roi.c0 - r.ext.c0,
-                                r.roi.rows, r.roi.cols, slots[q]->req.out, S.stream);
+                                r.roi.rows, r.roi.cols, slots[q]->req.out, r.roi.cols, S.stream);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(S.stream);
         const double tnow = now_ms();

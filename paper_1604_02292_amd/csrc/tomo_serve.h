@@ -20,9 +20,10 @@ struct SinoState {
     std::atomic<int> users{0};
 };
 
+// outs[i]: ROI i's crop, row pitch ldo (0: the ROI's width, i.e. contiguous).
 tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* x_ext_user,
                         const SinoState* reg, int count, const roi_params* params,
-                        float* const* outs, hipStream_t s);
+                        float* const* outs, hipStream_t s, int ldo = 0);
 
 // Compute x_ext (Ram-Lak FBP) and r into a SinoState's buffers on stream s.
 tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s);

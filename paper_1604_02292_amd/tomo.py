@@ -178,6 +178,19 @@ class Context:
                                              _ptr(x_ext, (n, n), "x_ext"), cnt, parr, oarr,
                                              _stream(stream)))
 
+    def roi_solve_stitched(self, geom, sino, params, img, x_ext=None, stream=None):
+        """Batched solve with every ROI's crop written into img (a contiguous float32
+        [n][ld] tensor, ld >= n) at the ROI's position."""
+        n, na, nd = self.geoms[geom]
+        cnt = len(params)
+        parr = (roi_params * cnt)(*params)
+        ptr = _ptr(img, None, "img")
+        if img.dim() != 2 or img.shape[0] != n or img.shape[1] < n:
+            raise ValueError(f"img has shape {tuple(img.shape)}, expected ({n}, >= {n})")
+        self._check(self.lib.roi_solve_stitched(
+            self.h, geom, _ptr(sino, (na, nd), "sino"), _ptr(x_ext, (n, n), "x_ext"), cnt, parr,
+            ptr, int(img.shape[1]), _stream(stream)))
+
     # -- the paper's local method (Alg. 1 filters, filtered data, Alg. 2) ----
     def tomo_sirt_filters(self, geom, iters, filters, stream=None):
         n, na, nd = self.geoms[geom]

@@ -20,8 +20,11 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_roofline_peak_is_the_alu_roof():
-    # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, 4.5 lane-instructions per update
-    assert abs(bench.PEAK_UPDATES - 256 * 4 * 16 * 2.4e9 / 4.5) <= 1e-6 * bench.PEAK_UPDATES
+    # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, 2.5 lane-instructions per minimal Joseph update
+    assert abs(bench.PEAK_UPDATES - 256 * 4 * 16 * 2.4e9 / 2.5) <= 1e-6 * bench.PEAK_UPDATES
+    r = bench.alu_roofline("fp_kernel", 1e9, 100.0)
+    assert abs(r["frac"] - 1e13 / bench.PEAK_UPDATES) < 1e-12
+    assert abs(r["valu_frac_at_4_5"] - 1e13 * 4.5 / (256 * 4 * 16 * 2.4e9)) < 1e-12
 
 
 def _record(h, nbytes):
