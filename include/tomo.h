@@ -341,7 +341,12 @@ tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
  *                         of 8 waves, one group of 64 rays each)
  *   fp_rays_per_lane      1, or 2 (with one segment): each lane projects two
  *                         adjacent rays from 4-pixel reads (detector spacing
- *                         below sqrt 2 pixels; otherwise 1 is used)
+ *                         below sqrt 2 pixels; otherwise 1 is used), or 4: the
+ *                         LDS-staged forward projector (32 lines of the regions
+ *                         at a time in LDS, shared by groups of up to 64 angles;
+ *                         regions whose padded lines hold at most 400 entries,
+ *                         about 394 pixels a side, and bands of at most 2048
+ *                         rays; elsewhere 2 is used)
  *   fp_xcd_order          order in which forward-projector work items are dealt
  *                         to the chip's 8 XCDs: 1 = one contiguous eighth of the
  *                         item list per XCD (L2 locality), 2 = round-robin

@@ -37,7 +37,16 @@ static void apply_knobs(LaunchCfg& L, const tomo_launch& k) {
     if (L.seg != 1) L.rp = 1;
 }
 
-LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels) {
+// The LDS-staged forward projector runs where the regions' lines and bands fit it;
+// elsewhere a request for it falls back to two rays per lane.
+static void settle_fp_variant(LaunchCfg& L, int max_pitch, int max_w) {
+    const bool fits = max_pitch > 0 && max_pitch <= kFpsMaxPitch && max_w <= kFpsMaxPairs;
+    if (L.rp == kFpStaged && !fits) L.rp = 2;
+    L.spitch = L.rp == kFpStaged ? max_pitch : 0;
+}
+
+LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels,
+                        int max_pitch, int max_w) {
     LaunchCfg L;
     // Split rays / pixels across more waves while the whole problem is too small
     // to fill 256 CUs with at least ~8 waves each.
@@ -51,14 +60,16 @@ LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long tot
     // band in LDS (one angle group, two pixels per thread).  Small ones are
     // latency-bound: read the band directly, angles split over groups.
     L.staged = total_pixels >= 4 * want;
-    // one segment per ray: two rays per lane from 4-pixel reads (half the
-    // gathers, the rate that bounds large forward projections)
+    // one segment per ray: two rays per lane from 4-pixel reads (half the gathers,
+    // the rate that bounds large forward projections); the LDS-staged variant is
+    // chosen by the autotuner or the rays-per-lane knob
     L.rp = L.seg == 1 ? 2 : 1;
     if (L.staged) {
         L.ag = 1;
         L.ppt = 2;
     }
     apply_knobs(L, ctx->knobs);
+    settle_fp_variant(L, max_pitch, max_w);
     return L;
 }
 
@@ -69,9 +80,9 @@ std::tuple<int, int, int> tune_key(int gid, int jobs, long long total_pixels) {
 }
 
 LaunchCfg choose_launch_for(tomo_ctx* ctx, int gid, int jobs, long long total_rays,
-                            long long total_pixels) {
+                            long long total_pixels, int max_pitch, int max_w) {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    LaunchCfg L = choose_launch(ctx, total_rays, total_pixels);
+    LaunchCfg L = choose_launch(ctx, total_rays, total_pixels, max_pitch, max_w);
     // Many jobs of uneven cost: deal items round-robin over the XCDs so every
     // XCD gets an equal share of each job (contiguous eighths of the item list
     // can differ in cost by half).
@@ -79,6 +90,7 @@ LaunchCfg choose_launch_for(tomo_ctx* ctx, int gid, int jobs, long long total_ra
     auto it = ctx->tuned.find(tune_key(gid, jobs, total_pixels));
     if (it != ctx->tuned.end()) apply_knobs(L, it->second);
     apply_knobs(L, ctx->knobs);   // forced fields win
+    settle_fp_variant(L, max_pitch, max_w);
     return L;
 }
 
@@ -174,8 +186,33 @@ Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int nt
 // rays per forward-projector block: 4 waves (SEG waves when SEG > 4), SEG per ray group
 static int fp_rays_per_block(int seg, int rp) { return (seg > 4 ? 64 * seg : 256) * rp / seg; }
 
+// Items of the LDS-staged forward projector: runs of consecutive angles that step
+// along the same lines (rows, or columns), cut into groups of at most 64 angles whose
+// (angle, ray) pairs fit one block; item (job, first angle, pair slots per angle =
+// the group's widest band, angles).
+static void fps_items(std::vector<Item>* out, size_t* count, int jj,
+                      const std::vector<AngFP>& afp, const AngFP* d_afp) {
+    const int na = (int)afp.size();
+    int k = 0;
+    while (k < na) {
+        int W = std::max(afp[k].w, 0), n = 1;
+        while (k + n < na && n < 64 && afp[k + n].tr == afp[k].tr &&
+               (n + 1) * std::max(W, afp[k + n].w) <= kFpsMaxPairs) {
+            W = std::max(W, afp[k + n].w);
+            ++n;
+        }
+        if (out) out->push_back(Item{jj, k, W, n, d_afp + k, 0});
+        if (count) ++*count;
+        k += n;
+    }
+}
+
 void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int seg, int rp,
               const AngFP* d_afp) {
+    if (rp == kFpStaged) {
+        fps_items(&out, nullptr, jj, afp, d_afp);
+        return;
+    }
     const int rpb = fp_rays_per_block(seg, rp);
     for (int k = 0; k < (int)afp.size(); ++k) {
         const int nch = (afp[k].w + rpb - 1) / rpb;
@@ -184,6 +221,11 @@ void fp_items(std::vector<Item>& out, int jj, const std::vector<AngFP>& afp, int
 }
 
 size_t count_fp_items(const std::vector<AngFP>& afp, int seg, int rp) {
+    if (rp == kFpStaged) {
+        size_t n = 0;
+        fps_items(nullptr, &n, 0, afp, nullptr);
+        return n;
+    }
     const int rpb = fp_rays_per_block(seg, rp);
     size_t n = 0;
     for (const AngFP& a : afp) n += (size_t)((a.w + rpb - 1) / rpb);
@@ -559,7 +601,15 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     float* rbuf = nullptr;
     const bool global_resid = !reg && band_sum > g.nd;
 
+    // L: the exterior projections (full-grid images); Li: the iteration loop, whose
+    // forward projector may stage the regions' lines in LDS
+    int max_pitch = 0, max_w = 0;
+    for (auto& r : R) {
+        max_pitch = std::max(max_pitch, std::max(r.plan.xp, r.plan.tp));
+        max_w = std::max(max_w, r.plan.wmax);
+    }
     const LaunchCfg L = choose_launch_for(ctx, gid, count, rays, pix);
+    const LaunchCfg Li = choose_launch_for(ctx, gid, count, rays, pix, max_pitch, max_w);
     int th, tw;
     bp_tile(L.ag, L.ppt, &th, &tw);
 
@@ -722,7 +772,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         const bool cp = r.prm.method == ROI_TV_NONNEG_CP;
         jobs[q] = make_job(g, r, cp ? FP_CP_DUAL : FP_SIRT, cp ? BP_CP : BP_SIRT,
                            (r.ext.cols + tw - 1) / tw);
-        fp_items(fi, q, r.plan.afp, L.seg, L.rp, r.d_afp);
+        fp_items(fi, q, r.plan.afp, Li.seg, Li.rp, r.d_afp);
         bp_items(bi, q, r.ext.rows, r.ext.cols, L.ag, L.ppt, r.d_abp);
         fi_end[q] = (int)fi.size();
         bi_end[q] = (int)bi.size();
@@ -749,7 +799,8 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
                 e2 = timing_event(ctx);
                 if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
             }
-            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, st, L.cfp, L.rp)) != hipSuccess)
+            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, Li.seg, st, Li.cfp, Li.rp,
+                               Li.spitch)) != hipSuccess)
                 return e;
             if (timed && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
             if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, st, L.cbp,
@@ -784,8 +835,8 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
             hipError_t le = hipSuccess;
             for (int q = 0; q < kReps && le == hipSuccess; ++q)
                 le = kind == 0 ? launch_fp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_fi),
-                                           fi_end[count - 1], q, L.seg, ctx->cap_stream, L.cfp,
-                                           L.rp)
+                                           fi_end[count - 1], q, Li.seg, ctx->cap_stream, Li.cfp,
+                                           Li.rp, Li.spitch)
                                : launch_bp((const Job*)(dmt + o_jobs), (const Item*)(dmt + o_bi),
                                            bi_end[count - 1], q, L.ag, L.ppt, ctx->cap_stream,
                                            L.cbp, L.staged);
@@ -1079,7 +1130,8 @@ tomo_status tomo_fp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
     hipStream_t s = (hipStream_t)hip_stream;
     const Rect r{region.row0, region.col0, region.rows, region.cols};
     const Plan P = make_plan(g, r, r);
-    const LaunchCfg L = choose_launch(ctx, (long long)g.na * P.wmax, 0);
+    const LaunchCfg L = choose_launch(ctx, (long long)g.na * P.wmax, 0, std::max(P.xp, P.tp),
+                                      P.wmax);
     std::vector<Item> items;
     Meta m;
     const size_t o_afp = m.add(P.afp.data(), P.afp.size() * sizeof(AngFP));
@@ -1114,7 +1166,7 @@ tomo_status tomo_fp(tomo_ctx* ctx, int32_t geom, tomo_rect region, const float* 
                                   0, s));
     if (!accumulate) TOMO_HIP(ctx, launch_fill(sino, (size_t)g.na * g.nd, 0.f, s));
     TOMO_HIP(ctx, launch_fp((const Job*)(dm + o_job), (const Item*)(dm + o_it), (int)items.size(),
-                            0, L.seg, s, L.cfp, L.rp));
+                            0, L.seg, s, L.cfp, L.rp, L.spitch));
     return TOMO_OK;
     GUARD_END(ctx)
 }
@@ -1337,14 +1389,20 @@ static tomo_launch to_knobs(const LaunchCfg& L) {
 
 // Ray and pixel totals of a batch (as solve_batch counts them).
 static void batch_size(const Geom& g, int count, const roi_params* params, long long* rays,
-                       long long* pix) {
+                       long long* pix, int* max_pitch = nullptr, int* max_w = nullptr) {
     *rays = *pix = 0;
+    int mp = 0, mw = 0;
     for (int i = 0; i < count; ++i) {
         const roi_params& q = params[i];
         const Rect e = extend_rect(Rect{q.roi.row0, q.roi.col0, q.roi.rows, q.roi.cols}, q.margin, g.n);
-        *rays += (long long)g.na * make_plan(g, e, e).wmax;
+        const Plan P = make_plan(g, e, e);
+        *rays += (long long)g.na * P.wmax;
         *pix += (long long)e.rows * e.cols;
+        mp = std::max(mp, std::max(P.xp, P.tp));
+        mw = std::max(mw, P.wmax);
     }
+    if (max_pitch) *max_pitch = mp;
+    if (max_w) *max_w = mw;
 }
 
 tomo_status tomo_resolve_launch(tomo_ctx* ctx, int32_t geom, int32_t count,
@@ -1357,8 +1415,9 @@ tomo_status tomo_resolve_launch(tomo_ctx* ctx, int32_t geom, int32_t count,
     for (int i = 0; i < count; ++i)
         if ((st = validate_params(ctx, *gp, params[i])) != TOMO_OK) return st;
     long long rays, pix;
-    batch_size(*gp, count, params, &rays, &pix);
-    *out = to_knobs(choose_launch_for(ctx, geom, count, rays, pix));
+    int mp = 0, mw = 0;
+    batch_size(*gp, count, params, &rays, &pix, &mp, &mw);
+    *out = to_knobs(choose_launch_for(ctx, geom, count, rays, pix, mp, mw));
     return TOMO_OK;
     GUARD_END(ctx)
 }
@@ -1386,7 +1445,8 @@ tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const 
     std::vector<tomo_launch> fpc, bpc;
     for (int xo = 1; xo <= 2; ++xo)
         for (int sg : {1, 2, 4, 8})
-            for (int rp = 1; rp <= (sg == 1 ? 2 : 1); ++rp) {
+            for (int rp : {1, 2, kFpStaged}) {
+                if (sg != 1 && rp != 1) continue;
                 tomo_launch k{};
                 k.fp_segments = sg;
                 k.fp_rays_per_lane = rp;
@@ -1530,10 +1590,12 @@ tomo_status tomo_set_launch(tomo_ctx* ctx, const tomo_launch* cfg) {
     auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
     auto in012 = [](int v) { return v >= 0 && v <= 2; };
     if (!(ok(k.fp_segments) || k.fp_segments == 8) || !(ok(k.bp_groups) || k.bp_groups == 8) ||
-        !in012(k.bp_pixels_per_thread) || !in012(k.fp_rays_per_lane) ||
+        !in012(k.bp_pixels_per_thread) ||
+        !(in012(k.fp_rays_per_lane) || k.fp_rays_per_lane == kFpStaged) ||
         !in012(k.bp_variant) || !in012(k.fp_xcd_order) || !in012(k.bp_xcd_order))
         return fail(ctx, TOMO_EINVAL, "launch knobs: segments and groups in {0,1,2,4,8}, "
-                    "pixels in {0,1,2}, variant and xcd order in {0,1,2}");
+                    "rays per lane in {0,1,2,4}, pixels in {0,1,2}, variant and xcd order in "
+                    "{0,1,2}");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     ctx->knobs = k;
     return TOMO_OK;

@@ -125,13 +125,24 @@ struct Item {
 };
 static_assert(sizeof(Item) == 32, "Item layout");
 
+// LDS-staged forward projector: kFpsLines image lines per stage, kFpsThreads threads,
+// at most kFpsMaxPairs (angle, ray) pairs per block, line pitch at most kFpsMaxPitch.
+constexpr int kFpStaged = 4;   // the rays_per_lane value that selects it
+constexpr int kFpsThreads = 256, kFpsLines = 32, kFpsStride = kFpsLines + 1;
+constexpr int kFpsMaxRounds = 8, kFpsMaxPairs = kFpsMaxRounds * kFpsThreads;
+constexpr int kFpsMaxPitch = 400;
+
 // Launchers (tomo_kernels.hip).
 // contiguous = 1: each XCD runs one contiguous eighth of the items (L2
 // locality for many small jobs); 0: item b runs on XCD b mod 8 (balanced).
 // rays_per_lane = 2: each lane projects two adjacent rays from 4-pixel reads
 // (segments must be 1; the items must be built for 512 rays per block).
+// rays_per_lane = kFpStaged: the LDS-staged forward projector (items from fps_items;
+// stage_pitch = the largest line pitch, xp or tp, of the launch's jobs, at most
+// kFpsMaxPitch).
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
-                     hipStream_t s, int contiguous = 1, int rays_per_lane = 1);
+                     hipStream_t s, int contiguous = 1, int rays_per_lane = 1,
+                     int stage_pitch = 0);
 // staged = 1: band windows staged in LDS (one angle group; throughput shape),
 // 0: direct band reads (any group count; latency shape).  Same results.
 // compensated = 1: compensated sums over angles, staged, groups 1, ppt 2 only

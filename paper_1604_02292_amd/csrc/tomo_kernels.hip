@@ -102,6 +102,85 @@ __device__ __forceinline__ v4f load4(__amdgpu_buffer_rsrc_t rs, unsigned voff, u
     return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
 }
 
+// Epilogue operands of ray j (band position) of angle k: the values the forward
+// projector's mode combines with the ray sum (0 for rays off the band or detector).
+__device__ __forceinline__ void fp_operands(const CONST_AS Job* J, const AngFP& A, int k, int j,
+                                            int step, float& pre0, float& pre1) {
+    const int gi = A.i0 + j;
+    if (j >= A.w || gi < 0 || gi >= J->n_det) return;
+    const size_t bidx = (size_t)k * J->bpitch + 1 + j;
+    const size_t gidx = (size_t)k * J->n_det + gi;
+    switch (J->fp_mode) {
+        case FP_ACCUM: pre0 = J->gout[gidx]; break;
+        case FP_BAND_FROM_GLOBAL:
+        case FP_RESID:
+        case FP_FILTER: pre0 = J->gbase[gidx]; break;
+        case FP_LOCAL:
+            pre0 = J->gbase[(size_t)(step + J->dk0) * (size_t)J->gstride + gidx];
+            break;
+        case FP_BAND_ADD: pre0 = J->y[bidx]; break;
+        case FP_CP_DUAL: pre0 = J->y[bidx]; pre1 = J->b[bidx]; break;
+        case FP_SIRT: pre1 = J->b[bidx]; break;
+        default: break;
+    }
+}
+
+// The forward projector's fused epilogue for ray j of angle k with ray sum acc.
+__device__ __forceinline__ void fp_store(const CONST_AS Job* J, const AngFP& A, int k, int j,
+                                         float acc, float pre0, float pre1) {
+    float* y = J->y;
+    float* gout = J->gout;
+    const int gi = A.i0 + j;
+    const bool ondet = (gi >= 0) && (gi < J->n_det);
+    const size_t bidx = (size_t)k * J->bpitch + 1 + j;
+    const size_t gidx = (size_t)k * J->n_det + gi;
+    const float fpv = acc * A.inv_m;
+    const int mode = J->fp_mode;
+    switch (mode) {
+        case FP_STORE:
+            if (ondet) gout[gidx] = fpv;
+            break;
+        case FP_ACCUM:
+            if (ondet) gout[gidx] = pre0 + fpv;
+            break;
+        case FP_BAND_FROM_GLOBAL:
+            y[bidx] = ondet ? pre0 + J->scale * fpv : 0.f;
+            break;
+        case FP_BAND_ADD:
+            y[bidx] = ondet ? pre0 + J->scale * fpv : 0.f;
+            break;
+        case FP_CP_DUAL:
+            // prox of sigma F1*, F1(v) = ||v - h b||^2 (or 1/2 ||v - h b||^2) on the rows
+            // h W_L of K, kept as B * h y: h y <- (h y + sigma h^2 (W_L xbar - b)) / (1 + sigma/2)
+            y[bidx] = ondet ? (pre0 + (J->sigma_y * A.bscale) * (fpv - pre1)) * J->dual_div : 0.f;
+            break;
+        case FP_SIRT:
+            y[bidx] = ondet ? (J->alpha * A.bscale) * (pre1 - fpv) : 0.f;
+            break;
+        case FP_BAND_STORE:
+            y[bidx] = ondet ? A.bscale * fpv : 0.f;
+            break;
+        case FP_RESID:
+            if (ondet) gout[gidx] = pre0 + J->scale * fpv;
+            break;
+        case FP_FILTER:
+            // one step of the filter recursion: the band carries -alpha W c for
+            // the update of c, the filter accumulates alpha W c
+            y[bidx] = ondet ? -(J->alpha * A.bscale) * fpv : 0.f;
+            if (ondet) gout[gidx] = pre0 + J->alpha * fpv;
+            break;
+        case FP_LOCAL: {
+            // two-channel band: (d - alpha W_L v, d), d the filtered data
+            const float d = ondet ? pre0 : 0.f;
+            const v2f o = ondet ? v2f{A.bscale * (d - J->alpha * fpv), A.bscale * d}
+                                : v2f{0.f, 0.f};
+            *(v2f*)(y + 2 * bidx) = o;
+        } break;
+        default:
+            break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Forward projection.  One block = one angle of one job and 64 * max(4, SEG) / SEG
 // rays (4 waves, or SEG waves when SEG > 4); each ray is split into SEG consecutive
@@ -139,30 +218,11 @@ __global__ __launch_bounds__(fp_threads<SEG>()) void fp_kernel(const Job* __rest
 
     // Epilogue operands are independent of the ray sums: fetch them first so
     // their memory latency overlaps the loop.
-    const int mode = J->fp_mode;
     float pre0[RP], pre1[RP];
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
-        const int j = j0 + r;
-        const int gi = A.i0 + j;
         pre0[r] = pre1[r] = 0.f;
-        if (seg == 0 && j < A.w && gi >= 0 && gi < J->n_det) {
-            const size_t bidx = (size_t)k * J->bpitch + 1 + j;
-            const size_t gidx = (size_t)k * J->n_det + gi;
-            switch (mode) {
-                case FP_ACCUM: pre0[r] = J->gout[gidx]; break;
-                case FP_BAND_FROM_GLOBAL:
-                case FP_RESID:
-                case FP_FILTER: pre0[r] = J->gbase[gidx]; break;
-                case FP_LOCAL:
-                    pre0[r] = J->gbase[(size_t)(step + J->dk0) * (size_t)J->gstride + gidx];
-                    break;
-                case FP_BAND_ADD: pre0[r] = J->y[bidx]; break;
-                case FP_CP_DUAL: pre0[r] = J->y[bidx]; pre1[r] = J->b[bidx]; break;
-                case FP_SIRT: pre1[r] = J->b[bidx]; break;
-                default: break;
-            }
-        }
+        if (seg == 0) fp_operands(J, A, k, j0 + r, step, pre0[r], pre1[r]);
     }
 
     float acc[RP];
@@ -364,60 +424,203 @@ __global__ __launch_bounds__(fp_threads<SEG>()) void fp_kernel(const Job* __rest
         }
     }
 
-    float* y = J->y;
-    float* gout = J->gout;
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
-        const int j = j0 + r;
-        if (j >= A.w) break;
-        const int gi = A.i0 + j;
-        const bool ondet = (gi >= 0) && (gi < J->n_det);
-        const size_t bidx = (size_t)k * J->bpitch + 1 + j;
-        const size_t gidx = (size_t)k * J->n_det + gi;
-        const float fpv = acc[r] * A.inv_m;
-        switch (mode) {
-            case FP_STORE:
-                if (ondet) gout[gidx] = fpv;
-                break;
-            case FP_ACCUM:
-                if (ondet) gout[gidx] = pre0[r] + fpv;
-                break;
-            case FP_BAND_FROM_GLOBAL:
-                y[bidx] = ondet ? pre0[r] + J->scale * fpv : 0.f;
-                break;
-            case FP_BAND_ADD:
-                y[bidx] = ondet ? pre0[r] + J->scale * fpv : 0.f;
-                break;
-            case FP_CP_DUAL:
-                // prox of sigma F1*, F1(v) = ||v - h b||^2 (or 1/2 ||v - h b||^2) on the rows
-                // h W_L of K, kept as B * h y: h y <- (h y + sigma h^2 (W_L xbar - b)) / (1 + sigma/2)
-                y[bidx] = ondet ? (pre0[r] + (J->sigma_y * A.bscale) * (fpv - pre1[r])) * J->dual_div : 0.f;
-                break;
-            case FP_SIRT:
-                y[bidx] = ondet ? (J->alpha * A.bscale) * (pre1[r] - fpv) : 0.f;
-                break;
-            case FP_BAND_STORE:
-                y[bidx] = ondet ? A.bscale * fpv : 0.f;
-                break;
-            case FP_RESID:
-                if (ondet) gout[gidx] = pre0[r] + J->scale * fpv;
-                break;
-            case FP_FILTER:
-                // one step of the filter recursion: the band carries -alpha W c for
-                // the update of c, the filter accumulates alpha W c
-                y[bidx] = ondet ? -(J->alpha * A.bscale) * fpv : 0.f;
-                if (ondet) gout[gidx] = pre0[r] + J->alpha * fpv;
-                break;
-            case FP_LOCAL: {
-                // two-channel band: (d - alpha W_L v, d), d the filtered data
-                const float d = ondet ? pre0[r] : 0.f;
-                const v2f o = ondet ? v2f{A.bscale * (d - J->alpha * fpv), A.bscale * d}
-                                    : v2f{0.f, 0.f};
-                *(v2f*)(y + 2 * bidx) = o;
-            } break;
-            default:
-                break;
+        if (j0 + r >= A.w) break;
+        fp_store(J, A, k, j0 + r, acc[r], pre0[r], pre1[r]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward projection, LDS-staged (the throughput shape for batches).  One block =
+// a group of angles of one job that step along the same image lines (rows, or
+// columns through the transposed copy) and all rays of their bands.  The block
+// copies kFpsLines whole padded lines of the region at a time into LDS with
+// coalesced reads - each pixel is read once per group instead of once per ray that
+// crosses it - stored column-major with an odd stride, so that a ray's two taps are
+// one ds_read2 and adjacent rays fall on distinct banks.  The (angle, ray) pairs of
+// the group are dealt to the threads in rounds, rays adjacent within an angle, and
+// every pair takes its interpolation steps from LDS.  A wave skips a stage when none
+// of its rays meets the image inside the staged lines, and clamps the tap index
+// only in stages where one of its rays leaves the padded line (the pads and the
+// clamp give the exact zeros that the direct kernel's range-checked reads give).
+// Ray sums run in the same two levels as fp_kernel: per chunk of staged lines, then
+// into the ray.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __restrict__ jobs,
+                                                                const Item* __restrict__ items,
+                                                                int n_items, int step,
+                                                                int contiguous) {
+    extern __shared__ float fps_lds[];   // [kFpsMaxRounds][threads] sums, then [pitch][stride] lines
+    constexpr int NT = kFpsThreads, L = kFpsLines, STR = kFpsStride;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
+    if (bid >= n_items) return;
+    const Item it = cview(items)[bid];
+    const CONST_AS Job* J = cview(jobs) + it.job;
+    const int k0 = it.a, W = it.b, nang = it.pad;   // angles k0 .. k0 + nang - 1, W pair slots each
+    if (W <= 0 || nang <= 0) return;
+    const AngFP* tabs = (const AngFP*)it.tab;
+    const int t = threadIdx.x, lane = t & 63;
+    const int tr = cview(tabs)[0].tr;
+    const int rpar = (step + J->parity0) & 1;
+    gcfloat* img = gview(tr ? J->xt : J->xb[rpar]);
+    const int pitch = tr ? J->tp : J->xp;
+    const int n_outer = tr ? J->nc : J->nr;
+    const int n_inner = tr ? J->nr : J->nc;
+    const int npairs = nang * W;
+    const int rounds = (npairs + NT - 1) / NT;
+    if (rounds > kFpsMaxRounds) return;   // the host never builds such a group
+    float* sums = fps_lds;
+    LDS_AS float* S = (LDS_AS float*)(fps_lds + kFpsMaxRounds * NT);
+    const unsigned s_base = (unsigned)(size_t)S;
+    const float rcp_w = 1.0f / (float)W;
+    const unsigned rowb = (unsigned)pitch * 4u;
+    const __amdgpu_buffer_rsrc_t img_rs = make_rsrc(img, (size_t)n_outer * rowb);
+
+    // Lines on which some ray of the group lies strictly inside the interpolation
+    // range (kLpad - 1, n_inner + kLpad) of storage coordinates: lane a of every wave
+    // takes angle a (rays 0 and w - 1 bound its range), then a wave-wide min / max.
+    const double lo_in = (double)(kLpad - 1), hi_in = (double)(n_inner + kLpad);
+    int o_lo = n_outer, o_hi = 0;
+    for (int a0 = 0; a0 < nang; a0 += 64) {
+        const int a = a0 + lane;
+        int lo_a = n_outer, hi_a = 0;
+        if (a < nang) {
+            const AngFP A = tabs[a];
+            if (A.w > 0) {
+                const double pa = A.a0, pb = A.a0 + (double)(A.w - 1) * A.aj;
+                if (A.step == 0.0) {
+                    if ((fmax(pa, pb) > lo_in) && (fmin(pa, pb) < hi_in)) {
+                        lo_a = 0;
+                        hi_a = n_outer;
+                    }
+                } else {
+                    const double inv = 1.0 / A.step;
+                    const double t1 = (lo_in - pa) * inv, t2 = (hi_in - pa) * inv;
+                    const double t3 = (lo_in - pb) * inv, t4 = (hi_in - pb) * inv;
+                    double lo = fmin(fmin(t1, t2), fmin(t3, t4));
+                    double hi = fmax(fmax(t1, t2), fmax(t3, t4));
+                    lo = fmin(fmax(lo, -2.0), (double)n_outer + 2.0);
+                    hi = fmin(fmax(hi, -2.0), (double)n_outer + 2.0);
+                    lo_a = max(0, (int)floor(lo) - 1);
+                    hi_a = min(n_outer, (int)ceil(hi) + 2);
+                    if (hi_a <= lo_a) {
+                        lo_a = n_outer;
+                        hi_a = 0;
+                    }
+                }
+            }
         }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo_a = min(lo_a, __shfl_xor(lo_a, d));
+            hi_a = max(hi_a, __shfl_xor(hi_a, d));
+        }
+        o_lo = min(o_lo, lo_a);
+        o_hi = max(o_hi, hi_a);
+    }
+    o_lo = uniform_int(o_lo);
+    o_hi = uniform_int(o_hi);
+    for (int r = 0; r < rounds; ++r) sums[r * NT + t] = 0.f;
+
+    for (int oc = o_lo; oc < o_hi; oc += L) {
+        const int cnt = min(L, o_hi - oc);
+        __syncthreads();   // the previous stage's readers are done
+        // (lines past the region's last read 0 from the buffer's range check; lines
+        // past the stage's count are staged but never read)
+        for (int i = t; i < pitch; i += NT) {
+            float v[L];
+#pragma unroll
+            for (int u = 0; u < L; ++u)
+                v[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                     img_rs, (unsigned)i * 4u,
+                                                     (unsigned)(oc + u) * rowb, 0));
+#pragma unroll
+            for (int u = 0; u < L; ++u) S[i * STR + u] = v[u];
+        }
+        __syncthreads();
+        for (int r = 0; r < rounds; ++r) {
+            const int p = r * NT + t;
+            const int a = min((int)(((float)p + 0.5f) * rcp_w), nang - 1);
+            const int j = p - a * W;
+            const AngFP A = tabs[a];
+            const bool valid = (p < npairs) && (j < A.w);
+            // storage coordinate of the ray at line oc (FP64), and at the stage's last line
+            double p0 = fma((double)oc, A.step, fma((double)j, A.aj, A.a0));
+            double dp = A.step;
+            if (!valid) {   // harmless in-range reads, discarded
+                p0 = (double)kLpad;
+                dp = 0.0;
+            }
+            const double p1 = fma((double)(cnt - 1), dp, p0);
+            const double pmin = fmin(p0, p1), pmax = fmax(p0, p1);
+            const bool touches = valid && (pmax > lo_in - 1.0) && (pmin < hi_in + 1.0);
+            if (__ballot(touches) == 0) continue;   // only exact zeros on these lines
+            const bool safe = (pmin >= 1.0) && (pmax < (double)(pitch - 2));
+            const double fl0 = floor(p0);
+            const float base64 = (float)(p0 - fl0) + 64.f;
+            const float stepf = (float)dp;
+            const int ib = (int)fl0 - 64;
+            // four partial sums (independent add chains), combined in a fixed order
+            float c4[4] = {0.f, 0.f, 0.f, 0.f};
+            const bool clamp = __ballot(!safe) != 0;   // some tap of the wave leaves the line
+            const unsigned lb = (unsigned)(ib * STR) * 4u + s_base;
+            if (cnt == L) {
+                // line u of the tap's column sits u floats further: an immediate offset of
+                // the ds_read2 (u, u + STR dwords)
+                float f[L], v0[L], v1[L];
+                if (!clamp) {
+#pragma unroll
+                    for (int u = 0; u < L; ++u) {
+                        const float loc = fmaf((float)u, stepf, base64);
+                        f[u] = __builtin_amdgcn_fractf(loc);
+                        const LDS_AS float* col = (const LDS_AS float*)(size_t)(
+                            __umul24((unsigned)loc, STR * 4u) + lb);
+                        v0[u] = col[u];
+                        v1[u] = col[u + STR];
+                    }
+                } else {
+                    // the tap index clamped into the padded line (its first and last two
+                    // entries are zeros, so a clamped tap adds exactly 0)
+#pragma unroll
+                    for (int u = 0; u < L; ++u) {
+                        const float loc = fmaf((float)u, stepf, base64);
+                        f[u] = __builtin_amdgcn_fractf(loc);
+                        const int idx = min(max(ib + (int)(unsigned)loc, 0), pitch - 2);
+                        const LDS_AS float* col = (const LDS_AS float*)(size_t)(
+                            __umul24((unsigned)idx, STR * 4u) + s_base);
+                        v0[u] = col[u];
+                        v1[u] = col[u + STR];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < L; ++u) c4[u & 3] += fmaf(f[u], v1[u] - v0[u], v0[u]);
+            } else {
+                for (int u = 0; u < cnt; ++u) {
+                    const float loc = fmaf((float)u, stepf, base64);
+                    const float f = __builtin_amdgcn_fractf(loc);
+                    const int idx = min(max(ib + (int)(unsigned)loc, 0), pitch - 2);
+                    const LDS_AS float* col =
+                        (const LDS_AS float*)(size_t)((unsigned)(idx * STR + u) * 4u + s_base);
+                    c4[u & 3] += fmaf(f, col[STR] - col[0], col[0]);
+                }
+            }
+            (void)lb;
+            const float cs = (c4[0] + c4[1]) + (c4[2] + c4[3]);
+            sums[r * NT + t] += cs;
+        }
+    }
+    // fused epilogue of every valid pair
+    for (int r = 0; r < rounds; ++r) {
+        const int p = r * NT + t;
+        if (p >= npairs) break;
+        const int a = min((int)(((float)p + 0.5f) * rcp_w), nang - 1);
+        const int j = p - a * W;
+        const AngFP A = tabs[a];
+        if (j >= A.w) continue;
+        float pre0 = 0.f, pre1 = 0.f;
+        fp_operands(J, A, k0 + a, j, step, pre0, pre1);
+        fp_store(J, A, k0 + a, j, sums[r * NT + t], pre0, pre1);
     }
 }
 
@@ -2014,9 +2217,17 @@ inline unsigned pad8(int n) { return (unsigned)((n + 7) & ~7); }
 }  // namespace
 
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
-                     hipStream_t s, int contiguous, int rays_per_lane) {
+                     hipStream_t s, int contiguous, int rays_per_lane, int stage_pitch) {
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items));
+    if (rays_per_lane == kFpStaged) {
+        if (stage_pitch < 1 || stage_pitch > kFpsMaxPitch) return hipErrorInvalidValue;
+        const size_t lds = ((size_t)kFpsMaxRounds * kFpsThreads +
+                            (size_t)stage_pitch * kFpsStride) * sizeof(float);
+        hipLaunchKernelGGL(fp_staged_kernel, grid, dim3(kFpsThreads), lds, s, jobs, items,
+                           n_items, step, contiguous);
+        return hipGetLastError();
+    }
 #define TOMO_FP(SG, R)                                                                 \
     hipLaunchKernelGGL((fp_kernel<SG, R>), grid, dim3(fp_threads<SG>()), 0, s, jobs, items, \
                        n_items, step, contiguous)

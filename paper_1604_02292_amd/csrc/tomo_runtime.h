@@ -208,12 +208,16 @@ struct LaunchCfg {
     int rp = 1;             // forward projector rays per lane (2 only with seg 1)
     int cfp = 1, cbp = 1;   // XCD order of FP / BP items: 1 contiguous, 0 round-robin
     int staged = 0;         // backprojector variant: 1 = LDS-staged band windows
+    int spitch = 0;         // rp == kFpStaged: the largest line pitch of the launch's jobs
 };
 
-LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels);
+// max_pitch, max_w: the largest line pitch (xp or tp) and band width of the jobs the
+// forward projector will run on (0 = not known: the LDS-staged variant is not used).
+LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long total_pixels,
+                        int max_pitch = 0, int max_w = 0);
 // As choose_launch, preferring an autotuned shape for (geometry, pixels, jobs).
 LaunchCfg choose_launch_for(tomo_ctx* ctx, int gid, int jobs, long long total_rays,
-                            long long total_pixels);
+                            long long total_pixels, int max_pitch = 0, int max_w = 0);
 std::tuple<int, int, int> tune_key(int gid, int jobs, long long total_pixels);
 void bp_tile(int ag, int ppt, int* th, int* tw);
 size_t state_bytes(const Geom& g, const Plan& p);

@@ -96,8 +96,8 @@ SHAPES_BP = [dict(bp_variant=1, bp_groups=a, bp_pixels_per_thread=q) for a in (1
                                         ("c4", (1000, 37, 300, 261)), ("odd", (3, 5, 31, 77)),
                                         ("odd", (96, 0, 1, 1)), ("c1", (0, 127, 128, 1))])
 def test_every_launch_shape_matches_oracle(ctx, gname, rect):
-    """Every forward-projector and backprojector launch shape (segments, XCD
-    order, direct or LDS-staged band reads, groups, pixels per thread) agrees
+    """Every forward-projector and backprojector launch shape (segments, rays per lane,
+    LDS-staged lines, XCD order, direct or LDS-staged band reads, groups, pixels per thread) agrees
     with the oracle; the staged and direct backprojectors give identical bits
     for the same groups and pixels per thread."""
     n, na, nd = GEOMS[gname]
@@ -109,13 +109,15 @@ def test_every_launch_shape_matches_oracle(ctx, gname, rect):
     ref_fp = oracle.fp_ray(geo, img.astype(np.float64), rect)
     ref_bp = oracle.bp_pixel(geo, y.astype(np.float64), rect)
     try:
-        for seg in (1, 2, 4, 8):
+        # segments 1..8 with one ray per lane, two rays per lane, and the LDS-staged
+        # projector (rays per lane 4; regions up to 394 pixels a side)
+        for seg, rpl in [(1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (1, 4)]:
             for xo in (1, 2):
-                ctx.tomo_set_launch(fp_segments=seg, fp_xcd_order=xo)
+                ctx.tomo_set_launch(fp_segments=seg, fp_rays_per_lane=rpl, fp_xcd_order=xo)
                 sino = torch.empty((na, nd), dtype=torch.float32, device="cuda")
                 ctx.tomo_fp(g, rect, dev(img), sino)
                 e = rel(host(sino), ref_fp)
-                say(f"    {gname} {rect} fp seg {seg} xcd {xo}: {e:.2e}")
+                say(f"    {gname} {rect} fp seg {seg} rays/lane {rpl} xcd {xo}: {e:.2e}")
                 assert e <= PROJ_TOL
         got = {}
         for shp in SHAPES_BP:
