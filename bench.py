@@ -561,7 +561,7 @@ def tiles_cpu_baseline(d, n_ang_sample=16, n_cp=3, n_pow=3):
     tm["exterior_sample"] = time.perf_counter() - t0
     shape, h = (ext[2], ext[3]), 1.0 / n
     t0 = time.perf_counter()
-    oracle.power_norm_sq(WL, shape, n_pow, h)
+    oracle.power_norm_sq(WL, shape, n_pow)
     tm["power_sample"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.cp_tv_nonneg(WL, b, shape, cfg["lam"], 0.35, 0.35, n_cp, h=h)

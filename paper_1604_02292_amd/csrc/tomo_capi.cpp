@@ -60,10 +60,11 @@ LaunchCfg choose_launch(const tomo_ctx* ctx, long long total_rays, long long tot
     // band in LDS (one angle group, two pixels per thread).  Small ones are
     // latency-bound: read the band directly, angles split over groups.
     L.staged = total_pixels >= 4 * want;
-    // one segment per ray: two rays per lane from 4-pixel reads (half the gathers,
-    // the rate that bounds large forward projections); the LDS-staged variant is
-    // chosen by the autotuner or the rays-per-lane knob
-    L.rp = L.seg == 1 ? 2 : 1;
+    // one segment per ray: the regions' lines staged in LDS for groups of angles
+    // where they fit (no gather per ray-line: the rate of vector-memory gathers bounds
+    // large forward projections), else two rays per lane from 4-pixel reads (half the
+    // gathers)
+    L.rp = L.seg == 1 ? kFpStaged : 1;
     if (L.staged) {
         L.ag = 1;
         L.ppt = 2;

@@ -130,7 +130,8 @@ static_assert(sizeof(Item) == 32, "Item layout");
 constexpr int kFpStaged = 4;   // the rays_per_lane value that selects it
 constexpr int kFpsThreads = 256, kFpsLines = 32, kFpsStride = kFpsLines + 1;
 constexpr int kFpsMaxRounds = 8, kFpsMaxPairs = kFpsMaxRounds * kFpsThreads;
-constexpr int kFpsMaxPitch = 400;
+constexpr int kFpsMaxPitch = 336;   // LDS (336 + 68) x 33 x 4 B: three blocks per CU
+constexpr int kFpsZeroPad = 34;   // zero columns staged before and after each line
 
 // Launchers (tomo_kernels.hip).
 // contiguous = 1: each XCD runs one contiguous eighth of the items (L2

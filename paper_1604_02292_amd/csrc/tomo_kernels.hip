@@ -451,7 +451,9 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
                                                                 const Item* __restrict__ items,
                                                                 int n_items, int step,
                                                                 int contiguous) {
-    extern __shared__ float fps_lds[];   // [kFpsMaxRounds][threads] sums, then [pitch][stride] lines
+    // [kFpsZeroPad + pitch + kFpsZeroPad][stride]: the staged lines, column-major, with
+    // zero columns on both sides
+    extern __shared__ float fps_lds[];
     constexpr int NT = kFpsThreads, L = kFpsLines, STR = kFpsStride;
     const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
     if (bid >= n_items) return;
@@ -470,8 +472,7 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
     const int npairs = nang * W;
     const int rounds = (npairs + NT - 1) / NT;
     if (rounds > kFpsMaxRounds) return;   // the host never builds such a group
-    float* sums = fps_lds;
-    LDS_AS float* S = (LDS_AS float*)(fps_lds + kFpsMaxRounds * NT);
+    LDS_AS float* S = (LDS_AS float*)fps_lds + kFpsZeroPad * STR;   // column 0 of the line
     const unsigned s_base = (unsigned)(size_t)S;
     const float rcp_w = 1.0f / (float)W;
     const unsigned rowb = (unsigned)pitch * 4u;
@@ -521,7 +522,34 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
     }
     o_lo = uniform_int(o_lo);
     o_hi = uniform_int(o_hi);
-    for (int r = 0; r < rounds; ++r) sums[r * NT + t] = 0.f;
+    // The zero columns: a ray that meets the image inside a stage stays within 32
+    // line steps (|step| <= 1) of it, so its taps fall in [-30, pitch + 32] and need no
+    // clamp (the first four and last two entries of a padded line are zeros too).
+    for (int e = t; e < kFpsZeroPad * STR; e += NT) {
+        S[-kFpsZeroPad * STR + e] = 0.f;
+        S[pitch * STR + e] = 0.f;
+    }
+    // Per round: this thread's pair (angle a, ray j), its ray's storage coordinate at
+    // line o_lo and step per line (FP64), kept in registers across the stages.
+    double pb[kFpsMaxRounds], ps[kFpsMaxRounds];
+    float acc[kFpsMaxRounds];
+    bool val[kFpsMaxRounds];
+#pragma unroll
+    for (int r = 0; r < kFpsMaxRounds; ++r) {
+        acc[r] = 0.f;
+        pb[r] = 0.0;
+        ps[r] = 0.0;
+        val[r] = false;
+        if (r < rounds) {
+            const int p = r * NT + t;
+            const int a = min((int)(((float)p + 0.5f) * rcp_w), nang - 1);
+            const int j = p - a * W;
+            const AngFP A = tabs[a];
+            val[r] = (p < npairs) && (j < A.w);
+            pb[r] = fma((double)o_lo, A.step, fma((double)j, A.aj, A.a0));
+            ps[r] = A.step;
+        }
+    }
 
     for (int oc = o_lo; oc < o_hi; oc += L) {
         const int cnt = min(L, o_hi - oc);
@@ -539,59 +567,42 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
             for (int u = 0; u < L; ++u) S[i * STR + u] = v[u];
         }
         __syncthreads();
-        for (int r = 0; r < rounds; ++r) {
-            const int p = r * NT + t;
-            const int a = min((int)(((float)p + 0.5f) * rcp_w), nang - 1);
-            const int j = p - a * W;
-            const AngFP A = tabs[a];
-            const bool valid = (p < npairs) && (j < A.w);
-            // storage coordinate of the ray at line oc (FP64), and at the stage's last line
-            double p0 = fma((double)oc, A.step, fma((double)j, A.aj, A.a0));
-            double dp = A.step;
-            if (!valid) {   // harmless in-range reads, discarded
-                p0 = (double)kLpad;
-                dp = 0.0;
-            }
+        const double doc = (double)(oc - o_lo);
+#pragma unroll
+        for (int r = 0; r < kFpsMaxRounds; ++r) {
+            if (r >= rounds) break;
+            // storage coordinate of the ray at line oc, and at the stage's last line
+            double p0 = fma(doc, ps[r], pb[r]);
+            double dp = ps[r];
             const double p1 = fma((double)(cnt - 1), dp, p0);
             const double pmin = fmin(p0, p1), pmax = fmax(p0, p1);
-            const bool touches = valid && (pmax > lo_in - 1.0) && (pmin < hi_in + 1.0);
+            const bool touches = val[r] && (pmax > lo_in - 1.0) && (pmin < hi_in + 1.0);
             if (__ballot(touches) == 0) continue;   // only exact zeros on these lines
-            const bool safe = (pmin >= 1.0) && (pmax < (double)(pitch - 2));
+            if (!touches) {   // reads of the leading zeros, discarded or adding 0
+                p0 = 2.0;
+                dp = 0.0;
+            }
             const double fl0 = floor(p0);
             const float base64 = (float)(p0 - fl0) + 64.f;
             const float stepf = (float)dp;
             const int ib = (int)fl0 - 64;
+            // loc = base64 + u step lies in [33, 97) (|step| <= 1): positive, so the
+            // truncation below is a floor
+            const unsigned lb = (unsigned)(ib * STR) * 4u + s_base;
             // four partial sums (independent add chains), combined in a fixed order
             float c4[4] = {0.f, 0.f, 0.f, 0.f};
-            const bool clamp = __ballot(!safe) != 0;   // some tap of the wave leaves the line
-            const unsigned lb = (unsigned)(ib * STR) * 4u + s_base;
             if (cnt == L) {
-                // line u of the tap's column sits u floats further: an immediate offset of
-                // the ds_read2 (u, u + STR dwords)
+                // line u of the tap's column sits u floats further: an immediate offset
+                // of the ds_read2 (u, u + STR dwords)
                 float f[L], v0[L], v1[L];
-                if (!clamp) {
 #pragma unroll
-                    for (int u = 0; u < L; ++u) {
-                        const float loc = fmaf((float)u, stepf, base64);
-                        f[u] = __builtin_amdgcn_fractf(loc);
-                        const LDS_AS float* col = (const LDS_AS float*)(size_t)(
-                            __umul24((unsigned)loc, STR * 4u) + lb);
-                        v0[u] = col[u];
-                        v1[u] = col[u + STR];
-                    }
-                } else {
-                    // the tap index clamped into the padded line (its first and last two
-                    // entries are zeros, so a clamped tap adds exactly 0)
-#pragma unroll
-                    for (int u = 0; u < L; ++u) {
-                        const float loc = fmaf((float)u, stepf, base64);
-                        f[u] = __builtin_amdgcn_fractf(loc);
-                        const int idx = min(max(ib + (int)(unsigned)loc, 0), pitch - 2);
-                        const LDS_AS float* col = (const LDS_AS float*)(size_t)(
-                            __umul24((unsigned)idx, STR * 4u) + s_base);
-                        v0[u] = col[u];
-                        v1[u] = col[u + STR];
-                    }
+                for (int u = 0; u < L; ++u) {
+                    const float loc = fmaf((float)u, stepf, base64);
+                    f[u] = __builtin_amdgcn_fractf(loc);
+                    const LDS_AS float* col = (const LDS_AS float*)(size_t)(
+                        __umul24((unsigned)loc, STR * 4u) + lb);
+                    v0[u] = col[u];
+                    v1[u] = col[u + STR];
                 }
 #pragma unroll
                 for (int u = 0; u < L; ++u) c4[u & 3] += fmaf(f[u], v1[u] - v0[u], v0[u]);
@@ -599,28 +610,26 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
                 for (int u = 0; u < cnt; ++u) {
                     const float loc = fmaf((float)u, stepf, base64);
                     const float f = __builtin_amdgcn_fractf(loc);
-                    const int idx = min(max(ib + (int)(unsigned)loc, 0), pitch - 2);
-                    const LDS_AS float* col =
-                        (const LDS_AS float*)(size_t)((unsigned)(idx * STR + u) * 4u + s_base);
+                    const LDS_AS float* col = (const LDS_AS float*)(size_t)(
+                        __umul24((unsigned)loc, STR * 4u) + lb + 4u * (unsigned)u);
                     c4[u & 3] += fmaf(f, col[STR] - col[0], col[0]);
                 }
             }
-            (void)lb;
-            const float cs = (c4[0] + c4[1]) + (c4[2] + c4[3]);
-            sums[r * NT + t] += cs;
+            acc[r] += (c4[0] + c4[1]) + (c4[2] + c4[3]);
         }
     }
     // fused epilogue of every valid pair
-    for (int r = 0; r < rounds; ++r) {
+#pragma unroll
+    for (int r = 0; r < kFpsMaxRounds; ++r) {
+        if (r >= rounds) break;
         const int p = r * NT + t;
-        if (p >= npairs) break;
+        if (!val[r]) continue;
         const int a = min((int)(((float)p + 0.5f) * rcp_w), nang - 1);
         const int j = p - a * W;
         const AngFP A = tabs[a];
-        if (j >= A.w) continue;
         float pre0 = 0.f, pre1 = 0.f;
         fp_operands(J, A, k0 + a, j, step, pre0, pre1);
-        fp_store(J, A, k0 + a, j, sums[r * NT + t], pre0, pre1);
+        fp_store(J, A, k0 + a, j, acc[r], pre0, pre1);
     }
 }
 
@@ -2222,8 +2231,7 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
     const dim3 grid(pad8(n_items));
     if (rays_per_lane == kFpStaged) {
         if (stage_pitch < 1 || stage_pitch > kFpsMaxPitch) return hipErrorInvalidValue;
-        const size_t lds = ((size_t)kFpsMaxRounds * kFpsThreads +
-                            (size_t)stage_pitch * kFpsStride) * sizeof(float);
+        const size_t lds = (size_t)(stage_pitch + 2 * kFpsZeroPad) * kFpsStride * sizeof(float);
         hipLaunchKernelGGL(fp_staged_kernel, grid, dim3(kFpsThreads), lds, s, jobs, items,
                            n_items, step, contiguous);
         return hipGetLastError();

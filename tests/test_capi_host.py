@@ -108,10 +108,10 @@ def test_launch_shapes_by_problem_size():
     """The size heuristics: a single small region (the 1024^2 workload's 192^2 extended ROI,
     128 angles: 35 k rays, 37 k pixels) gets the most waves per ray and per pixel (8
     forward-projector segments, 8 backprojector angle groups, direct band reads); the
-    64-ROI batch on 2048^2 (extended parts up to 384^2) gets one segment with two rays
-    per lane and the LDS-staged backprojector with two pixels per thread.  The LDS-staged
-    forward projector (rays per lane 4) is taken when forced and the regions fit it, and
-    falls back to two rays per lane for a batch with a wider region.  Forced knobs are
+    256 tiles of 4096^2 (extended parts up to 320^2) get the LDS-staged forward projector
+    (rays per lane 4), the 64-ROI batch on 2048^2 (extended parts up to 384^2, wider than
+    the staged lines hold) two rays per lane, also when the staged projector is forced; both
+    get the LDS-staged backprojector with two pixels per thread.  Forced knobs are
     validated and kept."""
     import synth
     from paper_1604_02292_amd.tomo import make_params
@@ -125,13 +125,17 @@ def test_launch_shapes_by_problem_size():
     big = ctx.tomo_resolve_launch(g3, batch)
     assert (big["fp_segments"], big["fp_rays_per_lane"]) == (1, 2)
     assert (big["bp_variant"], big["bp_groups"], big["bp_pixels_per_thread"]) == (2, 1, 2)
-    ctx.tomo_set_launch(fp_rays_per_lane=4)
-    assert ctx.tomo_resolve_launch(g3, batch)["fp_rays_per_lane"] == 4
-    wide = ctx.tomo_resolve_launch(g3, batch + [make_params((0, 0, 400, 100), 0, "cp", 0.02, 200)])
-    assert wide["fp_rays_per_lane"] == 2
     g4 = ctx.tomo_set_geometry(4096, 512, 6144)
     tiles = [make_params(r[:4], r[4], "cp", 0.01, 200) for r in synth.roi_list("c4")]
-    assert ctx.tomo_resolve_launch(g4, tiles)["fp_rays_per_lane"] == 4
+    t4 = ctx.tomo_resolve_launch(g4, tiles)
+    assert (t4["fp_segments"], t4["fp_rays_per_lane"]) == (1, 4)
+    assert (t4["bp_variant"], t4["bp_groups"], t4["bp_pixels_per_thread"]) == (2, 1, 2)
+    ctx.tomo_set_launch(fp_rays_per_lane=4)
+    assert ctx.tomo_resolve_launch(g3, batch)["fp_rays_per_lane"] == 2
+    small_batch = [p for p in batch if p.roi.rows <= 128]
+    assert ctx.tomo_resolve_launch(g3, small_batch)["fp_rays_per_lane"] == 4
+    ctx.tomo_set_launch(fp_rays_per_lane=2)
+    assert ctx.tomo_resolve_launch(g4, tiles)["fp_rays_per_lane"] == 2
     ctx.tomo_set_launch()
     ctx.tomo_set_launch(fp_segments=4, bp_groups=2)
     forced = ctx.tomo_resolve_launch(g, [make_params((448, 448, 128, 128), 32, "cp", 0.02, 300)])
