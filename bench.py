@@ -635,7 +635,8 @@ def tiles_leg(torch, d, steps, warmup, quality=True):
         torch.cuda.synchronize()
         fbp_ms = ev0.elapsed_time(ev1) / 3
         dom_fp = fp_us >= bp_us
-        kname = "fp_kernel" if dom_fp else "bp_kernel"
+        fp_name = "fp_staged_kernel" if launch.get("fp_rays_per_lane") == 4 else "fp_kernel"
+        kname = fp_name if dom_fp else "bp_kernel"
         traffic = profiled_traffic("tiles256-n4096-a512", kname)
         roof = alu_roofline(kname, nnz, fp_us if dom_fp else bp_us, traffic)
         if traffic:

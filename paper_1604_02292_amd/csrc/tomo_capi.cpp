@@ -602,8 +602,8 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     float* rbuf = nullptr;
     const bool global_resid = !reg && band_sum > g.nd;
 
-    // L: the exterior projections (full-grid images); Li: the iteration loop, whose
-    // forward projector may stage the regions' lines in LDS
+    // L: the exterior projections of the full-grid image; Li: the projections of the
+    // regions' own images (band addition, iterations), which may stage their lines in LDS
     int max_pitch = 0, max_w = 0;
     for (auto& r : R) {
         max_pitch = std::max(max_pitch, std::max(r.plan.xp, r.plan.tp));
@@ -650,7 +650,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     size_t n_e1 = 0, n_e2 = 0, n_g = 0;
     for (int i = 0; i < count; ++i) {
         n_e1 += count_fp_items(R[i].plan_full.afp, L.seg, L.rp);
-        n_e2 += count_fp_items(R[i].plan.afp, L.seg, L.rp);
+        n_e2 += count_fp_items(R[i].plan.afp, Li.seg, Li.rp);
     }
     if (global_resid) n_g = count_fp_items(Pfull.afp, Lg.seg, Lg.rp);
     const size_t o_it_e1 = m.reserve(n_e1 * sizeof(Item));
@@ -672,7 +672,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         R[i].d_abp = (AngBP*)(dm + o_abp[i]);
         R[i].d_afp_full = (AngFP*)(dm + o_afpf[i]);
         fp_items(it_e1, i, R[i].plan_full.afp, L.seg, L.rp, R[i].d_afp_full);
-        fp_items(it_e2, i, R[i].plan.afp, L.seg, L.rp, R[i].d_afp);
+        fp_items(it_e2, i, R[i].plan.afp, Li.seg, Li.rp, R[i].d_afp);
     }
     if (global_resid) fp_items(it_g, 0, Pfull.afp, Lg.seg, Lg.rp, (const AngFP*)(dm + o_afp_glob));
     m.put(o_it_e1, it_e1.data(), it_e1.size() * sizeof(Item));
@@ -744,7 +744,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         CK(launch_pad_copy(E.plain, g.n, r.ext.r0, r.ext.c0, r.ext.rows, r.ext.cols, r.xb0,
                            r.plan.xp, r.xt, r.plan.tp, nullptr, 0, s));
     CK(launch_fp((const Job*)(dm + o_jobs_e2), (const Item*)(dm + o_it_e2), (int)it_e2.size(), 0,
-                 L.seg, s, L.cfp, L.rp));
+                 Li.seg, s, Li.cfp, Li.rp, Li.spitch));
     // Step sizes (cached per shape; the power iteration reuses the state buffers).
     for (auto& r : R) {
         tomo_status st = step_size_for(ctx, gid, r, s, ctx->staging);
