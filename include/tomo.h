@@ -301,7 +301,8 @@ tomo_status roi_step_size(tomo_ctx* ctx, int32_t geom, tomo_rect ext, float* sig
  * Ram-Lak FBP exterior estimate x_ext and the residual r = sino - W x_ext in
  * the workspace (Section 3.3: precompute once, reuse for every local part).
  * `sino` (float[n_angles][n_det]) is borrowed: it must stay alive and unchanged
- * until tomo_unregister_sinogram.  Blocking.  Errors: EINVAL, ENOENT, ENOMEM, EHIP. */
+ * until tomo_unregister_sinogram.  Blocking.  Errors: EINVAL (also for a sinogram
+ * that holds NaN or infinite values: nothing is registered), ENOENT, ENOMEM, EHIP. */
 tomo_status tomo_register_sinogram(tomo_ctx* ctx, int32_t geom, const float* sino,
                                    int32_t* sino_id);
 

@@ -190,6 +190,8 @@ hipError_t launch_pad_copy(const float* src, int lds, int r0, int c0, int nr, in
 // out[r][c] (row pitch ldo) = x[r + dr][c + dc] (row pitch ldx), r < rows, c < cols.
 hipError_t launch_crop(const float* x, int ldx, int dr, int dc, int rows, int cols, float* out,
                        int ldo, hipStream_t s);
+// *flag = 1 when any of p[0 .. n) is NaN or infinite (flag left as it is otherwise).
+hipError_t launch_check_finite(const float* p, size_t n, unsigned* flag, hipStream_t s);
 hipError_t launch_band_gather(const float* sino, int n_det, const AngFP* afp, int n_angles,
                               float* band, int bpitch, hipStream_t s);
 hipError_t launch_band_scatter(const float* band, int bpitch, const AngFP* afp, int n_angles,

@@ -1272,6 +1272,17 @@ __global__ void pad_copy_kernel(const float* __restrict__ src, int lds, int r0, 
     }
 }
 
+// *flag = 1 when any of the n values is NaN or infinite (a plain store from every
+// lane that finds one: all write the same value).
+__global__ void check_finite_kernel(const float* __restrict__ p, size_t n,
+                                    unsigned* __restrict__ flag) {
+    bool bad = false;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(p[i]);
+    if (bad) *flag = 1u;
+}
+
 __global__ void crop_kernel(const float* __restrict__ x, int ldx, int dr, int dc, int rows,
                             int cols, float* __restrict__ out, int ldo) {
     const size_t n = (size_t)rows * cols;
@@ -2330,6 +2341,11 @@ hipError_t launch_crop(const float* x, int ldx, int dr, int dc, int rows, int co
                        int ldo, hipStream_t s) {
     hipLaunchKernelGGL(crop_kernel, dim3(grid_for((size_t)rows * cols, 256)), dim3(256), 0, s, x,
                        ldx, dr, dc, rows, cols, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float* p, size_t n, unsigned* flag, hipStream_t s) {
+    hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, flag);
     return hipGetLastError();
 }
 

@@ -90,13 +90,16 @@ tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s) {
     S.tp = P.tp;
     const size_t nb = (size_t)g.n * P.xp, nt = (size_t)g.n * P.tp, np = (size_t)g.n * g.n;
     const size_t nr = (size_t)g.na * g.nd;
-    S.block = ctx->arena.alloc((nb + nt + np + nr) * sizeof(float) + 1024);
+    S.block = ctx->arena.alloc((nb + nt + np + nr + 64) * sizeof(float) + 1280);
     if (!S.block) return fail(ctx, TOMO_ENOMEM, "workspace too small to register the sinogram");
     S.xb = (float*)S.block;
     S.xt = S.xb + align_up(nb, 64);
     S.x_plain = S.xt + align_up(nt, 64);
     S.resid = S.x_plain + align_up(np, 64);
+    unsigned* d_bad = (unsigned*)(S.resid + align_up(nr, 64));   // non-finite input flag
     std::vector<char*> allocs;
+    TOMO_HIP(ctx, launch_fill((float*)d_bad, 1, 0.f, s));
+    TOMO_HIP(ctx, launch_check_finite(S.sino, nr, d_bad, s));
     TOMO_HIP(ctx, launch_fill(S.xb, (size_t)(S.resid - S.xb), 0.f, s));
     tomo_status st = fbp_into(ctx, S.gid, S.sino, S.x_plain, S.xb, S.xt, P, s, allocs, ctx->staging);
     if (st != TOMO_OK) {
@@ -142,6 +145,9 @@ tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     ctx->arena.free_after(allocs, s);
     if (e != hipSuccess) return fail(ctx, TOMO_EHIP, "registering: %s", hipGetErrorString(e));
+    unsigned bad = 0;
+    TOMO_HIP(ctx, hipMemcpy(&bad, d_bad, sizeof bad, hipMemcpyDeviceToHost));
+    if (bad) return fail(ctx, TOMO_EINVAL, "the sinogram holds NaN or infinite values");
     return TOMO_OK;
 }
 

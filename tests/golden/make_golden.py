@@ -3,7 +3,7 @@
 Every stored value is computed by the FP64 oracle (`oracle/`) from the seeded
 generator (`synth/`); nothing here touches the HIP library.
 
-    python tests/golden/make_golden.py [c2] [c3] [c4]
+    python tests/golden/make_golden.py [c2] [c3] [c4] [c5]
 """
 
 import os
@@ -45,6 +45,65 @@ def golden_workload(name, roi_indices=None, lam_scale=1.0, iters=None):
     np.savez_compressed(os.path.join(HERE, f"{name}_oracle.npz"), **out)
 
 
+def c5_sample(n=8, cp_count=6, max_side=256, n_slices=4):
+    """Requests of the serving workload's capacity stream for the served-parity test: the
+    first ones in stream order that fill two per side class ([32, 64), [64, 128),
+    [128, 192), [192, max_side]) with cp_count CP-TV and n - cp_count SIRT requests, on at
+    most n_slices slices (each slice costs the oracle one FBP)."""
+    reqs = synth.serving_requests(4000, 1.0, seed_offset=2)
+    edges = [32, 64, 128, 192, max_side + 1]
+    need = {c: n // 4 for c in range(4)}
+    cp_left, sirt_left = cp_count, n - cp_count
+    slices, pick = [], []
+    for i, r in enumerate(reqs):
+        side = r["rect"][2]
+        if side > max_side:
+            continue
+        c = next(k for k in range(4) if edges[k] <= side < edges[k + 1])
+        if need[c] == 0:
+            continue
+        if r["method"] == "cp" and cp_left == 0 or r["method"] == "sirt" and sirt_left == 0:
+            continue
+        if r["slice"] not in slices and len(slices) == n_slices:
+            continue
+        if r["slice"] not in slices:
+            slices.append(r["slice"])
+        need[c] -= 1
+        if r["method"] == "cp":
+            cp_left -= 1
+        else:
+            sirt_left -= 1
+        pick.append(i)
+        if len(pick) == n:
+            break
+    return reqs, pick
+
+
+def golden_serving():
+    t0 = time.time()
+    cfg = synth.workload("c5")
+    g = oracle.make_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+    reqs, pick = c5_sample()
+    slices = sorted({reqs[i]["slice"] for i in pick})
+    sinos = dict(zip(slices, synth.make_slices("c5", indices=slices)))
+    xes = {k: oracle.fbp_ramlak(g, v.astype(np.float32).astype(np.float64), workers=WORKERS)
+           for k, v in sinos.items()}
+    print(f"c5 slices {slices}: FBPs ({time.time() - t0:.1f}s)", flush=True)
+    out = {"pick": np.array(pick)}
+    for i in pick:
+        r = reqs[i]
+        p = sinos[r["slice"]].astype(np.float32).astype(np.float64)
+        res = oracle.local_solve(g, p, r["rect"], r["margin"], method=r["method"], lam=r["lam"],
+                                 iters=r["iters"], x_ext=xes[r["slice"]], full=True)
+        out[f"x_{i}"] = res["x"].astype(np.float32)
+        out[f"sigma_{i}"] = np.float64(res["sigma"] if r["method"] == "cp" else 0.0)
+        out[f"req_{i}"] = np.array([r["slice"], *r["rect"], r["margin"], r["iters"],
+                                    1 if r["method"] == "cp" else 0])
+        print(f"c5 request {i} slice {r['slice']} rect {r['rect']} {r['method']} "
+              f"{r['iters']} its ({time.time() - t0:.1f}s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c5_oracle.npz"), **out)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["c2"]
     if "c2" in which:
@@ -59,3 +118,5 @@ if __name__ == "__main__":
     if "c4" in which:
         # corner, edge and two interior tiles of the 16 x 16 grid
         golden_workload("c4", [0, 7, 16 * 5 + 6, 16 * 10 + 9])
+    if "c5" in which:
+        golden_serving()

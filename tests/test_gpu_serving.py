@@ -132,6 +132,17 @@ def test_admission_errors(served):
     with pytest.raises(TomoError) as e:
         ctx.roi_poll(123456789)
     assert e.value.status == _lib.TOMO_ENOENT
+    # a sinogram with a NaN or an infinity is refused and nothing stays registered
+    for bad in (float("nan"), float("inf")):
+        ctx.tomo_synchronize()
+        used0, _ = ctx.tomo_workspace_usage()
+        poisoned = sino.clone()
+        poisoned[3, 17] = bad
+        with pytest.raises(TomoError) as e:
+            ctx.tomo_register_sinogram(g, poisoned)
+        assert e.value.status == _lib.TOMO_EINVAL
+        ctx.tomo_synchronize()
+        assert ctx.tomo_workspace_usage()[0] == used0
     # invalid request
     o16 = torch.empty((16, 16), device="cuda")
     with pytest.raises(TomoError) as e:
@@ -187,3 +198,69 @@ def test_small_budget_admission(served):
         small.tomo_unregister_sinogram(sid2)
     finally:
         small.close()
+
+
+def _slices_in_subprocess(indices, tmpdir):
+    """The serving workload's slices, generated in a fresh process (the generator forks
+    worker processes, which must not inherit this process's GPU state)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(str(tmpdir), "c5_slices.npy")
+    code = ("import sys, numpy; sys.path.insert(0, %r); import synth; "
+            "numpy.save(%r, numpy.stack(synth.make_slices('c5', indices=%r)))"
+            % (root, path, list(indices)))
+    subprocess.run([sys.executable, "-c", code], check=True, timeout=600)
+    return dict(zip(indices, np.load(path)))
+
+
+def test_full_size_served_requests_match_oracle(tmp_path_factory):
+    """The serving workload at full size (2048^2 slices, 512 angles x 3072 bins): eight
+    sampled requests of its request stream (sides 41-200, 6 CP-TV and 2 SIRT, 161-292
+    iterations, on 4 resident slices), submitted interleaved with 24 other requests of the
+    same stream on the same slices, each against the stored FP64 oracle result at the 1e-3
+    reconstruction bar (tests/golden/make_golden.py c5; the oracle's FBP exterior, the
+    library's own resident FBP and residual on the GPU)."""
+    import os
+    from paper_1604_02292_amd import Context, make_params
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle result for the serving workload")
+    gold = np.load(path)
+    pick = [int(i) for i in gold["pick"]]
+    cfg = synth.workload("c5")
+    reqs = synth.serving_requests(4000, 1.0, seed_offset=2)
+    slices = sorted({reqs[i]["slice"] for i in pick})
+    others = [i for i in range(len(reqs)) if reqs[i]["slice"] in slices and i not in pick][:24]
+    print(f"[serve c5] slices {slices}: generating", flush=True)
+    data = _slices_in_subprocess(slices, tmp_path_factory.mktemp("c5"))
+    ctx = Context(0, workspace_bytes=4 << 30)
+    try:
+        g = ctx.tomo_set_geometry(cfg["n"], cfg["n_angles"], cfg["n_det"])
+        sinos = {k: dev(v) for k, v in data.items()}
+        sids = {k: ctx.tomo_register_sinogram(g, s) for k, s in sinos.items()}
+        order = sorted(pick + others)   # stream order: sampled requests among the others
+        outs, tickets = {}, []
+        for i in order:
+            r = reqs[i]
+            s = float(gold[f"sigma_{i}"]) if i in pick and r["method"] == "cp" else 0.0
+            p = make_params(r["rect"], r["margin"], r["method"], r["lam"], r["iters"], s, s)
+            outs[i] = torch.empty((r["rect"][2], r["rect"][3]), device="cuda")
+            tickets.append(ctx.roi_submit(sids[r["slice"]], p, outs[i]))
+        wait_all(ctx, tickets, timeout=300.0)
+        torch.cuda.synchronize()
+        for i in pick:
+            r = reqs[i]
+            assert tuple(gold[f"req_{i}"][1:5]) == tuple(r["rect"])
+            e = rel(outs[i].double().cpu().numpy(), gold[f"x_{i}"])
+            print(f"    request {i} slice {r['slice']} {r['rect']} {r['method']} "
+                  f"{r['iters']} its: rel {e:.2e}", flush=True)
+            assert e <= 1e-3
+        for i in others:
+            assert torch.isfinite(outs[i]).all()
+        ctx.tomo_synchronize()
+        for sid in sids.values():
+            ctx.tomo_unregister_sinogram(sid)
+    finally:
+        ctx.close()

@@ -1,0 +1,111 @@
+"""The host runtime (geometry, planning tables, launch selection, argument checks, the
+host-only context) built with AddressSanitizer and UndefinedBehaviorSanitizer and driven
+through the C ABI in a fresh process; any sanitizer report fails the test.  The device
+code is compiled as usual (the sanitizers cover the host objects only); no GPU call is
+made: the calls run on a host-only context (device -1)."""
+
+import os
+import subprocess
+import sys
+import textwrap
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1604_02292_amd", "csrc")
+HOST_SOURCES = ["tomo_plan.cpp", "tomo_capi.cpp", "tomo_serve.cpp", "tomo_local.cpp"]
+DEVICE_SOURCES = ["tomo_kernels.hip", "tomo_noalloc.hip"]
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+       "-fno-omit-frame-pointer", "-g", "-O1"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+
+
+def _build(out):
+    from paper_1604_02292_amd.build import COMMON, DEVICE_FLAGS, _hipcc
+    objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(out, src + ".o")
+        _run(["g++", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + SAN +
+             ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"])
+        objs.append(obj)
+    for src in DEVICE_SOURCES:
+        obj = os.path.join(out, src + ".o")
+        _run([_hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + ["-x", "hip"] +
+             DEVICE_FLAGS)
+        objs.append(obj)
+    lib = os.path.join(out, "libtomo_san.so")
+    _run(["g++", "-shared", "-o", lib] + objs + SAN +
+         ["-L/opt/rocm/lib", "-lamdhip64", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"])
+    return lib
+
+
+DRIVER = textwrap.dedent("""
+    import sys
+    sys.path.insert(0, {root!r})
+    from paper_1604_02292_amd import _lib
+    _lib.LIB_PATH = {lib!r}
+    import synth
+    from paper_1604_02292_amd import Context, TomoError, make_params
+    ctx = Context(device=-1)
+    for n, na, nd in [(128, 32, 192), (97, 45, 150), (2048, 256, 3072), (4096, 512, 6144)]:
+        g = ctx.tomo_set_geometry(n, na, nd)
+        for rect in [(0, 0, n, n), (0, 0, 1, 1), (n - 7, 3, 7, n - 3), (n // 3, n // 4, 16, 40)]:
+            i0, w = ctx.tomo_roi_band(g, rect)
+            assert len(i0) == na and min(w) >= 1
+            ext = ctx.tomo_roi_ext(g, rect, 9)
+            if n <= 2048 and rect[2] * rect[3] <= 4096:
+                assert ctx.tomo_roi_nnz(g, rect) > 0
+    g3 = ctx.tomo_set_geometry(2048, 256, 3072)
+    batch = [make_params(r[:4], r[4], "cp", 0.02, 200) for r in synth.roi_list("c3")]
+    print(ctx.tomo_resolve_launch(g3, batch))
+    g4 = ctx.tomo_set_geometry(4096, 512, 6144)
+    tiles = [make_params(r[:4], r[4], "cp", 0.01, 200) for r in synth.roi_list("c4")]
+    print(ctx.tomo_resolve_launch(g4, tiles))
+    for knobs in [dict(fp_rays_per_lane=4), dict(fp_segments=8, bp_groups=8), {{}}]:
+        ctx.tomo_set_launch(**knobs)
+        ctx.tomo_resolve_launch(g3, batch[:5])
+    bad = 0
+    for kw in [dict(fp_segments=3), dict(fp_rays_per_lane=3), dict(bp_variant=7)]:
+        try:
+            ctx.tomo_set_launch(**kw)
+        except TomoError:
+            bad += 1
+    assert bad == 3
+    for args in [(0, 32, 192), (128, 0, 192), (128, 32, -1)]:
+        try:
+            ctx.tomo_set_geometry(*args)
+            raise AssertionError("accepted " + str(args))
+        except TomoError:
+            pass
+    for rect in [(0, 0, 0, 4), (-1, 0, 4, 4), (120, 120, 16, 16)]:
+        try:
+            ctx.tomo_roi_band(0, rect)   # the 128-pixel geometry
+            raise AssertionError("accepted " + str(rect))
+        except TomoError:
+            pass
+    ctx.close()
+    print("host calls done")
+""")
+
+
+@pytest.mark.timeout(900)
+def test_host_runtime_under_address_and_ub_sanitizers(tmp_path):
+    lib = _build(str(tmp_path))
+    asan = subprocess.run(["g++", "-print-file-name=libasan.so"], capture_output=True,
+                          text=True).stdout.strip()
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = asan
+    env["ASAN_OPTIONS"] = "detect_leaks=0:alloc_dealloc_mismatch=0:abort_on_error=0"
+    env["UBSAN_OPTIONS"] = "print_stacktrace=1"
+    r = subprocess.run([sys.executable, "-c", DRIVER.format(root=ROOT, lib=lib)],
+                       capture_output=True, text=True, timeout=600, env=env)
+    report = r.stdout + r.stderr
+    assert "AddressSanitizer" not in report, report[-4000:]
+    assert "runtime error" not in report, report[-4000:]
+    assert r.returncode == 0, report[-4000:]
+    assert "host calls done" in r.stdout
