@@ -439,13 +439,12 @@ __global__ __launch_bounds__(fp_threads<SEG>()) void fp_kernel(const Job* __rest
 // coalesced reads - each pixel is read once per group instead of once per ray that
 // crosses it - stored column-major with an odd stride, so that a ray's two taps are
 // one ds_read2 and adjacent rays fall on distinct banks.  The (angle, ray) pairs of
-// the group are dealt to the threads in rounds, rays adjacent within an angle, and
+// the group are dealt to the threads in rounds, the angles of one ray adjacent, and
 // every pair takes its interpolation steps from LDS.  A wave skips a stage when none
-// of its rays meets the image inside the staged lines, and clamps the tap index
-// only in stages where one of its rays leaves the padded line (the pads and the
-// clamp give the exact zeros that the direct kernel's range-checked reads give).
-// Ray sums run in the same two levels as fp_kernel: per chunk of staged lines, then
-// into the ray.
+// of its rays meets the image inside the staged lines; zero columns on both sides of
+// the staged lines give the exact zeros that the direct kernel's range-checked reads
+// give, so no tap index is clamped.  Ray sums run in the same two levels as
+// fp_kernel: per chunk of staged lines, then into the ray.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __restrict__ jobs,
                                                                 const Item* __restrict__ items,
@@ -474,7 +473,11 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
     if (rounds > kFpsMaxRounds) return;   // the host never builds such a group
     LDS_AS float* S = (LDS_AS float*)fps_lds + kFpsZeroPad * STR;   // column 0 of the line
     const unsigned s_base = (unsigned)(size_t)S;
-    const float rcp_w = 1.0f / (float)W;
+    // pair p = ray j * nang + angle a: a wave holds the same few rays of every angle of
+    // the group, whose line ranges nearly coincide (adjacent rays of one angle enter and
+    // leave the region over a slanted front, which would idle lanes of a wave), and whose
+    // taps fall on few adjacent columns (distinct banks, or the same address)
+    const float rcp_n = 1.0f / (float)nang;
     const unsigned rowb = (unsigned)pitch * 4u;
     const __amdgpu_buffer_rsrc_t img_rs = make_rsrc(img, (size_t)n_outer * rowb);
 
@@ -542,8 +545,8 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
         val[r] = false;
         if (r < rounds) {
             const int p = r * NT + t;
-            const int a = min((int)(((float)p + 0.5f) * rcp_w), nang - 1);
-            const int j = p - a * W;
+            const int j = (int)(((float)p + 0.5f) * rcp_n);   // exact: p < 2^11, nang <= 64
+            const int a = p - j * nang;
             const AngFP A = tabs[a];
             val[r] = (p < npairs) && (j < A.w);
             pb[r] = fma((double)o_lo, A.step, fma((double)j, A.aj, A.a0));
@@ -624,8 +627,8 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
         if (r >= rounds) break;
         const int p = r * NT + t;
         if (!val[r]) continue;
-        const int a = min((int)(((float)p + 0.5f) * rcp_w), nang - 1);
-        const int j = p - a * W;
+        const int j = (int)(((float)p + 0.5f) * rcp_n);
+        const int a = p - j * nang;
         const AngFP A = tabs[a];
         float pre0 = 0.f, pre1 = 0.f;
         fp_operands(J, A, k0 + a, j, step, pre0, pre1);
