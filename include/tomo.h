@@ -325,9 +325,29 @@ tomo_status roi_submit(tomo_ctx* ctx, int32_t sino_id, const roi_params* params,
  * Errors: ENOENT (unknown or already reported ticket), EHIP (the request failed). */
 tomo_status roi_poll(tomo_ctx* ctx, uint64_t ticket, int* done, float* latency_ms);
 
+/* roi_poll with the request's timeline: stages_ms (float[4]) receives, once
+ * *done = 1, the host-clock times from submission to admission (queued), from
+ * admission to its first iteration (preparation: tables, b = r + W_L x_ext|L, step
+ * size), from there to completion (iterations, crop), and the total (the latency of
+ * roi_poll); -1 while not done.  Same ticket rules and errors as roi_poll. */
+tomo_status roi_poll_stages(tomo_ctx* ctx, uint64_t ticket, int* done, float* stages_ms);
+
 /* Serving knobs: maximum concurrent slots (default 32) and iterations per
  * scheduler tick (default 4); 0 leaves a value unchanged. */
 tomo_status tomo_serving_config(tomo_ctx* ctx, int32_t max_slots, int32_t iters_per_tick);
+
+/* Host-side testing of serving without a GPU.  On a host-only context (device -1)
+ * the first call (budget_bytes > 0) replaces the GPU work of serving by a test
+ * executor: registration, submission, admission against a workspace budget of
+ * budget_bytes (bookkeeping only: no memory is allocated or touched),
+ * continuous batching, ticket lifecycle and retirement run as on a GPU context,
+ * but `sino` and `out` are host memory, nothing is reconstructed, and a retired
+ * request's out holds the number of iterations that its slot ran.  Each tick takes
+ * tick_us microseconds per iteration; tick_us < 0 stalls the executor (ticks wait)
+ * until a later call with budget_bytes = 0 sets tick_us >= 0.  tomo_destroy ends a
+ * stall.  Errors: EINVAL (budget under 1 MiB), ESTATE (GPU context; a second
+ * set-up; a tick change before the set-up). */
+tomo_status tomo_serving_fake(tomo_ctx* ctx, size_t budget_bytes, int32_t tick_us);
 
 /* Iteration graphs: when enabled (the default), the second and later solves
  * with the same work-list layout replay a captured hipGraph of the whole
@@ -418,7 +438,9 @@ tomo_status tomo_kernel_time(tomo_ctx* ctx, int32_t kernel, int64_t* launches, d
 /* Workspace bytes in use now and at peak (host outputs). */
 tomo_status tomo_workspace_usage(tomo_ctx* ctx, size_t* used, size_t* peak);
 
-/* Wait until all GPU work issued by the context's own streams is done. */
+/* Wait until all GPU work issued by the context's own streams is done (with the
+ * serving test executor on a host-only context: until no request is queued or
+ * running). */
 tomo_status tomo_synchronize(tomo_ctx* ctx);
 
 #ifdef __cplusplus

@@ -69,7 +69,9 @@ SIGNATURES = {
     "tomo_unregister_sinogram": (C.c_int, [_P, _I]),
     "roi_submit": (C.c_int, [_P, _I, C.POINTER(roi_params), _P, C.POINTER(C.c_uint64)]),
     "roi_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_float)]),
+    "roi_poll_stages": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_float)]),
     "tomo_serving_config": (C.c_int, [_P, _I, _I]),
+    "tomo_serving_fake": (C.c_int, [_P, C.c_size_t, _I]),
     "tomo_set_launch": (C.c_int, [_P, C.POINTER(tomo_launch)]),
     "tomo_get_launch": (C.c_int, [_P, C.POINTER(tomo_launch)]),
     "tomo_resolve_launch": (C.c_int, [_P, _I, _I, C.POINTER(roi_params), C.POINTER(tomo_launch)]),

@@ -463,6 +463,15 @@ tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, S
 
 // Workspace bytes step_size_for will allocate for st (0 when the step is given
 // or cached): the power iteration's temporary state, tables and item lists.
+void step_size_assume_cached(tomo_ctx* ctx, int gid, const RoiState& st) {
+    if (st.prm.method != ROI_TV_NONNEG_CP) return;
+    const Geom& g = ctx->geoms[gid];
+    const int nr = std::min(g.n, (st.ext.rows + 15) / 16 * 16);
+    const int nc = std::min(g.n, (st.ext.cols + 15) / 16 * 16);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->step_cache.emplace(std::make_tuple(gid, nr, nc), std::nanf(""));
+}
+
 size_t step_size_scratch_bytes(tomo_ctx* ctx, int gid, const RoiState& st) {
     if (st.prm.method != ROI_TV_NONNEG_CP) return 0;
     if (st.prm.sigma > 0.f && st.prm.tau > 0.f) return 0;
@@ -1002,6 +1011,7 @@ tomo_status tomo_create(int device, void* workspace, size_t workspace_bytes, tom
 
 tomo_status tomo_destroy(tomo_ctx* ctx) {
     if (!ctx) return TOMO_EINVAL;
+    if (ctx->host_only) serve_shutdown(ctx);   // the test executor's scheduler, if any
     if (!ctx->host_only) {
         (void)hipSetDevice(ctx->device);
         serve_shutdown(ctx);
@@ -1673,6 +1683,10 @@ tomo_status tomo_workspace_usage(tomo_ctx* ctx, size_t* used, size_t* peak) {
 }
 
 tomo_status tomo_synchronize(tomo_ctx* ctx) {
+    if (ctx && ctx->host_only && serve_is_fake(ctx)) {
+        serve_drain(ctx);
+        return TOMO_OK;
+    }
     tomo_status st = need_gpu(ctx);
     if (st != TOMO_OK) return st;
     serve_drain(ctx);

@@ -225,6 +225,9 @@ tomo_status validate_params(tomo_ctx* ctx, const Geom& g, const roi_params& p);
 hipEvent_t timing_event(tomo_ctx* ctx);
 long long count_nnz(const Geom& g, const Rect& reg);
 size_t step_size_scratch_bytes(tomo_ctx* ctx, int gid, const RoiState& st);
+// The serving test executor (host-only contexts, which never solve): the request's
+// step-size shape counts as computed from now on, as after a GPU preparation.
+void step_size_assume_cached(tomo_ctx* ctx, int gid, const RoiState& st);
 tomo_status step_size_for(tomo_ctx* ctx, int gid, RoiState& st, hipStream_t s, Staging& stg);
 Job make_job(const Geom& g, const RoiState& st, int fp_mode, int bp_mode, int ntc);
 // Work items; the device table pointers must already be known (items store them).

@@ -47,7 +47,9 @@ struct Request {
     int sino_id = 0;
     roi_params prm{};
     float* out = nullptr;
-    double t_submit = 0.0;
+    double t_submit = 0.0;   // host clock (ms) at roi_submit
+    double t_admit = 0.0;    // admitted and prepared
+    double t_first = 0.0;    // its first iteration enqueued
 };
 
 struct Slot {
@@ -62,6 +64,9 @@ struct Slot {
 struct TicketInfo {
     int state = 0;   // 0 pending, 1 done, 2 failed
     float latency_ms = 0.f;
+    // submit -> admitted, admitted -> first iteration, first iteration -> done
+    // (negative until reached)
+    float stage_ms[3] = {-1.f, -1.f, -1.f};
     std::string err;
 };
 
@@ -80,17 +85,32 @@ struct ServeState {
     hipStream_t stream = nullptr;
     Staging staging;
     long long step = 0;   // global iteration counter of the batch
+    // Host-side test executor (host-only contexts): the scheduler runs its admission,
+    // batching and retirement logic unchanged, but a tick launches nothing; it takes
+    // fake_tick_us per iteration, or waits while fake_tick_us < 0 (a stalled
+    // executor), and a retired request's output holds the number of iterations that
+    // its slot ran.
+    bool fake = false;
+    int fake_tick_us = 0;
+    std::condition_variable cv_fake;
 };
+
+// Workspace bytes of a resident sinogram: padded x_ext and its transpose, the plain
+// x_ext, the residual and a flag word.
+static size_t resident_bytes(const Geom& g, const Plan& P) {
+    const size_t nb = (size_t)g.n * P.xp, nt = (size_t)g.n * P.tp, np = (size_t)g.n * g.n;
+    const size_t nr = (size_t)g.na * g.nd;
+    return (nb + nt + np + nr + 64) * sizeof(float) + 1280;
+}
 
 tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s) {
     const Geom& g = ctx->geoms[S.gid];
-    const Rect full{0, 0, g.n, g.n};
-    const Plan P = make_plan(g, full, full);
+    const Plan& P = g.full;
     S.xp = P.xp;
     S.tp = P.tp;
     const size_t nb = (size_t)g.n * P.xp, nt = (size_t)g.n * P.tp, np = (size_t)g.n * g.n;
     const size_t nr = (size_t)g.na * g.nd;
-    S.block = ctx->arena.alloc((nb + nt + np + nr + 64) * sizeof(float) + 1280);
+    S.block = ctx->arena.alloc(resident_bytes(g, P));
     if (!S.block) return fail(ctx, TOMO_ENOMEM, "workspace too small to register the sinogram");
     S.xb = (float*)S.block;
     S.xt = S.xb + align_up(nb, 64);
@@ -216,10 +236,42 @@ void finish_ticket(ServeState& S, uint64_t t, int state, float lat, const std::s
     it->second.err = err;
 }
 
+// Memory of retired work: after the stream's pending work (nothing is pending in the
+// test executor).
+void release(tomo_ctx* ctx, ServeState& S, const std::vector<char*>& ps) {
+    if (S.fake) {
+        for (char* p : ps)
+            if (p) ctx->arena.free_now(p);
+        return;
+    }
+    ctx->arena.free_after(ps, S.stream);
+}
+
+void record_stages(ServeState& S, const Request& q, double t_done) {
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.tickets.find(q.ticket);
+    if (it == S.tickets.end()) return;
+    it->second.stage_ms[0] = (float)(q.t_admit - q.t_submit);
+    it->second.stage_ms[1] = (float)(q.t_first - q.t_admit);
+    it->second.stage_ms[2] = (float)(t_done - q.t_first);
+}
+
+// One tick of the test executor: wait while stalled (or until shutdown), then take
+// the configured time per iteration.
+void fake_tick(ServeState& S, int iters) {
+    int us = 0;
+    {
+        std::unique_lock<std::mutex> lk(S.mu);
+        S.cv_fake.wait(lk, [&] { return S.stop || S.fake_tick_us >= 0; });
+        us = std::max(S.fake_tick_us, 0);
+    }
+    if (us > 0) std::this_thread::sleep_for(std::chrono::microseconds((long long)us * iters));
+}
+
 void scheduler(tomo_ctx* ctx) {
     t_serve = true;
     ServeState& S = *ctx->serve;
-    (void)hipSetDevice(ctx->device);
+    if (!S.fake) (void)hipSetDevice(ctx->device);
     std::vector<std::unique_ptr<Slot>> slots;
     char* d_lists = nullptr;
     size_t list_bytes = 0;   // the admitted slots' shares of the batch lists
@@ -230,6 +282,10 @@ void scheduler(tomo_ctx* ctx) {
     bool staged = false;
     bool changed = false;
     for (;;) {
+        if (slots.empty() && d_lists) {   // idle: hold nothing beyond the registrations
+            release(ctx, S, {d_lists});
+            d_lists = nullptr;
+        }
         // ---- admission ----
         {
             std::unique_lock<std::mutex> lk(S.mu);
@@ -331,14 +387,19 @@ void scheduler(tomo_ctx* ctx) {
             carve_state(g, r, blk);
             if (probe) ctx->arena.free_now(probe);
             t_err.clear();
-            tomo_status st = prepare_slot(ctx, S, *sl, T, tab);
+            tomo_status st = TOMO_OK;
+            if (S.fake)
+                step_size_assume_cached(ctx, sl->sino->gid, r);
+            else
+                st = prepare_slot(ctx, S, *sl, T, tab);
             if (st != TOMO_OK) {
                 finish_ticket(S, req.ticket, 2, 0.f, t_err);
                 (void)hipStreamSynchronize(S.stream);
-                ctx->arena.free_after(sl->allocs, S.stream);
+                release(ctx, S, sl->allocs);
                 sl->sino->users--;
                 continue;
             }
+            sl->req.t_admit = now_ms();
             sl->parity0 = (int)((2 - (S.step & 1)) & 1);   // (step + parity0) even at it = 0
             list_bytes += slot_list_bytes(sl->st);
             slots.push_back(std::move(sl));
@@ -367,15 +428,18 @@ void scheduler(tomo_ctx* ctx) {
             const size_t o_j = m.add(jobs.data(), jobs.size() * sizeof(Job));
             const size_t o_f = m.add(fi.data(), fi.size() * sizeof(Item));
             const size_t o_b = m.add(bi.data(), bi.size() * sizeof(Item));
-            if (d_lists) ctx->arena.free_after({d_lists}, S.stream);
-            d_lists = ctx->arena.alloc(m.buf.size(), true);
+            if (d_lists) release(ctx, S, {d_lists});
+            d_lists = ctx->arena.alloc(m.buf.size(), !S.fake);
             if (!d_lists ||
-                S.staging.upload(d_lists, m.buf.data(), m.buf.size(), S.stream) != hipSuccess) {
+                (!S.fake &&
+                 S.staging.upload(d_lists, m.buf.data(), m.buf.size(), S.stream) != hipSuccess)) {
                 for (auto& sl : slots) {
                     finish_ticket(S, sl->req.ticket, 2, 0.f, "cannot upload the batch lists");
-                    ctx->arena.free_after(sl->allocs, S.stream);
+                    release(ctx, S, sl->allocs);
                     sl->sino->users--;
                 }
+                if (d_lists) release(ctx, S, {d_lists});
+                d_lists = nullptr;
                 slots.clear();
                 list_bytes = 0;
                 continue;
@@ -394,7 +458,14 @@ void scheduler(tomo_ctx* ctx) {
         int tick = S.iters_per_tick;
         for (auto& sl : slots) tick = std::min(tick, sl->req.prm.iters - sl->it);
         hipError_t e = hipSuccess;
-        for (int t = 0; t < tick && e == hipSuccess; ++t) {
+        const double t_tick = now_ms();
+        for (auto& sl : slots)
+            if (sl->it == 0) sl->req.t_first = t_tick;
+        if (S.fake) {
+            fake_tick(S, tick);
+            S.step += tick;
+        }
+        for (int t = 0; t < tick && e == hipSuccess && !S.fake; ++t) {
             const int stp = (int)(S.step & 0x3fffffff);
             // slots of uneven size: items dealt round-robin over the XCDs
             e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream, 0, kServeRP);
@@ -409,16 +480,21 @@ void scheduler(tomo_ctx* ctx) {
             if (slots[q]->it >= slots[q]->req.prm.iters) done.push_back(q);
         for (size_t q : done) {
             const RoiState& r = slots[q]->st;
+            if (S.fake) {
+                std::fill(slots[q]->req.out, slots[q]->req.out + (size_t)r.roi.rows * r.roi.cols,
+                          (float)slots[q]->it);
+                continue;
+            }
             if (e == hipSuccess)
                 e = launch_crop(r.x, r.ext.cols, r.roi.r0 - r.ext.r0, r.roi.c0 - r.ext.c0,
                                 r.roi.rows, r.roi.cols, slots[q]->req.out, r.roi.cols, S.stream);
         }
-        if (e == hipSuccess) e = hipStreamSynchronize(S.stream);
+        if (e == hipSuccess && !S.fake) e = hipStreamSynchronize(S.stream);
         const double tnow = now_ms();
         if (e != hipSuccess) {
             for (auto& sl : slots) {
                 finish_ticket(S, sl->req.ticket, 2, 0.f, hipGetErrorString(e));
-                ctx->arena.free_after(sl->allocs, S.stream);
+                release(ctx, S, sl->allocs);
                 sl->sino->users--;
             }
             slots.clear();
@@ -428,23 +504,25 @@ void scheduler(tomo_ctx* ctx) {
         }
         for (auto qi = done.rbegin(); qi != done.rend(); ++qi) {
             Slot& sl = *slots[*qi];
+            record_stages(S, sl.req, tnow);
             finish_ticket(S, sl.req.ticket, 1, (float)(tnow - sl.req.t_submit), "");
-            ctx->arena.free_after(sl.allocs, S.stream);
+            release(ctx, S, sl.allocs);
             sl.sino->users--;
             list_bytes -= slot_list_bytes(sl.st);
             slots.erase(slots.begin() + (long)*qi);
             changed = true;
         }
     }
-    if (d_lists) ctx->arena.free_after({d_lists}, S.stream);
-    (void)hipStreamSynchronize(S.stream);
+    if (d_lists) release(ctx, S, {d_lists});
+    if (!S.fake) (void)hipStreamSynchronize(S.stream);
 }
 
 tomo_status ensure_serving(tomo_ctx* ctx) {
     if (ctx->serve && ctx->serve->th.joinable()) return TOMO_OK;
     if (!ctx->serve) ctx->serve = std::make_unique<ServeState>();
     ServeState& S = *ctx->serve;
-    if (!S.stream) TOMO_HIP(ctx, hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
+    if (!S.stream && !S.fake)
+        TOMO_HIP(ctx, hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
     S.stop = false;
     S.th = std::thread(scheduler, ctx);
     return TOMO_OK;
@@ -460,11 +538,14 @@ void serve_shutdown(tomo_ctx* ctx) {
         S.stop = true;
     }
     S.cv.notify_all();
+    S.cv_fake.notify_all();
     if (S.th.joinable()) S.th.join();
     S.staging.destroy();
     if (S.stream) (void)hipStreamDestroy(S.stream);
     S.stream = nullptr;
 }
+
+bool serve_is_fake(const tomo_ctx* ctx) { return ctx->serve && ctx->serve->fake; }
 
 void serve_drain(tomo_ctx* ctx) {
     if (!ctx->serve) return;
@@ -482,20 +563,40 @@ tomo_ctx::~tomo_ctx() = default;
 
 extern "C" {
 
+static bool fake_serving(const tomo_ctx* ctx) { return serve_is_fake(ctx); }
+
+// The test executor's registration: the same workspace share, the sinogram (host
+// memory) checked on the host, no exterior estimate.
+static tomo_status register_fake(tomo_ctx* ctx, SinoState& S) {
+    const Geom& g = ctx->geoms[S.gid];
+    const size_t nr = (size_t)g.na * g.nd;
+    for (size_t i = 0; i < nr; ++i)
+        if (!std::isfinite(S.sino[i]))
+            return fail(ctx, TOMO_EINVAL, "the sinogram holds NaN or infinite values");
+    S.xp = g.full.xp;
+    S.tp = g.full.tp;
+    S.block = ctx->arena.alloc(resident_bytes(g, g.full), false);
+    if (!S.block) return fail(ctx, TOMO_ENOMEM, "workspace too small to register the sinogram");
+    return TOMO_OK;
+}
+
 tomo_status tomo_register_sinogram(tomo_ctx* ctx, int32_t geom, const float* sino,
                                    int32_t* sino_id) {
     if (!ctx || !sino || !sino_id) return ctx ? fail(ctx, TOMO_EINVAL, "null pointer") : TOMO_EINVAL;
-    if (ctx->host_only) return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
+    if (ctx->host_only && !fake_serving(ctx))
+        return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
     try {
         if (geom < 0 || geom >= (int)ctx->geoms.size())
             return fail(ctx, TOMO_ENOENT, "unknown geometry %d", geom);
-        TOMO_HIP(ctx, hipSetDevice(ctx->device));
+        const bool fake = fake_serving(ctx);
+        if (!fake) TOMO_HIP(ctx, hipSetDevice(ctx->device));
         auto S = std::make_unique<SinoState>();
         S->gid = geom;
         S->sino = sino;
-        tomo_status st = build_resident(ctx, *S, nullptr);
+        tomo_status st = fake ? register_fake(ctx, *S) : build_resident(ctx, *S, nullptr);
         if (st != TOMO_OK) {
-            if (S->block) ctx->arena.free_after({S->block}, nullptr);
+            if (S->block && fake) ctx->arena.free_now(S->block);
+            else if (S->block) ctx->arena.free_after({S->block}, nullptr);
             return st;
         }
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -516,8 +617,12 @@ tomo_status tomo_unregister_sinogram(tomo_ctx* ctx, int32_t sino_id) {
     if (it->second->users.load() > 0)
         return fail(ctx, TOMO_EBUSY, "sinogram %d has %d live requests", sino_id,
                     it->second->users.load());
-    (void)hipSetDevice(ctx->device);
-    ctx->arena.free_after({it->second->block}, nullptr);
+    if (fake_serving(ctx)) {
+        ctx->arena.free_now(it->second->block);
+    } else {
+        (void)hipSetDevice(ctx->device);
+        ctx->arena.free_after({it->second->block}, nullptr);
+    }
     ctx->sinos.erase(it);
     return TOMO_OK;
 }
@@ -526,7 +631,8 @@ tomo_status roi_submit(tomo_ctx* ctx, int32_t sino_id, const roi_params* params,
                        uint64_t* ticket) {
     if (!ctx || !params || !out || !ticket)
         return ctx ? fail(ctx, TOMO_EINVAL, "null pointer") : TOMO_EINVAL;
-    if (ctx->host_only) return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
+    if (ctx->host_only && !fake_serving(ctx))
+        return fail(ctx, TOMO_ESTATE, "host-only context: no GPU calls");
     try {
         SinoState* sp = nullptr;
         {
@@ -594,6 +700,57 @@ tomo_status roi_poll(tomo_ctx* ctx, uint64_t ticket, int* done, float* latency_m
     if (latency_ms) *latency_ms = it->second.latency_ms;
     S.tickets.erase(it);
     return TOMO_OK;
+}
+
+tomo_status roi_poll_stages(tomo_ctx* ctx, uint64_t ticket, int* done, float* stages_ms) {
+    if (!ctx || !done || !stages_ms) return ctx ? fail(ctx, TOMO_EINVAL, "null pointer") : TOMO_EINVAL;
+    *done = 0;
+    for (int i = 0; i < 4; ++i) stages_ms[i] = -1.f;
+    if (!ctx->serve) return fail(ctx, TOMO_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    ServeState& S = *ctx->serve;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.tickets.find(ticket);
+    if (it == S.tickets.end())
+        return fail(ctx, TOMO_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second.state == 0) return TOMO_OK;
+    if (it->second.state == 2) {
+        const std::string err = it->second.err;
+        S.tickets.erase(it);
+        return fail(ctx, TOMO_EHIP, "request failed: %s", err.c_str());
+    }
+    *done = 1;
+    for (int i = 0; i < 3; ++i) stages_ms[i] = it->second.stage_ms[i];
+    stages_ms[3] = it->second.latency_ms;
+    S.tickets.erase(it);
+    return TOMO_OK;
+}
+
+tomo_status tomo_serving_fake(tomo_ctx* ctx, size_t budget_bytes, int32_t tick_us) {
+    if (!ctx) return TOMO_EINVAL;
+    if (!ctx->host_only)
+        return fail(ctx, TOMO_ESTATE, "the test executor runs on host-only contexts only");
+    try {
+        if (!ctx->serve) ctx->serve = std::make_unique<ServeState>();
+        ServeState& S = *ctx->serve;
+        if (budget_bytes) {
+            if (S.fake) return fail(ctx, TOMO_ESTATE, "the test executor is already set up");
+            if (budget_bytes < (1u << 20))
+                return fail(ctx, TOMO_EINVAL, "the budget must be at least 1 MiB");
+            // offsets only: no memory stands behind this range, and nothing reads it
+            ctx->arena.init(reinterpret_cast<char*>((uintptr_t)1 << 40), budget_bytes);
+            S.fake = true;
+        } else if (!S.fake) {
+            return fail(ctx, TOMO_ESTATE, "set the test executor up with a budget first");
+        }
+        {
+            std::lock_guard<std::mutex> lk(S.mu);
+            S.fake_tick_us = tick_us;
+        }
+        S.cv_fake.notify_all();
+        return TOMO_OK;
+    } catch (...) {
+        return fail(ctx, TOMO_ENOMEM, "host allocation failed");
+    }
 }
 
 tomo_status tomo_serving_config(tomo_ctx* ctx, int32_t max_slots, int32_t iters_per_tick) {

@@ -29,7 +29,8 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
 tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s);
 
 void serve_shutdown(tomo_ctx* ctx);
-void serve_drain(tomo_ctx* ctx);
+void serve_drain(tomo_ctx* ctx);   // until no request is queued or running
+bool serve_is_fake(const tomo_ctx* ctx);   // serving through the host test executor
 
 // Errors raised on the scheduler thread go to a thread-local buffer instead of
 // the context's last-error string (which belongs to the caller's thread).

@@ -24,7 +24,7 @@ def _rect(r):
     return tomo_rect(*[int(v) for v in r])
 
 
-def _ptr(t, shape=None, name="array"):
+def _ptr(t, shape=None, name="array", host=False):
     import torch
     if t is None:
         return None
@@ -32,8 +32,8 @@ def _ptr(t, shape=None, name="array"):
         raise TypeError(f"{name} must be a torch tensor")
     if t.dtype != torch.float32:
         raise TypeError(f"{name} must be float32")
-    if t.device.type != "cuda":
-        raise ValueError(f"{name} must be on the GPU")
+    if t.device.type != ("cpu" if host else "cuda"):
+        raise ValueError(f"{name} must be on the {'host' if host else 'GPU'}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -84,6 +84,7 @@ class Context:
             raise TomoError(st, "tomo_create failed")
         self.h = h
         self.geoms = {}
+        self.fake = False   # serving through the host test executor (host memory)
 
     def close(self):
         if getattr(self, "h", None):
@@ -243,8 +244,8 @@ class Context:
     def tomo_register_sinogram(self, geom, sino):
         n, na, nd = self.geoms[geom]
         sid = C.c_int32()
-        self._check(self.lib.tomo_register_sinogram(self.h, geom, _ptr(sino, (na, nd), "sino"),
-                                                    C.byref(sid)))
+        self._check(self.lib.tomo_register_sinogram(
+            self.h, geom, _ptr(sino, (na, nd), "sino", self.fake), C.byref(sid)))
         return sid.value
 
     def tomo_unregister_sinogram(self, sino_id):
@@ -254,7 +255,8 @@ class Context:
         t = C.c_uint64()
         p = params
         st = self.lib.roi_submit(self.h, int(sino_id), C.byref(p),
-                                 _ptr(out, (p.roi.rows, p.roi.cols), "out"), C.byref(t))
+                                 _ptr(out, (p.roi.rows, p.roi.cols), "out", self.fake),
+                                 C.byref(t))
         self._check(st)
         return t.value
 
@@ -263,6 +265,22 @@ class Context:
         lat = C.c_float()
         self._check(self.lib.roi_poll(self.h, C.c_uint64(ticket), C.byref(done), C.byref(lat)))
         return bool(done.value), (lat.value if done.value else None)
+
+    def roi_poll_stages(self, ticket):
+        """(done, None) or (True, dict(queued_ms, prepare_ms, run_ms, latency_ms))."""
+        done = C.c_int()
+        st = (C.c_float * 4)()
+        self._check(self.lib.roi_poll_stages(self.h, C.c_uint64(ticket), C.byref(done), st))
+        if not done.value:
+            return False, None
+        return True, dict(zip(("queued_ms", "prepare_ms", "run_ms", "latency_ms"), list(st)))
+
+    def tomo_serving_fake(self, budget_bytes=0, tick_us=0):
+        """Host test executor of serving (host-only context): budget_bytes > 0 sets it
+        up; later calls with budget_bytes = 0 change tick_us (< 0 stalls)."""
+        self._check(self.lib.tomo_serving_fake(self.h, C.c_size_t(int(budget_bytes)),
+                                               int(tick_us)))
+        self.fake = True
 
     def tomo_serving_config(self, max_slots=0, iters_per_tick=0):
         self._check(self.lib.tomo_serving_config(self.h, int(max_slots), int(iters_per_tick)))

@@ -1,6 +1,7 @@
 """The host runtime (geometry, planning tables, launch selection, argument checks, the
-host-only context) built with AddressSanitizer and UndefinedBehaviorSanitizer and driven
-through the C ABI in a fresh process; any sanitizer report fails the test.  The device
+host-only context, the serving scheduler thread through its host test executor) built
+with AddressSanitizer and UndefinedBehaviorSanitizer and driven through the C ABI in a
+fresh process; any sanitizer report fails the test.  The device
 code is compiled as usual (the sanitizers cover the host objects only); no GPU call is
 made: the calls run on a host-only context (device -1)."""
 
@@ -88,6 +89,51 @@ DRIVER = textwrap.dedent("""
             raise AssertionError("accepted " + str(rect))
         except TomoError:
             pass
+    ctx.close()
+    # the serving scheduler (its own thread) through the host test executor, with
+    # host buffers passed straight through the C ABI
+    import ctypes as C, time
+    from paper_1604_02292_amd import _lib as L
+    ctx = Context(device=-1)
+    lib, h = ctx.lib, ctx.h
+    assert lib.tomo_serving_fake(h, 64 << 20, 0) == 0
+    assert lib.tomo_serving_config(h, 4, 3) == 0
+    g = ctx.tomo_set_geometry(128, 32, 192)
+    sino = (C.c_float * (32 * 192))()
+    sid = C.c_int32()
+    assert lib.tomo_register_sinogram(h, g, C.cast(sino, C.c_void_p), C.byref(sid)) == 0
+    outs, tickets = [], []
+    for k in range(24):
+        out = (C.c_float * 256)()
+        p = make_params((10 + k, 20, 16, 16), 4, "cp", 0.05, 3 + k)
+        t = C.c_uint64()
+        assert lib.roi_submit(h, sid.value, C.byref(p), C.cast(out, C.c_void_p),
+                              C.byref(t)) == 0
+        outs.append((out, 3 + k))
+        tickets.append(t.value)
+    pending, t0 = set(tickets), time.time()
+    stages = (C.c_float * 4)()
+    while pending and time.time() - t0 < 60:
+        for t in list(pending):
+            done = C.c_int()
+            assert lib.roi_poll_stages(h, C.c_uint64(t), C.byref(done), stages) == 0
+            if done.value:
+                pending.discard(t)
+        time.sleep(0.001)
+    assert not pending
+    for out, it in outs:
+        assert all(v == float(it) for v in out)
+    assert lib.tomo_synchronize(h) == 0
+    assert lib.tomo_unregister_sinogram(h, sid.value) == 0
+    # a stalled executor with queued work, ended by destroy
+    assert lib.tomo_serving_fake(h, 0, -1) == 0
+    assert lib.tomo_register_sinogram(h, g, C.cast(sino, C.c_void_p), C.byref(sid)) == 0
+    keep = [(C.c_float * 256)() for _ in range(8)]
+    for out in keep:
+        p = make_params((40, 40, 16, 16), 4, "cp", 0.05, 50)
+        t = C.c_uint64()
+        assert lib.roi_submit(h, sid.value, C.byref(p), C.cast(out, C.c_void_p),
+                              C.byref(t)) == 0
     ctx.close()
     print("host calls done")
 """)
