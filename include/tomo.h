@@ -219,6 +219,26 @@ tomo_status roi_solve_stitched(tomo_ctx* ctx, int32_t geom, const float* sino,
                                const float* x_ext, int32_t count, const roi_params* params,
                                float* img, int32_t ld, void* hip_stream);
 
+/* Bytes of the iteration state of one CP-TV or SIRT solve (Section 2.2, Algorithm
+ * CP: the primal x, the extrapolated primal in two buffers and its transposed copy,
+ * the TV dual in two buffers, the data dual on the detector band), for
+ * roi_solve_resume.  Host call.  Errors: EINVAL (also for the local methods), ENOENT. */
+tomo_status roi_state_bytes(tomo_ctx* ctx, int32_t geom, const roi_params* params,
+                            size_t* bytes);
+
+/* roi_solve in pieces: runs params->iters iterations that follow `done` earlier
+ * ones.  state (device, roi_state_bytes, caller-owned) holds the iteration state
+ * after those `done` iterations (ignored when done = 0: the solve starts from
+ * zero) and receives the state after done + iters; out receives the crop as in
+ * roi_solve.  Running K1 iterations from done = 0 and then K2 from done = K1 with
+ * the same params otherwise gives the bits of one roi_solve of K1 + K2 iterations
+ * (the steps of a CP-TV solve are fixed by the region's shape, as in roi_solve).
+ * A state of other params, or a wrong `done` parity, gives wrong results.
+ * Stream-ordered on hip_stream.  Errors as roi_solve, and EINVAL for done < 0. */
+tomo_status roi_solve_resume(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                             const roi_params* params, int32_t done, void* state, float* out,
+                             void* hip_stream);
+
 /* SIRT-approximating FBP filters (Section 3.1: eq. filtcalc, eq. sirtapp, Alg. 1).
  * filters: device float[iters][n_angles][n_det], caller-owned; plane k - 1
  * receives u_k = alpha W q_k with q_k = sum_{j<k} A^j e, A = I - alpha W^T W,

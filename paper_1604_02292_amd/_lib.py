@@ -59,6 +59,8 @@ SIGNATURES = {
     "roi_solve_batch": (C.c_int, [_P, _I, _P, _P, _I, C.POINTER(roi_params), C.POINTER(_P), _P]),
     "roi_solve_stitched": (C.c_int, [_P, _I, _P, _P, _I, C.POINTER(roi_params), _P, _I, _P]),
     "roi_step_size": (C.c_int, [_P, _I, tomo_rect, C.POINTER(C.c_float)]),
+    "roi_state_bytes": (C.c_int, [_P, _I, C.POINTER(roi_params), C.POINTER(C.c_size_t)]),
+    "roi_solve_resume": (C.c_int, [_P, _I, _P, _P, C.POINTER(roi_params), _I, _P, _P, _P]),
     "tomo_sirt_filters": (C.c_int, [_P, _I, _I, _P, _P]),
     "tomo_sirt_filter_sino": (C.c_int, [_P, _I, _P, _I, _P, _P, _P]),
     "roi_solve_local": (C.c_int, [_P, _I, _P, _I, _I, C.POINTER(roi_params), C.POINTER(_P), _P]),

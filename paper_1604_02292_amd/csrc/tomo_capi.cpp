@@ -342,10 +342,10 @@ static tomo_status prepare_exterior(tomo_ctx* ctx, int gid, const float* sino,
 void carve_state(const Geom& g, RoiState& st, char* blk) {
     const Plan& p = st.plan;
     const size_t nr = p.reg.rows, nc = p.reg.cols;
-    float* f = (float*)blk;
+    size_t off = 0;   // floats; blk = nullptr computes the sizes only
     auto take = [&](size_t n) {
-        float* q = f;
-        f += align_up(n, 64);
+        float* q = blk ? (float*)blk + off : nullptr;
+        off += align_up(n, 64);
         return q;
     };
     st.x = take(nr * nc);
@@ -355,10 +355,10 @@ void carve_state(const Geom& g, RoiState& st, char* blk) {
     st.z0 = take(2 * nr * nc);
     st.z1 = take(2 * nr * nc);
     st.y = take((size_t)g.na * p.bpitch);
-    st.state_floats = (size_t)(f - (float*)blk);
+    st.state_floats = off;   // the iteration state: the resumable head of the block
     st.b = take((size_t)g.na * p.bpitch);
     st.part = take(((nr + 7) / 8) * ((nc + 7) / 8));
-    st.total_floats = (size_t)(f - (float*)blk);
+    st.total_floats = off;
     st.block = blk;
 }
 
@@ -559,7 +559,8 @@ tomo_status run_loop(tomo_ctx* ctx, const std::vector<long long>& key, const Met
 // registered sinogram whose x_ext and residual r = p - W x_ext are resident.
 tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* x_ext_user,
                         const SinoState* reg, int count, const roi_params* params,
-                        float* const* outs, hipStream_t s, int ldo) {
+                        float* const* outs, hipStream_t s, int ldo, float* const* states,
+                        int done) {
     const Geom& g = ctx->geoms[gid];
     const Rect full{0, 0, g.n, g.n};
     std::vector<RoiState> R(count);
@@ -762,8 +763,21 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
             return st;
         }
     }
-    // Zero the iteration state again (x, xbar, xbar^T, z, y; b is kept).
-    for (auto& r : R) CK(launch_fill((float*)r.block, r.state_floats, 0.f, s));
+    // The iteration state (x, both xbar buffers, xbar^T, both z buffers, y; b is kept):
+    // zero, or the caller's saved state after `done` earlier iterations.
+    auto start_state = [&]() -> hipError_t {
+        for (auto& r : R) {
+            const size_t i = (size_t)(&r - R.data());
+            const hipError_t e =
+                (states && done > 0)
+                    ? hipMemcpyAsync(r.block, states[i], r.state_floats * sizeof(float),
+                                     hipMemcpyDeviceToDevice, s)
+                    : launch_fill((float*)r.block, r.state_floats, 0.f, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    CK(start_state());
 
     // Iteration jobs; ROIs ordered by decreasing iteration count so that the
     // work items of the still-running ROIs always form a prefix of the list,
@@ -782,6 +796,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         const bool cp = r.prm.method == ROI_TV_NONNEG_CP;
         jobs[q] = make_job(g, r, cp ? FP_CP_DUAL : FP_SIRT, cp ? BP_CP : BP_SIRT,
                            (r.ext.cols + tw - 1) / tw);
+        jobs[q].parity0 = done & 1;   // the double buffers hold iteration `done`'s values
         fp_items(fi, q, r.plan.afp, Li.seg, Li.rp, r.d_afp);
         bp_items(bi, q, r.ext.rows, r.ext.cols, L.ag, L.ppt, r.d_abp);
         fi_end[q] = (int)fi.size();
@@ -869,7 +884,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
             (void)hipGraphExecDestroy(ex);
             (void)hipGraphDestroy(gr);
         }
-        for (auto& r : R) CK(launch_fill((float*)r.block, r.state_floats, 0.f, s));
+        CK(start_state());
     }
     if (!timed) {
         std::vector<long long> key = {0,     max_it, L.seg, L.ag,  L.ppt, L.rp,
@@ -898,6 +913,9 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
         const RoiState& r = R[i];
         CK(launch_crop(r.x, r.ext.cols, r.roi.r0 - r.ext.r0, r.roi.c0 - r.ext.c0, r.roi.rows,
                        r.roi.cols, outs[i], ldo > 0 ? ldo : r.roi.cols, s));
+        if (states)
+            CK(hipMemcpyAsync(states[i], r.block, r.state_floats * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
     }
 #undef CK
     cleanup();
@@ -1370,6 +1388,43 @@ tomo_status roi_solve(tomo_ctx* ctx, int32_t geom, const float* sino, const floa
     if (!params) return ctx ? fail(ctx, TOMO_EINVAL, "null params") : TOMO_EINVAL;
     float* outs[1] = {out};
     return roi_solve_batch(ctx, geom, sino, x_ext, 1, params, outs, hip_stream);
+}
+
+tomo_status roi_state_bytes(tomo_ctx* ctx, int32_t geom, const roi_params* params,
+                            size_t* bytes) {
+    if (!ctx || !params || !bytes) return ctx ? fail(ctx, TOMO_EINVAL, "null pointer") : TOMO_EINVAL;
+    GUARD_BEGIN
+    const Geom* gp;
+    tomo_status st = get_geom(ctx, geom, &gp);
+    if (st != TOMO_OK) return st;
+    if ((st = validate_params(ctx, *gp, *params)) != TOMO_OK) return st;
+    if (params->method >= ROI_LOCAL_SIRT)
+        return fail(ctx, TOMO_EINVAL, "local-method solves are not resumable");
+    RoiState r;
+    r.roi = Rect{params->roi.row0, params->roi.col0, params->roi.rows, params->roi.cols};
+    r.ext = extend_rect(r.roi, params->margin, gp->n);
+    r.plan = make_plan(*gp, r.ext, r.ext);
+    carve_state(*gp, r, nullptr);   // sizes only
+    *bytes = r.state_floats * sizeof(float);
+    return TOMO_OK;
+    GUARD_END(ctx)
+}
+
+tomo_status roi_solve_resume(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,
+                             const roi_params* params, int32_t done, void* state, float* out,
+                             void* hip_stream) {
+    tomo_status st = need_gpu(ctx);
+    if (st != TOMO_OK) return st;
+    if (!sino || !params || !state || !out) return fail(ctx, TOMO_EINVAL, "null pointer");
+    if (done < 0) return fail(ctx, TOMO_EINVAL, "done = %d iterations", done);
+    GUARD_BEGIN
+    const Geom* gp;
+    if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
+    float* outs[1] = {out};
+    float* states[1] = {(float*)state};
+    return solve_batch(ctx, geom, sino, x_ext, nullptr, 1, params, outs, (hipStream_t)hip_stream,
+                       0, states, done);
+    GUARD_END(ctx)
 }
 
 tomo_status roi_solve_batch(tomo_ctx* ctx, int32_t geom, const float* sino, const float* x_ext,

@@ -21,9 +21,12 @@ struct SinoState {
 };
 
 // outs[i]: ROI i's crop, row pitch ldo (0: the ROI's width, i.e. contiguous).
+// states[i] (optional, device): ROI i's iteration state, read when done > 0 (the
+// state after `done` earlier iterations) and written after the solve.
 tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* x_ext_user,
                         const SinoState* reg, int count, const roi_params* params,
-                        float* const* outs, hipStream_t s, int ldo = 0);
+                        float* const* outs, hipStream_t s, int ldo = 0,
+                        float* const* states = nullptr, int done = 0);
 
 // Compute x_ext (Ram-Lak FBP) and r into a SinoState's buffers on stream s.
 tomo_status build_resident(tomo_ctx* ctx, SinoState& S, hipStream_t s);

@@ -169,6 +169,22 @@ class Context:
                                        _ptr(out, (p.roi.rows, p.roi.cols), "out"),
                                        _stream(stream)))
 
+    def roi_state_bytes(self, geom, params):
+        b = C.c_size_t()
+        self._check(self.lib.roi_state_bytes(self.h, geom, C.byref(params), C.byref(b)))
+        return b.value
+
+    def roi_solve_resume(self, geom, sino, params, done, state, out, x_ext=None, stream=None):
+        """state: float32 GPU tensor of roi_state_bytes / 4 entries (caller-owned)."""
+        n, na, nd = self.geoms[geom]
+        p = params
+        nbytes = self.roi_state_bytes(geom, p)
+        self._check(self.lib.roi_solve_resume(self.h, geom, _ptr(sino, (na, nd), "sino"),
+                                              _ptr(x_ext, (n, n), "x_ext"), C.byref(p),
+                                              int(done), _ptr(state, (nbytes // 4,), "state"),
+                                              _ptr(out, (p.roi.rows, p.roi.cols), "out"),
+                                              _stream(stream)))
+
     def roi_solve_batch(self, geom, sino, params, outs, x_ext=None, stream=None):
         n, na, nd = self.geoms[geom]
         cnt = len(params)
