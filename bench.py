@@ -183,7 +183,155 @@ def local_cpu_baseline(d, iters):
                       "(filter recursion excluded)"}
 
 
-def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
+def _oracle_region_costs(geo, sino, ext, lam, h, n_it=3, n_ang_sample=32):
+    """Single-thread FP64 oracle costs on one extended region: the sparse W_L build; the
+    exterior subtraction over its band (from a zero exterior image: the same work) on
+    n_ang_sample of the angles, scaled to all; and one power-iteration step, one CP-TV
+    iteration and one SIRT iteration (each the mean of n_it)."""
+    import oracle
+    n, na = geo.n, geo.n_angles
+    t0 = time.perf_counter()
+    WL = oracle.sparse_local(geo, ext)
+    t_wl = time.perf_counter() - t0
+    used = np.zeros(na * geo.n_det, bool)
+    used[np.unique(WL.tocoo().row)] = True
+    used = used.reshape(na, geo.n_det)
+    pick = np.arange(0, na, max(1, na // n_ang_sample))[:n_ang_sample]
+    sample = np.zeros_like(used)
+    sample[pick] = used[pick]
+    t0 = time.perf_counter()
+    oracle.exterior_subtract(geo, sino, np.zeros((n, n)), ext, bins=sample)
+    t_ext = (time.perf_counter() - t0) * na / len(pick)
+    shape = (ext[2], ext[3])
+    t0 = time.perf_counter()
+    oracle.power_norm_sq(WL, shape, n_it)
+    t_pow = (time.perf_counter() - t0) / n_it
+    bfull = np.zeros(na * geo.n_det)
+    t0 = time.perf_counter()
+    oracle.cp_tv_nonneg(WL, bfull, shape, lam, 0.35, 0.35, n_it, h=h)
+    t_cp = (time.perf_counter() - t0) / n_it
+    t0 = time.perf_counter()
+    oracle.sirt_nonneg(WL, bfull, shape, 1e-6, n_it)
+    t_sirt = (time.perf_counter() - t0) / n_it
+    return {"area": ext[2] * ext[3], "side": max(ext[2], ext[3]), "wl": t_wl, "ext": t_ext,
+            "power": t_pow, "cp": t_cp, "sirt": t_sirt}
+
+
+def _fit(c1, c2):
+    """Per-region oracle cost from two samples: W_L build, power, CP and SIRT steps linear
+    in the extended area (their sparse products are), the exterior subtraction linear in
+    the extended side (the band width); nondecreasing, never below the smaller sample."""
+    def f(key, ext):
+        x = "side" if key == "ext" else "area"
+        v = ext[2] * ext[3] if x == "area" else max(ext[2], ext[3])
+        x1, x2, v1, v2 = c1[x], c2[x], c1[key], c2[key]
+        return max(v1, v1 + max(v2 - v1, 0.0) * (v - x1) / (x2 - x1))
+    return f
+
+
+def _oracle_fbp_cost(geo, sino, tile=256):
+    """Single-thread oracle Ram-Lak FBP of the whole grid: the filter of the whole
+    sinogram plus the backprojection of one tile x (n / tile)^2."""
+    import oracle
+    n = geo.n
+    t0 = time.perf_counter()
+    q = oracle.fbp.ramp_filter(geo, sino)
+    t_ramp = time.perf_counter() - t0
+    c = (n - tile) // 2
+    t0 = time.perf_counter()
+    oracle.bp_pixel(geo, q, (c, c, tile, tile), workers=1)
+    return t_ramp + (time.perf_counter() - t0) * (n * n) / (tile * tile)
+
+
+def batch_cpu_baseline(d):
+    """The FP64 oracle, one thread, on a bounded sample of the 64-ROI batch: the FBP
+    exterior (filter + one 256^2 tile of the backprojection), and for one ROI of side 32
+    and one of side 128 the W_L build, exterior subtraction, and 3 power-iteration and 3
+    CP steps; per-ROI costs fitted to those (linear in the extended area, the exterior
+    subtraction in the side), summed over the 64 ROIs x 200 iterations plus 100 power
+    steps per extended shape class."""
+    import oracle
+    import synth
+    cfg = d["cfg"]
+    n = cfg["n"]
+    geo = oracle.make_geometry(n, cfg["n_angles"], cfg["n_det"])
+    sino = d["sino"].astype(np.float32).astype(np.float64)
+    rois = synth.roi_list("c3")
+    t_meas = time.perf_counter()
+    t_fbp = _oracle_fbp_cost(geo, sino)
+    pts = []
+    for side in (32, 128):
+        r = next(q for q in rois if q[2] == side)
+        pts.append(_oracle_region_costs(geo, sino, oracle.roi_extend(r[:4], r[4], n),
+                                        cfg["lam"], 1.0 / n))
+    f = _fit(*pts)
+    total, shapes = t_fbp, set()
+    for r in rois:
+        e = oracle.roi_extend(r[:4], r[4], n)
+        total += f("wl", e) + f("ext", e) + cfg["iters"] * f("cp", e)
+        shapes.add((0, 0, min(n, (e[2] + 15) // 16 * 16), min(n, (e[3] + 15) // 16 * 16)))
+    for e in shapes:
+        total += 100 * f("power", e)
+    t_meas = time.perf_counter() - t_meas
+    log(f"cpu oracle (batch): {total:.0f}s per batch extrapolated (measured {t_meas:.1f}s)")
+    return {"value": len(rois) / total, "unit": "ROI solves/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 NumPy oracle, single thread: Ram-Lak filter and one 256^2 tile of "
+                      "the FBP backprojection (x 64 tiles); W_L build, exterior subtraction (32 "
+                      "of 256 angles x 8), 3 power and 3 CP-TV steps on one side-32 and one "
+                      "side-128 ROI; per-ROI costs linear in the extended area (the exterior "
+                      "subtraction in the side), summed over the 64 ROIs x 200 "
+                      f"iterations (extrapolation; measured {t_meas:.1f}s)"}
+
+
+def serve_cpu_baseline(slices, reqs, cfg, n_ang_sample=16):
+    """The FP64 oracle, one thread, on a bounded sample of the serving workload: per
+    slice the FBP exterior and the residual over the whole detector (the residual on
+    n_ang_sample of the 512 angles, x 512 / n_ang_sample); per request the W_L build,
+    exterior subtraction and iterations (CP-TV or SIRT), with costs linear in the
+    extended area (the exterior subtraction in the side) fitted to a side-32 and a
+    side-128 request shape, plus 100 power steps per extended shape class; summed over
+    the 64 slices and the request list."""
+    import oracle
+    n, na = cfg["n"], cfg["n_angles"]
+    geo = oracle.make_geometry(n, na, cfg["n_det"])
+    sino = slices[0].astype(np.float32).astype(np.float64)
+    t_meas = time.perf_counter()
+    t_fbp = _oracle_fbp_cost(geo, sino)
+    pick = np.arange(0, na, na // n_ang_sample)[:n_ang_sample]
+    bins = np.zeros((na, geo.n_det), bool)
+    bins[pick] = True
+    t0 = time.perf_counter()
+    oracle.exterior_subtract(geo, sino, np.zeros((n, n)), (0, 0, 1, 1), bins=bins)
+    t_resid = (time.perf_counter() - t0) * na / len(pick)
+    pts = []
+    for side in (32, 128):
+        c = (n - side) // 2
+        m = -(-side // 4)
+        pts.append(_oracle_region_costs(geo, sino, oracle.roi_extend((c, c, side, side), m, n),
+                                        0.02, 1.0 / n))
+    f = _fit(*pts)
+    total, shapes = len(slices) * (t_fbp + t_resid), set()
+    for r in reqs:
+        e = oracle.roi_extend(r["rect"], r["margin"], n)
+        total += f("wl", e) + f("ext", e) + r["iters"] * f(r["method"], e)
+        if r["method"] == "cp":
+            shapes.add((0, 0, min(n, (e[2] + 15) // 16 * 16), min(n, (e[3] + 15) // 16 * 16)))
+    for e in shapes:
+        total += 100 * f("power", e)
+    t_meas = time.perf_counter() - t_meas
+    log(f"cpu oracle (serving): {total:.0f}s for {len(reqs)} requests extrapolated "
+        f"(measured {t_meas:.1f}s)")
+    return {"value": len(reqs) / total, "unit": "requests/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 NumPy oracle, single thread: per slice the Ram-Lak FBP (filter + "
+                      "one 256^2 backprojection tile x 64) and the residual (16 of 512 angles "
+                      "x 32); per request W_L build, exterior subtraction (32 of 512 angles x "
+                      "16) and 3 steps of each solver on a side-32 and a side-128 request, "
+                      "costs linear in the extended area (the exterior subtraction in the "
+                      "side), summed over the 64 slices and the capacity run's "
+                      f"requests (extrapolation; measured {t_meas:.1f}s)"}
+
+
+def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0, cpu=False):
     """64 uneven ROIs (sides 32..256, margin side/4) on a 2048^2 grid, 256 angles,
     3072 bins, 200 CP-TV iterations: one roi_solve_batch call vs the same ROIs
     solved one at a time, both from the same precomputed FBP exterior."""
@@ -218,9 +366,12 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
                 "fp_updates_per_s": nnz / (t_fp * 1e-3), "bp_updates_per_s": nnz / (t_bp * 1e-3)}
         # the batch's dominant iteration kernel against the ALU roof of the projectors
         dom_fp = t_fp >= t_bp
-        kname = "fp_kernel" if dom_fp else "bp_kernel"
-        kern["roofline"] = alu_roofline(kname, nnz, 1e3 * (t_fp if dom_fp else t_bp),
-                                        profiled_traffic("batch64-n2048-a256", kname))
+        fp_name = "fp_staged_kernel" if best.get("fp_rays_per_lane") == 4 else "fp_kernel"
+        kname = fp_name if dom_fp else "bp_kernel"
+        traffic = profiled_traffic("batch64-n2048-a256", kname)
+        kern["roofline"] = alu_roofline(kname, nnz, 1e3 * (t_fp if dom_fp else t_bp), traffic)
+        if traffic:
+            kern["roofline"]["hbm_gb_per_s"] = traffic / ((t_fp if dom_fp else t_bp) * 1e-3) / 1e9
         if not compare:
             return {"roi_solves_per_s": len(rois) / t_batch, "ms_per_batch": 1e3 * t_batch,
                     "updates_per_s": updates / t_batch, **kern}
@@ -236,6 +387,8 @@ def batched_leg(torch, d, reps=3, compare=True, iters=None, fixed_step=0.0):
         diff = max(float((a - b).abs().max() / (b.abs().max() + 1e-30)) for a, b in zip(outs, one))
         log(f"batched: 64 ROIs {1e3 * t_batch:.1f} ms per batch; one at a time {1e3 * t_seq:.1f} ms; "
             f"{updates / t_batch / 1e9:.0f} Gupd/s")
+        if cpu:
+            kern["cpu_baseline"] = batch_cpu_baseline(d)
         return {"workload": "batch64-n2048-a256: 64 ROIs, sides {32,64,128,256}, margin side/4, "
                             "256 angles, 3072 bins, CP-TV 200 its",
                 "roi_solves_per_s": len(rois) / t_batch, "ms_per_batch": 1e3 * t_batch,
@@ -414,7 +567,8 @@ def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
         ctx.close()
 
 
-def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.75, 0.9)):
+def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.75, 0.9),
+                cpu=False):
     """64 resident 2048^2 slices (512 angles x 3072 bins); requests with side
     U{32..512}, margin ceil(side/4), 80% CP-TV / 20% nonnegative SIRT, 100-300
     iterations.  Capacity = completion rate with all requests queued at once;
@@ -506,6 +660,7 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
     finally:
         ctx.close()
     mid = sweep[min(1, len(sweep) - 1)]
+    base = serve_cpu_baseline(slices, reqs, cfg) if cpu else None
     log(f"serving: register {t_reg:.2f}s; capacity {cap:.1f} req/s; plain {n_plain / t_plain:.1f} "
         f"req/s; {small >> 20} MiB budget: {len(reqs_small) / t_small:.1f} req/s")
     return {"workload": "serve-64x2048-a512: 64 resident slices, side U{32..512}, 80% CP-TV / "
@@ -518,7 +673,8 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
             "small_budget": {"workspace_mib": small >> 20, "resident_slices": 2,
                              "capacity_solves_per_s": len(reqs_small) / t_small,
                              "p50_ms": pct(lat_small, 50), "p99_ms": pct(lat_small, 99),
-                             "workspace_usage": peak}}
+                             "workspace_usage": peak},
+            **({"cpu_baseline": base} if base else {})}
 
 
 def tiles_cpu_baseline(d, n_ang_sample=16, n_cp=3, n_pow=3):
@@ -900,7 +1056,7 @@ def main():
             res["single_roi"] = {"error": repr(e)}
     if not args.skip_batch:
         try:
-            res["batched"] = batched_leg(torch, d3)
+            res["batched"] = batched_leg(torch, d3, cpu=not args.no_cpu_baseline)
         except Exception as e:
             res["batched"] = {"error": repr(e)}
     if not args.skip_local:
@@ -910,7 +1066,8 @@ def main():
             res["local_method"] = {"error": repr(e)}
     if not args.skip_serve:
         try:
-            res["serving"] = serving_leg(torch, slices, args.serve_requests, args.serve_warmup)
+            res["serving"] = serving_leg(torch, slices, args.serve_requests, args.serve_warmup,
+                                         cpu=not args.no_cpu_baseline)
         except Exception as e:
             res["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
