@@ -610,13 +610,21 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
 #pragma unroll
                 for (int u = 0; u < L; ++u) c4[u & 3] += fmaf(f[u], v1[u] - v0[u], v0[u]);
             } else {
-                for (int u = 0; u < cnt; ++u) {
+                // the stage's last lines: four at a time into the four sums, the rest
+                // into the first
+                auto tap = [&](int u) {
                     const float loc = fmaf((float)u, stepf, base64);
                     const float f = __builtin_amdgcn_fractf(loc);
                     const LDS_AS float* col = (const LDS_AS float*)(size_t)(
                         __umul24((unsigned)loc, STR * 4u) + lb + 4u * (unsigned)u);
-                    c4[u & 3] += fmaf(f, col[STR] - col[0], col[0]);
+                    return fmaf(f, col[STR] - col[0], col[0]);
+                };
+                int u = 0;
+                for (; u + 4 <= cnt; u += 4) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) c4[q] += tap(u + q);
                 }
+                for (; u < cnt; ++u) c4[0] += tap(u);
             }
             acc[r] += (c4[0] + c4[1]) + (c4[2] + c4[3]);
         }
