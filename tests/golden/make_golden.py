@@ -3,7 +3,7 @@
 Every stored value is computed by the FP64 oracle (`oracle/`) from the seeded
 generator (`synth/`); nothing here touches the HIP library.
 
-    python tests/golden/make_golden.py [c2] [c3] [c4] [c5]
+    python tests/golden/make_golden.py [c2] [c3] [c4] [c5] [c3local]
 """
 
 import os
@@ -104,6 +104,40 @@ def golden_serving():
     np.savez_compressed(os.path.join(HERE, "c5_oracle.npz"), **out)
 
 
+LOCAL_K = 20
+LOCAL_ROIS = (1, 0)     # batch ROIs of side 64 and 128
+
+
+def golden_local_depth():
+    """The paper's local methods at full batch size after LOCAL_K iterations on two sampled
+    ROIs: the oracle's Alg. 1 filters u_1..u_K of the 2048^2 geometry, then Alg. 2 with the
+    box [0, inf), local FISTA-TV (100 FGP steps, prox weight 0.02) and local FISTA with the
+    4-level Haar prior (threshold 0.02) on each ROI."""
+    from oracle.filters import sirt_filters, local_method_box
+    from oracle.fista import local_fista_tv
+    from oracle.haar import local_fista_haar
+    t0 = time.time()
+    d = synth.make_inputs("c3", with_image=False)
+    cfg = d["cfg"]
+    na, nd = cfg["n_angles"], cfg["n_det"]
+    g = oracle.make_geometry(cfg["n"], na, nd)
+    p = d["sino"].astype(np.float32).astype(np.float64)
+    U = sirt_filters(g, LOCAL_K, workers=WORKERS)
+    print(f"c3local: {LOCAL_K} filters ({time.time() - t0:.1f}s)", flush=True)
+    lam = 2 * 0.02 * na * nd
+    rois = synth.roi_list("c3")
+    out = {"rois": np.array(LOCAL_ROIS), "iters": np.int64(LOCAL_K)}
+    for i in LOCAL_ROIS:
+        r0, c0, rr, cc, m = rois[i]
+        rect = (r0, c0, rr, cc)
+        out[f"alg2_{i}"] = local_method_box(g, p, rect, m, U, 0.0, np.inf).astype(np.float32)
+        out[f"fista_{i}"] = local_fista_tv(g, p, rect, m, U, lam, 100).astype(np.float32)
+        out[f"haar_{i}"] = local_fista_haar(g, p, rect, m, U, lam, 4).astype(np.float32)
+        out[f"rect_{i}"] = np.array([r0, c0, rr, cc, m])
+        print(f"c3local roi {i} {rois[i]} ({time.time() - t0:.1f}s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c3_local_oracle.npz"), **out)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["c2"]
     if "c2" in which:
@@ -120,3 +154,5 @@ if __name__ == "__main__":
         golden_workload("c4", [0, 7, 16 * 5 + 6, 16 * 10 + 9])
     if "c5" in which:
         golden_serving()
+    if "c3local" in which:
+        golden_local_depth()

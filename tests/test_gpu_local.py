@@ -482,3 +482,48 @@ def test_local_methods_full_size_first_iterate(ctx, tmp_path_factory, name, samp
             print(f"    {method} roi {i} {rois[i]} rel {e:.2e}", flush=True)
             assert e <= bar
         del outs
+
+
+def test_local_methods_full_size_depth(ctx, tmp_path_factory):
+    """The batched workload at full size (64 uneven ROIs on 2048^2, 256 angles, 3072 bins)
+    in the benchmark's launch shape (all 64 ROIs in one call), 20 iterations of Alg. 2
+    (box [0, inf)), local FISTA-TV (100 FGP steps, prox weight 0.02) and FISTA with the
+    4-level Haar prior, each from the library's own Alg. 1 filters and filtered data, on
+    two sampled ROIs (sides 64 and 128) against the oracle's results with its own filters
+    (tests/golden/make_golden.py c3local) at the 1e-3 reconstruction bar."""
+    from paper_1604_02292_amd import make_params
+    path = os.path.join(HERE, "golden", "c3_local_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle result for the local methods at full size")
+    gold = np.load(path)
+    K = int(gold["iters"])
+    cfg = synth.workload("c3")
+    n, na, nd = cfg["n"], cfg["n_angles"], cfg["n_det"]
+    print(f"[local depth] generating inputs", flush=True)
+    p32 = _sino_in_subprocess("c3", tmp_path_factory.mktemp("c3d")).astype(np.float32)
+    g = ctx.tomo_set_geometry(n, na, nd)
+    F = torch.empty((K, na, nd), dtype=torch.float32, device="cuda")
+    ctx.tomo_sirt_filters(g, K, F)
+    D = torch.empty_like(F)
+    ctx.tomo_sirt_filter_sino(g, F, torch.from_numpy(p32).cuda(), D)
+    del F
+    rois = synth.roi_list("c3")
+    lam = 2 * 0.02 * na * nd          # prox weight gamma = alpha lam / 2 = 0.02
+    for method, key in (("local", "alg2"), ("fista", "fista"), ("haar", "haar")):
+        params, outs = [], []
+        for (r0, c0, rr, cc, m) in rois:
+            if method == "local":
+                params.append(make_params((r0, c0, rr, cc), m, "local", iters=K,
+                                          box=(0.0, float("inf"))))
+            else:
+                params.append(make_params((r0, c0, rr, cc), m, method, lam=lam, iters=K,
+                                          inner_iters=100 if method == "fista" else 4))
+            outs.append(torch.empty((rr, cc), dtype=torch.float32, device="cuda"))
+        ctx.roi_solve_local(g, D, params, outs)
+        torch.cuda.synchronize()
+        for i in (int(v) for v in gold["rois"]):
+            assert tuple(gold[f"rect_{i}"]) == tuple(rois[i])
+            e = rel(outs[i].double().cpu().numpy(), gold[f"{key}_{i}"])
+            print(f"    {method} roi {i} {rois[i]} {K} its: rel {e:.2e}", flush=True)
+            assert e <= 1e-3
+        del outs
