@@ -20,7 +20,8 @@ from oracle import make_geometry, fp_ray, sparse_local, roi_extend
 from oracle.local import exterior_subtract, crop
 from oracle.tv import grad
 from oracle.filters import default_alpha, sirt_filters, sirt_iterates, local_method_box
-from oracle.fista import fgp, fgp_with_dual, fgp_dual_gap, local_fista_tv, prox_weight
+from oracle.fista import (fgp, fgp_with_dual, fgp_dual_gap, local_fista, local_fista_tv,
+                          prox_weight)
 from test_oracle_solvers import _admm_tv_nonneg
 
 
@@ -149,3 +150,27 @@ def test_alg3_without_tv_is_accelerated_alg2():
     a4 = local_fista_tv(g, p, rect, margin, U, 0.0, 10)
     b4 = local_method_box(g, p, rect, margin, U, -np.inf, np.inf)
     assert np.abs(a4 - b4).max() > 1e-6 * np.abs(b4).max()
+
+
+def test_outer_momentum_has_nesterov_asymptotics():
+    """The outer momentum of Alg. 3, read off the method itself: with alpha = 0 and the
+    identity as prox on one pixel, fed the SIRT iterates x_s^k = k, the output increments obey
+    D_k = beta_{k-1} D_{k-1} + 1 (D_1 = 1), so beta_k = (D_{k+1} - 1) / D_k is visible in runs
+    of K and K + 1 iterations.  Beck and Teboulle's rule gives t_k = (k + 1)/2 + O(log k), hence
+    beta_1 = 0 and beta_k = 1 - 3/(k + 2) + O(log k / k^2), the momentum of Nesterov's method;
+    a rule without the square tends to 1/2, a shifted index to 1 - 2/(k + 1)."""
+    n = 4
+    g = make_geometry(n, 3, 7)
+    kmax = 121
+    xs = [np.full((n, n), float(k + 1)) for k in range(kmax)]
+    out = [0.0]
+    for K in range(1, kmax + 1):
+        x = local_fista(g, np.zeros((3, 7)), (1, 1, 1, 1), 0, None, lambda w: w, alpha=0.0,
+                        xs_iterates=xs[:K])
+        out.append(float(x[0, 0]))
+    D = np.diff(out)   # D[k - 1] = D_k
+    assert D[0] == pytest.approx(1.0) and D[1] == pytest.approx(1.0)   # beta_1 = 0
+    beta = (D[1:] - 1.0) / D[:-1]                                       # beta[k - 1] = beta_k
+    assert np.all(np.diff(beta) > 0) and beta[-1] < 1.0
+    for k in (20, 60, 120):
+        assert abs(beta[k - 1] - (1.0 - 3.0 / (k + 2))) < 2.0 * np.log(k) / k ** 2
