@@ -125,13 +125,20 @@ struct Item {
 };
 static_assert(sizeof(Item) == 32, "Item layout");
 
-// LDS-staged forward projector: kFpsLines image lines per stage, kFpsThreads threads,
-// at most kFpsMaxPairs (angle, ray) pairs per block, line pitch at most kFpsMaxPitch.
+// LDS-staged forward projector: L image lines per stage (stride L + 1, L + 2 zero
+// columns on each side), kFpsThreads threads, at most kFpsMaxPairs (angle, ray) pairs per
+// block.  32 lines per stage for line pitches up to kFpsMaxPitch, 24 up to
+// kFpsMaxPitch24: both keep the LDS of a block under a third of the CU's 160 KB.
 constexpr int kFpStaged = 4;   // the rays_per_lane value that selects it
-constexpr int kFpsThreads = 256, kFpsLines = 32, kFpsStride = kFpsLines + 1;
+constexpr int kFpsThreads = 256;
 constexpr int kFpsMaxRounds = 8, kFpsMaxPairs = kFpsMaxRounds * kFpsThreads;
-constexpr int kFpsMaxPitch = 336;   // LDS (336 + 68) x 33 x 4 B: three blocks per CU
-constexpr int kFpsZeroPad = 34;   // zero columns staged before and after each line
+constexpr int kFpsMaxPitch = 336;     // (336 + 68) x 33 x 4 B = 53.3 KB
+constexpr int kFpsMaxPitch24 = 480;   // (480 + 52) x 25 x 4 B = 53.2 KB
+inline int fps_lines(int pitch) { return pitch <= kFpsMaxPitch ? 32 : 24; }
+inline size_t fps_lds_bytes(int pitch) {
+    const int L = fps_lines(pitch);
+    return (size_t)(pitch + 2 * (L + 2)) * (L + 1) * sizeof(float);
+}
 
 // Launchers (tomo_kernels.hip).
 // contiguous = 1: each XCD runs one contiguous eighth of the items (L2
@@ -140,7 +147,7 @@ constexpr int kFpsZeroPad = 34;   // zero columns staged before and after each l
 // (segments must be 1; the items must be built for 512 rays per block).
 // rays_per_lane = kFpStaged: the LDS-staged forward projector (items from fps_items;
 // stage_pitch = the largest line pitch, xp or tp, of the launch's jobs, at most
-// kFpsMaxPitch).
+// kFpsMaxPitch24).
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
                      hipStream_t s, int contiguous = 1, int rays_per_lane = 1,
                      int stage_pitch = 0);

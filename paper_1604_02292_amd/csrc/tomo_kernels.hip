@@ -446,14 +446,16 @@ __global__ __launch_bounds__(fp_threads<SEG>()) void fp_kernel(const Job* __rest
 // give, so no tap index is clamped.  Ray sums run in the same two levels as
 // fp_kernel: per chunk of staged lines, then into the ray.
 // ---------------------------------------------------------------------------
+template <int L>
 __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __restrict__ jobs,
                                                                 const Item* __restrict__ items,
                                                                 int n_items, int step,
                                                                 int contiguous) {
-    // [kFpsZeroPad + pitch + kFpsZeroPad][stride]: the staged lines, column-major, with
+    // [ZP + pitch + ZP][STR]: the staged lines, column-major, with
     // zero columns on both sides
     extern __shared__ float fps_lds[];
-    constexpr int NT = kFpsThreads, L = kFpsLines, STR = kFpsStride;
+    constexpr int NT = kFpsThreads, STR = L + 1, ZP = L + 2;
+    static_assert(L <= 32, "a stage's rays must stay inside the zero columns");
     const int bid = xcd_remap(blockIdx.x, gridDim.x, contiguous);
     if (bid >= n_items) return;
     const Item it = cview(items)[bid];
@@ -471,7 +473,7 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
     const int npairs = nang * W;
     const int rounds = (npairs + NT - 1) / NT;
     if (rounds > kFpsMaxRounds) return;   // the host never builds such a group
-    LDS_AS float* S = (LDS_AS float*)fps_lds + kFpsZeroPad * STR;   // column 0 of the line
+    LDS_AS float* S = (LDS_AS float*)fps_lds + ZP * STR;   // column 0 of the line
     const unsigned s_base = (unsigned)(size_t)S;
     // pair p = ray j * nang + angle a: a wave holds the same few rays of every angle of
     // the group, whose line ranges nearly coincide (adjacent rays of one angle enter and
@@ -525,11 +527,11 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
     }
     o_lo = uniform_int(o_lo);
     o_hi = uniform_int(o_hi);
-    // The zero columns: a ray that meets the image inside a stage stays within 32
-    // line steps (|step| <= 1) of it, so its taps fall in [-30, pitch + 32] and need no
+    // The zero columns: a ray that meets the image inside a stage stays within L - 1
+    // line steps (|step| <= 1) of it, so its taps fall in [2 - L, pitch + L] and need no
     // clamp (the first four and last two entries of a padded line are zeros too).
-    for (int e = t; e < kFpsZeroPad * STR; e += NT) {
-        S[-kFpsZeroPad * STR + e] = 0.f;
+    for (int e = t; e < ZP * STR; e += NT) {
+        S[-ZP * STR + e] = 0.f;
         S[pitch * STR + e] = 0.f;
     }
     // Per round: this thread's pair (angle a, ray j), its ray's storage coordinate at
@@ -589,8 +591,8 @@ __global__ __launch_bounds__(kFpsThreads) void fp_staged_kernel(const Job* __res
             const float base64 = (float)(p0 - fl0) + 64.f;
             const float stepf = (float)dp;
             const int ib = (int)fl0 - 64;
-            // loc = base64 + u step lies in [33, 97) (|step| <= 1): positive, so the
-            // truncation below is a floor
+            // loc = base64 + u step lies in [65 - L, 63 + L) (|step| <= 1, u < L <= 32):
+            // positive, so the truncation below is a floor
             const unsigned lb = (unsigned)(ib * STR) * 4u + s_base;
             // four partial sums (independent add chains), combined in a fixed order
             float c4[4] = {0.f, 0.f, 0.f, 0.f};
@@ -2252,10 +2254,14 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items));
     if (rays_per_lane == kFpStaged) {
-        if (stage_pitch < 1 || stage_pitch > kFpsMaxPitch) return hipErrorInvalidValue;
-        const size_t lds = (size_t)(stage_pitch + 2 * kFpsZeroPad) * kFpsStride * sizeof(float);
-        hipLaunchKernelGGL(fp_staged_kernel, grid, dim3(kFpsThreads), lds, s, jobs, items,
-                           n_items, step, contiguous);
+        if (stage_pitch < 1 || stage_pitch > kFpsMaxPitch24) return hipErrorInvalidValue;
+        const size_t lds = fps_lds_bytes(stage_pitch);
+        if (fps_lines(stage_pitch) == 32)
+            hipLaunchKernelGGL(fp_staged_kernel<32>, grid, dim3(kFpsThreads), lds, s, jobs,
+                               items, n_items, step, contiguous);
+        else
+            hipLaunchKernelGGL(fp_staged_kernel<24>, grid, dim3(kFpsThreads), lds, s, jobs,
+                               items, n_items, step, contiguous);
         return hipGetLastError();
     }
 #define TOMO_FP(SG, R)                                                                 \

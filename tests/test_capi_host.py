@@ -108,11 +108,11 @@ def test_launch_shapes_by_problem_size():
     """The size heuristics: a single small region (the 1024^2 workload's 192^2 extended ROI,
     128 angles: 35 k rays, 37 k pixels) gets the most waves per ray and per pixel (8
     forward-projector segments, 8 backprojector angle groups, direct band reads); the
-    256 tiles of 4096^2 (extended parts up to 320^2) get the LDS-staged forward projector
-    (rays per lane 4), the 64-ROI batch on 2048^2 (extended parts up to 384^2, wider than
-    the staged lines hold) two rays per lane, also when the staged projector is forced; both
-    get the LDS-staged backprojector with two pixels per thread.  Forced knobs are
-    validated and kept."""
+    256 tiles of 4096^2 (extended parts up to 320^2) and the 64-ROI batch on 2048^2
+    (extended parts up to 384^2, staged 24 lines at a time) get the LDS-staged forward
+    projector (rays per lane 4), a region wider than the staged lines hold two rays per lane,
+    also when the staged projector is forced; all get the LDS-staged backprojector with two
+    pixels per thread.  Forced knobs are validated and kept."""
     import synth
     from paper_1604_02292_amd.tomo import make_params
     ctx = Context(device=-1)
@@ -123,17 +123,18 @@ def test_launch_shapes_by_problem_size():
     g3 = ctx.tomo_set_geometry(2048, 256, 3072)
     batch = [make_params(r[:4], r[4], "cp", 0.02, 200) for r in synth.roi_list("c3")]
     big = ctx.tomo_resolve_launch(g3, batch)
-    assert (big["fp_segments"], big["fp_rays_per_lane"]) == (1, 2)
+    assert (big["fp_segments"], big["fp_rays_per_lane"]) == (1, 4)
     assert (big["bp_variant"], big["bp_groups"], big["bp_pixels_per_thread"]) == (2, 1, 2)
     g4 = ctx.tomo_set_geometry(4096, 512, 6144)
     tiles = [make_params(r[:4], r[4], "cp", 0.01, 200) for r in synth.roi_list("c4")]
     t4 = ctx.tomo_resolve_launch(g4, tiles)
     assert (t4["fp_segments"], t4["fp_rays_per_lane"]) == (1, 4)
     assert (t4["bp_variant"], t4["bp_groups"], t4["bp_pixels_per_thread"]) == (2, 1, 2)
+    wide = batch + [make_params((600, 600, 512, 512), 64, "cp", 0.02, 200)]   # 640^2
+    assert ctx.tomo_resolve_launch(g3, wide)["fp_rays_per_lane"] == 2
     ctx.tomo_set_launch(fp_rays_per_lane=4)
-    assert ctx.tomo_resolve_launch(g3, batch)["fp_rays_per_lane"] == 2
-    small_batch = [p for p in batch if p.roi.rows <= 128]
-    assert ctx.tomo_resolve_launch(g3, small_batch)["fp_rays_per_lane"] == 4
+    assert ctx.tomo_resolve_launch(g3, wide)["fp_rays_per_lane"] == 2
+    assert ctx.tomo_resolve_launch(g3, batch)["fp_rays_per_lane"] == 4
     ctx.tomo_set_launch(fp_rays_per_lane=2)
     assert ctx.tomo_resolve_launch(g4, tiles)["fp_rays_per_lane"] == 2
     ctx.tomo_set_launch()
