@@ -583,7 +583,7 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
     def prm(r):
         return make_params(r["rect"], r["margin"], r["method"], r["lam"], r["iters"])
 
-    def run(ctx, sids, reqs, open_loop):
+    def run(ctx, sids, reqs, open_loop, stages=None):
         outs = [torch.empty((r["rect"][2], r["rect"][3]), device="cuda") for r in reqs]
         lat, pend = [], {}
         i = 0
@@ -597,9 +597,11 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
                 if i % 500 == 0:
                     log(f"serving: {i} of {len(reqs)} requests submitted")
             for t in list(pend):
-                done, ms = ctx.roi_poll(t)
+                done, st = ctx.roi_poll_stages(t)
                 if done:
-                    lat.append(ms)
+                    lat.append(st["latency_ms"])
+                    if stages is not None:
+                        stages.append(st)
                     del pend[t]
             time.sleep(0.0002)
         return time.perf_counter() - t_start, lat, outs
@@ -621,10 +623,17 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
         sweep = []
         for k, fr in enumerate(fractions):
             reqs_open = synth.serving_requests(n_req, fr * cap, seed_offset=3 + k)
-            t_open, lat_open, _ = run(ctx, sids, reqs_open, True)
+            stages = []
+            t_open, lat_open, _ = run(ctx, sids, reqs_open, True, stages)
+            # where a request's time goes: queued (submit -> admitted), preparation
+            # (admitted -> first iteration), iterations (-> done)
+            split = {f"{key}_p50_ms": pct([q[key] for q in stages], 50)
+                     for key in ("queued_ms", "prepare_ms", "run_ms")}
+            split.update({f"{key}_p99_ms": pct([q[key] for q in stages], 99)
+                          for key in ("queued_ms", "prepare_ms", "run_ms")})
             sweep.append({"fraction_of_capacity": fr, "offered_qps": fr * cap,
                           "achieved_qps": n_req / t_open, "p50_ms": pct(lat_open, 50),
-                          "p99_ms": pct(lat_open, 99)})
+                          "p99_ms": pct(lat_open, 99), "stages": split})
             log(f"serving: {fr:.2f} x capacity ({fr * cap:.1f} req/s): p50 {pct(lat_open, 50):.1f} "
                 f"ms p99 {pct(lat_open, 99):.1f} ms")
         # plain one-at-a-time solves of the first n_plain capacity requests (same

@@ -346,10 +346,12 @@ tomo_status roi_submit(tomo_ctx* ctx, int32_t sino_id, const roi_params* params,
 tomo_status roi_poll(tomo_ctx* ctx, uint64_t ticket, int* done, float* latency_ms);
 
 /* roi_poll with the request's timeline: stages_ms (float[4]) receives, once
- * *done = 1, the host-clock times from submission to admission (queued), from
- * admission to its first iteration (preparation: tables, b = r + W_L x_ext|L, step
- * size), from there to completion (iterations, crop), and the total (the latency of
- * roi_poll); -1 while not done.  Same ticket rules and errors as roi_poll. */
+ * *done = 1, host-clock times on the scheduler thread: from submission to admission
+ * (queued), from admission to the enqueueing of its first iteration (preparation:
+ * tables, b = r + W_L x_ext|L, step size; work that only needs enqueueing costs
+ * little here and runs on the GPU during the next stage), from there to completion
+ * (iterations, crop), and the total (the latency of roi_poll); -1 while not done.
+ * Same ticket rules and errors as roi_poll. */
 tomo_status roi_poll_stages(tomo_ctx* ctx, uint64_t ticket, int* done, float* stages_ms);
 
 /* Serving knobs: maximum concurrent slots (default 32) and iterations per

@@ -104,6 +104,36 @@ def test_alone_equals_mix_and_matches_roi_solve(served):
         assert rel(o.double().cpu().numpy(), a.double().cpu().numpy()) <= 1e-4
 
 
+def test_request_timeline(served):
+    """roi_poll_stages on the GPU path: every finished request reports its queueing,
+    preparation and iteration times, which add up to its latency; a request that waited
+    behind a full slot set shows it as queueing time."""
+    from paper_1604_02292_amd import make_params
+    ctx, g, sid, sino, p32, cfg = served
+    ctx.tomo_serving_config(max_slots=2)
+    try:
+        params = [make_params(r, m, meth, lam, it) for r, m, meth, lam, it in REQS]
+        outs = [torch.empty((p.roi.rows, p.roi.cols), device="cuda") for p in params]
+        tickets = [ctx.roi_submit(sid, p, o) for p, o in zip(params, outs)]
+        got, t0 = {}, time.time()
+        while len(got) < len(tickets) and time.time() - t0 < 120:
+            for t in tickets:
+                if t not in got:
+                    done, st = ctx.roi_poll_stages(t)
+                    if done:
+                        got[t] = st
+            time.sleep(0.0005)
+        assert len(got) == len(tickets)
+        for t in tickets:
+            st = got[t]
+            assert min(st.values()) >= 0.0 and st["run_ms"] > 0.0
+            assert abs(st["queued_ms"] + st["prepare_ms"] + st["run_ms"] - st["latency_ms"]) < 1.0
+        # two slots: the last request waited for earlier ones to retire
+        assert got[tickets[-1]]["queued_ms"] > 0.5 * min(got[t]["run_ms"] for t in tickets[:2])
+    finally:
+        ctx.tomo_serving_config(max_slots=32)
+
+
 def test_served_matches_oracle(served):
     from paper_1604_02292_amd import make_params
     ctx, g, sid, sino, p32, cfg = served
