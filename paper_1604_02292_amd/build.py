@@ -53,7 +53,8 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", "-o", tmp] + objs + DEVICE_FLAGS + ["-lpthread"]
+    cmd = [_hipcc(), "-shared", "-o", tmp] + objs + DEVICE_FLAGS + [
+        "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

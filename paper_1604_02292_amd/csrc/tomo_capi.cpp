@@ -561,6 +561,7 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
                         const SinoState* reg, int count, const roi_params* params,
                         float* const* outs, hipStream_t s, int ldo, float* const* states,
                         int done) {
+    TraceRange trace_solve("solve_batch: %d ROIs", count);
     const Geom& g = ctx->geoms[gid];
     const Rect full{0, 0, g.n, g.n};
     std::vector<RoiState> R(count);
@@ -756,11 +757,14 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
     CK(launch_fp((const Job*)(dm + o_jobs_e2), (const Item*)(dm + o_it_e2), (int)it_e2.size(), 0,
                  Li.seg, s, Li.cfp, Li.rp, Li.spitch));
     // Step sizes (cached per shape; the power iteration reuses the state buffers).
-    for (auto& r : R) {
-        tomo_status st = step_size_for(ctx, gid, r, s, ctx->staging);
-        if (st != TOMO_OK) {
-            cleanup();
-            return st;
+    {
+        TraceRange trace_steps("step sizes");
+        for (auto& r : R) {
+            tomo_status st = step_size_for(ctx, gid, r, s, ctx->staging);
+            if (st != TOMO_OK) {
+                cleanup();
+                return st;
+            }
         }
     }
     // The iteration state (x, both xbar buffers, xbar^T, both z buffers, y; b is kept):
@@ -894,7 +898,11 @@ tomo_status solve_batch(tomo_ctx* ctx, int gid, const float* sino, const float* 
             key.push_back(fi_end[q]);
             key.push_back(bi_end[q]);
         }
-        tomo_status rs = run_loop(ctx, key, m2, enqueue_loop, s, allocs);
+        tomo_status rs;
+        {
+            TraceRange trace_iter("iterations: %d", max_it);
+            rs = run_loop(ctx, key, m2, enqueue_loop, s, allocs);
+        }
         if (rs != TOMO_OK) {
             cleanup();
             return rs;

@@ -92,6 +92,7 @@ tomo_status tomo_sirt_filters(tomo_ctx* ctx, int32_t geom, int32_t iters, float*
     if (st != TOMO_OK) return st;
     if (!filters || iters < 1) return fail(ctx, TOMO_EINVAL, "null filters or iters < 1");
     GUARD_BEGIN
+    TraceRange trace("sirt filters: %d", iters);
     const Geom* gp;
     if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
     const Geom& g = *gp;
@@ -228,6 +229,7 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
     if (!filtered || !params || !outs || count < 1 || planes < 1)
         return fail(ctx, TOMO_EINVAL, "null pointer, count < 1 or planes < 1");
     GUARD_BEGIN
+    TraceRange trace("roi_solve_local: %d ROIs", count);
     const Geom* gp;
     if ((st = get_geom(ctx, geom, &gp)) != TOMO_OK) return st;
     const Geom& g = *gp;

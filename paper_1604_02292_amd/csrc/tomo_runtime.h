@@ -7,6 +7,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -19,6 +20,7 @@
 #include <vector>
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "../../include/tomo.h"
 #include "tomo_internal.h"
@@ -148,6 +150,23 @@ struct tomo_ctx {
 namespace tomo {
 
 tomo_status fail(tomo_ctx* ctx, tomo_status st, const char* fmt, ...);
+
+// A named host range for profilers that record ROCTx markers (rocprofv3
+// --marker-trace): pushed on construction, popped on destruction.
+class TraceRange {
+public:
+    TraceRange(const char* fmt, ...) {
+        char buf[160];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        roctxRangePushA(buf);
+    }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 #define TOMO_HIP(ctx, expr)                                                                 \
     do {                                                                                     \

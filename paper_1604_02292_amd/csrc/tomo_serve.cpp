@@ -458,6 +458,7 @@ void scheduler(tomo_ctx* ctx) {
         int tick = S.iters_per_tick;
         for (auto& sl : slots) tick = std::min(tick, sl->req.prm.iters - sl->it);
         hipError_t e = hipSuccess;
+        TraceRange trace_tick("serve tick: %d slots x %d its", (int)slots.size(), tick);
         const double t_tick = now_ms();
         for (auto& sl : slots)
             if (sl->it == 0) sl->req.t_first = t_tick;

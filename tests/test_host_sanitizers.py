@@ -41,7 +41,8 @@ def _build(out):
         objs.append(obj)
     lib = os.path.join(out, "libtomo_san.so")
     _run(["g++", "-shared", "-o", lib] + objs + SAN +
-         ["-L/opt/rocm/lib", "-lamdhip64", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"])
+         ["-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-lpthread",
+          "-Wl,-rpath,/opt/rocm/lib"])
     return lib
 
 
