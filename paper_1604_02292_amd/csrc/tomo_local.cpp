@@ -262,7 +262,13 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
             max_nf = std::max(max_nf, params[i].inner_iters > 0 ? params[i].inner_iters : 100);
         max_iters = std::max(max_iters, params[i].iters);
     }
-    LaunchCfg L = choose_launch_for(ctx, geom, count, rays, pix);
+    // the regions' own projections may stage their lines in LDS
+    int max_pitch = 0, max_w = 0;
+    for (const RoiState& r : R) {
+        max_pitch = std::max(max_pitch, std::max(r.plan.xp, r.plan.tp));
+        max_w = std::max(max_w, r.plan.wmax);
+    }
+    LaunchCfg L = choose_launch_for(ctx, geom, count, rays, pix, max_pitch, max_w);
     int th, tw;
     bp_tile(L.ag, L.ppt, &th, &tw);
 
@@ -385,8 +391,8 @@ tomo_status roi_solve_local(tomo_ctx* ctx, int32_t geom, const float* filtered, 
                 e2 = timing_event(ctx);
                 if ((e = hipEventRecord(e0, sq)) != hipSuccess) return e;
             }
-            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, sq, L.cfp, L.rp)) !=
-                hipSuccess)
+            if ((e = launch_fp(d_jobs, d_fi, fi_end[active - 1], it, L.seg, sq, L.cfp, L.rp,
+                               L.spitch)) != hipSuccess)
                 return e;
             if (timed && (e = hipEventRecord(e1, sq)) != hipSuccess) return e;
             if ((e = launch_bp(d_jobs, d_bi, bi_end[active - 1], it, L.ag, L.ppt, sq, L.cbp,
