@@ -469,7 +469,9 @@ def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
                # (both channels share one weight per update), and the filtered data
                # against HBM (algorithmic bytes: filters and data spectra read,
                # filtered data written)
-               "roofline": alu_roofline("bp_kernel (two-channel)", nnz, bp_us),
+               "roofline": alu_roofline("bp_kernel (two-channel)", nnz, bp_us,
+                                        profiled_traffic("batch64-n2048-a256-alg2",
+                                                         "bp_kernel (two-channel)")),
                "filtered_data_roofline": {"bound": "hbm", "kernel": "filter_conv_kernel",
                                           "achieved": conv_bytes / t_conv / 1e9,
                                           "peak": 8000.0, "unit": "GB/s",
