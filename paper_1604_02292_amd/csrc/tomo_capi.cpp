@@ -84,10 +84,16 @@ LaunchCfg choose_launch_for(tomo_ctx* ctx, int gid, int jobs, long long total_ra
                             long long total_pixels, int max_pitch, int max_w) {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     LaunchCfg L = choose_launch(ctx, total_rays, total_pixels, max_pitch, max_w);
-    // Many jobs of uneven cost: deal items round-robin over the XCDs so every
-    // XCD gets an equal share of each job (contiguous eighths of the item list
-    // can differ in cost by half).
-    if (jobs > 1) L.cfp = L.cbp = 0;
+    // Many jobs: the forward projector's items (ray chunks or angle groups, whose cost
+    // grows with the job's region) round-robin over the XCDs, so every XCD gets an
+    // equal share of each job (contiguous eighths of the item list can differ in cost
+    // by half); the backprojector's items (tiles of equal size whatever the job) in
+    // contiguous eighths, so a tile's band windows are read into one XCD's L2 (on 256
+    // equal tiles: 1.02 x the algorithmic bytes instead of 3.1 x, 2 % faster).
+    if (jobs > 1) {
+        L.cfp = 0;
+        L.cbp = 1;
+    }
     auto it = ctx->tuned.find(tune_key(gid, jobs, total_pixels));
     if (it != ctx->tuned.end()) apply_knobs(L, it->second);
     apply_knobs(L, ctx->knobs);   // forced fields win
@@ -1549,7 +1555,10 @@ tomo_status tomo_autotune(tomo_ctx* ctx, int32_t geom, const float* sino, const 
         long long rays, px;
         batch_size(*gp, count, p1.data(), &rays, &px);
         LaunchCfg D = choose_launch(ctx, rays, px);
-        if (count > 1) D.cfp = D.cbp = 0;
+        if (count > 1) {
+            D.cfp = 0;
+            D.cbp = 1;
+        }
         const tomo_launch d = to_knobs(D);
         fpc.insert(fpc.begin(), d);
         bpc.insert(bpc.begin(), d);

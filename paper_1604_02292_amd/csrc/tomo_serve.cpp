@@ -468,10 +468,11 @@ void scheduler(tomo_ctx* ctx) {
         }
         for (int t = 0; t < tick && e == hipSuccess && !S.fake; ++t) {
             const int stp = (int)(S.step & 0x3fffffff);
-            // slots of uneven size: items dealt round-robin over the XCDs
+            // slots of uneven size: the forward projector's items dealt round-robin over
+            // the XCDs, the backprojector's (equal tiles) in contiguous eighths
             e = launch_fp(d_jobs, d_fi, n_fi, stp, kServeSeg, S.stream, 0, kServeRP);
             if (e == hipSuccess)
-                e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, kServePPT, S.stream, 0, staged);
+                e = launch_bp(d_jobs, d_bi, n_bi, stp, kServeAG, kServePPT, S.stream, 1, staged);
             S.step++;
         }
         for (auto& sl : slots) sl->it += tick;

@@ -130,6 +130,10 @@ def test_launch_shapes_by_problem_size():
     t4 = ctx.tomo_resolve_launch(g4, tiles)
     assert (t4["fp_segments"], t4["fp_rays_per_lane"]) == (1, 4)
     assert (t4["bp_variant"], t4["bp_groups"], t4["bp_pixels_per_thread"]) == (2, 1, 2)
+    # many jobs: the forward projector's items round-robin over the XCDs, the
+    # backprojector's (equal tiles) in contiguous eighths
+    assert (t4["fp_xcd_order"], t4["bp_xcd_order"]) == (2, 1)
+    assert (big["fp_xcd_order"], big["bp_xcd_order"]) == (2, 1)
     wide = batch + [make_params((600, 600, 512, 512), 64, "cp", 0.02, 200)]   # 640^2
     assert ctx.tomo_resolve_launch(g3, wide)["fp_rays_per_lane"] == 2
     ctx.tomo_set_launch(fp_rays_per_lane=4)
