@@ -59,6 +59,45 @@ def alu_roofline(kernel, updates_per_launch, launch_us, traffic=None):
             "valu_frac_at_4_5": rate * KERNEL_OPS_PER_UPDATE / VALU_LANE_OPS}
 
 
+def measured_peaks(torch, blocks=2048, iters=2048, reps=5):
+    """What the chip sustains, measured beside the nominal figures: the vector FP32
+    lane-instruction rate (the library's calibration kernel, blocks x 256 lanes each
+    running iters x 128 independent-chain FMAs, timed with events on its stream) and
+    the HBM rate of a plain 1 GiB device-to-device copy (bytes read + written)."""
+    from paper_1604_02292_amd import Context
+    ctx = Context(0, workspace_bytes=1 << 20)
+    try:
+        out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+        ctx.tomo_valu_probe(blocks, iters, 0.999, 1e-3, out)   # warm-up
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            ctx.tomo_valu_probe(blocks, iters, 0.999, 1e-3, out)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_valu = ev0.elapsed_time(ev1) * 1e-3 / reps
+        lane_ops = blocks * 256 * iters * 128
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        ev0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_copy = ev0.elapsed_time(ev1) * 1e-3 / reps
+        del src, dst
+        rate = lane_ops / t_valu
+        return {"valu_lane_instr_per_s": rate, "valu_frac_of_nominal": rate / VALU_LANE_OPS,
+                "updates_per_s_at_2_5": rate / OPS_PER_UPDATE,
+                "hbm_copy_gb_per_s": 2 * (1 << 30) / t_copy / 1e9,
+                "hbm_copy_frac_of_nominal": 2 * (1 << 30) / t_copy / 1e9 / HBM_PEAK_GBS,
+                "sample": f"FMA kernel {blocks} x 256 lanes x {iters * 128} FMAs, {reps} "
+                          f"launches ({1e3 * t_valu:.2f} ms each); 1 GiB copy x {reps}"}
+    finally:
+        ctx.close()
+
+
 def total_nnz(ctx, g, exts, workers=16):
     """Exact nonzero count of W_L summed over the regions (host count, in threads: the
     library call releases the interpreter)."""
@@ -969,7 +1008,8 @@ def main():
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the untimed quality comparisons (global solves, FBP, Alg. 2 "
                          "against the phantom)")
-    ap.add_argument("--only", choices=["tiles", "single", "batch", "serve", "local"], default=None,
+    ap.add_argument("--only", choices=["tiles", "single", "batch", "serve", "local", "peaks"],
+                    default=None,
                     help="run only one leg (for profiling) and print its JSON")
     ap.add_argument("--iters", type=int, default=None,
                     help="override the iteration count of the batch and local legs (profiling)")
@@ -1002,6 +1042,10 @@ def main():
               "per-iteration communication, but no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
 
+    if args.only == "peaks":
+        import torch
+        print(json.dumps(measured_peaks(torch)), flush=True)
+        return
     import synth
     gw = args.gen_workers or None
     want = (lambda leg: args.only == leg) if args.only else (lambda leg: True)
@@ -1055,6 +1099,13 @@ def main():
         "roofline": t.pop("roofline"),
     }
     res.update(t)
+    try:
+        peaks = measured_peaks(torch)
+        res["measured_peaks"] = peaks
+        res["roofline"]["frac_of_measured_alu"] = (res["roofline"]["achieved"] * 1e9 /
+                                                   peaks["updates_per_s_at_2_5"])
+    except Exception as e:   # the headline line must still print
+        res["measured_peaks"] = {"error": repr(e)}
     if args.only == "tiles":
         print(json.dumps(res), flush=True)
         return

@@ -16,7 +16,7 @@ OUT = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtomo.so")
 
 SOURCES = ["tomo_kernels.hip", "tomo_plan.cpp", "tomo_capi.cpp", "tomo_serve.cpp", "tomo_local.cpp",
-           "tomo_noalloc.hip"]
+           "tomo_noalloc.hip", "tomo_probe.hip"]
 
 # Packed FP32 instructions are disabled for all device code on this target.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

@@ -352,6 +352,11 @@ class Context:
                                               int(bool(reset))))
         return n.value, ms.value
 
+    def tomo_valu_probe(self, blocks, iters, a, b, out, stream=None):
+        self._check(self.lib.tomo_valu_probe(self.h, int(blocks), int(iters), float(a), float(b),
+                                             _ptr(out, (int(blocks) * 256,), "out"),
+                                             _stream(stream)))
+
     def tomo_workspace_usage(self):
         u, p = C.c_size_t(), C.c_size_t()
         self._check(self.lib.tomo_workspace_usage(self.h, C.byref(u), C.byref(p)))

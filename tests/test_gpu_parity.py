@@ -95,7 +95,8 @@ SHAPES_BP = [dict(bp_variant=1, bp_groups=a, bp_pixels_per_thread=q) for a in (1
 @pytest.mark.parametrize("gname,rect", [("c1", (0, 100, 40, 28)), ("c2", (416, 416, 192, 192)),
                                         ("c4", (1000, 37, 300, 261)), ("odd", (3, 5, 31, 77)),
                                         ("odd", (96, 0, 1, 1)), ("c1", (0, 127, 128, 1)),
-                                        ("c2", (300, 310, 400, 380)), ("c2", (0, 724, 470, 300))])
+                                        ("c2", (300, 310, 400, 380)), ("c2", (0, 724, 470, 300)),
+                                        ("c2", (200, 150, 360, 380))])
 def test_every_launch_shape_matches_oracle(ctx, gname, rect):
     """Every forward-projector and backprojector launch shape (segments, rays per lane,
     LDS-staged lines, XCD order, direct or LDS-staged band reads, groups, pixels per thread) agrees

@@ -15,7 +15,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1604_02292_amd", "csrc")
 HOST_SOURCES = ["tomo_plan.cpp", "tomo_capi.cpp", "tomo_serve.cpp", "tomo_local.cpp"]
-DEVICE_SOURCES = ["tomo_kernels.hip", "tomo_noalloc.hip"]
+DEVICE_SOURCES = ["tomo_kernels.hip", "tomo_noalloc.hip", "tomo_probe.hip"]
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
        "-fno-omit-frame-pointer", "-g", "-O1"]
 
