@@ -608,13 +608,14 @@ def local_leg(torch, d, reps=3, iters=None, compare=True, cpu=True):
         ctx.close()
 
 
-def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.75, 0.9),
-                cpu=False):
+def serving_leg(torch, slices, n_req=1000, n_warm=200, fractions=(0.25, 0.5, 0.75, 0.9),
+                cpu=False, n_main=2000):
     """64 resident 2048^2 slices (512 angles x 3072 bins); requests with side
     U{32..512}, margin ceil(side/4), 80% CP-TV / 20% nonnegative SIRT, 100-300
     iterations.  Capacity = completion rate with all requests queued at once;
     latency = submit-to-done at Poisson arrivals of the given fractions of that
-    rate; plain = the first 200 of those requests solved one at a time with roi_solve; small
+    rate (n_main requests at half of it, the point the line quotes, n_req at the
+    others); plain = the first 200 of those requests solved one at a time with roi_solve; small
     budget = the capacity run again with a workspace that holds only a few
     slots next to two resident slices, so admission by HBM budget binds."""
     import synth
@@ -663,7 +664,8 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
         cap = n_req / t_cap
         sweep = []
         for k, fr in enumerate(fractions):
-            reqs_open = synth.serving_requests(n_req, fr * cap, seed_offset=3 + k)
+            n_fr = max(n_req, n_main) if fr == 0.5 else n_req
+            reqs_open = synth.serving_requests(n_fr, fr * cap, seed_offset=3 + k)
             stages = []
             t_open, lat_open, _ = run(ctx, sids, reqs_open, True, stages)
             # where a request's time goes: queued (submit -> admitted), preparation
@@ -672,8 +674,8 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
                      for key in ("queued_ms", "prepare_ms", "run_ms")}
             split.update({f"{key}_p99_ms": pct([q[key] for q in stages], 99)
                           for key in ("queued_ms", "prepare_ms", "run_ms")})
-            sweep.append({"fraction_of_capacity": fr, "offered_qps": fr * cap,
-                          "achieved_qps": n_req / t_open, "p50_ms": pct(lat_open, 50),
+            sweep.append({"fraction_of_capacity": fr, "offered_qps": fr * cap, "requests": n_fr,
+                          "achieved_qps": n_fr / t_open, "p50_ms": pct(lat_open, 50),
                           "p99_ms": pct(lat_open, 99), "stages": split})
             log(f"serving: {fr:.2f} x capacity ({fr * cap:.1f} req/s): p50 {pct(lat_open, 50):.1f} "
                 f"ms p99 {pct(lat_open, 99):.1f} ms")
@@ -709,7 +711,7 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
         peak = ctx.tomo_workspace_usage()
     finally:
         ctx.close()
-    mid = sweep[min(1, len(sweep) - 1)]
+    mid = next((p for p in sweep if p["fraction_of_capacity"] == 0.5), sweep[0])
     base = serve_cpu_baseline(slices, reqs, cfg) if cpu else None
     log(f"serving: register {t_reg:.2f}s; capacity {cap:.1f} req/s; plain {n_plain / t_plain:.1f} "
         f"req/s; {small >> 20} MiB budget: {len(reqs_small) / t_small:.1f} req/s")
@@ -719,7 +721,8 @@ def serving_leg(torch, slices, n_req=1000, n_warm=100, fractions=(0.25, 0.5, 0.7
             "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "latency_sweep": sweep,
             "saturated_p50_ms": pct(lat_cap, 50), "saturated_p99_ms": pct(lat_cap, 99),
             "one_at_a_time_solves_per_s": n_plain / t_plain, "one_at_a_time_requests": n_plain,
-            "requests": n_req, "warmup_requests": n_warm, "max_rel_diff_served_vs_plain": diff,
+            "requests": n_req, "requests_at_half_capacity": mid["requests"],
+            "warmup_requests": n_warm, "max_rel_diff_served_vs_plain": diff,
             "small_budget": {"workspace_mib": small >> 20, "resident_slices": 2,
                              "capacity_solves_per_s": len(reqs_small) / t_small,
                              "p50_ms": pct(lat_small, 50), "p99_ms": pct(lat_small, 99),
@@ -1003,8 +1006,8 @@ def main():
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-local", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000,
-                    help="requests per serving load point")
-    ap.add_argument("--serve-warmup", type=int, default=100)
+                    help="requests per serving load point (at least 2000 at half of capacity)")
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the untimed quality comparisons (global solves, FBP, Alg. 2 "
                          "against the phantom)")
