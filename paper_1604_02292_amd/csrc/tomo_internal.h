@@ -130,7 +130,7 @@ static_assert(sizeof(Item) == 32, "Item layout");
 // block.  32 lines per stage for line pitches up to kFpsMaxPitch, 24 up to
 // kFpsMaxPitch24: both keep the LDS of a block under a third of the CU's 160 KB.
 constexpr int kFpStaged = 4;   // the rays_per_lane value that selects it
-constexpr int kFpsThreads = 256;
+constexpr int kFpsThreads = 512;   // eight waves: three blocks per CU give six waves per SIMD
 constexpr int kFpsMaxRounds = 8, kFpsMaxPairs = kFpsMaxRounds * kFpsThreads;
 constexpr int kFpsMaxPitch = 336;     // (336 + 68) x 33 x 4 B = 53.3 KB
 constexpr int kFpsMaxPitch24 = 480;   // (480 + 52) x 25 x 4 B = 53.2 KB
