@@ -459,15 +459,16 @@ tomo_status tomo_kernel_time(tomo_ctx* ctx, int32_t kernel, int64_t* launches, d
                              int reset);
 
 /* Calibration of the projectors' ALU roof; not a step of the method.  One launch on
- * hip_stream of `blocks` blocks of 256 threads in which every lane runs iters x 128
- * FP32 fused multiply-adds v = v a + b (eight independent chains of iters x 16) and
- * writes the sum of its chains to out[block * 256 + lane] (device, caller-owned,
- * blocks x 256 floats).  The launch issues blocks x 256 x iters x 128 vector FP32
- * lane-instructions besides a few per lane; timed by the caller (events on the same
- * stream), it gives the lane-instruction rate the chip sustains.
- * Errors: EINVAL (null out, blocks or iters outside [1, 2^20]), EHIP. */
-tomo_status tomo_valu_probe(tomo_ctx* ctx, int32_t blocks, int32_t iters, float a, float b,
-                            float* out, void* hip_stream);
+ * hip_stream of `blocks` blocks of 256 threads in which every lane runs iters x 16
+ * steps on each of eight independent chains and writes the sum of its chains to
+ * out[block * 256 + lane] (device, caller-owned, blocks x 256 floats).  A step is, by
+ * mode: 0 one FP32 FMA v = v a + b; 1 an FMA and a fraction, v = fract(v a + b) (two
+ * instructions); 2 one FP32 add v = v + b.  The launch issues blocks x 256 x iters x
+ * 128 steps' vector lane-instructions besides a few per lane; timed by the caller
+ * (events on the same stream), it gives the rate at which the chip retires them.
+ * Errors: EINVAL (null out, blocks or iters outside [1, 2^20], unknown mode), EHIP. */
+tomo_status tomo_valu_probe(tomo_ctx* ctx, int32_t blocks, int32_t iters, int32_t mode, float a,
+                            float b, float* out, void* hip_stream);
 
 /* Workspace bytes in use now and at peak (host outputs). */
 tomo_status tomo_workspace_usage(tomo_ctx* ctx, size_t* used, size_t* peak);

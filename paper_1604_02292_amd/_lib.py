@@ -83,7 +83,7 @@ SIGNATURES = {
     "tomo_roi_nnz": (C.c_int, [_P, _I, tomo_rect, C.POINTER(C.c_int64)]),
     "tomo_kernel_timing": (C.c_int, [_P, C.c_int]),
     "tomo_kernel_time": (C.c_int, [_P, _I, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int]),
-    "tomo_valu_probe": (C.c_int, [_P, _I, _I, C.c_float, C.c_float, _P, _P]),
+    "tomo_valu_probe": (C.c_int, [_P, _I, _I, _I, C.c_float, C.c_float, _P, _P]),
     "tomo_workspace_usage": (C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "tomo_synchronize": (C.c_int, [_P]),
 }

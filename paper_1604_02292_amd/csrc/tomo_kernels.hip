@@ -671,7 +671,7 @@ template <int AG>
 constexpr int bp_threads() { return AG > 4 ? 64 * AG : 256; }
 
 template <int AG, int PPT, bool STAGED, bool COMP, bool TWO>
-__global__ __launch_bounds__(bp_threads<AG>()) void bp_kernel(const Job* __restrict__ jobs,
+__global__ __launch_bounds__(bp_threads<AG>(), (STAGED && !TWO) ? 8 : 1) void bp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
                                                  int step, int contiguous) {
     constexpr int NT = bp_threads<AG>();     // 4 waves, or one wave per group beyond 4
@@ -695,9 +695,11 @@ __global__ __launch_bounds__(bp_threads<AG>()) void bp_kernel(const Job* __restr
     constexpr int SHIFT = 32, WS = 64;
     constexpr int PSH = isqrt_above((TW / 2) * (TW / 2) + (TH / 2) * (TH / 2)) + 1;
     static_assert(PSH <= SHIFT, "pixel offsets exceed the window");
-    // per stage: angles per group, windows, windows per wave (two-channel windows hold
-    // twice the data, so half as many per stage keep the LDS footprint)
-    constexpr int KA = (TWO ? 16 : 32) / AG, NW = AG * KA, WPW = NW / 4;
+    // per stage: angles per group, windows, windows per wave.  16 windows of 64 entries
+    // keep the single-channel block at 18 KB of LDS and, with the launch bounded to
+    // eight waves per SIMD, 62 VGPRs: eight blocks per CU, which pays for the extra
+    // stage barriers (32 windows per stage allowed six)
+    constexpr int KA = 16 / AG, NW = AG * KA, WPW = NW / 4;
     static_assert(TW * TW + TH * TH <= 36 * 36, "tile too large for the band window");
     __shared__ Anchor anc[ANC];
     // [guard][buffer 0: NW windows][buffer 1][guard]: stray lanes of ragged tiles

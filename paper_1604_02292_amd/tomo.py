@@ -352,9 +352,9 @@ class Context:
                                               int(bool(reset))))
         return n.value, ms.value
 
-    def tomo_valu_probe(self, blocks, iters, a, b, out, stream=None):
-        self._check(self.lib.tomo_valu_probe(self.h, int(blocks), int(iters), float(a), float(b),
-                                             _ptr(out, (int(blocks) * 256,), "out"),
+    def tomo_valu_probe(self, blocks, iters, a, b, out, mode=0, stream=None):
+        self._check(self.lib.tomo_valu_probe(self.h, int(blocks), int(iters), int(mode), float(a),
+                                             float(b), _ptr(out, (int(blocks) * 256,), "out"),
                                              _stream(stream)))
 
     def tomo_workspace_usage(self):
