@@ -671,7 +671,7 @@ template <int AG>
 constexpr int bp_threads() { return AG > 4 ? 64 * AG : 256; }
 
 template <int AG, int PPT, bool STAGED, bool COMP, bool TWO>
-__global__ __launch_bounds__(bp_threads<AG>(), (STAGED && !TWO) ? 8 : 1) void bp_kernel(const Job* __restrict__ jobs,
+__global__ __launch_bounds__(bp_threads<AG>(), STAGED ? (TWO ? 6 : 8) : 1) void bp_kernel(const Job* __restrict__ jobs,
                                                  const Item* __restrict__ items, int n_items,
                                                  int step, int contiguous) {
     constexpr int NT = bp_threads<AG>();     // 4 waves, or one wave per group beyond 4
@@ -698,7 +698,8 @@ __global__ __launch_bounds__(bp_threads<AG>(), (STAGED && !TWO) ? 8 : 1) void bp
     // per stage: angles per group, windows, windows per wave.  16 windows of 64 entries
     // keep the single-channel block at 18 KB of LDS and, with the launch bounded to
     // eight waves per SIMD, 62 VGPRs: eight blocks per CU, which pays for the extra
-    // stage barriers (32 windows per stage allowed six)
+    // stage barriers (32 windows per stage allowed six).  The two-channel block (27 KB)
+    // is bounded to six waves, the most its LDS allows.
     constexpr int KA = 16 / AG, NW = AG * KA, WPW = NW / 4;
     static_assert(TW * TW + TH * TH <= 36 * 36, "tile too large for the band window");
     __shared__ Anchor anc[ANC];
