@@ -387,10 +387,10 @@ tomo_status tomo_set_graphs(tomo_ctx* ctx, int enable);
  *                         below sqrt 2 pixels; otherwise 1 is used), or 4: the
  *                         LDS-staged forward projector (32 lines of the regions
  *                         at a time in LDS, 24 when the padded lines hold more
- *                         than 336 entries, shared by groups of up to 64 angles;
- *                         regions whose padded lines hold at most 480 entries,
- *                         about 470 pixels a side, and bands of at most 2048
- *                         rays; elsewhere 2 is used)
+ *                         than 336 entries, 16 when more than 480, shared by
+ *                         groups of up to 64 angles; regions whose padded lines
+ *                         hold at most 784 entries, about 776 pixels a side, and
+ *                         bands of at most 4096 rays; elsewhere 2 is used)
  *   fp_xcd_order          order in which forward-projector work items are dealt
  *                         to the chip's 8 XCDs: 1 = one contiguous eighth of the
  *                         item list per XCD (L2 locality), 2 = round-robin

@@ -40,7 +40,7 @@ static void apply_knobs(LaunchCfg& L, const tomo_launch& k) {
 // The LDS-staged forward projector runs where the regions' lines and bands fit it;
 // elsewhere a request for it falls back to two rays per lane.
 static void settle_fp_variant(LaunchCfg& L, int max_pitch, int max_w) {
-    const bool fits = max_pitch > 0 && max_pitch <= kFpsMaxPitch24 && max_w <= kFpsMaxPairs;
+    const bool fits = max_pitch > 0 && max_pitch <= kFpsMaxPitch16 && max_w <= kFpsMaxPairs;
     if (L.rp == kFpStaged && !fits) L.rp = 2;
     L.spitch = L.rp == kFpStaged ? max_pitch : 0;
 }

@@ -128,13 +128,17 @@ static_assert(sizeof(Item) == 32, "Item layout");
 // LDS-staged forward projector: L image lines per stage (stride L + 1, L + 2 zero
 // columns on each side), kFpsThreads threads, at most kFpsMaxPairs (angle, ray) pairs per
 // block.  32 lines per stage for line pitches up to kFpsMaxPitch, 24 up to
-// kFpsMaxPitch24: both keep the LDS of a block under a third of the CU's 160 KB.
+// kFpsMaxPitch24, 16 up to kFpsMaxPitch16: each keeps the LDS of a block under a third
+// of the CU's 160 KB (beyond 752 entries, 16-line stages fit two blocks per CU).
 constexpr int kFpStaged = 4;   // the rays_per_lane value that selects it
 constexpr int kFpsThreads = 512;   // eight waves: three blocks per CU give six waves per SIMD
 constexpr int kFpsMaxRounds = 8, kFpsMaxPairs = kFpsMaxRounds * kFpsThreads;
 constexpr int kFpsMaxPitch = 336;     // (336 + 68) x 33 x 4 B = 53.3 KB
 constexpr int kFpsMaxPitch24 = 480;   // (480 + 52) x 25 x 4 B = 53.2 KB
-inline int fps_lines(int pitch) { return pitch <= kFpsMaxPitch ? 32 : 24; }
+constexpr int kFpsMaxPitch16 = 784;   // (784 + 36) x 17 x 4 B = 55.8 KB
+inline int fps_lines(int pitch) {
+    return pitch <= kFpsMaxPitch ? 32 : pitch <= kFpsMaxPitch24 ? 24 : 16;
+}
 inline size_t fps_lds_bytes(int pitch) {
     const int L = fps_lines(pitch);
     return (size_t)(pitch + 2 * (L + 2)) * (L + 1) * sizeof(float);
@@ -147,7 +151,7 @@ inline size_t fps_lds_bytes(int pitch) {
 // (segments must be 1; the items must be built for 512 rays per block).
 // rays_per_lane = kFpStaged: the LDS-staged forward projector (items from fps_items;
 // stage_pitch = the largest line pitch, xp or tp, of the launch's jobs, at most
-// kFpsMaxPitch24).
+// kFpsMaxPitch16; a larger value than the jobs need only selects shorter stages).
 hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, int segments,
                      hipStream_t s, int contiguous = 1, int rays_per_lane = 1,
                      int stage_pitch = 0);

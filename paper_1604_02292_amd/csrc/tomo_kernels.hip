@@ -2268,13 +2268,17 @@ hipError_t launch_fp(const Job* jobs, const Item* items, int n_items, int step, 
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(pad8(n_items));
     if (rays_per_lane == kFpStaged) {
-        if (stage_pitch < 1 || stage_pitch > kFpsMaxPitch24) return hipErrorInvalidValue;
+        if (stage_pitch < 1 || stage_pitch > kFpsMaxPitch16) return hipErrorInvalidValue;
         const size_t lds = fps_lds_bytes(stage_pitch);
-        if (fps_lines(stage_pitch) == 32)
+        const int L = fps_lines(stage_pitch);
+        if (L == 32)
             hipLaunchKernelGGL(fp_staged_kernel<32>, grid, dim3(kFpsThreads), lds, s, jobs,
                                items, n_items, step, contiguous);
-        else
+        else if (L == 24)
             hipLaunchKernelGGL(fp_staged_kernel<24>, grid, dim3(kFpsThreads), lds, s, jobs,
+                               items, n_items, step, contiguous);
+        else
+            hipLaunchKernelGGL(fp_staged_kernel<16>, grid, dim3(kFpsThreads), lds, s, jobs,
                                items, n_items, step, contiguous);
         return hipGetLastError();
     }

@@ -110,7 +110,7 @@ def test_launch_shapes_by_problem_size():
     forward-projector segments, 8 backprojector angle groups, direct band reads); the
     256 tiles of 4096^2 (extended parts up to 320^2) and the 64-ROI batch on 2048^2
     (extended parts up to 384^2, staged 24 lines at a time) get the LDS-staged forward
-    projector (rays per lane 4), a region wider than the staged lines hold two rays per lane,
+    projector (rays per lane 4), a region wider than 16-line stages hold two rays per lane,
     also when the staged projector is forced; all get the LDS-staged backprojector with two
     pixels per thread.  Forced knobs are validated and kept."""
     import synth
@@ -134,7 +134,7 @@ def test_launch_shapes_by_problem_size():
     # backprojector's (equal tiles) in contiguous eighths
     assert (t4["fp_xcd_order"], t4["bp_xcd_order"]) == (2, 1)
     assert (big["fp_xcd_order"], big["bp_xcd_order"]) == (2, 1)
-    wide = batch + [make_params((600, 600, 512, 512), 64, "cp", 0.02, 200)]   # 640^2
+    wide = batch + [make_params((500, 500, 800, 800), 64, "cp", 0.02, 200)]   # 928^2
     assert ctx.tomo_resolve_launch(g3, wide)["fp_rays_per_lane"] == 2
     ctx.tomo_set_launch(fp_rays_per_lane=4)
     assert ctx.tomo_resolve_launch(g3, wide)["fp_rays_per_lane"] == 2

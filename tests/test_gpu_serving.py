@@ -104,6 +104,37 @@ def test_alone_equals_mix_and_matches_roi_solve(served):
         assert rel(o.double().cpu().numpy(), a.double().cpu().numpy()) <= 1e-4
 
 
+def test_uneven_slots_alone_equal_mix():
+    """Slots of very different sizes (an 800^2 region beside 96^2 and 280 x 230 ones,
+    CP and SIRT) share ticks; every result is bit-identical alone and in the mix."""
+    from paper_1604_02292_amd import Context, make_params
+    ctx = Context(0, workspace_bytes=4 << 30)
+    try:
+        g = ctx.tomo_set_geometry(1024, 128, 1536)
+        rng = np.random.default_rng(1604)
+        sino = dev(10.0 * rng.random((128, 1536)))
+        sid = ctx.tomo_register_sinogram(g, sino)
+        reqs = [make_params((100, 100, 800, 800), 0, "cp", 0.05, 12),
+                make_params((40, 900, 64, 64), 16, "cp", 0.05, 20),
+                make_params((700, 20, 200, 150), 40, "sirt", 0.0, 16)]
+        print("[serving] wide + narrow slots", flush=True)
+        alone = []
+        for p in reqs:
+            o = torch.empty((p.roi.rows, p.roi.cols), device="cuda")
+            wait_all(ctx, [ctx.roi_submit(sid, p, o)])
+            alone.append(o.clone())
+        outs = [torch.empty((p.roi.rows, p.roi.cols), device="cuda") for p in reqs]
+        wait_all(ctx, [ctx.roi_submit(sid, p, o) for p, o in zip(reqs, outs)])
+        torch.cuda.synchronize()
+        for a, b in zip(alone, outs):
+            assert bool(torch.isfinite(a).all())
+            assert torch.equal(a, b)
+        ctx.tomo_synchronize()
+        ctx.tomo_unregister_sinogram(sid)
+    finally:
+        ctx.close()
+
+
 def test_request_timeline(served):
     """roi_poll_stages on the GPU path: every finished request reports its queueing,
     preparation and iteration times, which add up to its latency; a request that waited
