@@ -10,14 +10,15 @@ namespace {
 
 constexpr int kProbeThreads = 256;
 constexpr int kProbeChains = 8;    // independent dependency chains per lane
-constexpr int kProbeUnroll = 16;   // FMAs per chain per loop trip
+constexpr int kProbeUnroll = 16;   // steps per chain per loop trip
 
 // Each lane runs iters x kProbeUnroll steps on each of eight independent chains
 // (enough to cover the latency at one wave per SIMD), then stores the chains' sum so
 // that none of the work is dead.  A step is, by MODE:
-//   0  one FMA, v = v a + b                       (one instruction class)
+//   0  one FMA, v = v a + b                       (one class, a scalar operand)
 //   1  an FMA then a fraction, v = fract(v a + b) (two classes the chip can pair)
-//   2  one add, v = v + b                         (a class issued at twice the FMA rate)
+//   2  one add, v = v + b                         (one class, a scalar operand: adds
+//                                                  with vector operands only pair)
 template <int MODE>
 __global__ __launch_bounds__(kProbeThreads) void valu_probe_kernel(float* __restrict__ out,
                                                                    int iters, float a, float b) {
