@@ -96,7 +96,8 @@ SHAPES_BP = [dict(bp_variant=1, bp_groups=a, bp_pixels_per_thread=q) for a in (1
                                         ("c4", (1000, 37, 300, 261)), ("odd", (3, 5, 31, 77)),
                                         ("odd", (96, 0, 1, 1)), ("c1", (0, 127, 128, 1)),
                                         ("c2", (300, 310, 400, 380)), ("c2", (0, 724, 470, 300)),
-                                        ("c2", (200, 150, 360, 380)), ("c2", (100, 100, 600, 500))])
+                                        ("c2", (200, 150, 360, 380)), ("c2", (100, 100, 600, 500)),
+                                        ("c2", (100, 200, 778, 700))])
 def test_every_launch_shape_matches_oracle(ctx, gname, rect):
     """Every forward-projector and backprojector launch shape (segments, rays per lane,
     LDS-staged lines, XCD order, direct or LDS-staged band reads, groups, pixels per thread) agrees
@@ -113,7 +114,7 @@ def test_every_launch_shape_matches_oracle(ctx, gname, rect):
     try:
         # segments 1..8 with one ray per lane, two rays per lane, and the LDS-staged
         # projector (rays per lane 4; 32 lines per stage, 24 for the regions of more than
-        # 330 pixels a side, 16 for more than 470, up to 778)
+        # 330 pixels a side, 16 for more than 470, up to 778: the largest stage, 56 KB)
         for seg, rpl in [(1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (1, 4)]:
             for xo in (1, 2):
                 ctx.tomo_set_launch(fp_segments=seg, fp_rays_per_lane=rpl, fp_xcd_order=xo)
