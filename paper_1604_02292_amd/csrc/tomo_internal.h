@@ -167,8 +167,10 @@ hipError_t launch_bp(const Job* jobs, const Item* items, int n_items, int step, 
 // FGP iterations [i0, i0 + kFgpSteps) of every FISTA job, on tiles of
 // kFgpTile x kFgpTile pixels (items: job, tile row, tile column); the launch that
 // reaches a job's last inner iteration also forms x, the FISTA momentum point and
-// the new correction v (written to the padded copies read at step + 1).
-constexpr int kFgpTile = 32, kFgpSteps = 8;
+// the new correction v (written to the padded copies read at step + 1).  48-pixel tiles
+// recompute a smaller share of halo pixels than 32-pixel ones (66^2 windows against 50^2)
+// and, with 1024-thread blocks, keep five pixels per thread in registers.
+constexpr int kFgpTile = 48, kFgpSteps = 8;
 hipError_t launch_fgp(const Job* jobs, const Item* items, int n_items, int step, int i0,
                       hipStream_t s);
 // Haar l1 prox of local FISTA: per aligned 2^levels tile of the job (items: job, tile

@@ -1510,7 +1510,7 @@ __global__ void pad_truncated_kernel(const float* __restrict__ trunc, int nb, in
 // the gradient is zero on the region's last row / column (Neumann), so the duals
 // stay zero there, as in the CP kernel's TV.
 // ---------------------------------------------------------------------------
-constexpr int kFgpThreads = 512;
+constexpr int kFgpThreads = 1024;   // 16 waves; two blocks per CU: eight waves per SIMD
 
 __global__ __launch_bounds__(kFgpThreads) void fgp_kernel(const Job* __restrict__ jobs,
                                                   const Item* __restrict__ items, int n_items,
