@@ -48,3 +48,39 @@ def test_traffic_record_needs_the_current_kernel_source(tmp_path, monkeypatch):
     # any edit of the kernel source voids the record
     src.write_text("// kernel source, changed\n")
     assert bench.profiled_traffic("single-roi-1024", "bp_kernel") is None
+
+
+def _committed_records():
+    recs = []
+    prof = os.path.join(ROOT, "profiles")
+    for fn in sorted(os.listdir(prof)):
+        if fn.endswith(".md"):
+            with open(os.path.join(prof, fn)) as f:
+                recs += [(fn, json.loads(line[len("traffic-json: "):]))
+                         for line in f if line.startswith("traffic-json: ")]
+    return recs
+
+
+def test_committed_traffic_records_are_consistent():
+    recs = _committed_records()
+    assert recs
+    # one set, all taken on one kernel source
+    assert len({r["kernel_source_sha256"] for _, r in recs}) == 1
+    keys = {(r["workload"], r["kernel"]) for _, r in recs}
+    assert len(keys) == len(recs)
+    # the pairs the benchmark looks up
+    for key in [("tiles256-n4096-a512", "bp_kernel"), ("batch64-n2048-a256", "bp_kernel"),
+                ("single-roi-1024", "bp_kernel"), ("single-roi-1024", "fp_kernel"),
+                ("batch64-n2048-a256-alg2", "bp_kernel (two-channel)")]:
+        assert key in keys, key
+    for fn, r in recs:
+        # bytes = FETCH_SIZE x scale + WRITE_SIZE x scale, the counters printed to 0.1 KiB
+        est = 1024.0 * (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"])
+        tol = 0.05 * 1024.0 * (r["fetch_scale"] + r["write_scale"]) + 1.0
+        assert abs(r["bytes_per_launch"] - est) <= tol, (fn, r["kernel"])
+        # the copy calibration: on a 256 MiB copy FETCH_SIZE counts half of the bytes read,
+        # WRITE_SIZE all of those written
+        assert abs(r["fetch_scale"] - 2.0) < 0.01 and abs(r["write_scale"] - 1.0) < 0.01
+        # a unit slip (KiB taken for bytes, a scale left out) would put the bytes far below
+        # the kernel's algorithmic bytes
+        assert r["bytes_per_launch"] > 0.5 * r["algorithmic_bytes_per_launch"], (fn, r["kernel"])
